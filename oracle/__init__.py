@@ -1,0 +1,309 @@
+"""FP64 CPU oracle for restarted PDHG (Python side of ``pdhg_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, the package smoke check and the
+benchmark's CPU-baseline leg may import this module.  The GPU library and its
+Python binding never import, call or fall back to it, and the two share no
+code: the only common input is the problem data built by ``lpgen``.
+
+The C library is plain double-precision loops in the order the paper states
+the method (see the header of ``pdhg_oracle.c`` for the section each function
+follows).  This wrapper only marshals arrays and performs one bookkeeping step
+of its own: the stable reordering of rows so that the ">=" rows come first
+(the stacked K = [G; A] of Section 2.2); vectors indexed by rows are taken and
+returned in the caller's row order.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pdhg_oracle.c")
+_LIB = os.path.join(_HERE, "liborc.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain IEEE double; x86-64 without FMA)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-fno-fast-math", "-ffp-contract=off", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class KKT(C.Structure):
+    _fields_ = [(k, C.c_double) for k in
+                ("pres", "dres", "pobj", "dobj", "gap", "rel_pres", "rel_dres", "rel_gap", "rel_kkt")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Opts(C.Structure):
+    _fields_ = [("ruiz_iters", C.c_int), ("use_restarts", C.c_int), ("use_pw_update", C.c_int),
+                ("check_every", C.c_int), ("max_iters", C.c_longlong), ("eps", C.c_double),
+                ("step_size", C.c_double), ("step_frac", C.c_double), ("primal_weight", C.c_double),
+                ("power_max_iters", C.c_int), ("power_tol", C.c_double), ("beta_suff", C.c_double),
+                ("beta_nec", C.c_double), ("beta_art", C.c_double), ("eps_zero", C.c_double)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int), ("from_avg", C.c_int), ("iters", C.c_longlong),
+                ("restarts", C.c_int), ("power_iters", C.c_int), ("knorm", C.c_double),
+                ("eta", C.c_double), ("omega0", C.c_double), ("omega", C.c_double),
+                ("tau", C.c_double), ("sigma", C.c_double), ("kkt", KKT), ("trace_len", C.c_int)]
+
+
+class TraceRec(C.Structure):
+    _fields_ = [("iter", C.c_longlong), ("restarted", C.c_int), ("cand_avg", C.c_int),
+                ("kkt_cand", C.c_double), ("omega", C.c_double), ("rel_kkt_cur", C.c_double),
+                ("rel_kkt_avg", C.c_double)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        P = C.c_void_p
+        D = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+        I64 = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+        I32 = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+        L.orc_prob_create.restype = P
+        L.orc_prob_create.argtypes = [C.c_int64, C.c_int64, C.c_int64, I64, I32, D, D, D, D, D]
+        L.orc_prob_free.argtypes = [P]
+        L.orc_spmv.argtypes = [P, D, D]
+        L.orc_spmv_t.argtypes = [P, D, D]
+        L.orc_kkt.argtypes = [P, D, D, C.POINTER(KKT)]
+        L.orc_ruiz.argtypes = [P, C.c_int, D, D]
+        L.orc_prob_scaled.restype = P
+        L.orc_prob_scaled.argtypes = [P, D, D]
+        L.orc_power_norm.restype = C.c_double
+        L.orc_power_norm.argtypes = [P, C.c_int, C.c_double, C.POINTER(C.c_int)]
+        L.orc_steps.argtypes = [P, C.c_double, C.c_double, D, D, C.c_longlong]
+        L.orc_solve.restype = C.c_int
+        L.orc_solve.argtypes = [P, C.POINTER(Opts), D, D, C.POINTER(Result), C.c_void_p, C.c_int]
+        L.orc_unrolled.argtypes = [P, D, D, C.c_double, C.c_double, D, D, D, D, D, D,
+                                   C.c_longlong, D, D]
+        L.orc_unrolled_vjp.argtypes = [P, D, D, C.c_double, C.c_double, D, D, D, D, D, D,
+                                       C.c_longlong, D, D, D, D, D, D, D, D]
+        _lib = L
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+@dataclass
+class SolveOpts:
+    """Options of the restarted solve; defaults are the paper's constants.
+
+    eps 1e-4 (Section 2.3.2), step 0.9/||K||_2 (Section 3.2), restart
+    constants 0.2 / 0.8 / 0.36 (Section 2.4.2), eps_zero 1e-6 (Section 2.4.3).
+    Choices the paper leaves open: 10 Ruiz passes, a check every 64 iterations,
+    power iteration to 1e-6 relative change or 1000 passes.
+    """
+
+    ruiz_iters: int = 10
+    use_restarts: bool = True
+    use_pw_update: bool = True
+    check_every: int = 64
+    max_iters: int = 1_000_000
+    eps: float = 1e-4
+    step_size: float = 0.0
+    step_frac: float = 0.9
+    primal_weight: float = 0.0
+    power_max_iters: int = 1000
+    power_tol: float = 1e-6
+    beta_suff: float = 0.2
+    beta_nec: float = 0.8
+    beta_art: float = 0.36
+    eps_zero: float = 1e-6
+
+    @staticmethod
+    def plain(**kw) -> "SolveOpts":
+        """Plain PDHG: no scaling, no restarts, no primal-weight updates."""
+        o = SolveOpts(ruiz_iters=0, use_restarts=False, use_pw_update=False)
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+
+    def c(self) -> Opts:
+        return Opts(self.ruiz_iters, int(self.use_restarts), int(self.use_pw_update),
+                    self.check_every, self.max_iters, self.eps, self.step_size, self.step_frac,
+                    self.primal_weight, self.power_max_iters, self.power_tol, self.beta_suff,
+                    self.beta_nec, self.beta_art, self.eps_zero)
+
+
+@dataclass
+class SolveResult:
+    status: int
+    x: np.ndarray
+    y: np.ndarray
+    iters: int
+    restarts: int
+    from_avg: bool
+    knorm: float
+    eta: float
+    omega0: float
+    omega: float
+    kkt: dict
+    power_iters: int
+    trace: list = field(default_factory=list)
+
+
+class Oracle:
+    """An LP loaded into the oracle (rows reordered to [G; A] internally)."""
+
+    def __init__(self, lp):
+        self.lib = _load()
+        self.lp = lp
+        rt = np.asarray(lp.row_type)
+        ge = np.nonzero(rt == 0)[0]
+        eq = np.nonzero(rt != 0)[0]
+        self.perm = np.concatenate([ge, eq]).astype(np.int64)  # internal row i = user row perm[i]
+        self.m1 = int(ge.shape[0])
+        self.n, self.m = int(lp.n), int(lp.m)
+        lens = np.diff(lp.rowptr)[self.perm]
+        rp = np.zeros(self.m + 1, dtype=np.int64)
+        np.cumsum(lens, out=rp[1:])
+        idx = _gather_rows(lp.rowptr, self.perm)
+        self._rp = rp
+        self._ci = np.ascontiguousarray(np.asarray(lp.col)[idx], dtype=np.int32)
+        self._v = _f64(np.asarray(lp.val)[idx])
+        self.q = _f64(np.asarray(lp.rhs)[self.perm])
+        self.c, self.l, self.u = _f64(lp.c), _f64(lp.l), _f64(lp.u)
+        self.h = self.lib.orc_prob_create(self.n, self.m, self.m1, self._rp, self._ci, self._v,
+                                          self.c, self.q, self.l, self.u)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            self.lib.orc_prob_free(h)
+            self.h = None
+
+    # row-order helpers ------------------------------------------------------
+    def to_internal_rows(self, y):
+        return _f64(np.asarray(y)[self.perm])
+
+    def to_user_rows(self, yi):
+        out = np.empty(self.m)
+        out[self.perm] = yi
+        return out
+
+    # primitives -------------------------------------------------------------
+    def spmv(self, x):
+        """K x in user row order."""
+        out = np.empty(self.m)
+        self.lib.orc_spmv(self.h, _f64(x), out)
+        return self.to_user_rows(out)
+
+    def spmv_t(self, y):
+        """K^T y for y in user row order."""
+        out = np.empty(self.n)
+        self.lib.orc_spmv_t(self.h, self.to_internal_rows(y), out)
+        return out
+
+    def kkt(self, x, y) -> dict:
+        """Relative KKT error terms (Section 2.3.2) of (x, y), y in user row order."""
+        k = KKT()
+        self.lib.orc_kkt(self.h, _f64(x), self.to_internal_rows(y), C.byref(k))
+        return k.as_dict()
+
+    def ruiz(self, iters: int):
+        """Ruiz factors (rho in user row order, kappa) after ``iters`` passes."""
+        rho = np.empty(self.m)
+        kap = np.empty(self.n)
+        self.lib.orc_ruiz(self.h, iters, rho, kap)
+        return self.to_user_rows(rho), kap
+
+    def scaled(self, iters: int) -> "_Scaled":
+        return _Scaled(self, iters)
+
+    def power_norm(self, ruiz_iters: int = 0, max_iters: int = 1000, tol: float = 1e-6):
+        s = self.scaled(ruiz_iters)
+        it = C.c_int(0)
+        v = self.lib.orc_power_norm(s.h, max_iters, tol, C.byref(it))
+        return v, it.value
+
+    def steps(self, x, y, tau, sigma, k, ruiz_iters: int = 0):
+        """k fixed PDHG steps on the scaled problem; (x, y) in scaled variables, y user order."""
+        s = self.scaled(ruiz_iters)
+        xi = _f64(np.array(x, copy=True))
+        yi = self.to_internal_rows(y)
+        self.lib.orc_steps(s.h, tau, sigma, xi, yi, k)
+        return xi, self.to_user_rows(yi)
+
+    def solve(self, opts: Optional[SolveOpts] = None, trace_cap: int = 4096) -> SolveResult:
+        opts = opts or SolveOpts()
+        x = np.empty(self.n)
+        y = np.empty(self.m)
+        r = Result()
+        tr = (TraceRec * trace_cap)()
+        self.lib.orc_solve(self.h, C.byref(opts.c()), x, y, C.byref(r), C.cast(tr, C.c_void_p),
+                           trace_cap)
+        trace = [dict(iter=t.iter, restarted=t.restarted, cand_avg=t.cand_avg,
+                      kkt_cand=t.kkt_cand, omega=t.omega, rel_kkt_cur=t.rel_kkt_cur,
+                      rel_kkt_avg=t.rel_kkt_avg) for t in tr[:r.trace_len]]
+        return SolveResult(r.status, x, self.to_user_rows(y), r.iters, r.restarts, bool(r.from_avg),
+                           r.knorm, r.eta, r.omega0, r.omega, r.kkt.as_dict(), r.power_iters, trace)
+
+    def unrolled(self, ruiz_iters, tau, sigma, c, q, l, u, x0, y0, K):
+        """K fixed PDHG steps with inputs and outputs in original variables (q, y user order)."""
+        s = self.scaled(ruiz_iters)
+        xk = np.empty(self.n)
+        yk = np.empty(self.m)
+        self.lib.orc_unrolled(s.h, s.rho_i, s.kap, tau, sigma, _f64(c), self.to_internal_rows(q),
+                              _f64(l), _f64(u), _f64(x0), self.to_internal_rows(y0), K, xk, yk)
+        return xk, self.to_user_rows(yk)
+
+    def unrolled_vjp(self, ruiz_iters, tau, sigma, c, q, l, u, x0, y0, K, gx, gy):
+        """Reverse-mode derivative of ``unrolled``: dict of dL/d{c,q,l,u,x0,y0}."""
+        s = self.scaled(ruiz_iters)
+        n, m = self.n, self.m
+        gc, gl, gu, gx0 = (np.empty(n) for _ in range(4))
+        gq, gy0 = np.empty(m), np.empty(m)
+        self.lib.orc_unrolled_vjp(s.h, s.rho_i, s.kap, tau, sigma, _f64(c), self.to_internal_rows(q),
+                                  _f64(l), _f64(u), _f64(x0), self.to_internal_rows(y0), K, _f64(gx),
+                                  self.to_internal_rows(gy), gc, gq, gl, gu, gx0, gy0)
+        return dict(c=gc, q=self.to_user_rows(gq), l=gl, u=gu, x0=gx0, y0=self.to_user_rows(gy0))
+
+
+class _Scaled:
+    """Scaled problem K~ = diag(rho) K diag(kappa) owned by the oracle."""
+
+    def __init__(self, o: Oracle, iters: int):
+        self.lib = o.lib
+        self.rho_i = np.empty(o.m)
+        self.kap = np.empty(o.n)
+        o.lib.orc_ruiz(o.h, iters, self.rho_i, self.kap)
+        self.h = o.lib.orc_prob_scaled(o.h, self.rho_i, self.kap)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            self.lib.orc_prob_free(h)
+            self.h = None
+
+
+def _gather_rows(rowptr, perm):
+    """Entry indices of rows ``perm`` concatenated (vectorised)."""
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    if perm.shape[0] == 0:
+        return np.zeros(0, dtype=np.int64)
+    lens = rowptr[perm + 1] - rowptr[perm]
+    starts = rowptr[perm]
+    tot = int(lens.sum())
+    out = np.repeat(starts - np.concatenate([[0], np.cumsum(lens)[:-1]]), lens)
+    return out + np.arange(tot, dtype=np.int64)

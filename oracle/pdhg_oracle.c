@@ -1,0 +1,731 @@
+/*
+ * pdhg_oracle.c -- plain FP64 CPU oracle for restarted PDHG on linear programs.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the GPU path.  Only
+ * the test-suite, the package's smoke check and the benchmark's CPU-baseline
+ * leg may load it; the GPU library never links it, includes it or falls back
+ * to it, and it shares no code with the GPU library.
+ *
+ * Everything is double precision, written as plain loops in the order the
+ * paper states the method.  The only parallelism is an OpenMP "parallel for"
+ * over rows in the sparse matrix-vector products; each row's sum runs in a
+ * fixed order, so results do not depend on the thread count.
+ *
+ * Problem (Section 2.2):  min c'x  s.t.  Gx >= h, Ax = b, l <= x <= u, with
+ * K = [G; A] (the m1 inequality rows first) and q = [h; b].  Infinite bounds
+ * are IEEE infinities.
+ *
+ * Parity status of each function (what pins it is listed in the tests):
+ *   orc_spmv / orc_spmv_t ....... pinned (scipy.sparse, brute force)
+ *   orc_kkt ...................... pinned (planted optimum, closed-form residuals)
+ *   orc_ruiz ..................... pinned (infinity-norm equilibration invariant)
+ *   orc_power_norm ............... pinned (numpy.linalg.norm(K, 2))
+ *   orc_steps .................... pinned (prox closed forms, convergence bound)
+ *   orc_solve .................... pinned (planted f*, HiGHS, vertex enumeration);
+ *                                  the restart/primal-weight trace itself is
+ *                                  parity unpinned: the paper prints no trace.
+ *   orc_unrolled_vjp ............. pinned (central finite differences)
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------- */
+/* problem container                                                          */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    int64_t n, m, m1, nnz;
+    int64_t *rp;  /* CSR of K: m+1 row pointers            */
+    int32_t *ci;  /*           nnz column indices          */
+    double *v;    /*           nnz values                  */
+    int64_t *trp; /* CSR of K^T: n+1 row pointers          */
+    int32_t *tci; /*             nnz column (= row of K)   */
+    double *tv;   /*             nnz values                */
+    double *c, *q, *l, *u;
+    double cnorm, qnorm; /* ||c||_2 and ||q||_2 of this problem */
+} orc_prob;
+
+static double dnrm2(int64_t k, const double *a)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < k; ++i) s += a[i] * a[i];
+    return sqrt(s);
+}
+
+static double ddot(int64_t k, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < k; ++i) s += a[i] * b[i];
+    return s;
+}
+
+/* K^T in CSR by a stable counting sort over the rows of K: row j of K^T lists
+ * the entries of column j of K in increasing row order. */
+static void transpose(orc_prob *p)
+{
+    int64_t n = p->n, m = p->m, nnz = p->nnz;
+    p->trp = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    p->tci = (int32_t *)malloc((size_t)(nnz ? nnz : 1) * sizeof(int32_t));
+    p->tv = (double *)malloc((size_t)(nnz ? nnz : 1) * sizeof(double));
+    for (int64_t k = 0; k < nnz; ++k) p->trp[p->ci[k] + 1]++;
+    for (int64_t j = 0; j < n; ++j) p->trp[j + 1] += p->trp[j];
+    int64_t *next = (int64_t *)malloc((size_t)(n ? n : 1) * sizeof(int64_t));
+    memcpy(next, p->trp, (size_t)n * sizeof(int64_t));
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t k = p->rp[i]; k < p->rp[i + 1]; ++k) {
+            int64_t dst = next[p->ci[k]]++;
+            p->tci[dst] = (int32_t)i;
+            p->tv[dst] = p->v[k];
+        }
+    free(next);
+}
+
+static double *dup(const double *a, int64_t k)
+{
+    double *r = (double *)malloc((size_t)(k ? k : 1) * sizeof(double));
+    if (k) memcpy(r, a, (size_t)k * sizeof(double));
+    return r;
+}
+
+orc_prob *orc_prob_create(int64_t n, int64_t m, int64_t m1, const int64_t *rp, const int32_t *ci,
+                          const double *v, const double *c, const double *q, const double *l,
+                          const double *u)
+{
+    orc_prob *p = (orc_prob *)calloc(1, sizeof(orc_prob));
+    p->n = n;
+    p->m = m;
+    p->m1 = m1;
+    p->nnz = rp[m];
+    p->rp = (int64_t *)malloc((size_t)(m + 1) * sizeof(int64_t));
+    memcpy(p->rp, rp, (size_t)(m + 1) * sizeof(int64_t));
+    p->ci = (int32_t *)malloc((size_t)(p->nnz ? p->nnz : 1) * sizeof(int32_t));
+    if (p->nnz) memcpy(p->ci, ci, (size_t)p->nnz * sizeof(int32_t));
+    p->v = dup(v, p->nnz);
+    p->c = dup(c, n);
+    p->q = dup(q, m);
+    p->l = dup(l, n);
+    p->u = dup(u, n);
+    p->cnorm = dnrm2(n, c);
+    p->qnorm = dnrm2(m, q);
+    transpose(p);
+    return p;
+}
+
+void orc_prob_free(orc_prob *p)
+{
+    if (!p) return;
+    free(p->rp); free(p->ci); free(p->v);
+    free(p->trp); free(p->tci); free(p->tv);
+    free(p->c); free(p->q); free(p->l); free(p->u);
+    free(p);
+}
+
+/* ------------------------------------------------------------------------- */
+/* sparse products                                                            */
+/* ------------------------------------------------------------------------- */
+
+/* out = K x  (row i: sum_k K_ik x_k in storage order) */
+void orc_spmv(const orc_prob *p, const double *x, double *out)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < p->m; ++i) {
+        double s = 0.0;
+        for (int64_t k = p->rp[i]; k < p->rp[i + 1]; ++k) s += p->v[k] * x[p->ci[k]];
+        out[i] = s;
+    }
+}
+
+/* out = K^T y */
+void orc_spmv_t(const orc_prob *p, const double *y, double *out)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < p->n; ++j) {
+        double s = 0.0;
+        for (int64_t k = p->trp[j]; k < p->trp[j + 1]; ++k) s += p->tv[k] * y[p->tci[k]];
+        out[j] = s;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* projections (Appendix C: prox of the box indicator is a clip, the dual     */
+/* prox clips the inequality multipliers at zero)                             */
+/* ------------------------------------------------------------------------- */
+
+static double clip(double v, double lo, double hi)
+{
+    if (v < lo) return lo;
+    if (v > hi) return hi;
+    return v;
+}
+
+/* projection onto the dual cone Lambda_j (Section 2.2): {0} for a free
+ * variable, R^- if only u is finite, R^+ if only l is finite, R otherwise */
+static double proj_lambda(double v, double l, double u)
+{
+    int lf = isfinite(l), uf = isfinite(u);
+    if (!lf && !uf) return 0.0;
+    if (!lf) return v < 0.0 ? v : 0.0;
+    if (!uf) return v > 0.0 ? v : 0.0;
+    return v;
+}
+
+/* ------------------------------------------------------------------------- */
+/* KKT error (Section 2.3.2, conditions term1-term3; dual of Section 2.2)     */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    double pres, dres;       /* ||(Ax-b, [h-Gx]^+)||_2, ||c - K^T y - lambda||_2 */
+    double pobj, dobj, gap;  /* c'x, q'y + l'lambda^+ + u'lambda^-, |dobj - pobj| */
+    double rel_pres, rel_dres, rel_gap, rel_kkt;
+} orc_kkt_t;
+
+/* All three terms of the relative KKT error for (x, y) on problem p.  The
+ * products l_j * lambda_j^+ and u_j * lambda_j^- are only formed when the
+ * factor lambda is nonzero: the cone Lambda makes lambda^+ = 0 whenever
+ * l_j = -inf (and lambda^- = 0 whenever u_j = +inf), where IEEE would give
+ * 0 * inf = NaN. */
+void orc_kkt(const orc_prob *p, const double *x, const double *y, orc_kkt_t *o)
+{
+    double *kx = (double *)malloc((size_t)(p->m ? p->m : 1) * sizeof(double));
+    double *kty = (double *)malloc((size_t)(p->n ? p->n : 1) * sizeof(double));
+    orc_spmv(p, x, kx);
+    orc_spmv_t(p, y, kty);
+    double pr2 = 0.0;
+    for (int64_t i = 0; i < p->m; ++i) {
+        double r = kx[i] - p->q[i]; /* (Ax - b)_i, or (Gx - h)_i */
+        if (i < p->m1) r = (r < 0.0) ? -r : 0.0; /* [h - Gx]^+ */
+        pr2 += r * r;
+    }
+    double dr2 = 0.0, lu = 0.0;
+    for (int64_t j = 0; j < p->n; ++j) {
+        double d = p->c[j] - kty[j];
+        double lam = proj_lambda(d, p->l[j], p->u[j]);
+        double r = d - lam;
+        dr2 += r * r;
+        if (lam > 0.0) lu += p->l[j] * lam;
+        if (lam < 0.0) lu += p->u[j] * lam;
+    }
+    o->pres = sqrt(pr2);
+    o->dres = sqrt(dr2);
+    o->pobj = ddot(p->n, p->c, x);
+    o->dobj = ddot(p->m, p->q, y) + lu;
+    o->gap = fabs(o->dobj - o->pobj);
+    o->rel_gap = o->gap / (1.0 + fabs(o->dobj) + fabs(o->pobj));
+    o->rel_pres = o->pres / (1.0 + p->qnorm);
+    o->rel_dres = o->dres / (1.0 + p->cnorm);
+    o->rel_kkt = o->rel_gap;
+    if (o->rel_pres > o->rel_kkt) o->rel_kkt = o->rel_pres;
+    if (o->rel_dres > o->rel_kkt) o->rel_kkt = o->rel_dres;
+    free(kx);
+    free(kty);
+}
+
+/* KKT error in the omega-weighted form used as the restart metric
+ * (Section 2.4.2):  sqrt(w^2 pres^2 + dres^2 / w^2 + (dobj - pobj)^2). */
+static double kkt_omega(const orc_kkt_t *k, double w)
+{
+    return sqrt(w * w * k->pres * k->pres + k->dres * k->dres / (w * w) + k->gap * k->gap);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Ruiz equilibration (Section 2.4.1, Algorithm 3)                            */
+/* ------------------------------------------------------------------------- */
+
+/* Runs `iters` passes.  Each pass takes the infinity norm of every row and
+ * every column of the current scaled matrix Kt = diag(rho) K diag(kappa)
+ * (both from the same Kt), then rho_i /= sqrt(rownorm_i) and
+ * kappa_j /= sqrt(colnorm_j); a zero norm (empty row or column) leaves the
+ * factor unchanged.  The scaled entries are recomputed from K as
+ * (rho_i * K_ij) * kappa_j each time.  No early exit, so every caller with the
+ * same pass count gets the same factors. */
+void orc_ruiz(const orc_prob *p, int iters, double *rho, double *kappa)
+{
+    int64_t m = p->m, n = p->n;
+    double *rn = (double *)malloc((size_t)(m ? m : 1) * sizeof(double));
+    double *cn = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+    for (int64_t i = 0; i < m; ++i) rho[i] = 1.0;
+    for (int64_t j = 0; j < n; ++j) kappa[j] = 1.0;
+    for (int it = 0; it < iters; ++it) {
+        for (int64_t i = 0; i < m; ++i) rn[i] = 0.0;
+        for (int64_t j = 0; j < n; ++j) cn[j] = 0.0;
+        for (int64_t i = 0; i < m; ++i)
+            for (int64_t k = p->rp[i]; k < p->rp[i + 1]; ++k) {
+                int64_t j = p->ci[k];
+                double a = fabs(rho[i] * p->v[k] * kappa[j]);
+                if (a > rn[i]) rn[i] = a;
+                if (a > cn[j]) cn[j] = a;
+            }
+        for (int64_t i = 0; i < m; ++i)
+            if (rn[i] > 0.0) rho[i] = rho[i] / sqrt(rn[i]);
+        for (int64_t j = 0; j < n; ++j)
+            if (cn[j] > 0.0) kappa[j] = kappa[j] / sqrt(cn[j]);
+    }
+    free(rn);
+    free(cn);
+}
+
+/* Problem in the scaled variables: K~ = diag(rho) K diag(kappa),
+ * c~ = kappa c, q~ = rho q, l~ = l / kappa, u~ = u / kappa  (x = kappa x~,
+ * y = rho y~).  This is the paper's K~ = Dr^-1 K Dc^-1, x~ = Dc x with
+ * Dc = diag(1/kappa), Dr = diag(1/rho). */
+orc_prob *orc_prob_scaled(const orc_prob *p, const double *rho, const double *kappa)
+{
+    int64_t m = p->m, n = p->n;
+    double *v = (double *)malloc((size_t)(p->nnz ? p->nnz : 1) * sizeof(double));
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t k = p->rp[i]; k < p->rp[i + 1]; ++k) v[k] = rho[i] * p->v[k] * kappa[p->ci[k]];
+    double *c = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+    double *l = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+    double *u = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+    double *q = (double *)malloc((size_t)(m ? m : 1) * sizeof(double));
+    for (int64_t j = 0; j < n; ++j) {
+        c[j] = kappa[j] * p->c[j];
+        l[j] = p->l[j] / kappa[j];
+        u[j] = p->u[j] / kappa[j];
+    }
+    for (int64_t i = 0; i < m; ++i) q[i] = rho[i] * p->q[i];
+    orc_prob *s = orc_prob_create(n, m, p->m1, p->rp, p->ci, v, c, q, l, u);
+    free(v); free(c); free(l); free(u); free(q);
+    return s;
+}
+
+/* ------------------------------------------------------------------------- */
+/* spectral norm by power iteration (Section 2.3.1, Algorithm 2)              */
+/* ------------------------------------------------------------------------- */
+
+/* b starts at the all-ones vector; each pass forms w = K b, then
+ * b = K^T w / ||K^T w||.  The value returned is ||K b|| for the last
+ * normalised b.  Algorithm 2 leaves the pass count open; the loop stops when
+ * two successive values of ||K b|| (b normalised) differ by at most
+ * tol * value, or after max_iters passes. */
+double orc_power_norm(const orc_prob *p, int max_iters, double tol, int *iters_out)
+{
+    int64_t m = p->m, n = p->n;
+    double *b = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+    double *w = (double *)malloc((size_t)(m ? m : 1) * sizeof(double));
+    for (int64_t j = 0; j < n; ++j) b[j] = 1.0;
+    double prev = -1.0, est = 0.0;
+    int it;
+    for (it = 0; it < max_iters; ++it) {
+        orc_spmv(p, b, w);
+        if (it > 0) {
+            est = dnrm2(m, w);
+            if (prev >= 0.0 && fabs(est - prev) <= tol * est) break;
+            prev = est;
+        }
+        orc_spmv_t(p, w, b);
+        double nb = dnrm2(n, b);
+        if (nb == 0.0) { est = 0.0; break; }
+        for (int64_t j = 0; j < n; ++j) b[j] /= nb;
+    }
+    if (it == max_iters) {
+        orc_spmv(p, b, w);
+        est = dnrm2(m, w);
+    }
+    if (iters_out) *iters_out = it;
+    free(b);
+    free(w);
+    return est;
+}
+
+/* ------------------------------------------------------------------------- */
+/* one PDHG step (appendix form of Algorithm 1, theta = 1)                    */
+/*   x+ = proj_X(x - tau (c - K^T y))                                         */
+/*   xbar = 2 x+ - x                                                          */
+/*   y+ = proj_Y(y + sigma (q - K xbar)),  Y = {y : y_1..m1 >= 0}             */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    double *kty, *xbar, *kxb;
+} orc_work;
+
+static void step(const orc_prob *p, double tau, double sigma, double *x, double *y, orc_work *w)
+{
+    orc_spmv_t(p, y, w->kty);
+    for (int64_t j = 0; j < p->n; ++j) {
+        double xn = clip(x[j] - tau * (p->c[j] - w->kty[j]), p->l[j], p->u[j]);
+        w->xbar[j] = 2.0 * xn - x[j];
+        x[j] = xn;
+    }
+    orc_spmv(p, w->xbar, w->kxb);
+    for (int64_t i = 0; i < p->m; ++i) {
+        double yn = y[i] + sigma * (p->q[i] - w->kxb[i]);
+        if (i < p->m1 && yn < 0.0) yn = 0.0;
+        y[i] = yn;
+    }
+}
+
+static void work_alloc(const orc_prob *p, orc_work *w)
+{
+    w->kty = (double *)malloc((size_t)(p->n ? p->n : 1) * sizeof(double));
+    w->xbar = (double *)malloc((size_t)(p->n ? p->n : 1) * sizeof(double));
+    w->kxb = (double *)malloc((size_t)(p->m ? p->m : 1) * sizeof(double));
+}
+
+static void work_free(orc_work *w)
+{
+    free(w->kty); free(w->xbar); free(w->kxb);
+}
+
+/* k fixed-step PDHG iterations on problem p, in place on (x, y). */
+void orc_steps(const orc_prob *p, double tau, double sigma, double *x, double *y, long long k)
+{
+    orc_work w;
+    work_alloc(p, &w);
+    for (long long t = 0; t < k; ++t) step(p, tau, sigma, x, y, &w);
+    work_free(&w);
+}
+
+/* ------------------------------------------------------------------------- */
+/* restarted PDHG solve (Sections 2.3-2.4: Algorithms 1-4, restarts)          */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    int ruiz_iters;        /* Ruiz passes (0 = no scaling)                     */
+    int use_restarts;      /* adaptive restarts, Section 2.4.2                 */
+    int use_pw_update;     /* primal-weight update, Algorithm 4                */
+    int check_every;       /* iterations between KKT checks                    */
+    long long max_iters;   /* iteration limit                                  */
+    double eps;            /* relative KKT tolerance                           */
+    double step_size;      /* eta; <= 0 picks step_frac / ||K~||_2             */
+    double step_frac;      /* 0.9                                              */
+    double primal_weight;  /* omega_0; <= 0 picks ||c~|| / ||q~|| (or 1)       */
+    int power_max_iters;   /* power-iteration pass limit                       */
+    double power_tol;      /* power-iteration relative change tolerance        */
+    double beta_suff, beta_nec, beta_art; /* restart constants 0.2 0.8 0.36   */
+    double eps_zero;       /* 1e-6                                             */
+} orc_opts;
+
+typedef struct {
+    int status;            /* 0 optimal, 1 iteration limit                     */
+    int from_avg;          /* returned point is the average (1) or iterate (0) */
+    long long iters;
+    int restarts;
+    int power_iters;
+    double knorm, eta, omega0, omega, tau, sigma;
+    orc_kkt_t kkt;         /* relative KKT of the returned point, original LP  */
+    int trace_len;
+} orc_result;
+
+/* one restart (or check) record */
+typedef struct {
+    long long iter;        /* total iterations at the check                    */
+    int restarted;         /* 1 when a restart happened at this check          */
+    int cand_avg;          /* restart candidate is the average                 */
+    double kkt_cand;       /* KKT_omega of the candidate                       */
+    double omega;          /* primal weight after the check                    */
+    double rel_kkt_cur, rel_kkt_avg;
+} orc_trace_rec;
+
+/* Solves the LP (rows already ordered [G; A]).  x_out / y_out receive the
+ * returned point in the original variables.  trace (may be NULL) receives up
+ * to trace_cap check records. */
+int orc_solve(const orc_prob *p, const orc_opts *o, double *x_out, double *y_out, orc_result *res,
+              orc_trace_rec *trace, int trace_cap)
+{
+    int64_t n = p->n, m = p->m;
+    memset(res, 0, sizeof(*res));
+    /* preconditioning (Section 2.4.1) */
+    double *rho = (double *)malloc((size_t)(m ? m : 1) * sizeof(double));
+    double *kap = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+    orc_ruiz(p, o->ruiz_iters, rho, kap);
+    orc_prob *s = orc_prob_scaled(p, rho, kap);
+
+    /* step size and primal weight (Sections 2.3.1, 2.4.3) */
+    res->knorm = orc_power_norm(s, o->power_max_iters, o->power_tol, &res->power_iters);
+    double eta = o->step_size > 0.0 ? o->step_size
+               : (res->knorm > 0.0 ? o->step_frac / res->knorm : 1.0); /* K = 0: any step is stable */
+    double omega;
+    if (o->primal_weight > 0.0)
+        omega = o->primal_weight;
+    else if (s->cnorm > o->eps_zero && s->qnorm > o->eps_zero)
+        omega = s->cnorm / s->qnorm;
+    else
+        omega = 1.0;
+    res->eta = eta;
+    res->omega0 = omega;
+
+    double *x = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+    double *y = (double *)calloc((size_t)(m ? m : 1), sizeof(double));
+    double *xs = (double *)calloc((size_t)(n ? n : 1), sizeof(double)); /* running sums */
+    double *ys = (double *)calloc((size_t)(m ? m : 1), sizeof(double));
+    double *xa = (double *)malloc((size_t)(n ? n : 1) * sizeof(double)); /* averages */
+    double *ya = (double *)malloc((size_t)(m ? m : 1) * sizeof(double));
+    double *x0 = (double *)malloc((size_t)(n ? n : 1) * sizeof(double)); /* epoch start */
+    double *y0 = (double *)malloc((size_t)(m ? m : 1) * sizeof(double));
+    double *xu = (double *)malloc((size_t)(n ? n : 1) * sizeof(double)); /* unscaled */
+    double *yu = (double *)malloc((size_t)(m ? m : 1) * sizeof(double));
+    for (int64_t j = 0; j < n; ++j) x[j] = clip(0.0, s->l[j], s->u[j]);
+    memcpy(x0, x, (size_t)n * sizeof(double));
+    memcpy(y0, y, (size_t)m * sizeof(double));
+    orc_work w;
+    work_alloc(s, &w);
+
+    long long k_total = 0, t_inner = 0;
+    int restarts = 0, tl = 0;
+    double kkt0, kkt_prev = INFINITY;
+    orc_kkt_t kc, ka, ksc, ksa;
+    const double *ret_x = x, *ret_y = y;
+    int status = 1, from_avg = 0;
+
+    /* the starting point is checked for termination before any iteration */
+    for (int64_t j = 0; j < n; ++j) xu[j] = kap[j] * x[j];
+    for (int64_t i = 0; i < m; ++i) yu[i] = rho[i] * y[i];
+    orc_kkt(p, xu, yu, &kc);
+    orc_kkt(s, x, y, &ksc);
+    kkt0 = kkt_omega(&ksc, omega);
+    if (kc.rel_kkt <= o->eps) {
+        status = 0;
+        res->kkt = kc;
+        goto done;
+    }
+
+    for (;;) {
+        for (int it = 0; it < o->check_every; ++it) {
+            step(s, eta / omega, eta * omega, x, y, &w);
+            ++k_total;
+            ++t_inner;
+            if (o->use_restarts) {
+                for (int64_t j = 0; j < n; ++j) xs[j] += x[j];
+                for (int64_t i = 0; i < m; ++i) ys[i] += y[i];
+            }
+        }
+        /* termination metric on the original LP, restart metric on the scaled one */
+        for (int64_t j = 0; j < n; ++j) xu[j] = kap[j] * x[j];
+        for (int64_t i = 0; i < m; ++i) yu[i] = rho[i] * y[i];
+        orc_kkt(p, xu, yu, &kc);
+        orc_kkt(s, x, y, &ksc);
+        double kw_c = kkt_omega(&ksc, omega), kw_a = INFINITY;
+        if (o->use_restarts) {
+            for (int64_t j = 0; j < n; ++j) xa[j] = xs[j] / (double)t_inner;
+            for (int64_t i = 0; i < m; ++i) ya[i] = ys[i] / (double)t_inner;
+            for (int64_t j = 0; j < n; ++j) xu[j] = kap[j] * xa[j];
+            for (int64_t i = 0; i < m; ++i) yu[i] = rho[i] * ya[i];
+            orc_kkt(p, xu, yu, &ka);
+            orc_kkt(s, xa, ya, &ksa);
+            kw_a = kkt_omega(&ksa, omega);
+        }
+        /* restart candidate: the iterate if strictly better, else the average */
+        int cand_avg = o->use_restarts && !(kw_c < kw_a);
+        double kw_cand = cand_avg ? kw_a : kw_c;
+        const orc_kkt_t *k_cand = cand_avg ? &ka : &kc;
+        const orc_kkt_t *k_other = cand_avg ? &kc : &ka;
+        orc_trace_rec rec = {k_total, 0, cand_avg, kw_cand, omega, kc.rel_kkt,
+                             o->use_restarts ? ka.rel_kkt : INFINITY};
+
+        /* termination (Section 2.3.2): candidate first, then the other point */
+        if (k_cand->rel_kkt <= o->eps) {
+            status = 0;
+            from_avg = cand_avg;
+        } else if (o->use_restarts && k_other->rel_kkt <= o->eps) {
+            status = 0;
+            from_avg = !cand_avg;
+        }
+        if (status == 0 || k_total >= o->max_iters) {
+            if (status != 0) from_avg = cand_avg;
+            res->kkt = from_avg ? ka : kc;
+            ret_x = from_avg ? xa : x;
+            ret_y = from_avg ? ya : y;
+            if (trace && tl < trace_cap) trace[tl++] = rec;
+            break;
+        }
+
+        if (o->use_restarts) {
+            int restart = 0;
+            if (kw_cand <= o->beta_suff * kkt0) restart = 1;                      /* sufficient decay */
+            if (kw_cand <= o->beta_nec * kkt0 && kw_cand > kkt_prev) restart = 1; /* necessary + no progress */
+            if ((double)t_inner > o->beta_art * (double)k_total) restart = 1;    /* long inner loop */
+            if (restart) {
+                double *cx = cand_avg ? xa : x, *cy = cand_avg ? ya : y;
+                double dx = 0.0, dy = 0.0;
+                for (int64_t j = 0; j < n; ++j) dx += (cx[j] - x0[j]) * (cx[j] - x0[j]);
+                for (int64_t i = 0; i < m; ++i) dy += (cy[i] - y0[i]) * (cy[i] - y0[i]);
+                dx = sqrt(dx);
+                dy = sqrt(dy);
+                if (cand_avg) {
+                    memcpy(x, xa, (size_t)n * sizeof(double));
+                    memcpy(y, ya, (size_t)m * sizeof(double));
+                }
+                memcpy(x0, x, (size_t)n * sizeof(double));
+                memcpy(y0, y, (size_t)m * sizeof(double));
+                /* primal weight update (Algorithm 4, read as Delta_y / Delta_x) */
+                if (o->use_pw_update && dx > o->eps_zero && dy > o->eps_zero)
+                    omega = exp(0.5 * log(dy / dx) + 0.5 * log(omega));
+                /* the new epoch's reference value is the candidate's metric at the new omega */
+                kkt0 = kkt_omega(cand_avg ? &ksa : &ksc, omega);
+                kkt_prev = INFINITY;
+                t_inner = 0;
+                memset(xs, 0, (size_t)n * sizeof(double));
+                memset(ys, 0, (size_t)m * sizeof(double));
+                ++restarts;
+                rec.restarted = 1;
+                rec.omega = omega;
+            } else {
+                kkt_prev = kw_cand;
+            }
+        }
+        if (trace && tl < trace_cap) trace[tl++] = rec;
+    }
+
+done:
+    for (int64_t j = 0; j < n; ++j) x_out[j] = kap[j] * ret_x[j];
+    for (int64_t i = 0; i < m; ++i) y_out[i] = rho[i] * ret_y[i];
+    res->status = status;
+    res->from_avg = from_avg;
+    res->iters = k_total;
+    res->restarts = restarts;
+    res->omega = omega;
+    res->tau = eta / omega;
+    res->sigma = eta * omega;
+    res->trace_len = tl;
+    work_free(&w);
+    free(x); free(y); free(xs); free(ys); free(xa); free(ya);
+    free(x0); free(y0); free(xu); free(yu);
+    free(rho); free(kap);
+    orc_prob_free(s);
+    return status;
+}
+
+/* ------------------------------------------------------------------------- */
+/* unrolled fixed-step map and its adjoint (differentiation oracle)           */
+/* ------------------------------------------------------------------------- */
+
+/* K fixed PDHG steps in the scaled variables of problem p (unscaled data,
+ * factors rho / kappa, scaled matrix s), with every input and output in the
+ * original variables:
+ *   c~ = kappa c, q~ = rho q, l~ = l/kappa, u~ = u/kappa,
+ *   x~0 = x0/kappa, y~0 = y0/rho, and x_K = kappa x~_K, y_K = rho y~_K.
+ * The scaled matrix s must come from orc_prob_scaled(p, rho, kappa). */
+static void to_scaled(const orc_prob *s, const double *rho, const double *kap, const double *c,
+                      const double *q, const double *l, const double *u, orc_prob *t)
+{
+    *t = *s;
+    for (int64_t j = 0; j < s->n; ++j) {
+        t->c[j] = kap[j] * c[j];
+        t->l[j] = l[j] / kap[j];
+        t->u[j] = u[j] / kap[j];
+    }
+    for (int64_t i = 0; i < s->m; ++i) t->q[i] = rho[i] * q[i];
+}
+
+void orc_unrolled(const orc_prob *s, const double *rho, const double *kap, double tau, double sigma,
+                  const double *c, const double *q, const double *l, const double *u,
+                  const double *x0, const double *y0, long long K, double *xK, double *yK)
+{
+    int64_t n = s->n, m = s->m;
+    orc_prob t;
+    orc_prob *tmp = orc_prob_create(n, m, s->m1, s->rp, s->ci, s->v, s->c, s->q, s->l, s->u);
+    to_scaled(tmp, rho, kap, c, q, l, u, &t);
+    double *x = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+    double *y = (double *)malloc((size_t)(m ? m : 1) * sizeof(double));
+    for (int64_t j = 0; j < n; ++j) x[j] = x0[j] / kap[j];
+    for (int64_t i = 0; i < m; ++i) y[i] = y0[i] / rho[i];
+    orc_steps(&t, tau, sigma, x, y, K);
+    for (int64_t j = 0; j < n; ++j) xK[j] = kap[j] * x[j];
+    for (int64_t i = 0; i < m; ++i) yK[i] = rho[i] * y[i];
+    free(x);
+    free(y);
+    orc_prob_free(tmp);
+}
+
+/* Reverse-mode derivative of orc_unrolled: given gx = dL/dx_K and
+ * gy = dL/dy_K, writes dL/dc, dL/dq, dL/dl, dL/du, dL/dx0, dL/dy0.  Every
+ * forward state is stored, then each step is differentiated by the chain rule:
+ * the clip passes the gradient to v where l < v < u and to l (v <= l) or
+ * u (v >= u) otherwise; the dual projection passes it where the row is an
+ * equality or w > 0. */
+void orc_unrolled_vjp(const orc_prob *s, const double *rho, const double *kap, double tau,
+                      double sigma, const double *c, const double *q, const double *l,
+                      const double *u, const double *x0, const double *y0, long long K,
+                      const double *gx, const double *gy, double *gc, double *gq, double *gl,
+                      double *gu, double *gx0, double *gy0)
+{
+    int64_t n = s->n, m = s->m;
+    orc_prob t;
+    orc_prob *tmp = orc_prob_create(n, m, s->m1, s->rp, s->ci, s->v, s->c, s->q, s->l, s->u);
+    to_scaled(tmp, rho, kap, c, q, l, u, &t);
+    double *X = (double *)malloc((size_t)(K + 1) * (size_t)(n ? n : 1) * sizeof(double));
+    double *Y = (double *)malloc((size_t)(K + 1) * (size_t)(m ? m : 1) * sizeof(double));
+    for (int64_t j = 0; j < n; ++j) X[j] = x0[j] / kap[j];
+    for (int64_t i = 0; i < m; ++i) Y[i] = y0[i] / rho[i];
+    orc_work w;
+    work_alloc(&t, &w);
+    for (long long k = 0; k < K; ++k) {
+        memcpy(X + (k + 1) * n, X + k * n, (size_t)n * sizeof(double));
+        memcpy(Y + (k + 1) * m, Y + k * m, (size_t)m * sizeof(double));
+        step(&t, tau, sigma, X + (k + 1) * n, Y + (k + 1) * m, &w);
+    }
+    /* adjoints in scaled variables */
+    double *ax = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+    double *ay = (double *)malloc((size_t)(m ? m : 1) * sizeof(double));
+    double *ac = (double *)calloc((size_t)(n ? n : 1), sizeof(double));
+    double *al = (double *)calloc((size_t)(n ? n : 1), sizeof(double));
+    double *au = (double *)calloc((size_t)(n ? n : 1), sizeof(double));
+    double *aq = (double *)calloc((size_t)(m ? m : 1), sizeof(double));
+    double *aw = (double *)malloc((size_t)(m ? m : 1) * sizeof(double));
+    double *axb = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+    double *av = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+    double *v = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+    double *xb = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+    double *kxb = (double *)malloc((size_t)(m ? m : 1) * sizeof(double));
+    double *kty = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+    double *kav = (double *)malloc((size_t)(m ? m : 1) * sizeof(double));
+    /* dL/dx~_K = kappa dL/dx_K  (x_K = kappa x~_K), dL/dy~_K = rho dL/dy_K */
+    for (int64_t j = 0; j < n; ++j) ax[j] = kap[j] * gx[j];
+    for (int64_t i = 0; i < m; ++i) ay[i] = rho[i] * gy[i];
+    for (long long k = K - 1; k >= 0; --k) {
+        const double *xk = X + k * n, *yk = Y + k * m, *xk1 = X + (k + 1) * n;
+        /* recompute the step's intermediates */
+        orc_spmv_t(&t, yk, kty);
+        for (int64_t j = 0; j < n; ++j) {
+            v[j] = xk[j] - tau * (t.c[j] - kty[j]);
+            xb[j] = 2.0 * xk1[j] - xk[j];
+        }
+        orc_spmv(&t, xb, kxb);
+        /* y+ = proj_Y(w), w = y + sigma (q - K xbar) */
+        for (int64_t i = 0; i < m; ++i) {
+            double wi = yk[i] + sigma * (t.q[i] - kxb[i]);
+            int pass = (i >= t.m1) || (wi > 0.0);
+            aw[i] = pass ? ay[i] : 0.0;
+            aq[i] += sigma * aw[i];
+        }
+        /* xbar enters w through -sigma K xbar */
+        orc_spmv_t(&t, aw, axb);
+        for (int64_t j = 0; j < n; ++j) axb[j] *= -sigma;
+        /* x+ enters the output directly and through xbar = 2 x+ - x */
+        for (int64_t j = 0; j < n; ++j) {
+            double g = ax[j] + 2.0 * axb[j];
+            if (v[j] <= t.l[j]) {
+                al[j] += g;
+                av[j] = 0.0;
+            } else if (v[j] >= t.u[j]) {
+                au[j] += g;
+                av[j] = 0.0;
+            } else {
+                av[j] = g;
+            }
+            ac[j] += -tau * av[j];
+            ax[j] = av[j] - axb[j]; /* dL/dx_k: through v and through xbar */
+        }
+        /* v = x - tau c + tau K^T y  ->  dL/dy_k = aw + tau K av */
+        orc_spmv(&t, av, kav);
+        for (int64_t i = 0; i < m; ++i) ay[i] = aw[i] + tau * kav[i];
+    }
+    /* back to the original variables */
+    for (int64_t j = 0; j < n; ++j) {
+        if (gc) gc[j] = kap[j] * ac[j];
+        if (gl) gl[j] = al[j] / kap[j];
+        if (gu) gu[j] = au[j] / kap[j];
+        if (gx0) gx0[j] = ax[j] / kap[j];
+    }
+    for (int64_t i = 0; i < m; ++i) {
+        if (gq) gq[i] = rho[i] * aq[i];
+        if (gy0) gy0[i] = ay[i] / rho[i];
+    }
+    work_free(&w);
+    free(X); free(Y); free(ax); free(ay); free(ac); free(al); free(au); free(aq);
+    free(aw); free(axb); free(av); free(v); free(xb); free(kxb); free(kty); free(kav);
+    orc_prob_free(tmp);
+}
