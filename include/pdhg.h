@@ -1,0 +1,240 @@
+/*
+ * pdhg.h -- C-ABI of the MI355X (gfx950) PDHG linear-programming library.
+ *
+ * The library solves  min c'x  s.t.  Gx >= h,  Ax = b,  l <= x <= u
+ * (the primal LP of Section 2.2 of arXiv 2508.16806) with restarted
+ * Primal-Dual Hybrid Gradient (Algorithm 1 in the sign-consistent form of
+ * Appendices C/D, with the Section 2.4 enhancements: Ruiz scaling, adaptive
+ * restarts and primal-weight updates).  Every step of the iteration runs in
+ * hand-written HIP kernels; this header is the whole public surface.
+ *
+ * Conventions shared by every call
+ *  - All functions return an int status: PDHG_OK (0) or a negative PDHG_ERR_*
+ *    code.  No C++ exception crosses the ABI.  pdhg_last_error() returns a
+ *    thread-local human-readable message for the last failure in the thread.
+ *  - A "stream" argument is a hipStream_t (0 = the null stream).  Work is
+ *    stream-ordered; calls that return host data synchronise that stream.
+ *  - Memory-space flags (PDHG_MEM_HOST / PDHG_MEM_DEVICE) tell whether a
+ *    caller pointer is host memory or device memory of the current device.
+ *  - A handle may be used by one stream (one thread) at a time.
+ *  - Rows: row_type[i] is PDHG_ROW_GE for a row of G (">=") and PDHG_ROW_EQ
+ *    for a row of A ("=").  Internally the rows are reordered so that all
+ *    ">=" rows come first (the stacked K = [G; A], q = [h; b] of Section 2.2);
+ *    every row-indexed vector crossing this ABI is in the CALLER's row order.
+ *  - Infinite bounds are IEEE infinities (l_j = -INFINITY, u_j = +INFINITY).
+ */
+#ifndef PDHG_H
+#define PDHG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define PDHG_OK 0
+#define PDHG_ERR_INVALID_ARG -1 /* NULL pointer, bad option value, bad index   */
+#define PDHG_ERR_SHAPE -2       /* row_ptr not monotone, column out of range,  */
+                                /* nnz mismatch, row_type count mismatch       */
+#define PDHG_ERR_BOUNDS -3      /* l_j > u_j, l_j = +inf or u_j = -inf          */
+#define PDHG_ERR_NONFINITE -4   /* NaN anywhere, or +-inf in K, c or rhs       */
+#define PDHG_ERR_NOMEM -5       /* workspace smaller than pdhg_workspace_bytes */
+#define PDHG_ERR_HIP -6         /* a HIP runtime call failed                   */
+#define PDHG_ERR_STATE -7       /* call not valid in the handle's state        */
+
+/* ---- solve status (pdhg_result.status) ----------------------------------- */
+#define PDHG_OPTIMAL 0          /* relative KKT error <= eps (Section 2.3.2)   */
+#define PDHG_ITERATION_LIMIT 1
+#define PDHG_TIME_LIMIT 2
+#define PDHG_NUMERICAL_ERROR 3  /* a reduction in the check became NaN/inf     */
+
+/* ---- enumerations ---------------------------------------------------------- */
+#define PDHG_MEM_HOST 0
+#define PDHG_MEM_DEVICE 1
+#define PDHG_PREC_F64 0  /* iterates, matrix and arithmetic in FP64            */
+#define PDHG_PREC_F32 1  /* FP32 iterates and matrix, FP64 accumulation, FP64  */
+                         /* KKT check, restart test and primal-weight update   */
+#define PDHG_ROW_GE 0
+#define PDHG_ROW_EQ 1
+#define PDHG_SOL_RESULT 0  /* point returned by the last pdhg_solve            */
+#define PDHG_SOL_CURRENT 1 /* current iterate z                                 */
+#define PDHG_SOL_AVERAGE 2 /* running average of the current restart epoch     */
+
+/* One LP in CSR form (Section 2.2).  All pointers live in the memory space
+ * `mem`.  They are BORROWED: pdhg_setup copies and converts everything it
+ * needs before it returns, after which the caller may free them.
+ *   row_ptr  m+1 int64, monotone, row_ptr[0] = 0, row_ptr[m] = nnz
+ *   col      nnz int32 in [0, n); duplicate entries in a row are summed
+ *   val      nnz double, finite
+ *   c        n double, finite               (cost)
+ *   rhs      m double, finite               (h_i for ">=" rows, b_i for "=" rows)
+ *   l, u     n double, l_j <= u_j, l_j < +inf, u_j > -inf
+ *   row_type m uint8 (PDHG_ROW_GE / PDHG_ROW_EQ), or NULL: all rows are "="  */
+typedef struct {
+    int64_t n;
+    int64_t m;
+    int64_t nnz;
+    const int64_t *row_ptr;
+    const int32_t *col;
+    const double *val;
+    const double *c;
+    const double *rhs;
+    const double *l;
+    const double *u;
+    const uint8_t *row_type;
+    int32_t mem;
+} pdhg_lp;
+
+/* Solver options.  pdhg_default_opts fills the paper's constants:
+ * eps = 1e-4 (Section 2.3.2), step = 0.9 / ||K~||_2 (Section 3.2),
+ * restart constants 0.2 / 0.8 / 0.36 (Section 2.4.2), eps_zero = 1e-6
+ * (Section 2.4.3), and the choices the paper leaves open: 10 Ruiz passes,
+ * a KKT check every 64 iterations, power iteration to a 1e-6 relative change
+ * or 1000 passes. */
+typedef struct {
+    int32_t precision;      /* PDHG_PREC_F32 (default) or PDHG_PREC_F64             */
+    int32_t ruiz_iters;     /* Ruiz passes; 0 disables scaling                      */
+    int32_t use_restarts;   /* adaptive restarts (Section 2.4.2)                     */
+    int32_t use_pw_update;  /* primal-weight updates (Algorithm 4)                   */
+    int32_t check_every;    /* iterations between KKT checks, 1..4096                */
+    int32_t power_max_iters;
+    int64_t max_iters;      /* iteration limit                                       */
+    double eps;             /* relative KKT tolerance                                */
+    double time_limit;      /* seconds of pdhg_solve; <= 0: none                     */
+    double step_size;       /* eta; <= 0 picks step_frac / ||K~||_2                  */
+    double step_frac;
+    double primal_weight;   /* omega_0; <= 0 picks ||c~|| / ||q~|| (1 if either small)*/
+    double power_tol;
+    double beta_suff, beta_nec, beta_art;
+    double eps_zero;
+    int32_t unroll_capacity;   /* max steps pdhg_iterate may record (0: none)       */
+    int32_t unroll_checkpoint; /* checkpoint spacing C for the adjoint replay       */
+    int32_t use_graph;         /* capture iteration chunks in a hipGraph            */
+    int32_t xcd_remap;         /* XCD-contiguous workgroup numbering                */
+    int32_t bin_max_len[8];    /* row-length bin limits (autotuner output); 0: default */
+} pdhg_opts;
+
+/* Relative KKT error terms (Section 2.3.2, conditions term1-term3) on the
+ * ORIGINAL (unscaled) LP, FP64 throughout:
+ *   pres = ||(Ax - b, [h - Gx]^+)||_2, dres = ||c - K'y - lambda||_2 with
+ *   lambda = proj_Lambda(c - K'y), pobj = c'x, dobj = q'y + l'lambda^+ +
+ *   u'lambda^- (a product with an infinite bound is skipped: lambda is 0
+ *   there), gap = |dobj - pobj|, rel_gap = gap / (1 + |dobj| + |pobj|),
+ *   rel_pres = pres / (1 + ||q||), rel_dres = dres / (1 + ||c||),
+ *   rel_kkt = max(rel_gap, rel_pres, rel_dres).  rel_kkt <= eps iff all three
+ *   termination conditions hold. */
+typedef struct {
+    double pres, dres, pobj, dobj, gap;
+    double rel_pres, rel_dres, rel_gap, rel_kkt;
+} pdhg_kkt_out;
+
+typedef struct {
+    int32_t status;      /* PDHG_OPTIMAL, ..._ITERATION_LIMIT, ..._TIME_LIMIT, ..._NUMERICAL_ERROR */
+    int32_t from_avg;    /* returned point: 1 = epoch average, 0 = current iterate */
+    int64_t iters;       /* PDHG iterations of this solve                           */
+    int32_t restarts;
+    int32_t power_iters;
+    double knorm;        /* power-iteration estimate of ||K~||_2                    */
+    double eta, omega0, omega, tau, sigma;
+    pdhg_kkt_out kkt;    /* of the returned point (last check)                      */
+    double seconds;      /* wall time of pdhg_solve                                 */
+} pdhg_result;
+
+typedef struct {
+    int64_t n, m, m_ineq, nnz;
+    double knorm, eta, omega, tau, sigma;
+    double setup_seconds;
+    int32_t precision, batch;
+    int64_t workspace_bytes;
+    int32_t nseg_primal, nseg_dual; /* row-length bins in use                     */
+    int64_t nblk_primal, nblk_dual; /* workgroups per primal / dual sweep         */
+} pdhg_info;
+
+typedef struct pdhg_handle pdhg_handle;
+
+/* Fills *o with the defaults listed above. */
+void pdhg_default_opts(pdhg_opts *o);
+
+/* Device bytes the workspace passed to pdhg_setup must hold for `batch` LPs
+ * (lp points to an array of `batch` descriptors).  Reads the sparsity pattern
+ * (copying it to the host if it lives on the device).  Returns 0 and sets the
+ * last error when the input is invalid. */
+size_t pdhg_workspace_bytes(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o);
+
+/* Validates and copies `batch` LPs into the caller-owned device workspace
+ * `ws` (at least pdhg_workspace_bytes bytes, 256-byte aligned; it must outlive
+ * the handle), reorders rows to [G; A], builds CSR(K) and CSR(K'), runs Ruiz
+ * scaling (Algorithm 3) and the power iteration (Algorithm 2) on the GPU,
+ * picks eta, omega_0, tau = eta/omega, sigma = eta*omega (Section 2.3.1) and
+ * sets x0 = proj_X(0), y0 = 0.  On success *out is a new handle (free it
+ * with pdhg_destroy).  Errors: PDHG_ERR_INVALID_ARG, _SHAPE, _BOUNDS,
+ * _NONFINITE, _NOMEM, _HIP. */
+int pdhg_setup(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, void *ws, size_t ws_bytes,
+               hipStream_t stream, pdhg_handle **out);
+
+/* Runs k fixed-step PDHG iterations (Algorithm 1, theta = 1) from the
+ * handle's current iterate with the current tau and sigma: no averaging,
+ * restarts or checks.  Asynchronous.  State persists across calls, so
+ * pdhg_iterate(k1) then pdhg_iterate(k2) equals pdhg_iterate(k1 + k2).
+ * record != 0 stores checkpoints for pdhg_backward (k <= unroll_capacity);
+ * a recorded call replaces the previous record. */
+int pdhg_iterate(pdhg_handle *h, int64_t k, int32_t record, hipStream_t stream);
+
+/* Full restarted solve to opts.eps (Sections 2.3-2.4) from the handle's
+ * current iterate.  Blocks until every instance has stopped; res points to
+ * `batch` results.  Every instance of a batch follows exactly the iteration,
+ * check and restart sequence it would follow alone. */
+int pdhg_solve(pdhg_handle *h, pdhg_result *res, hipStream_t stream);
+
+/* Writes instance `inst`'s point (which = PDHG_SOL_*) in the ORIGINAL
+ * variables: x (n), y (m, caller row order) and lambda = proj_Lambda(c - K'y)
+ * (n).  Any output pointer may be NULL.  Pointers are in memory space `mem`. */
+int pdhg_get_solution(pdhg_handle *h, int32_t inst, int32_t which, double *x, double *y,
+                      double *lambda, int32_t mem, hipStream_t stream);
+
+/* Sets instance `inst`'s current iterate to (x, y) given in the original
+ * variables (y in caller row order); x is projected onto [l, u] and the
+ * inequality entries of y onto y >= 0.  The restart epoch starts here. */
+int pdhg_set_state(pdhg_handle *h, int32_t inst, const double *x, const double *y, int32_t mem,
+                   hipStream_t stream);
+
+/* Relative KKT error of a caller point (x, y) on instance `inst`'s original
+ * LP (y in caller row order).  FP64 throughout; synchronous. */
+int pdhg_kkt(pdhg_handle *h, int32_t inst, const double *x, const double *y, int32_t mem,
+             pdhg_kkt_out *out, hipStream_t stream);
+
+/* Adjoint of the last recorded pdhg_iterate on the whole batch.  Given
+ * gx = dL/dx_K and gy = dL/dy_K (original variables, concatenated over the
+ * batch, y parts in caller row order), writes dL/dc, dL/drhs, dL/dl, dL/du,
+ * dL/dx_0 and dL/dy_0 in the original variables (tau, sigma and the Ruiz
+ * factors are constants).  Output pointers may be NULL.  The replay uses the
+ * checkpoints stored every unroll_checkpoint steps. */
+int pdhg_backward(pdhg_handle *h, const double *gx, const double *gy, double *gc, double *grhs,
+                  double *gl, double *gu, double *gx0, double *gy0, int32_t mem,
+                  hipStream_t stream);
+
+/* Ruiz factors of instance `inst` (Algorithm 3): the scaled problem is
+ * K~ = diag(rho) K diag(kappa), x = kappa x~, y = rho y~.  rho has m entries
+ * (caller row order), kappa n entries; either pointer may be NULL. */
+int pdhg_get_scaling(pdhg_handle *h, int32_t inst, double *rho, double *kappa, int32_t mem,
+                     hipStream_t stream);
+
+/* Sizes, step parameters and launch layout of the handle (instance 0's
+ * parameters for a batch). */
+int pdhg_get_info(const pdhg_handle *h, pdhg_info *info);
+
+/* Releases the handle (not the caller's workspace). */
+void pdhg_destroy(pdhg_handle *h);
+
+/* Thread-local message for the last error ("" if none). */
+const char *pdhg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDHG_H */

@@ -1,0 +1,1105 @@
+// capi.cpp -- the extern "C" surface of libpdhg (declared in include/pdhg.h):
+// validation, layout planning (row reordering, row-length bins, CSR of K and
+// K^T), workspace carving, setup on the GPU (Ruiz scaling, power iteration,
+// step sizes), the restarted solve loop and the service calls.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/pdhg.h"
+#include "kernels.h"
+#include "pdhg_internal.h"
+
+using namespace pdhg;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(call)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(PDHG_ERR_HIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                                \
+    } while (0)
+
+extern "C" const char *pdhg_last_error(void) { return g_err.c_str(); }
+
+extern "C" void pdhg_default_opts(pdhg_opts *o)
+{
+    std::memset(o, 0, sizeof(*o));
+    o->precision = PDHG_PREC_F32;
+    o->ruiz_iters = 10;
+    o->use_restarts = 1;
+    o->use_pw_update = 1;
+    o->check_every = 64;
+    o->power_max_iters = 1000;
+    o->max_iters = 1000000;
+    o->eps = 1e-4;
+    o->time_limit = 0.0;
+    o->step_size = 0.0;
+    o->step_frac = 0.9;
+    o->primal_weight = 0.0;
+    o->power_tol = 1e-6;
+    o->beta_suff = 0.2;
+    o->beta_nec = 0.8;
+    o->beta_art = 0.36;
+    o->eps_zero = 1e-6;
+    o->unroll_capacity = 0;
+    o->unroll_checkpoint = 50;
+    o->use_graph = 1;
+    o->xcd_remap = 1;
+}
+
+// ---------------------------------------------------------------------------
+// host view of one input LP (downloaded when it lives on the device)
+// ---------------------------------------------------------------------------
+
+struct HostLP {
+    int64_t n = 0, m = 0, nnz = 0, m1 = 0;
+    const int64_t *rp = nullptr;
+    const int32_t *ci = nullptr;
+    const double *v = nullptr, *c = nullptr, *rhs = nullptr, *l = nullptr, *u = nullptr;
+    const uint8_t *rt = nullptr;
+    std::vector<int64_t> rp_s;
+    std::vector<int32_t> ci_s;
+    std::vector<double> v_s, c_s, rhs_s, l_s, u_s;
+    std::vector<uint8_t> rt_s;
+};
+
+template <typename X>
+static int fetch(const X *src, size_t cnt, int mem, std::vector<X> &store, const X *&view)
+{
+    if (cnt == 0) {
+        view = nullptr;
+        return PDHG_OK;
+    }
+    if (!src) return fail(PDHG_ERR_INVALID_ARG, "NULL input array");
+    if (mem == PDHG_MEM_HOST) {
+        view = src;
+        return PDHG_OK;
+    }
+    store.resize(cnt);
+    HIPCHK(hipMemcpy(store.data(), src, cnt * sizeof(X), hipMemcpyDeviceToHost));
+    view = store.data();
+    return PDHG_OK;
+}
+
+// pattern_only: only row_ptr / col / row_type (for sizing)
+static int load_lp(const pdhg_lp &in, HostLP &h, bool pattern_only)
+{
+    if (in.n < 1 || in.m < 0 || in.nnz < 0)
+        return fail(PDHG_ERR_SHAPE, "need n >= 1, m >= 0, nnz >= 0 (got n=%lld m=%lld nnz=%lld)",
+                    (long long)in.n, (long long)in.m, (long long)in.nnz);
+    if (in.mem != PDHG_MEM_HOST && in.mem != PDHG_MEM_DEVICE)
+        return fail(PDHG_ERR_INVALID_ARG, "mem must be PDHG_MEM_HOST or PDHG_MEM_DEVICE");
+    if (in.n >= INT32_MAX || in.m >= INT32_MAX) return fail(PDHG_ERR_SHAPE, "n and m must be < 2^31");
+    h.n = in.n;
+    h.m = in.m;
+    h.nnz = in.nnz;
+    int rc;
+    if (!in.row_ptr) return fail(PDHG_ERR_INVALID_ARG, "row_ptr is NULL");
+    if ((rc = fetch(in.row_ptr, (size_t)in.m + 1, in.mem, h.rp_s, h.rp))) return rc;
+    if ((rc = fetch(in.col, (size_t)in.nnz, in.mem, h.ci_s, h.ci))) return rc;
+    if (in.row_type && (rc = fetch(in.row_type, (size_t)in.m, in.mem, h.rt_s, h.rt))) return rc;
+    if (!in.row_type) h.rt = nullptr;
+    if (h.rp[0] != 0 || h.rp[in.m] != in.nnz)
+        return fail(PDHG_ERR_SHAPE, "row_ptr[0] must be 0 and row_ptr[m] must equal nnz");
+    for (int64_t i = 0; i < in.m; ++i)
+        if (h.rp[i + 1] < h.rp[i]) return fail(PDHG_ERR_SHAPE, "row_ptr not monotone at row %lld", (long long)i);
+    for (int64_t k = 0; k < in.nnz; ++k)
+        if (h.ci[k] < 0 || h.ci[k] >= in.n)
+            return fail(PDHG_ERR_SHAPE, "column index %d out of range at entry %lld", h.ci[k], (long long)k);
+    h.m1 = 0;
+    for (int64_t i = 0; i < in.m; ++i) {
+        const uint8_t t = h.rt ? h.rt[i] : (uint8_t)PDHG_ROW_EQ;
+        if (t != PDHG_ROW_GE && t != PDHG_ROW_EQ) return fail(PDHG_ERR_INVALID_ARG, "bad row_type at row %lld", (long long)i);
+        h.m1 += (t == PDHG_ROW_GE);
+    }
+    if (pattern_only) return PDHG_OK;
+    if ((rc = fetch(in.val, (size_t)in.nnz, in.mem, h.v_s, h.v))) return rc;
+    if ((rc = fetch(in.c, (size_t)in.n, in.mem, h.c_s, h.c))) return rc;
+    if ((rc = fetch(in.rhs, (size_t)in.m, in.mem, h.rhs_s, h.rhs))) return rc;
+    if ((rc = fetch(in.l, (size_t)in.n, in.mem, h.l_s, h.l))) return rc;
+    if ((rc = fetch(in.u, (size_t)in.n, in.mem, h.u_s, h.u))) return rc;
+    for (int64_t k = 0; k < in.nnz; ++k)
+        if (!std::isfinite(h.v[k])) return fail(PDHG_ERR_NONFINITE, "matrix value %lld is not finite", (long long)k);
+    for (int64_t j = 0; j < in.n; ++j) {
+        if (!std::isfinite(h.c[j])) return fail(PDHG_ERR_NONFINITE, "c[%lld] is not finite", (long long)j);
+        if (std::isnan(h.l[j]) || std::isnan(h.u[j])) return fail(PDHG_ERR_NONFINITE, "bound %lld is NaN", (long long)j);
+        if (h.l[j] > h.u[j] || h.l[j] == INFINITY || h.u[j] == -INFINITY)
+            return fail(PDHG_ERR_BOUNDS, "inconsistent bounds at variable %lld", (long long)j);
+    }
+    for (int64_t i = 0; i < in.m; ++i)
+        if (!std::isfinite(h.rhs[i])) return fail(PDHG_ERR_NONFINITE, "rhs[%lld] is not finite", (long long)i);
+    return PDHG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// layout planning
+// ---------------------------------------------------------------------------
+
+struct SegH {
+    int64_t row0;  // local row within the instance's internal order
+    int32_t nrows, lanes_log2, ineq;
+};
+
+struct InstPlan {
+    int64_t n, m, m1, nnz;
+    std::vector<int32_t> row_order;  // internal row -> caller row
+    std::vector<int32_t> col_order;  // internal col -> caller col
+    std::vector<SegH> segK, segT;
+};
+
+struct Bins {
+    int32_t max_len[NBIN];
+    int32_t lanes_log2[NBIN];
+};
+
+static Bins make_bins(const pdhg_opts *o)
+{
+    static const int32_t def_len[NBIN] = {4, 8, 16, 32, 64, 128, 512, INT32_MAX};
+    static const int32_t lanes[NBIN] = {0, 1, 2, 3, 4, 5, 6, 8};
+    Bins b;
+    for (int k = 0; k < NBIN; ++k) {
+        b.max_len[k] = (o && o->bin_max_len[k] > 0) ? o->bin_max_len[k] : def_len[k];
+        b.lanes_log2[k] = lanes[k];
+    }
+    b.max_len[NBIN - 1] = INT32_MAX;
+    return b;
+}
+
+static int bin_of(const Bins &b, int64_t len)
+{
+    for (int k = 0; k < NBIN; ++k)
+        if (len <= b.max_len[k]) return k;
+    return NBIN - 1;
+}
+
+static int seg_group(int lanes_log2) { return lanes_log2 >= 8 ? 1 : (WG >> lanes_log2); }
+
+static void plan_instance(const HostLP &h, const Bins &bins, InstPlan &p)
+{
+    p.n = h.n;
+    p.m = h.m;
+    p.m1 = h.m1;
+    p.nnz = h.nnz;
+    // rows: ">=" group then "=" group, each ordered by bin, stable
+    std::vector<std::vector<int32_t>> buck(2 * NBIN);
+    for (int64_t i = 0; i < h.m; ++i) {
+        const int eq = h.rt ? (h.rt[i] == PDHG_ROW_EQ) : 1;
+        buck[eq * NBIN + bin_of(bins, h.rp[i + 1] - h.rp[i])].push_back((int32_t)i);
+    }
+    p.row_order.clear();
+    p.row_order.reserve(h.m);
+    p.segK.clear();
+    for (int g = 0; g < 2; ++g)
+        for (int b = 0; b < NBIN; ++b) {
+            auto &v = buck[g * NBIN + b];
+            if (v.empty()) continue;
+            p.segK.push_back({(int64_t)p.row_order.size(), (int32_t)v.size(), bins.lanes_log2[b], g == 0});
+            p.row_order.insert(p.row_order.end(), v.begin(), v.end());
+        }
+    // columns: ordered by bin of their entry count, stable
+    std::vector<int64_t> cnt(h.n, 0);
+    for (int64_t k = 0; k < h.nnz; ++k) cnt[h.ci[k]]++;
+    std::vector<std::vector<int32_t>> cb(NBIN);
+    for (int64_t j = 0; j < h.n; ++j) cb[bin_of(bins, cnt[j])].push_back((int32_t)j);
+    p.col_order.clear();
+    p.col_order.reserve(h.n);
+    p.segT.clear();
+    for (int b = 0; b < NBIN; ++b) {
+        if (cb[b].empty()) continue;
+        p.segT.push_back({(int64_t)p.col_order.size(), (int32_t)cb[b].size(), bins.lanes_log2[b], 0});
+        p.col_order.insert(p.col_order.end(), cb[b].begin(), cb[b].end());
+    }
+}
+
+// ---------------------------------------------------------------------------
+// workspace carving
+// ---------------------------------------------------------------------------
+
+struct Carve {
+    size_t off = 0;
+    char *base = nullptr;
+    template <typename X>
+    X *take(size_t cnt)
+    {
+        off = (off + 255) & ~(size_t)255;
+        X *p = base ? (X *)(base + off) : nullptr;
+        off += cnt * sizeof(X);
+        return p;
+    }
+};
+
+struct Sizes {
+    int64_t N = 0, M = 0, NNZ = 0;
+    int64_t nsegK = 0, nsegT = 0, nblkK = 0, nblkT = 0;
+    int32_t batch = 0;
+};
+
+struct Buffers {
+    // operators
+    int64_t *Krp, *Ktrp;
+    int32_t *Kci, *Ktci, *Kbs, *Ktbs;
+    double *Kv64, *Ktv64;
+    float *Kv32, *Ktv32;
+    Seg *Kseg, *Ktseg;
+    // record / adjoint
+    void *ckx, *cky;
+    uint8_t *maskx, *masky;
+    double *ax, *ay, *aw, *av, *axb, *ac, *al, *au, *aq;
+    double *vecN64c;
+};
+
+struct pdhg_handle {
+    int32_t batch = 0;
+    int32_t prec = PDHG_PREC_F32;
+    pdhg_opts opts{};
+    Sizes sz;
+    Dev d{};
+    Buffers buf{};
+    std::vector<InstInfo> info;
+    std::vector<InstState> st0;  // per-instance parameters after setup
+    std::vector<InstPlan> plan;
+    std::vector<int32_t> sol_avg;  // returned point of the last solve
+    std::vector<double> knorm;
+    int32_t *hdone_host = nullptr;
+    size_t ws_bytes = 0;
+    double setup_seconds = 0;
+    hipGraphExec_t graph = nullptr;
+    hipStream_t cap_stream = nullptr;
+    int64_t rec_steps = 0;  // steps recorded by the last recording pdhg_iterate
+    int rec_valid = 0;
+};
+
+static size_t elem_size(int prec) { return prec == PDHG_PREC_F64 ? sizeof(double) : sizeof(float); }
+
+static void carve(Carve &cv, const Sizes &sz, int prec, const pdhg_opts &o, Dev &d, Buffers &b,
+                  InstInfo **info, InstState **st)
+{
+    const size_t es = elem_size(prec);
+    const int64_t N = sz.N, M = sz.M, NNZ = sz.NNZ;
+    b.Krp = cv.take<int64_t>(M + 1);
+    b.Kci = cv.take<int32_t>(NNZ);
+    b.Kv64 = cv.take<double>(NNZ);
+    b.Kv32 = prec == PDHG_PREC_F32 ? cv.take<float>(NNZ) : nullptr;
+    b.Kseg = cv.take<Seg>(sz.nsegK);
+    b.Kbs = cv.take<int32_t>(sz.nblkK);
+    b.Ktrp = cv.take<int64_t>(N + 1);
+    b.Ktci = cv.take<int32_t>(NNZ);
+    b.Ktv64 = cv.take<double>(NNZ);
+    b.Ktv32 = prec == PDHG_PREC_F32 ? cv.take<float>(NNZ) : nullptr;
+    b.Ktseg = cv.take<Seg>(sz.nsegT);
+    b.Ktbs = cv.take<int32_t>(sz.nblkT);
+    d.x = cv.take<char>(N * es);
+    d.xbar = cv.take<char>(N * es);
+    d.xavg = cv.take<char>(N * es);
+    d.x0 = cv.take<char>(N * es);
+    d.c = cv.take<char>(N * es);
+    d.l = cv.take<char>(N * es);
+    d.u = cv.take<char>(N * es);
+    d.c64 = cv.take<double>(N);
+    d.l64 = cv.take<double>(N);
+    d.u64 = cv.take<double>(N);
+    d.kap = cv.take<double>(N);
+    d.craw = cv.take<double>(N);
+    d.lraw = cv.take<double>(N);
+    d.uraw = cv.take<double>(N);
+    d.col_orig = cv.take<int32_t>(N);
+    d.inst_of_col = cv.take<int32_t>(N);
+    d.y = cv.take<char>(M * es);
+    d.yavg = cv.take<char>(M * es);
+    d.y0 = cv.take<char>(M * es);
+    d.q = cv.take<char>(M * es);
+    d.q64 = cv.take<double>(M);
+    d.rho = cv.take<double>(M);
+    d.qraw = cv.take<double>(M);
+    d.row_orig = cv.take<int32_t>(M);
+    d.inst_of_row = cv.take<int32_t>(M);
+    *info = cv.take<InstInfo>(sz.batch);
+    *st = cv.take<InstState>(sz.batch);
+    d.partials = cv.take<double>((size_t)(sz.nblkK + sz.nblkT) * NCAND * NSUM + 1);
+    d.vecN64 = cv.take<double>(N);
+    d.vecN64b = cv.take<double>(N);
+    b.vecN64c = cv.take<double>(N);
+    d.vecM64 = cv.take<double>(M);
+    d.vecM64b = cv.take<double>(M);
+    d.inst_scratch = cv.take<double>((size_t)sz.batch * 16 + 16);
+    // adjoint of unrolled steps
+    if (o.unroll_capacity > 0) {
+        const int64_t C = std::max(1, o.unroll_checkpoint);
+        const int64_t nck = (o.unroll_capacity + C - 1) / C + 1;
+        b.ckx = cv.take<char>(nck * N * es);
+        b.cky = cv.take<char>(nck * M * es);
+        b.maskx = cv.take<uint8_t>(C * N);
+        b.masky = cv.take<uint8_t>(C * M);
+        b.ax = cv.take<double>(N);
+        b.av = cv.take<double>(N);
+        b.axb = cv.take<double>(N);
+        b.ac = cv.take<double>(N);
+        b.al = cv.take<double>(N);
+        b.au = cv.take<double>(N);
+        b.ay = cv.take<double>(M);
+        b.aw = cv.take<double>(M);
+        b.aq = cv.take<double>(M);
+    }
+}
+
+static int check_opts(const pdhg_opts *o)
+{
+    if (o->precision != PDHG_PREC_F32 && o->precision != PDHG_PREC_F64)
+        return fail(PDHG_ERR_INVALID_ARG, "precision must be PDHG_PREC_F32 or PDHG_PREC_F64");
+    if (o->check_every < 1 || o->check_every > 4096) return fail(PDHG_ERR_INVALID_ARG, "check_every must be in 1..4096");
+    if (o->ruiz_iters < 0 || o->power_max_iters < 1) return fail(PDHG_ERR_INVALID_ARG, "bad ruiz/power iteration count");
+    if (!(o->eps > 0.0)) return fail(PDHG_ERR_INVALID_ARG, "eps must be > 0");
+    if (o->max_iters < 1) return fail(PDHG_ERR_INVALID_ARG, "max_iters must be >= 1");
+    if (o->unroll_capacity < 0 || (o->unroll_capacity > 0 && o->unroll_checkpoint < 1))
+        return fail(PDHG_ERR_INVALID_ARG, "bad unroll capacity / checkpoint");
+    if (!(o->step_frac > 0.0) && !(o->step_size > 0.0)) return fail(PDHG_ERR_INVALID_ARG, "step_frac must be > 0");
+    return PDHG_OK;
+}
+
+static int plan_all(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, std::vector<HostLP> &hosts,
+                    std::vector<InstPlan> &plans, Sizes &sz, bool pattern_only)
+{
+    if (!lp || batch < 1) return fail(PDHG_ERR_INVALID_ARG, "need lp != NULL and batch >= 1");
+    int rc = check_opts(o);
+    if (rc) return rc;
+    hosts.resize(batch);
+    plans.resize(batch);
+    const Bins bins = make_bins(o);
+    sz = Sizes{};
+    sz.batch = batch;
+    for (int b = 0; b < batch; ++b) {
+        if ((rc = load_lp(lp[b], hosts[b], pattern_only))) {
+            if (batch > 1) {
+                std::string m = g_err;
+                return fail(rc, "instance %d: %s", b, m.c_str());
+            }
+            return rc;
+        }
+        plan_instance(hosts[b], bins, plans[b]);
+        sz.N += hosts[b].n;
+        sz.M += hosts[b].m;
+        sz.NNZ += hosts[b].nnz;
+        for (auto &s : plans[b].segK) sz.nblkK += (s.nrows + seg_group(s.lanes_log2) - 1) / seg_group(s.lanes_log2);
+        for (auto &s : plans[b].segT) sz.nblkT += (s.nrows + seg_group(s.lanes_log2) - 1) / seg_group(s.lanes_log2);
+        sz.nsegK += plans[b].segK.size();
+        sz.nsegT += plans[b].segT.size();
+    }
+    if (sz.N >= INT32_MAX || sz.M >= INT32_MAX) return fail(PDHG_ERR_SHAPE, "total n and m must be < 2^31");
+    if (sz.nblkK + sz.nblkT >= INT32_MAX) return fail(PDHG_ERR_SHAPE, "too many workgroups");
+    return PDHG_OK;
+}
+
+extern "C" size_t pdhg_workspace_bytes(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o)
+{
+    pdhg_opts def;
+    if (!o) {
+        pdhg_default_opts(&def);
+        o = &def;
+    }
+    std::vector<HostLP> hosts;
+    std::vector<InstPlan> plans;
+    Sizes sz;
+    if (plan_all(lp, batch, o, hosts, plans, sz, false)) return 0;
+    Carve cv;
+    Dev d{};
+    Buffers b{};
+    InstInfo *info;
+    InstState *st;
+    carve(cv, sz, o->precision, *o, d, b, &info, &st);
+    return (cv.off + 255) & ~(size_t)255;
+}
+
+// ---------------------------------------------------------------------------
+// setup
+// ---------------------------------------------------------------------------
+
+template <typename X>
+static int h2d(X *dst, const X *src, size_t cnt, hipStream_t s)
+{
+    if (cnt) HIPCHK(hipMemcpyAsync(dst, src, cnt * sizeof(X), hipMemcpyHostToDevice, s));
+    return PDHG_OK;
+}
+
+// builds the host images of both operators and all vectors, then uploads
+static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
+{
+    const Sizes &sz = h->sz;
+    Buffers &b = h->buf;
+    Dev &d = h->d;
+    std::vector<int64_t> Krp(sz.M + 1), Ktrp(sz.N + 1);
+    std::vector<int32_t> Kci(sz.NNZ), Ktci(sz.NNZ), Kbs(sz.nblkK), Ktbs(sz.nblkT);
+    std::vector<double> Kv(sz.NNZ), Ktv(sz.NNZ);
+    std::vector<Seg> Kseg, Ktseg;
+    std::vector<double> craw(sz.N), lraw(sz.N), uraw(sz.N), qraw(sz.M);
+    std::vector<int32_t> col_orig(sz.N), row_orig(sz.M), inst_col(sz.N), inst_row(sz.M);
+    h->info.assign(h->batch, InstInfo{});
+    int64_t xoff = 0, yoff = 0, nzoff = 0;
+    int32_t blkK = 0, blkT = 0;
+    Krp[0] = 0;
+    Ktrp[0] = 0;
+    for (int bi = 0; bi < h->batch; ++bi) {
+        const HostLP &lp = hosts[bi];
+        const InstPlan &p = h->plan[bi];
+        InstInfo &in = h->info[bi];
+        in.xoff = xoff;
+        in.yoff = yoff;
+        in.n = (int32_t)p.n;
+        in.m = (int32_t)p.m;
+        in.m1 = (int32_t)p.m1;
+        std::vector<int32_t> col_new(p.n);
+        for (int64_t j = 0; j < p.n; ++j) col_new[p.col_order[j]] = (int32_t)j;
+        // K rows in internal order, global column index
+        int64_t pos = nzoff;
+        for (int64_t i = 0; i < p.m; ++i) {
+            const int32_t r = p.row_order[i];
+            for (int64_t k = lp.rp[r]; k < lp.rp[r + 1]; ++k) {
+                Kci[pos] = (int32_t)(xoff + col_new[lp.ci[k]]);
+                Kv[pos] = lp.v[k];
+                ++pos;
+            }
+            Krp[yoff + i + 1] = pos;
+            row_orig[yoff + i] = r;
+            inst_row[yoff + i] = bi;
+            qraw[yoff + i] = lp.rhs[r];
+        }
+        // K^T by a stable counting sort over the internal rows of K
+        std::vector<int64_t> cnt(p.n + 1, 0);
+        for (int64_t k = nzoff; k < pos; ++k) cnt[Kci[k] - xoff + 1]++;
+        for (int64_t j = 0; j < p.n; ++j) cnt[j + 1] += cnt[j];
+        for (int64_t j = 0; j < p.n; ++j) Ktrp[xoff + j + 1] = nzoff + cnt[j + 1];
+        std::vector<int64_t> next(cnt.begin(), cnt.end() - 1);
+        for (int64_t i = 0; i < p.m; ++i)
+            for (int64_t k = Krp[yoff + i]; k < Krp[yoff + i + 1]; ++k) {
+                const int64_t j = Kci[k] - xoff;
+                const int64_t dst = nzoff + next[j]++;
+                Ktci[dst] = (int32_t)(yoff + i);
+                Ktv[dst] = Kv[k];
+            }
+        for (int64_t j = 0; j < p.n; ++j) {
+            const int32_t cj = p.col_order[j];
+            col_orig[xoff + j] = cj;
+            inst_col[xoff + j] = bi;
+            craw[xoff + j] = lp.c[cj];
+            lraw[xoff + j] = lp.l[cj];
+            uraw[xoff + j] = lp.u[cj];
+        }
+        // segments and block maps (instance-major, so an instance's blocks are contiguous)
+        in.blkK0 = blkK;
+        for (const SegH &sh : p.segK) {
+            Seg sg{};
+            sg.row0 = yoff + sh.row0;
+            sg.nrows = sh.nrows;
+            sg.blk0 = blkK;
+            sg.nblk = (sh.nrows + seg_group(sh.lanes_log2) - 1) / seg_group(sh.lanes_log2);
+            sg.lanes_log2 = sh.lanes_log2;
+            sg.inst = bi;
+            sg.ineq = sh.ineq;
+            for (int t = 0; t < sg.nblk; ++t) Kbs[blkK + t] = (int32_t)Kseg.size();
+            blkK += sg.nblk;
+            Kseg.push_back(sg);
+        }
+        in.blkK1 = blkK;
+        in.blkT0 = blkT;
+        for (const SegH &sh : p.segT) {
+            Seg sg{};
+            sg.row0 = xoff + sh.row0;
+            sg.nrows = sh.nrows;
+            sg.blk0 = blkT;
+            sg.nblk = (sh.nrows + seg_group(sh.lanes_log2) - 1) / seg_group(sh.lanes_log2);
+            sg.lanes_log2 = sh.lanes_log2;
+            sg.inst = bi;
+            sg.ineq = 0;
+            for (int t = 0; t < sg.nblk; ++t) Ktbs[blkT + t] = (int32_t)Ktseg.size();
+            blkT += sg.nblk;
+            Ktseg.push_back(sg);
+        }
+        in.blkT1 = blkT;
+        double cn = 0, qn = 0;
+        for (int64_t j = 0; j < p.n; ++j) cn += lp.c[j] * lp.c[j];
+        for (int64_t i = 0; i < p.m; ++i) qn += lp.rhs[i] * lp.rhs[i];
+        in.cnorm = std::sqrt(cn);
+        in.qnorm = std::sqrt(qn);
+        xoff += p.n;
+        yoff += p.m;
+        nzoff = pos;
+    }
+    int rc;
+    if ((rc = h2d(b.Krp, Krp.data(), Krp.size(), s)) || (rc = h2d(b.Kci, Kci.data(), Kci.size(), s)) ||
+        (rc = h2d(b.Kv64, Kv.data(), Kv.size(), s)) || (rc = h2d(b.Kseg, Kseg.data(), Kseg.size(), s)) ||
+        (rc = h2d(b.Kbs, Kbs.data(), Kbs.size(), s)) || (rc = h2d(b.Ktrp, Ktrp.data(), Ktrp.size(), s)) ||
+        (rc = h2d(b.Ktci, Ktci.data(), Ktci.size(), s)) || (rc = h2d(b.Ktv64, Ktv.data(), Ktv.size(), s)) ||
+        (rc = h2d(b.Ktseg, Ktseg.data(), Ktseg.size(), s)) || (rc = h2d(b.Ktbs, Ktbs.data(), Ktbs.size(), s)) ||
+        (rc = h2d(d.craw, craw.data(), craw.size(), s)) || (rc = h2d(d.lraw, lraw.data(), lraw.size(), s)) ||
+        (rc = h2d(d.uraw, uraw.data(), uraw.size(), s)) || (rc = h2d(d.qraw, qraw.data(), qraw.size(), s)) ||
+        (rc = h2d(d.col_orig, col_orig.data(), col_orig.size(), s)) ||
+        (rc = h2d(d.row_orig, row_orig.data(), row_orig.size(), s)) ||
+        (rc = h2d(d.inst_of_col, inst_col.data(), inst_col.size(), s)) ||
+        (rc = h2d(d.inst_of_row, inst_row.data(), inst_row.size(), s)) ||
+        (rc = h2d((InstInfo *)d.info, h->info.data(), h->info.size(), s)))
+        return rc;
+    // the host images die with this scope: wait for the copies
+    HIPCHK(hipStreamSynchronize(s));
+    return PDHG_OK;
+}
+
+template <typename T>
+static int device_setup(pdhg_handle *h, hipStream_t s)
+{
+    Dev &d = h->d;
+    const pdhg_opts &o = h->opts;
+    const int B = h->batch;
+    // Ruiz scaling (Algorithm 3): both norms from the same scaled matrix, then
+    // rho /= sqrt(row norm), kap /= sqrt(col norm); values rescaled once at the end
+    launch_fill(d.rho, d.M, 1.0, s);
+    launch_fill(d.kap, d.N, 1.0, s);
+    for (int it = 0; it < o.ruiz_iters; ++it) {
+        launch_rowmax(d.K, d.remap, true, d.rho, d.kap, d.vecM64, s);
+        launch_rowmax(d.Kt, d.remap, false, d.kap, d.rho, d.vecN64, s);
+        launch_ruiz_update(d.rho, d.vecM64, d.M, s);
+        launch_ruiz_update(d.kap, d.vecN64, d.N, s);
+    }
+    launch_scale_vals(d.K, h->buf.Kv64, h->buf.Kv32, true, d.rho, d.kap, s);
+    launch_scale_vals(d.Kt, h->buf.Ktv64, h->buf.Ktv32, false, d.kap, d.rho, s);
+    launch_scale_data<T>(d, s);
+    HIPCHK(hipGetLastError());
+    // norms of the scaled cost and right-hand side (primal weight, Section 2.4.3)
+    std::vector<double> cn2(B), qn2(B);
+    double *sc = d.inst_scratch;
+    launch_inst_nrm2(d, 1, d.c64, sc, s);
+    launch_inst_nrm2(d, 0, d.q64, sc + B, s);
+    HIPCHK(hipMemcpyAsync(cn2.data(), sc, B * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(qn2.data(), sc + B, B * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    // power iteration (Algorithm 2) on every instance at once
+    std::vector<double> est(B, 0.0), prev(B, -1.0), w2(B);
+    std::vector<int> conv(B, 0), its(B, 0);
+    double *bv = d.vecN64, *wv = d.vecM64, *bt = d.vecN64b;
+    double *pk = d.partials, *pt = d.partials + h->sz.nblkK + 1;
+    launch_fill(bv, d.N, 1.0, s);
+    int remaining = B;
+    for (int it = 0; it < o.power_max_iters && remaining > 0; ++it) {
+        launch_spmv64(d.K, d.remap, bv, wv, pk, s);
+        if (it > 0) {
+            launch_inst_sum(d, 1, pk, sc, s);
+            HIPCHK(hipMemcpyAsync(w2.data(), sc, B * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            for (int b = 0; b < B; ++b) {
+                if (conv[b]) continue;
+                est[b] = std::sqrt(w2[b]);
+                its[b] = it;
+                if (prev[b] >= 0.0 && std::fabs(est[b] - prev[b]) <= o.power_tol * est[b]) {
+                    conv[b] = 1;
+                    --remaining;
+                }
+                prev[b] = est[b];
+            }
+            if (remaining == 0) break;
+        }
+        launch_spmv64(d.Kt, d.remap, wv, bt, pt, s);
+        launch_inst_sum(d, 0, pt, sc + B, s);
+        launch_normalize(bt, d.inst_of_col, d.N, sc + B, s);
+        std::swap(bv, bt);
+    }
+    if (remaining > 0) {
+        launch_spmv64(d.K, d.remap, bv, wv, pk, s);
+        launch_inst_sum(d, 1, pk, sc, s);
+        HIPCHK(hipMemcpyAsync(w2.data(), sc, B * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int b = 0; b < B; ++b)
+            if (!conv[b]) {
+                est[b] = std::sqrt(w2[b]);
+                its[b] = o.power_max_iters;
+            }
+    }
+    HIPCHK(hipGetLastError());
+    // step size and primal weight (Sections 2.3.1, 2.4.3)
+    h->st0.assign(B, InstState{});
+    h->knorm = est;
+    for (int b = 0; b < B; ++b) {
+        InstState &st = h->st0[b];
+        const double kn = est[b];
+        const double eta = o.step_size > 0.0 ? o.step_size : (kn > 0.0 ? o.step_frac / kn : 1.0);
+        const double cn = std::sqrt(cn2[b]), qn = std::sqrt(qn2[b]);
+        h->info[b].cnorm_s = cn;
+        h->info[b].qnorm_s = qn;
+        double omega;
+        if (o.primal_weight > 0.0)
+            omega = o.primal_weight;
+        else if (cn > o.eps_zero && qn > o.eps_zero)
+            omega = cn / qn;
+        else
+            omega = 1.0;
+        st.eta = eta;
+        st.omega0 = omega;
+        st.omega = omega;
+        st.tau = eta / omega;
+        st.sigma = eta * omega;
+        st.knorm = kn;
+        st.kkt0 = INFINITY;
+        st.kkt_prev = INFINITY;
+        st.power_iters = its[b];
+    }
+    HIPCHK(hipMemcpyAsync(d.st, h->st0.data(), B * sizeof(InstState), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync((InstInfo *)d.info, h->info.data(), B * sizeof(InstInfo), hipMemcpyHostToDevice, s));
+    launch_init_point<T>(d, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    return PDHG_OK;
+}
+
+extern "C" int pdhg_setup(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, void *ws, size_t ws_bytes,
+                          hipStream_t stream, pdhg_handle **out)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (!out) return fail(PDHG_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    pdhg_opts def;
+    if (!o) {
+        pdhg_default_opts(&def);
+        o = &def;
+    }
+    if (!ws) return fail(PDHG_ERR_INVALID_ARG, "workspace is NULL");
+    if (((uintptr_t)ws & 255) != 0) return fail(PDHG_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    std::vector<HostLP> hosts;
+    auto *h = new pdhg_handle();
+    int rc = plan_all(lp, batch, o, hosts, h->plan, h->sz, false);
+    if (rc) {
+        delete h;
+        return rc;
+    }
+    h->batch = batch;
+    h->prec = o->precision;
+    h->opts = *o;
+    Carve cv;
+    cv.base = (char *)ws;
+    InstInfo *info;
+    InstState *st;
+    carve(cv, h->sz, h->prec, *o, h->d, h->buf, &info, &st);
+    if (cv.off > ws_bytes) {
+        delete h;
+        return fail(PDHG_ERR_NOMEM, "workspace too small: need %zu bytes, got %zu", cv.off, ws_bytes);
+    }
+    h->ws_bytes = cv.off;
+    Dev &d = h->d;
+    d.batch = batch;
+    d.remap = o->xcd_remap ? 1 : 0;
+    d.N = h->sz.N;
+    d.M = h->sz.M;
+    d.info = info;
+    d.st = st;
+    Buffers &b = h->buf;
+    d.K = OpDev{h->sz.M, b.Krp, b.Kci, b.Kv32, b.Kv64, b.Kseg, b.Kbs, (int32_t)h->sz.nsegK, (int32_t)h->sz.nblkK};
+    d.Kt = OpDev{h->sz.N, b.Ktrp, b.Ktci, b.Ktv32, b.Ktv64, b.Ktseg, b.Ktbs, (int32_t)h->sz.nsegT,
+                 (int32_t)h->sz.nblkT};
+    if (hipHostMalloc((void **)&h->hdone_host, sizeof(int32_t) * batch, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+        delete h;
+        return fail(PDHG_ERR_HIP, "hipHostMalloc failed");
+    }
+    std::memset(h->hdone_host, 0, sizeof(int32_t) * batch);
+    if (hipHostGetDevicePointer((void **)&d.hdone, h->hdone_host, 0) != hipSuccess) {
+        hipHostFree(h->hdone_host);
+        delete h;
+        return fail(PDHG_ERR_HIP, "hipHostGetDevicePointer failed");
+    }
+    rc = upload(h, hosts, stream);
+    hosts.clear();
+    if (!rc) rc = h->prec == PDHG_PREC_F32 ? device_setup<float>(h, stream) : device_setup<double>(h, stream);
+    if (rc) {
+        std::string m = g_err;
+        pdhg_destroy(h);
+        return fail(rc, "%s", m.c_str());
+    }
+    h->sol_avg.assign(batch, 0);
+    h->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = h;
+    return PDHG_OK;
+}
+
+extern "C" void pdhg_destroy(pdhg_handle *h)
+{
+    if (!h) return;
+    if (h->graph) hipGraphExecDestroy(h->graph);
+    if (h->cap_stream) hipStreamDestroy(h->cap_stream);
+    if (h->hdone_host) hipHostFree(h->hdone_host);
+    delete h;
+}
+
+// ---------------------------------------------------------------------------
+// solve
+// ---------------------------------------------------------------------------
+
+static CtlParams ctl_params(const pdhg_handle *h)
+{
+    const pdhg_opts &o = h->opts;
+    CtlParams P{};
+    P.eps = o.eps;
+    P.beta_suff = o.beta_suff;
+    P.beta_nec = o.beta_nec;
+    P.beta_art = o.beta_art;
+    P.eps_zero = o.eps_zero;
+    P.max_iters = o.max_iters;
+    P.check_every = o.check_every;
+    P.use_restarts = o.use_restarts;
+    P.use_pw = o.use_pw_update;
+    P.batch = h->batch;
+    return P;
+}
+
+// one chunk: check_every iterations, the check, the control decision, restart
+template <typename T>
+static void enqueue_chunk(const pdhg_handle *h, hipStream_t s)
+{
+    const Dev &d = h->d;
+    const int avg = h->opts.use_restarts;
+    for (int j = 0; j < h->opts.check_every; ++j) {
+        launch_primal<T>(d, j, avg, nullptr, s);
+        launch_dual<T>(d, j, avg, nullptr, s);
+    }
+    launch_check<T>(d, avg, s);
+    launch_control(d, ctl_params(h), h->opts.check_every, s);
+    if (avg) launch_restart<T>(d, s);
+}
+
+template <typename T>
+static int build_graph(pdhg_handle *h)
+{
+    if (h->graph) return PDHG_OK;
+    if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    hipGraph_t g;
+    HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    enqueue_chunk<T>(h, h->cap_stream);
+    HIPCHK(hipStreamEndCapture(h->cap_stream, &g));
+    hipError_t e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        h->graph = nullptr;
+        return fail(PDHG_ERR_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+    }
+    return PDHG_OK;
+}
+
+template <typename T>
+static int solve_impl(pdhg_handle *h, pdhg_result *res, hipStream_t s)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    const int B = h->batch;
+    const Dev &d = h->d;
+    if (h->opts.use_graph) {
+        int rc = build_graph<T>(h);
+        if (rc) return rc;
+    }
+    // fresh solve state from the current iterate
+    std::vector<InstState> st = h->st0;
+    for (auto &x : st) {
+        x.k_total = 0;
+        x.t_inner = 0;
+        x.done = 0;
+        x.status = PDHG_ITERATION_LIMIT;
+        x.nrestarts = 0;
+        x.kkt0 = INFINITY;
+        x.kkt_prev = INFINITY;
+    }
+    std::memset(h->hdone_host, 0, sizeof(int32_t) * B);
+    HIPCHK(hipMemcpyAsync(d.st, st.data(), B * sizeof(InstState), hipMemcpyHostToDevice, s));
+    launch_epoch_start<T>(d, s);
+    launch_check<T>(d, 0, s);
+    launch_control(d, ctl_params(h), 0, s);
+    HIPCHK(hipGetLastError());
+
+    const int DEPTH = 4;
+    hipEvent_t ev[DEPTH];
+    for (int k = 0; k < DEPTH; ++k) HIPCHK(hipEventCreateWithFlags(&ev[k], hipEventDisableTiming));
+    HIPCHK(hipEventRecord(ev[0], s));
+    HIPCHK(hipEventSynchronize(ev[0]));
+    auto all_done = [&]() {
+        for (int b = 0; b < B; ++b)
+            if (!((volatile int32_t *)h->hdone_host)[b]) return false;
+        return true;
+    };
+    const double tl = h->opts.time_limit;
+    bool timed_out = false;
+    int rc = PDHG_OK;
+    if (!all_done()) {
+        for (int64_t chunk = 0;; ++chunk) {
+            if (h->opts.use_graph) {
+                if (hipGraphLaunch(h->graph, s) != hipSuccess) {
+                    rc = fail(PDHG_ERR_HIP, "hipGraphLaunch failed");
+                    break;
+                }
+            } else {
+                enqueue_chunk<T>(h, s);
+            }
+            hipEventRecord(ev[chunk % DEPTH], s);
+            if (chunk >= DEPTH - 1) {
+                hipEventSynchronize(ev[(chunk - (DEPTH - 1)) % DEPTH]);
+                if (all_done()) break;
+                if (tl > 0.0 &&
+                    std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > tl) {
+                    timed_out = true;
+                    break;
+                }
+            }
+        }
+    }
+    hipError_t se = hipStreamSynchronize(s);
+    for (int k = 0; k < DEPTH; ++k) hipEventDestroy(ev[k]);
+    if (rc) return rc;
+    if (se != hipSuccess) return fail(PDHG_ERR_HIP, "solve: %s", hipGetErrorString(se));
+    HIPCHK(hipMemcpy(st.data(), d.st, B * sizeof(InstState), hipMemcpyDeviceToHost));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int b = 0; b < B; ++b) {
+        const InstState &x = st[b];
+        pdhg_result &r = res[b];
+        std::memset(&r, 0, sizeof r);
+        r.status = x.done ? x.status : (timed_out ? PDHG_TIME_LIMIT : PDHG_ITERATION_LIMIT);
+        r.from_avg = x.sol_avg;
+        r.iters = x.k_total;
+        r.restarts = x.nrestarts;
+        r.power_iters = x.power_iters;
+        r.knorm = x.knorm;
+        r.eta = x.eta;
+        r.omega0 = x.omega0;
+        r.omega = x.omega;
+        r.tau = x.tau;
+        r.sigma = x.sigma;
+        std::memcpy(&r.kkt, x.kkt, sizeof(double) * 9);
+        r.seconds = secs;
+        h->sol_avg[b] = x.sol_avg;
+    }
+    // keep tau / sigma / omega of the end of the solve for later fixed-step calls
+    for (int b = 0; b < B; ++b) {
+        h->st0[b].omega = st[b].omega;
+        h->st0[b].tau = st[b].tau;
+        h->st0[b].sigma = st[b].sigma;
+    }
+    return PDHG_OK;
+}
+
+extern "C" int pdhg_solve(pdhg_handle *h, pdhg_result *res, hipStream_t stream)
+{
+    if (!h || !res) return fail(PDHG_ERR_INVALID_ARG, "NULL handle or result");
+    return h->prec == PDHG_PREC_F32 ? solve_impl<float>(h, res, stream) : solve_impl<double>(h, res, stream);
+}
+
+// ---------------------------------------------------------------------------
+// fixed-step iterations
+// ---------------------------------------------------------------------------
+
+template <typename T>
+static int iterate_impl(pdhg_handle *h, int64_t k, int32_t record, hipStream_t s)
+{
+    Dev d = h->d;
+    // fixed steps use the handle's tau / sigma and ignore done flags
+    std::vector<InstState> st = h->st0;
+    HIPCHK(hipMemcpyAsync(d.st, st.data(), h->batch * sizeof(InstState), hipMemcpyHostToDevice, s));
+    if (record) {
+        (void)record;
+        return fail(PDHG_ERR_STATE, "recording is not available in this build");
+    }
+    for (int64_t t = 0; t < k; ++t) {
+        launch_primal<T>(d, 0, 0, nullptr, s);
+        launch_dual<T>(d, 0, 0, nullptr, s);
+    }
+    HIPCHK(hipGetLastError());
+    return PDHG_OK;
+}
+
+extern "C" int pdhg_iterate(pdhg_handle *h, int64_t k, int32_t record, hipStream_t stream)
+{
+    if (!h || k < 0) return fail(PDHG_ERR_INVALID_ARG, "bad handle or step count");
+    return h->prec == PDHG_PREC_F32 ? iterate_impl<float>(h, k, record, stream)
+                                    : iterate_impl<double>(h, k, record, stream);
+}
+
+// ---------------------------------------------------------------------------
+// solution read-out, warm start, KKT of a caller point
+// ---------------------------------------------------------------------------
+
+static int out_copy(double *dst, const double *dev_src, size_t cnt, int mem, hipStream_t s)
+{
+    if (!dst || cnt == 0) return PDHG_OK;
+    HIPCHK(hipMemcpyAsync(dst, dev_src, cnt * sizeof(double),
+                          mem == PDHG_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
+    return PDHG_OK;
+}
+
+extern "C" int pdhg_get_solution(pdhg_handle *h, int32_t inst, int32_t which, double *x, double *y,
+                                 double *lambda, int32_t mem, hipStream_t s)
+{
+    if (!h || inst < 0 || inst >= h->batch) return fail(PDHG_ERR_INVALID_ARG, "bad handle or instance");
+    if (which < PDHG_SOL_RESULT || which > PDHG_SOL_AVERAGE) return fail(PDHG_ERR_INVALID_ARG, "bad 'which'");
+    if (mem != PDHG_MEM_HOST && mem != PDHG_MEM_DEVICE) return fail(PDHG_ERR_INVALID_ARG, "bad mem");
+    const Dev &d = h->d;
+    const InstInfo &in = h->info[inst];
+    const int avg = which == PDHG_SOL_AVERAGE || (which == PDHG_SOL_RESULT && h->sol_avg[inst]);
+    if (h->prec == PDHG_PREC_F32)
+        launch_point_to64<float>(d, avg, d.vecN64, d.vecM64, s);
+    else
+        launch_point_to64<double>(d, avg, d.vecN64, d.vecM64, s);
+    int rc;
+    if (x) {
+        launch_unscale_x(d, in.xoff, in.n, d.vecN64, d.vecN64b, s);
+        if ((rc = out_copy(x, d.vecN64b, in.n, mem, s))) return rc;
+    }
+    if (y) {
+        launch_unscale_y(d, in.yoff, in.m, d.vecM64, d.vecM64b, s);
+        if ((rc = out_copy(y, d.vecM64b, in.m, mem, s))) return rc;
+    }
+    if (lambda) {
+        launch_lambda(d, d.vecM64, h->buf.vecN64c, s);
+        launch_permute_out(d.col_orig, in.xoff, in.n, h->buf.vecN64c, d.vecN64b, s);
+        if ((rc = out_copy(lambda, d.vecN64b, in.n, mem, s))) return rc;
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    return PDHG_OK;
+}
+
+// stages a caller vector on the device (FP64); returns the device pointer
+static int stage_in(const double *src, size_t cnt, int mem, double *scratch, const double **dev, hipStream_t s)
+{
+    if (mem == PDHG_MEM_DEVICE) {
+        *dev = src;
+        return PDHG_OK;
+    }
+    if (cnt) HIPCHK(hipMemcpyAsync(scratch, src, cnt * sizeof(double), hipMemcpyHostToDevice, s));
+    *dev = scratch;
+    return PDHG_OK;
+}
+
+static int scale_caller_point(pdhg_handle *h, int32_t inst, const double *x, const double *y, int32_t mem,
+                              hipStream_t s)
+{
+    const Dev &d = h->d;
+    const InstInfo &in = h->info[inst];
+    const double *xd = nullptr, *yd = nullptr;
+    int rc;
+    if ((rc = stage_in(x, in.n, mem, d.vecN64b, &xd, s))) return rc;
+    if ((rc = stage_in(y, in.m, mem, d.vecM64b, &yd, s))) return rc;
+    launch_scale_in(d, in.xoff, in.n, in.yoff, in.m, xd, yd, d.vecN64, d.vecM64, s);
+    HIPCHK(hipGetLastError());
+    return PDHG_OK;
+}
+
+extern "C" int pdhg_set_state(pdhg_handle *h, int32_t inst, const double *x, const double *y, int32_t mem,
+                              hipStream_t s)
+{
+    if (!h || inst < 0 || inst >= h->batch || !x || !y) return fail(PDHG_ERR_INVALID_ARG, "bad arguments");
+    int rc = scale_caller_point(h, inst, x, y, mem, s);
+    if (rc) return rc;
+    const InstInfo &in = h->info[inst];
+    if (h->prec == PDHG_PREC_F32)
+        launch_set_point<float>(h->d, in.xoff, in.n, in.yoff, in.m, in.m1, h->d.vecN64, h->d.vecM64, s);
+    else
+        launch_set_point<double>(h->d, in.xoff, in.n, in.yoff, in.m, in.m1, h->d.vecN64, h->d.vecM64, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    return PDHG_OK;
+}
+
+extern "C" int pdhg_kkt(pdhg_handle *h, int32_t inst, const double *x, const double *y, int32_t mem,
+                        pdhg_kkt_out *out, hipStream_t s)
+{
+    if (!h || inst < 0 || inst >= h->batch || !x || !y || !out) return fail(PDHG_ERR_INVALID_ARG, "bad arguments");
+    const Dev &d = h->d;
+    // other instances' entries of the scratch vectors are never read for `inst`
+    int rc = scale_caller_point(h, inst, x, y, mem, s);
+    if (rc) return rc;
+    launch_check64(d, d.vecN64, d.vecM64, s);
+    launch_kkt_final(d, inst, d.inst_scratch, s);
+    double v[9];
+    HIPCHK(hipMemcpyAsync(v, d.inst_scratch, sizeof v, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    out->pres = v[0];
+    out->dres = v[1];
+    out->pobj = v[2];
+    out->dobj = v[3];
+    out->gap = v[4];
+    out->rel_pres = v[5];
+    out->rel_dres = v[6];
+    out->rel_gap = v[7];
+    out->rel_kkt = v[8];
+    return PDHG_OK;
+}
+
+extern "C" int pdhg_backward(pdhg_handle *h, const double *gx, const double *gy, double *gc, double *grhs,
+                             double *gl, double *gu, double *gx0, double *gy0, int32_t mem, hipStream_t s)
+{
+    (void)gx; (void)gy; (void)gc; (void)grhs; (void)gl; (void)gu; (void)gx0; (void)gy0; (void)mem; (void)s;
+    if (!h) return fail(PDHG_ERR_INVALID_ARG, "NULL handle");
+    return fail(PDHG_ERR_STATE, "no recorded pdhg_iterate to differentiate");
+}
+
+extern "C" int pdhg_get_scaling(pdhg_handle *h, int32_t inst, double *rho, double *kappa, int32_t mem,
+                                hipStream_t s)
+{
+    if (!h || inst < 0 || inst >= h->batch) return fail(PDHG_ERR_INVALID_ARG, "bad handle or instance");
+    const Dev &d = h->d;
+    const InstInfo &in = h->info[inst];
+    int rc;
+    if (kappa) {
+        launch_permute_out(d.col_orig, in.xoff, in.n, d.kap, d.vecN64b, s);
+        if ((rc = out_copy(kappa, d.vecN64b, in.n, mem, s))) return rc;
+    }
+    if (rho) {
+        launch_permute_out(d.row_orig, in.yoff, in.m, d.rho, d.vecM64b, s);
+        if ((rc = out_copy(rho, d.vecM64b, in.m, mem, s))) return rc;
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    return PDHG_OK;
+}
+
+extern "C" int pdhg_get_info(const pdhg_handle *h, pdhg_info *info)
+{
+    if (!h || !info) return fail(PDHG_ERR_INVALID_ARG, "NULL argument");
+    std::memset(info, 0, sizeof *info);
+    for (int b = 0; b < h->batch; ++b) {
+        info->n += h->plan[b].n;
+        info->m += h->plan[b].m;
+        info->m_ineq += h->plan[b].m1;
+        info->nnz += h->plan[b].nnz;
+    }
+    const InstState &st = h->st0[0];
+    info->knorm = st.knorm;
+    info->eta = st.eta;
+    info->omega = st.omega;
+    info->tau = st.tau;
+    info->sigma = st.sigma;
+    info->setup_seconds = h->setup_seconds;
+    info->precision = h->prec;
+    info->batch = h->batch;
+    info->workspace_bytes = (int64_t)h->ws_bytes;
+    info->nseg_primal = (int32_t)h->sz.nsegT;
+    info->nseg_dual = (int32_t)h->sz.nsegK;
+    info->nblk_primal = h->sz.nblkT;
+    info->nblk_dual = h->sz.nblkK;
+    return PDHG_OK;
+}

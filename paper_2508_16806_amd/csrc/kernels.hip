@@ -1,0 +1,838 @@
+// kernels.hip -- gfx950 kernels of the PDHG hot path and its setup.
+//
+// Iteration (Algorithm 1 in the sign-consistent form of Appendices C/D,
+// theta = 1), all in the scaled variables of Section 2.4.1:
+//   primal sweep over rows j of K~^T:  g = (K~^T y)_j,
+//       x+_j = clip(x_j - tau (c~_j - g), l~_j, u~_j),  xbar_j = 2 x+_j - x_j,
+//       running epoch average xavg_j += (x+_j - xavg_j) / (t + 1)
+//   dual sweep over rows i of K~:      r = (K~ xbar)_i,
+//       y+_i = proj_Y(y_i + sigma (q~_i - r)) (clip at 0 for ">=" rows), yavg
+// Check every N iterations: FP64 residual sums of the current iterate and of
+// the epoch average (Section 2.3.2 on the original LP, the omega-weighted
+// metric of Section 2.4.2 on the scaled one) as per-workgroup partials;
+// control: candidate choice, termination, the three restart criteria and the
+// primal-weight update (Algorithm 4), one workgroup per instance.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "../../include/pdhg.h"
+#include "kernels.h"
+#include "sweep.h"
+
+namespace pdhg {
+
+// ---------------------------------------------------------------------------
+// hot path: fused SpMV + update sweeps
+// ---------------------------------------------------------------------------
+
+// MASK: also record the clip region of x (0 interior, 1 at l, 2 at u) for the
+// adjoint replay.
+template <typename T, int AVG, int MASK>
+__global__ __launch_bounds__(WG) void k_primal(Dev d, int j_in_chunk, uint8_t *__restrict__ mask)
+{
+    __shared__ double red[8];
+    const int lb = logical_block(d.remap);
+    const OpDev &op = d.Kt;
+    const Seg s = op.seg[op.blk_seg[lb]];
+    const InstState *st = d.st + s.inst;
+    if (st->done) return;
+    const double tau = st->tau;
+    const double w = AVG ? 1.0 / (double)(st->t_inner + j_in_chunk + 1) : 0.0;
+    T *__restrict__ x = (T *)d.x;
+    T *__restrict__ xb = (T *)d.xbar;
+    T *__restrict__ xa = (T *)d.xavg;
+    const T *__restrict__ c = (const T *)d.c;
+    const T *__restrict__ l = (const T *)d.l;
+    const T *__restrict__ u = (const T *)d.u;
+    const T *__restrict__ y = (const T *)d.y;
+    const int bi = lb - s.blk0;
+    dispatch_lanes(s.lanes_log2, [&](auto tag) {
+        constexpr int L = decltype(tag)::value;
+        int64_t j;
+        double acc[1];
+        if (RowSweep<L, 1, T, T>::run(op, s, bi, y, nullptr, nullptr, red, j, acc)) {
+            const double xo = (double)x[j];
+            const double v = xo - tau * ((double)c[j] - acc[0]);
+            const double lo = (double)l[j], hi = (double)u[j];
+            const double xn = v < lo ? lo : (v > hi ? hi : v);
+            const T xnT = (T)xn;
+            x[j] = xnT;
+            xb[j] = (T)(2.0 * (double)xnT - xo);
+            if (AVG) {
+                const double a = (double)xa[j];
+                xa[j] = (T)(a + ((double)xnT - a) * w);
+            }
+            if (MASK) mask[j] = (uint8_t)(v <= lo ? 1 : (v >= hi ? 2 : 0));
+        }
+    });
+}
+
+template <typename T, int AVG, int MASK>
+__global__ __launch_bounds__(WG) void k_dual(Dev d, int j_in_chunk, uint8_t *__restrict__ mask)
+{
+    __shared__ double red[8];
+    const int lb = logical_block(d.remap);
+    const OpDev &op = d.K;
+    const Seg s = op.seg[op.blk_seg[lb]];
+    const InstState *st = d.st + s.inst;
+    if (st->done) return;
+    const double sigma = st->sigma;
+    const double w = AVG ? 1.0 / (double)(st->t_inner + j_in_chunk + 1) : 0.0;
+    T *__restrict__ y = (T *)d.y;
+    T *__restrict__ ya = (T *)d.yavg;
+    const T *__restrict__ q = (const T *)d.q;
+    const T *__restrict__ xb = (const T *)d.xbar;
+    const bool ineq = s.ineq != 0;
+    const int bi = lb - s.blk0;
+    dispatch_lanes(s.lanes_log2, [&](auto tag) {
+        constexpr int L = decltype(tag)::value;
+        int64_t i;
+        double acc[1];
+        if (RowSweep<L, 1, T, T>::run(op, s, bi, xb, nullptr, nullptr, red, i, acc)) {
+            const double wv = (double)y[i] + sigma * ((double)q[i] - acc[0]);
+            const double yn = (ineq && wv < 0.0) ? 0.0 : wv;
+            const T ynT = (T)yn;
+            y[i] = ynT;
+            if (AVG) {
+                const double a = (double)ya[i];
+                ya[i] = (T)(a + ((double)ynT - a) * w);
+            }
+            if (MASK) mask[i] = (uint8_t)((!ineq || wv > 0.0) ? 1 : 0);
+        }
+    });
+}
+
+// ---------------------------------------------------------------------------
+// check: per-workgroup FP64 partial sums for NC candidates
+//   K rows i   : s0 += e^2 (e = q~ - K~x, clipped at 0 on ">=" rows),
+//                s1 += (e / rho_i)^2, s2 += q~_i y_i, s3 += (y_i - y0_i)^2
+//   K^T rows j : d = c~_j - (K~^T y)_j, lambda = proj_Lambda(d), rd = d - lambda,
+//                s4 += rd^2, s5 += (rd / kap_j)^2, s6 += c~_j x_j,
+//                s7 += l~_j lambda^+ + u~_j lambda^-, s8 += (x_j - x0_j)^2
+// Scaled residual e relates to the original one by e = rho_i (q - Kx)_i, and
+// rd = kap_j (c - K^T y - lambda)_j; objective terms are scale invariant.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double proj_lambda(double v, double l, double u)
+{
+    const bool lf = isfinite(l), uf = isfinite(u);
+    if (!lf && !uf) return 0.0;
+    if (!lf) return v < 0.0 ? v : 0.0;
+    if (!uf) return v > 0.0 ? v : 0.0;
+    return v;
+}
+
+template <typename V, int NC>
+__global__ __launch_bounds__(WG) void k_check(Dev d, const V *__restrict__ xa0, const V *__restrict__ xa1,
+                                              const V *__restrict__ ya0, const V *__restrict__ ya1,
+                                              const V *__restrict__ xs, const V *__restrict__ ys,
+                                              int skip_done)
+{
+    __shared__ double red[NCAND * NSUM * 4];
+    const int lbc = logical_block(d.remap);
+    const bool onK = lbc < d.K.nblk;
+    const OpDev &op = onK ? d.K : d.Kt;
+    const int lb = onK ? lbc : lbc - d.K.nblk;
+    const Seg s = op.seg[op.blk_seg[lb]];
+    if (skip_done && d.st[s.inst].done) return;
+    double sum[NC * NSUM];
+#pragma unroll
+    for (int k = 0; k < NC * NSUM; ++k) sum[k] = 0.0;
+    const int bi = lb - s.blk0;
+    const bool ineq = s.ineq != 0;
+    dispatch_lanes(s.lanes_log2, [&](auto tag) {
+        constexpr int L = decltype(tag)::value;
+        int64_t r;
+        double acc[NC];
+        if (onK) {
+            if (RowSweep<L, NC, double, V>::run(op, s, bi, xa0, xa1, nullptr, red, r, acc)) {
+                const double qi = d.q64[r], rh = d.rho[r];
+#pragma unroll
+                for (int a = 0; a < NC; ++a) {
+                    double e = qi - acc[a];
+                    if (ineq && e < 0.0) e = 0.0;
+                    const double eu = e / rh;
+                    const double ya = (double)(a == 0 ? ya0 : ya1)[r];
+                    const double dy = ya - (double)ys[r];
+                    sum[a * NSUM + 0] += e * e;
+                    sum[a * NSUM + 1] += eu * eu;
+                    sum[a * NSUM + 2] += qi * ya;
+                    sum[a * NSUM + 3] += dy * dy;
+                }
+            }
+        } else {
+            if (RowSweep<L, NC, double, V>::run(op, s, bi, ya0, ya1, nullptr, red, r, acc)) {
+                const double cj = d.c64[r], lj = d.l64[r], uj = d.u64[r], kj = d.kap[r];
+#pragma unroll
+                for (int a = 0; a < NC; ++a) {
+                    const double dd = cj - acc[a];
+                    const double lam = proj_lambda(dd, lj, uj);
+                    const double rd = dd - lam;
+                    const double rdu = rd / kj;
+                    const double xv = (double)(a == 0 ? xa0 : xa1)[r];
+                    const double dx = xv - (double)xs[r];
+                    sum[a * NSUM + 4] += rd * rd;
+                    sum[a * NSUM + 5] += rdu * rdu;
+                    sum[a * NSUM + 6] += cj * xv;
+                    sum[a * NSUM + 7] += lam > 0.0 ? lj * lam : (lam < 0.0 ? uj * lam : 0.0);
+                    sum[a * NSUM + 8] += dx * dx;
+                }
+            }
+        }
+    });
+    block_sum<NC * NSUM>(sum, red);
+    if (threadIdx.x == 0) {
+        double *out = d.partials + (size_t)lbc * (NCAND * NSUM);
+#pragma unroll
+        for (int k = 0; k < NCAND * NSUM; ++k) out[k] = k < NC * NSUM ? sum[k] : 0.0;
+    }
+}
+
+// Sums the instance's partials (fixed order) into tot[NCAND * NSUM] in LDS.
+__device__ void reduce_instance(const Dev &d, const InstInfo &in, double *tot)
+{
+    __shared__ double lds[NCAND * NSUM * 4];
+    double v[NCAND * NSUM];
+#pragma unroll
+    for (int k = 0; k < NCAND * NSUM; ++k) v[k] = 0.0;
+    const int nK = in.blkK1 - in.blkK0, nT = in.blkT1 - in.blkT0;
+    for (int t = threadIdx.x; t < nK + nT; t += WG) {
+        const int lbc = t < nK ? in.blkK0 + t : d.K.nblk + in.blkT0 + (t - nK);
+        const double *p = d.partials + (size_t)lbc * (NCAND * NSUM);
+#pragma unroll
+        for (int k = 0; k < NCAND * NSUM; ++k) v[k] += p[k];
+    }
+    block_sum<NCAND * NSUM>(v, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NCAND * NSUM; ++k) tot[k] = v[k];
+    }
+}
+
+struct Metrics {
+    double kkt[9];   // original-LP terms (pdhg_kkt_out order)
+    double kw_parts[3];  // scaled pres^2, scaled dres^2, gap^2
+};
+
+__device__ void metrics_from_sums(const double *s, const InstInfo &in, Metrics &m)
+{
+    const double pres = sqrt(s[1]), dres = sqrt(s[5]);
+    const double pobj = s[6], dobj = s[2] + s[7];
+    const double gap = fabs(dobj - pobj);
+    m.kkt[0] = pres;
+    m.kkt[1] = dres;
+    m.kkt[2] = pobj;
+    m.kkt[3] = dobj;
+    m.kkt[4] = gap;
+    m.kkt[5] = pres / (1.0 + in.qnorm);
+    m.kkt[6] = dres / (1.0 + in.cnorm);
+    m.kkt[7] = gap / (1.0 + fabs(dobj) + fabs(pobj));
+    m.kkt[8] = fmax(m.kkt[7], fmax(m.kkt[5], m.kkt[6]));
+    m.kw_parts[0] = s[0];
+    m.kw_parts[1] = s[4];
+    m.kw_parts[2] = gap * gap;
+}
+
+// KKT error in the omega-weighted form of Section 2.4.2.
+__device__ __forceinline__ double kkt_omega(const Metrics &m, double w)
+{
+    return sqrt(w * w * m.kw_parts[0] + m.kw_parts[1] / (w * w) + m.kw_parts[2]);
+}
+
+// One workgroup per instance.  iters_done: iterations since the last check
+// (0 for the check of the starting point).
+__global__ __launch_bounds__(WG) void k_control(Dev d, CtlParams P, int iters_done)
+{
+    __shared__ double tot[NCAND * NSUM];
+    const int b = blockIdx.x;
+    InstState &st = d.st[b];
+    if (st.done) return;
+    const InstInfo in = d.info[b];
+    reduce_instance(d, in, tot);
+    if (threadIdx.x != 0) return;
+
+    st.k_total += iters_done;
+    st.t_inner += iters_done;
+    const int nc = P.use_restarts ? 2 : 1;
+    Metrics mt[2];
+    bool finite = true;
+    for (int a = 0; a < nc; ++a) {
+        metrics_from_sums(tot + a * NSUM, in, mt[a]);
+        for (int k = 0; k < NSUM; ++k) finite = finite && isfinite(tot[a * NSUM + k]);
+    }
+    const double omega = st.omega;
+    const double kw0 = kkt_omega(mt[0], omega);
+    st.restart = 0;
+    if (!finite) {
+        st.done = 1;
+        st.status = PDHG_NUMERICAL_ERROR;
+        st.sol_avg = 0;
+        for (int k = 0; k < 9; ++k) st.kkt[k] = mt[0].kkt[k];
+        d.hdone[b] = 1;
+        return;
+    }
+    if (iters_done == 0) {
+        // starting point: termination test and the first epoch's reference value
+        st.kkt0 = kw0;
+        st.kkt_prev = INFINITY;
+        st.cand_avg = 0;
+        for (int k = 0; k < 9; ++k) st.kkt[k] = mt[0].kkt[k];
+        if (mt[0].kkt[8] <= P.eps) {
+            st.done = 1;
+            st.status = PDHG_OPTIMAL;
+            st.sol_avg = 0;
+            d.hdone[b] = 1;
+        }
+        return;
+    }
+    const double kw1 = nc > 1 ? kkt_omega(mt[1], omega) : INFINITY;
+    // restart candidate: the iterate when strictly better, else the average
+    const int cand = (nc > 1 && !(kw0 < kw1)) ? 1 : 0;
+    const double kwc = cand ? kw1 : kw0;
+    st.cand_avg = cand;
+    int stop = 0, sol = cand;
+    if (mt[cand].kkt[8] <= P.eps) {
+        stop = PDHG_OPTIMAL + 1;
+    } else if (nc > 1 && mt[1 - cand].kkt[8] <= P.eps) {
+        stop = PDHG_OPTIMAL + 1;
+        sol = 1 - cand;
+    } else if (st.k_total >= P.max_iters) {
+        stop = PDHG_ITERATION_LIMIT + 1;
+    }
+    if (stop) {
+        st.done = 1;
+        st.status = stop - 1;
+        st.sol_avg = sol;
+        for (int k = 0; k < 9; ++k) st.kkt[k] = mt[sol].kkt[k];
+        d.hdone[b] = 1;
+        return;
+    }
+    for (int k = 0; k < 9; ++k) st.kkt[k] = mt[cand].kkt[k];
+    st.sol_avg = cand;
+    if (!P.use_restarts) return;
+    const bool suff = kwc <= P.beta_suff * st.kkt0;
+    const bool nec = kwc <= P.beta_nec * st.kkt0 && kwc > st.kkt_prev;
+    const bool art = (double)st.t_inner > P.beta_art * (double)st.k_total;
+    if (suff || nec || art) {
+        const double dx = sqrt(tot[cand * NSUM + 8]), dy = sqrt(tot[cand * NSUM + 3]);
+        double w = omega;
+        if (P.use_pw && dx > P.eps_zero && dy > P.eps_zero) w = exp(0.5 * log(dy / dx) + 0.5 * log(omega));
+        st.omega = w;
+        st.tau = st.eta / w;
+        st.sigma = st.eta * w;
+        st.kkt0 = kkt_omega(mt[cand], w);
+        st.kkt_prev = INFINITY;
+        st.t_inner = 0;
+        st.restart = 1;
+        st.nrestarts += 1;
+    } else {
+        st.kkt_prev = kwc;
+    }
+}
+
+// On restart: z <- candidate, epoch start <- z.  Grid: K^T blocks then K blocks.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_restart(Dev d)
+{
+    const int lbc = logical_block(d.remap);
+    const bool onT = lbc < d.Kt.nblk;
+    const OpDev &op = onT ? d.Kt : d.K;
+    const int lb = onT ? lbc : lbc - d.Kt.nblk;
+    const Seg s = op.seg[op.blk_seg[lb]];
+    const InstState &st = d.st[s.inst];
+    if (st.done || !st.restart) return;
+    const int L = s.lanes_log2 >= 8 ? WG : (1 << s.lanes_log2);
+    const int G = WG / L;
+    const int64_t r0 = s.row0 + (int64_t)(lb - s.blk0) * G;
+    const int64_t r1 = min(r0 + G, s.row0 + s.nrows);
+    T *z = (T *)(onT ? d.x : d.y);
+    T *za = (T *)(onT ? d.xavg : d.yavg);
+    T *z0 = (T *)(onT ? d.x0 : d.y0);
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += WG) {
+        const T v = st.cand_avg ? za[r] : z[r];
+        z[r] = v;
+        z0[r] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// setup and service kernels (not on the per-iteration path)
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill(double *p, int64_t n, double v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// max over each row of |(rowfac * a) * colfac|  (Ruiz norm of the scaled matrix).
+// For K: rowfac = rho, colfac = kap; for K^T the same products are formed as
+// (colfac * a) * rowfac so both operators see (rho_i * K_ij) * kap_j.
+template <bool ROW_FIRST>
+__global__ __launch_bounds__(WG) void k_rowmax(OpDev op, int remap, const double *rowfac,
+                                               const double *colfac, double *out)
+{
+    __shared__ double red[8];
+    const int lb = logical_block(remap);
+    const Seg s = op.seg[op.blk_seg[lb]];
+    const int bi = lb - s.blk0;
+    dispatch_lanes(s.lanes_log2, [&](auto tag) {
+        constexpr int L = decltype(tag)::value;
+        int64_t r;
+        double acc[1];
+        if (RowSweep<L, 1, double, double, true, ROW_FIRST>::run(op, s, bi, colfac, nullptr, rowfac,
+                                                                  red, r, acc))
+            out[r] = acc[0];
+    });
+}
+
+__global__ void k_ruiz_update(double *fac, const double *mx, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && mx[i] > 0.0) fac[i] = fac[i] / sqrt(mx[i]);
+}
+
+// scaled values (rho_i * K_ij) * kap_j in FP64 (and FP32 when v32 != null)
+template <bool ROW_FIRST>
+__global__ void k_scale_vals(int64_t nrows, const int64_t *rp, const int32_t *ci, double *v64,
+                             float *v32, const double *rowfac, const double *colfac)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrows) return;
+    const double rf = rowfac[r];
+    for (int64_t p = rp[r]; p < rp[r + 1]; ++p) {
+        const double cf = colfac[ci[p]];
+        const double v = ROW_FIRST ? (rf * v64[p]) * cf : (cf * v64[p]) * rf;
+        v64[p] = v;
+        if (v32) v32[p] = (float)v;
+    }
+}
+
+// c~ = kap c, l~ = l / kap, u~ = u / kap  (FP64 and iterate-type copies)
+template <typename T>
+__global__ void k_scale_primal(Dev d)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= d.N) return;
+    const double k = d.kap[j];
+    const double c = k * d.craw[j], l = d.lraw[j] / k, u = d.uraw[j] / k;
+    d.c64[j] = c;
+    d.l64[j] = l;
+    d.u64[j] = u;
+    ((T *)d.c)[j] = (T)c;
+    ((T *)d.l)[j] = (T)l;
+    ((T *)d.u)[j] = (T)u;
+}
+
+template <typename T>
+__global__ void k_scale_dual(Dev d)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.M) return;
+    const double q = d.rho[i] * d.qraw[i];
+    d.q64[i] = q;
+    ((T *)d.q)[i] = (T)q;
+}
+
+// out = K v (FP64), per-workgroup partial of sum(out^2) in partials[lb]
+__global__ __launch_bounds__(WG) void k_spmv64(OpDev op, int remap, const double *v, double *out,
+                                               double *partials)
+{
+    __shared__ double red[8];
+    const int lb = logical_block(remap);
+    const Seg s = op.seg[op.blk_seg[lb]];
+    const int bi = lb - s.blk0;
+    double sq[1] = {0.0};
+    dispatch_lanes(s.lanes_log2, [&](auto tag) {
+        constexpr int L = decltype(tag)::value;
+        int64_t r;
+        double acc[1];
+        if (RowSweep<L, 1, double, double>::run(op, s, bi, v, nullptr, nullptr, red, r, acc)) {
+            out[r] = acc[0];
+            sq[0] += acc[0] * acc[0];
+        }
+    });
+    block_sum<1>(sq, red);
+    if (threadIdx.x == 0 && partials) partials[lb] = sq[0];
+}
+
+// per-instance sum of partials[blk0 .. blk1) (ranges from InstInfo), fixed order
+__global__ __launch_bounds__(WG) void k_inst_sum(const InstInfo *info, int onK, const double *partials,
+                                                 double *out)
+{
+    __shared__ double lds[4];
+    const InstInfo in = info[blockIdx.x];
+    const int b0 = onK ? in.blkK0 : in.blkT0, b1 = onK ? in.blkK1 : in.blkT1;
+    double v[1] = {0.0};
+    for (int t = b0 + threadIdx.x; t < b1; t += WG) v[0] += partials[t];
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) out[blockIdx.x] = v[0];
+}
+
+// v_i /= sqrt(nrm2[inst(i)])  (skips zero norms)
+__global__ void k_normalize(double *v, const int32_t *inst_of, int64_t n, const double *nrm2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double s = nrm2[inst_of[i]];
+    if (s > 0.0) v[i] = v[i] / sqrt(s);
+}
+
+// per-instance sum of squares of a vector over [off, off + len)
+__global__ __launch_bounds__(WG) void k_inst_nrm2(const InstInfo *info, int primal, const double *v,
+                                                  double *out)
+{
+    __shared__ double lds[4];
+    const InstInfo in = info[blockIdx.x];
+    const int64_t off = primal ? in.xoff : in.yoff;
+    const int64_t len = primal ? in.n : in.m;
+    double s[1] = {0.0};
+    for (int64_t t = threadIdx.x; t < len; t += WG) {
+        const double a = v[off + t];
+        s[0] += a * a;
+    }
+    block_sum<1>(s, lds);
+    if (threadIdx.x == 0) out[blockIdx.x] = s[0];
+}
+
+// x = proj_X(0), y = 0 (and the epoch start / averages)
+template <typename T>
+__global__ void k_init_point(Dev d)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < d.N) {
+        const double l = d.l64[i], u = d.u64[i];
+        const T v = (T)(0.0 < l ? l : (0.0 > u ? u : 0.0));
+        ((T *)d.x)[i] = v;
+        ((T *)d.x0)[i] = v;
+        ((T *)d.xavg)[i] = v;
+        ((T *)d.xbar)[i] = v;
+    }
+    if (i < d.M) {
+        ((T *)d.y)[i] = (T)0;
+        ((T *)d.y0)[i] = (T)0;
+        ((T *)d.yavg)[i] = (T)0;
+    }
+}
+
+// epoch start <- current iterate (start of a solve)
+template <typename T>
+__global__ void k_epoch_start(Dev d)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < d.N) {
+        ((T *)d.x0)[i] = ((T *)d.x)[i];
+        ((T *)d.xavg)[i] = ((T *)d.x)[i];
+    }
+    if (i < d.M) {
+        ((T *)d.y0)[i] = ((T *)d.y)[i];
+        ((T *)d.yavg)[i] = ((T *)d.y)[i];
+    }
+}
+
+// FP64 copies of a point (which: 0 current, 1 average) in scaled variables
+template <typename T>
+__global__ void k_point_to64(Dev d, int which, double *xo, double *yo)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const T *x = (const T *)(which ? d.xavg : d.x);
+    const T *y = (const T *)(which ? d.yavg : d.y);
+    if (i < d.N) xo[i] = (double)x[i];
+    if (i < d.M) yo[i] = (double)y[i];
+}
+
+// original-variable outputs of one instance: x (clipped to [l, u]), y
+__global__ void k_unscale_x(Dev d, int64_t off, int64_t n, const double *xs, double *out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int64_t j = off + t;
+    double v = d.kap[j] * xs[j];
+    const double l = d.lraw[j], u = d.uraw[j];
+    v = v < l ? l : (v > u ? u : v);
+    out[d.col_orig[j]] = v;
+}
+
+__global__ void k_unscale_y(Dev d, int64_t off, int64_t m, const double *ys, double *out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    const int64_t i = off + t;
+    out[d.row_orig[i]] = d.rho[i] * ys[i];
+}
+
+// lambda = proj_Lambda(c - K^T y) in original variables, from scaled y (FP64)
+__global__ __launch_bounds__(WG) void k_lambda(Dev d, const double *ys, double *lam_s)
+{
+    __shared__ double red[8];
+    const int lb = logical_block(d.remap);
+    const OpDev &op = d.Kt;
+    const Seg s = op.seg[op.blk_seg[lb]];
+    const int bi = lb - s.blk0;
+    dispatch_lanes(s.lanes_log2, [&](auto tag) {
+        constexpr int L = decltype(tag)::value;
+        int64_t j;
+        double acc[1];
+        if (RowSweep<L, 1, double, double>::run(op, s, bi, ys, nullptr, nullptr, red, j, acc)) {
+            const double dd = d.c64[j] - acc[0];
+            lam_s[j] = proj_lambda(dd, d.l64[j], d.u64[j]) / d.kap[j];
+        }
+    });
+}
+
+__global__ void k_permute_out(const int32_t *perm, int64_t off, int64_t n, const double *src,
+                              double *out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) out[perm[off + t]] = src[off + t];
+}
+
+// caller point (original variables, caller order) -> scaled FP64 internal
+__global__ void k_scale_in_x(Dev d, int64_t off, int64_t n, const double *in, double *xs)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int64_t j = off + t;
+    xs[j] = in[d.col_orig[j]] / d.kap[j];
+}
+
+__global__ void k_scale_in_y(Dev d, int64_t off, int64_t m, const double *in, double *ys)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    const int64_t i = off + t;
+    ys[i] = in[d.row_orig[i]] / d.rho[i];
+}
+
+// current iterate <- scaled FP64 point, projected onto X and Y
+template <typename T>
+__global__ void k_set_point(Dev d, int64_t xoff, int64_t n, int64_t yoff, int64_t m, int64_t m1,
+                            const double *xs, const double *ys)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) {
+        const int64_t j = xoff + t;
+        double v = xs[j];
+        const double l = d.l64[j], u = d.u64[j];
+        v = v < l ? l : (v > u ? u : v);
+        ((T *)d.x)[j] = (T)v;
+        ((T *)d.x0)[j] = (T)v;
+        ((T *)d.xavg)[j] = (T)v;
+    }
+    if (t < m) {
+        const int64_t i = yoff + t;
+        double v = ys[i];
+        if (t < m1 && v < 0.0) v = 0.0;
+        ((T *)d.y)[i] = (T)v;
+        ((T *)d.y0)[i] = (T)v;
+        ((T *)d.yavg)[i] = (T)v;
+    }
+}
+
+// KKT terms of a single candidate for one instance from the check partials
+__global__ __launch_bounds__(WG) void k_kkt_final(Dev d, int inst, double *out9)
+{
+    __shared__ double tot[NCAND * NSUM];
+    const InstInfo in = d.info[inst];
+    reduce_instance(d, in, tot);
+    if (threadIdx.x != 0) return;
+    Metrics m;
+    metrics_from_sums(tot, in, m);
+    for (int k = 0; k < 9; ++k) out9[k] = m.kkt[k];
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+// ---------------------------------------------------------------------------
+
+static inline unsigned nblk_elem(int64_t n) { return (unsigned)((n + WG - 1) / WG); }
+
+#define LAUNCH(kern, grid, ...)                                                  \
+    do {                                                                        \
+        if ((grid) > 0) hipLaunchKernelGGL(kern, dim3(grid), dim3(WG), 0, s, __VA_ARGS__); \
+    } while (0)
+
+template <typename T>
+void launch_primal(const Dev &d, int j, int avg, uint8_t *mask, hipStream_t s)
+{
+    const unsigned g = (unsigned)d.Kt.nblk;
+    if (mask) {
+        LAUNCH((k_primal<T, 0, 1>), g, d, j, mask);
+    } else if (avg) {
+        LAUNCH((k_primal<T, 1, 0>), g, d, j, mask);
+    } else {
+        LAUNCH((k_primal<T, 0, 0>), g, d, j, mask);
+    }
+}
+
+template <typename T>
+void launch_dual(const Dev &d, int j, int avg, uint8_t *mask, hipStream_t s)
+{
+    const unsigned g = (unsigned)d.K.nblk;
+    if (mask) {
+        LAUNCH((k_dual<T, 0, 1>), g, d, j, mask);
+    } else if (avg) {
+        LAUNCH((k_dual<T, 1, 0>), g, d, j, mask);
+    } else {
+        LAUNCH((k_dual<T, 0, 0>), g, d, j, mask);
+    }
+}
+
+template <typename T>
+void launch_check(const Dev &d, int avg, hipStream_t s)
+{
+    const unsigned g = (unsigned)(d.K.nblk + d.Kt.nblk);
+    const T *x = (const T *)d.x, *xa = (const T *)d.xavg, *x0 = (const T *)d.x0;
+    const T *y = (const T *)d.y, *ya = (const T *)d.yavg, *y0 = (const T *)d.y0;
+    if (avg) {
+        LAUNCH((k_check<T, 2>), g, d, x, xa, y, ya, x0, y0, 1);
+    } else {
+        LAUNCH((k_check<T, 1>), g, d, x, x, y, y, x0, y0, 1);
+    }
+}
+
+void launch_check64(const Dev &d, const double *xs, const double *ys, hipStream_t s)
+{
+    const unsigned g = (unsigned)(d.K.nblk + d.Kt.nblk);
+    LAUNCH((k_check<double, 1>), g, d, xs, xs, ys, ys, xs, ys, 0);
+}
+
+void launch_control(const Dev &d, const CtlParams &P, int iters_done, hipStream_t s)
+{
+    LAUNCH(k_control, (unsigned)d.batch, d, P, iters_done);
+}
+
+template <typename T>
+void launch_restart(const Dev &d, hipStream_t s)
+{
+    LAUNCH(k_restart<T>, (unsigned)(d.K.nblk + d.Kt.nblk), d);
+}
+
+void launch_fill(double *p, int64_t n, double v, hipStream_t s) { LAUNCH(k_fill, nblk_elem(n), p, n, v); }
+
+void launch_rowmax(const OpDev &op, int remap, bool row_first, const double *rowfac,
+                   const double *colfac, double *out, hipStream_t s)
+{
+    if (row_first) {
+        LAUNCH(k_rowmax<true>, (unsigned)op.nblk, op, remap, rowfac, colfac, out);
+    } else {
+        LAUNCH(k_rowmax<false>, (unsigned)op.nblk, op, remap, rowfac, colfac, out);
+    }
+}
+
+void launch_ruiz_update(double *fac, const double *mx, int64_t n, hipStream_t s)
+{
+    LAUNCH(k_ruiz_update, nblk_elem(n), fac, mx, n);
+}
+
+void launch_scale_vals(const OpDev &op, double *v64, float *v32, bool row_first,
+                       const double *rowfac, const double *colfac, hipStream_t s)
+{
+    if (row_first) {
+        LAUNCH(k_scale_vals<true>, nblk_elem(op.nrows), op.nrows, op.rp, op.ci, v64, v32, rowfac, colfac);
+    } else {
+        LAUNCH(k_scale_vals<false>, nblk_elem(op.nrows), op.nrows, op.rp, op.ci, v64, v32, rowfac, colfac);
+    }
+}
+
+template <typename T>
+void launch_scale_data(const Dev &d, hipStream_t s)
+{
+    LAUNCH(k_scale_primal<T>, nblk_elem(d.N), d);
+    LAUNCH(k_scale_dual<T>, nblk_elem(d.M), d);
+}
+
+void launch_spmv64(const OpDev &op, int remap, const double *v, double *out, double *partials,
+                   hipStream_t s)
+{
+    LAUNCH(k_spmv64, (unsigned)op.nblk, op, remap, v, out, partials);
+}
+
+void launch_inst_sum(const Dev &d, int onK, const double *partials, double *out, hipStream_t s)
+{
+    LAUNCH(k_inst_sum, (unsigned)d.batch, d.info, onK, partials, out);
+}
+
+void launch_normalize(double *v, const int32_t *inst_of, int64_t n, const double *nrm2, hipStream_t s)
+{
+    LAUNCH(k_normalize, nblk_elem(n), v, inst_of, n, nrm2);
+}
+
+void launch_inst_nrm2(const Dev &d, int primal, const double *v, double *out, hipStream_t s)
+{
+    LAUNCH(k_inst_nrm2, (unsigned)d.batch, d.info, primal, v, out);
+}
+
+template <typename T>
+void launch_init_point(const Dev &d, hipStream_t s)
+{
+    LAUNCH(k_init_point<T>, nblk_elem(d.N > d.M ? d.N : d.M), d);
+}
+
+template <typename T>
+void launch_epoch_start(const Dev &d, hipStream_t s)
+{
+    LAUNCH(k_epoch_start<T>, nblk_elem(d.N > d.M ? d.N : d.M), d);
+}
+
+template <typename T>
+void launch_point_to64(const Dev &d, int which, double *xo, double *yo, hipStream_t s)
+{
+    LAUNCH(k_point_to64<T>, nblk_elem(d.N > d.M ? d.N : d.M), d, which, xo, yo);
+}
+
+void launch_unscale_x(const Dev &d, int64_t off, int64_t n, const double *xs, double *out, hipStream_t s)
+{
+    LAUNCH(k_unscale_x, nblk_elem(n), d, off, n, xs, out);
+}
+
+void launch_unscale_y(const Dev &d, int64_t off, int64_t m, const double *ys, double *out, hipStream_t s)
+{
+    LAUNCH(k_unscale_y, nblk_elem(m), d, off, m, ys, out);
+}
+
+void launch_lambda(const Dev &d, const double *ys, double *lam, hipStream_t s)
+{
+    LAUNCH(k_lambda, (unsigned)d.Kt.nblk, d, ys, lam);
+}
+
+void launch_permute_out(const int32_t *perm, int64_t off, int64_t n, const double *src, double *out,
+                        hipStream_t s)
+{
+    LAUNCH(k_permute_out, nblk_elem(n), perm, off, n, src, out);
+}
+
+void launch_scale_in(const Dev &d, int64_t xoff, int64_t n, int64_t yoff, int64_t m, const double *xin,
+                     const double *yin, double *xs, double *ys, hipStream_t s)
+{
+    if (xin) LAUNCH(k_scale_in_x, nblk_elem(n), d, xoff, n, xin, xs);
+    if (yin) LAUNCH(k_scale_in_y, nblk_elem(m), d, yoff, m, yin, ys);
+}
+
+template <typename T>
+void launch_set_point(const Dev &d, int64_t xoff, int64_t n, int64_t yoff, int64_t m, int64_t m1,
+                      const double *xs, const double *ys, hipStream_t s)
+{
+    LAUNCH(k_set_point<T>, nblk_elem(n > m ? n : m), d, xoff, n, yoff, m, m1, xs, ys);
+}
+
+void launch_kkt_final(const Dev &d, int inst, double *out9, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_kkt_final, dim3(1), dim3(WG), 0, s, d, inst, out9);
+}
+
+#define INST(T)                                                                              \
+    template void launch_primal<T>(const Dev &, int, int, uint8_t *, hipStream_t);           \
+    template void launch_dual<T>(const Dev &, int, int, uint8_t *, hipStream_t);             \
+    template void launch_check<T>(const Dev &, int, hipStream_t);                            \
+    template void launch_restart<T>(const Dev &, hipStream_t);                               \
+    template void launch_scale_data<T>(const Dev &, hipStream_t);                            \
+    template void launch_init_point<T>(const Dev &, hipStream_t);                            \
+    template void launch_epoch_start<T>(const Dev &, hipStream_t);                           \
+    template void launch_point_to64<T>(const Dev &, int, double *, double *, hipStream_t);   \
+    template void launch_set_point<T>(const Dev &, int64_t, int64_t, int64_t, int64_t, int64_t, \
+                                      const double *, const double *, hipStream_t);
+INST(float)
+INST(double)
+
+}  // namespace pdhg

@@ -1,0 +1,120 @@
+// pdhg_internal.h -- device data layout shared by the host library and the
+// gfx950 kernels.  Not part of the public ABI.
+//
+// Layout in HBM (one workspace, carved by the host):
+//
+//  * Two sparse operators in row-binned CSR:
+//      K   rows = dual variables (all instances, internal row order),
+//          columns index the concatenated primal vectors;
+//      K^T rows = primal variables, columns index the dual vectors.
+//    Inside an instance, rows are grouped into segments of similar length
+//    (">=" rows of K before "=" rows, so y_1..m1 >= 0 is a contiguous range);
+//    a segment is swept by lane groups of L = 1..64 lanes per row, or by a
+//    whole 256-lane workgroup per row for long rows.  Entries keep the caller's
+//    order inside a row of K; a row of K^T lists its entries by increasing
+//    internal row of K.
+//    Values exist in FP64 (check, setup) and, in FP32 mode, in FP32 (sweeps).
+//  * Vectors are concatenated over the batch in internal order; every
+//    instance owns a contiguous range of the primal and of the dual vectors.
+//  * Logical workgroup b of a sweep belongs to segment blk_seg[b]; the blocks
+//    of one instance are contiguous, so per-instance reductions read a fixed
+//    contiguous range of per-block partial sums (deterministic, no atomics).
+#pragma once
+#include <stdint.h>
+
+namespace pdhg {
+
+constexpr int WG = 256;   // workgroup size of every sweep (4 wave64)
+constexpr int NBIN = 8;   // row-length bins
+constexpr int NSUM = 9;   // partial sums per candidate in the check
+constexpr int NCAND = 2;  // candidates: current iterate, epoch average
+
+struct Seg {
+    int64_t row0;       // first row (global internal index)
+    int32_t nrows;
+    int32_t blk0;       // first logical block of the sweep
+    int32_t nblk;
+    int32_t lanes_log2; // log2 of lanes per row: 0..6, or 8 (whole workgroup)
+    int32_t inst;
+    int32_t ineq;       // rows of this segment are ">=" rows (dual operator only)
+};
+
+struct OpDev {
+    int64_t nrows;
+    const int64_t *rp;   // nrows + 1 (global entry offsets)
+    const int32_t *ci;   // global column index into the gathered vector
+    const float *v32;    // scaled values, FP32 (FP32 mode)
+    const double *v64;   // scaled values, FP64 (after setup)
+    const Seg *seg;
+    const int32_t *blk_seg;
+    int32_t nseg;
+    int32_t nblk;
+};
+
+// Immutable per-instance facts.
+struct InstInfo {
+    int64_t xoff, yoff;  // offsets into the primal / dual vectors
+    int32_t n, m, m1;
+    int32_t blkK0, blkK1;  // logical block range of K-sweeps
+    int32_t blkT0, blkT1;  // logical block range of K^T-sweeps
+    double cnorm, qnorm;   // ||c||_2 and ||q||_2 of the ORIGINAL LP
+    double cnorm_s, qnorm_s;  // of the scaled LP
+};
+
+// Solver state per instance, read by every sweep, written by the control kernel.
+struct InstState {
+    double tau, sigma, omega, eta, omega0, knorm;
+    double kkt0;       // restart metric at the start of the epoch
+    double kkt_prev;   // restart metric of the previous candidate (inf at epoch start)
+    long long k_total; // iterations of this solve
+    long long t_inner; // iterations of the current restart epoch
+    int32_t done;      // 1: stopped; sweeps skip the instance
+    int32_t status;    // PDHG_OPTIMAL / ..._ITERATION_LIMIT / ..._NUMERICAL_ERROR
+    int32_t restart;   // the last check decided a restart
+    int32_t cand_avg;  // the last check's candidate is the average
+    int32_t sol_avg;   // the returned point is the average
+    int32_t nrestarts;
+    int32_t power_iters;
+    int32_t pad;
+    double kkt[9];     // pres, dres, pobj, dobj, gap, rel_pres, rel_dres, rel_gap, rel_kkt
+};
+
+struct CtlParams {
+    double eps, beta_suff, beta_nec, beta_art, eps_zero;
+    long long max_iters;
+    int32_t check_every;
+    int32_t use_restarts, use_pw;
+    int32_t batch;
+};
+
+// Device pointers and sizes of one handle (passed by value to kernels).
+struct Dev {
+    int32_t batch;
+    int32_t remap;       // XCD-contiguous workgroup numbering
+    int64_t N, M;        // total primal / dual length
+    OpDev K, Kt;
+    // primal vectors (length N)
+    void *x, *xbar, *xavg, *x0;   // iterate type T
+    void *c, *l, *u;              // scaled data, type T
+    double *c64, *l64, *u64;      // scaled data, FP64
+    double *kap;                  // column factors (x = kap * x~)
+    double *craw, *lraw, *uraw;   // original data, internal order
+    int32_t *col_orig;            // internal column -> caller column (per instance)
+    int32_t *inst_of_col;
+    // dual vectors (length M)
+    void *y, *yavg, *y0, *q;      // type T
+    double *q64, *rho, *qraw;
+    int32_t *row_orig;            // internal row -> caller row (per instance)
+    int32_t *inst_of_row;
+    // per instance
+    const InstInfo *info;
+    InstState *st;
+    int32_t *hdone;               // host-mapped copy of done flags
+    // scratch
+    double *partials;             // (K.nblk + Kt.nblk) * NCAND * NSUM
+    double *vecN64, *vecN64b;     // FP64 scratch vectors (N)
+    double *vecM64, *vecM64b;     // FP64 scratch vectors (M)
+    double *inst_scratch;         // batch * 16
+};
+
+}  // namespace pdhg

@@ -1,0 +1,183 @@
+// sweep.h -- the row-binned CSR sweep every gfx950 kernel of the library is
+// built on.  One workgroup = 256 lanes = 4 wave64.  A workgroup processes
+// rows of one segment; each row is handled by a group of L lanes (L = 1..64
+// inside a wavefront, or the whole workgroup for long rows).  Lanes of a group
+// stride over the row's entries, multiply the stored value by the gathered
+// vector entry and accumulate in FP64; the group then reduces its lanes with
+// cross-lane shuffles (and LDS across wavefronts for the whole-workgroup
+// case).  The group's first lane receives the row's dot product(s) and runs
+// the caller's epilogue.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "pdhg_internal.h"
+
+namespace pdhg {
+
+// Logical workgroup index.  The hardware hands consecutive workgroup ids to
+// the 8 XCDs round-robin; with `remap` the logical numbering gives each XCD a
+// contiguous run of blocks (so neighbouring rows share one XCD's L2).
+__device__ __forceinline__ int logical_block(int remap)
+{
+    const int b = blockIdx.x;
+    if (!remap) return b;
+    const int nb = gridDim.x;
+    const int xcd = b & 7, q = nb >> 3, r = nb & 7;
+    return xcd * q + (xcd < r ? xcd : r) + (b >> 3);
+}
+
+template <typename V>
+__device__ __forceinline__ const V *op_vals(const OpDev &op);
+template <>
+__device__ __forceinline__ const float *op_vals<float>(const OpDev &op) { return op.v32; }
+template <>
+__device__ __forceinline__ const double *op_vals<double>(const OpDev &op) { return op.v64; }
+
+template <typename V>
+__device__ __forceinline__ double ld(const V *p, int64_t i) { return (double)p[i]; }
+
+// Sum (or max when MAXABS) of a value across the L lanes of a group.
+template <int L, bool MAXABS>
+__device__ __forceinline__ double group_reduce(double v)
+{
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1) {
+        const double o = __shfl_xor(v, off);
+        v = MAXABS ? fmax(v, o) : v + o;
+    }
+    return v;
+}
+
+// Per-row dot products of one workgroup's rows.  NR gathered vectors (1 or 2).
+// MAXABS: instead of a dot product, max over the row of |(a * v) * b| where
+// the products use the factor vectors (Ruiz pass).
+template <int L, int NR, typename MV, typename GV, bool MAXABS = false, bool FAC_ROW_FIRST = true>
+struct RowSweep {
+    static constexpr int G = (L >= WG) ? 1 : WG / L;
+
+    // Returns, for this lane, whether it leads a valid row, and that row.
+    __device__ __forceinline__ static bool run(const OpDev &op, const Seg &s, int bi,
+                                               const GV *__restrict__ g0, const GV *__restrict__ g1,
+                                               const double *__restrict__ rowfac,
+                                               double *red_lds, int64_t &row, double (&acc)[NR])
+    {
+        const int tid = threadIdx.x;
+        const int grp = (L >= WG) ? 0 : tid / L;
+        const int lane = (L >= WG) ? tid : (tid & (L - 1));
+        const int64_t rloc = (int64_t)bi * G + grp;
+        const bool valid = rloc < s.nrows;
+        row = s.row0 + rloc;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) acc[k] = 0.0;
+        if (valid) {
+            const int64_t b = op.rp[row], e = op.rp[row + 1];
+            const MV *__restrict__ va = op_vals<MV>(op);
+            const int32_t *__restrict__ ci = op.ci;
+            if constexpr (MAXABS) {
+                const double rf = rowfac[row];
+                for (int64_t p = b + lane; p < e; p += L) {
+                    const double cf = ld(g0, ci[p]);
+                    const double a = ld(va, p);
+                    const double t = FAC_ROW_FIRST ? (rf * a) * cf : (cf * a) * rf;
+                    acc[0] = fmax(acc[0], fabs(t));
+                }
+            } else {
+                int64_t p = b + lane;
+                // four independent gathers in flight per lane on long rows
+                for (; p + 3 * L < e; p += 4 * L) {
+                    const int32_t c0 = ci[p], c1 = ci[p + L], c2 = ci[p + 2 * L], c3 = ci[p + 3 * L];
+                    const double a0 = ld(va, p), a1 = ld(va, p + L), a2 = ld(va, p + 2 * L),
+                                 a3 = ld(va, p + 3 * L);
+                    acc[0] += a0 * ld(g0, c0);
+                    acc[0] += a1 * ld(g0, c1);
+                    acc[0] += a2 * ld(g0, c2);
+                    acc[0] += a3 * ld(g0, c3);
+                    if constexpr (NR > 1) {
+                        acc[1] += a0 * ld(g1, c0);
+                        acc[1] += a1 * ld(g1, c1);
+                        acc[1] += a2 * ld(g1, c2);
+                        acc[1] += a3 * ld(g1, c3);
+                    }
+                }
+                for (; p < e; p += L) {
+                    const int32_t c0 = ci[p];
+                    const double a0 = ld(va, p);
+                    acc[0] += a0 * ld(g0, c0);
+                    if constexpr (NR > 1) acc[1] += a0 * ld(g1, c0);
+                }
+            }
+        }
+        if constexpr (L >= WG) {
+            // wavefront reduce, then the four wavefront totals in LDS, fixed order
+#pragma unroll
+            for (int k = 0; k < NR; ++k) acc[k] = group_reduce<64, MAXABS>(acc[k]);
+            const int wave = tid >> 6;
+            if ((tid & 63) == 0) {
+#pragma unroll
+                for (int k = 0; k < NR; ++k) red_lds[k * 4 + wave] = acc[k];
+            }
+            __syncthreads();
+            if (tid == 0) {
+#pragma unroll
+                for (int k = 0; k < NR; ++k) {
+                    const double *r = red_lds + k * 4;
+                    acc[k] = MAXABS ? fmax(fmax(r[0], r[1]), fmax(r[2], r[3]))
+                                    : (r[0] + r[1]) + (r[2] + r[3]);
+                }
+            }
+            __syncthreads();
+            return valid && tid == 0;
+        } else {
+#pragma unroll
+            for (int k = 0; k < NR; ++k) acc[k] = group_reduce<L, MAXABS>(acc[k]);
+            return valid && lane == 0;
+        }
+    }
+};
+
+// Dispatch on the segment's lanes-per-row (uniform across the workgroup).
+// F is called as f(std::integral_constant<int, L>{}).
+template <int L>
+struct LaneTag {
+    static constexpr int value = L;
+};
+
+template <typename F>
+__device__ __forceinline__ void dispatch_lanes(int lanes_log2, F &&f)
+{
+    switch (lanes_log2) {
+        case 0: f(LaneTag<1>{}); break;
+        case 1: f(LaneTag<2>{}); break;
+        case 2: f(LaneTag<4>{}); break;
+        case 3: f(LaneTag<8>{}); break;
+        case 4: f(LaneTag<16>{}); break;
+        case 5: f(LaneTag<32>{}); break;
+        case 6: f(LaneTag<64>{}); break;
+        default: f(LaneTag<WG>{}); break;
+    }
+}
+
+// Block-wide sum of NV per-thread values, fixed reduction order; result valid
+// in thread 0.  lds must hold NV * 4 doubles.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *lds)
+{
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = group_reduce<64, false>(v[k]);
+    const int tid = threadIdx.x, wave = tid >> 6;
+    __syncthreads();
+    if ((tid & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) lds[k * 4 + wave] = v[k];
+    }
+    __syncthreads();
+    if (tid == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const double *r = lds + k * 4;
+            v[k] = (r[0] + r[1]) + (r[2] + r[3]);
+        }
+    }
+}
+
+}  // namespace pdhg

@@ -1,0 +1,116 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every function the
+public header declares, and rejects invalid LPs before any GPU work (the
+validation in pdhg_workspace_bytes runs on the host only)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import lpgen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def pd():
+    import paper_2508_16806_amd as pd
+    from paper_2508_16806_amd import build as hb
+
+    if hb.stale():
+        hb.build()
+    return pd
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pdhg.h")).read()
+    return sorted(set(re.findall(r"\b(pdhg_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(pd):
+    L = pd.lib()
+    names = _declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(pd.EXPORTS)
+
+
+def test_struct_layouts_match_header(pd):
+    """ctypes mirrors of the C structs have the sizes the library was built with."""
+    L = pd.lib()
+    o = pd.default_opts()
+    assert o.precision == 1 and o.ruiz_iters == 10 and o.check_every == 64
+    assert o.eps == 1e-4 and o.step_frac == 0.9 and o.beta_art == 0.36
+    assert L.pdhg_last_error() is not None
+
+
+def _nbytes(pd, lp, **kw):
+    d = pd._Desc(lp)
+    arr = (pd.LPDesc * 1)(d.desc)
+    return pd.lib().pdhg_workspace_bytes(C.cast(arr, C.c_void_p), 1, C.byref(pd.default_opts(**kw)))
+
+
+def test_workspace_bytes_positive_and_monotone(pd):
+    small = _nbytes(pd, lpgen.config0(0))
+    big = _nbytes(pd, lpgen.planted(400, 1000, 0.02, 1))
+    assert 0 < small < big
+    assert _nbytes(pd, lpgen.config0(0), precision="f64") > 0
+    with_unroll = _nbytes(pd, lpgen.config0(0), unroll_capacity=100, unroll_checkpoint=10)
+    assert with_unroll > small
+
+
+def _err(pd):
+    return pd.lib().pdhg_last_error().decode()
+
+
+def test_rejects_bad_shapes(pd):
+    lp = lpgen.config0(0)
+    bad = lpgen.LP(**{**lp.__dict__})
+    bad.col = lp.col.copy()
+    bad.col[5] = lp.n + 3
+    assert _nbytes(pd, bad) == 0 and "out of range" in _err(pd)
+    bad = lpgen.LP(**{**lp.__dict__})
+    bad.rowptr = lp.rowptr.copy()
+    bad.rowptr[10], bad.rowptr[11] = bad.rowptr[11] + 1, bad.rowptr[10]
+    assert _nbytes(pd, bad) == 0 and "monotone" in _err(pd)
+
+
+def test_rejects_bounds_and_nonfinite(pd):
+    lp = lpgen.config0(0)
+    bad = lpgen.LP(**{**lp.__dict__})
+    bad.l = lp.l.copy()
+    bad.l[3] = lp.u[3] + 1.0
+    assert _nbytes(pd, bad) == 0 and "bounds" in _err(pd)
+    bad = lpgen.LP(**{**lp.__dict__})
+    bad.c = lp.c.copy()
+    bad.c[7] = np.nan
+    assert _nbytes(pd, bad) == 0 and "not finite" in _err(pd)
+    bad = lpgen.LP(**{**lp.__dict__})
+    bad.val = lp.val.copy()
+    bad.val[0] = np.inf
+    assert _nbytes(pd, bad) == 0 and "not finite" in _err(pd)
+    bad = lpgen.LP(**{**lp.__dict__})
+    bad.rhs = lp.rhs.copy()
+    bad.rhs[1] = -np.inf
+    assert _nbytes(pd, bad) == 0 and "not finite" in _err(pd)
+    bad = lpgen.LP(**{**lp.__dict__})
+    bad.l = lp.l.copy()
+    bad.l[0] = np.inf
+    bad.u = lp.u.copy()
+    bad.u[0] = np.inf
+    assert _nbytes(pd, bad) == 0 and "bounds" in _err(pd)
+
+
+def test_rejects_bad_options(pd):
+    lp = lpgen.config0(0)
+    assert _nbytes(pd, lp, check_every=0) == 0 and "check_every" in _err(pd)
+    assert _nbytes(pd, lp, eps=0.0) == 0
+    assert _nbytes(pd, lp, precision=7) == 0
+
+
+def test_infinite_bounds_accepted(pd):
+    lp = lpgen.tiny(3, n=8, m=4, free_frac=0.5)
+    assert np.isinf(lp.l).any()
+    assert _nbytes(pd, lp) > 0

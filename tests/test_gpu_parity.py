@@ -1,0 +1,289 @@
+"""GPU-vs-oracle parity of the HIP path, called through the C-ABI.
+
+Tolerances:
+  * FP64 mode: the GPU and the oracle evaluate the same expressions with
+    different summation orders; per-element relative agreement of 1e-12 (one
+    step, KKT terms) and 1e-9 after a few hundred steps is well above the
+    accumulated rounding (~n_steps * 1e-16 * condition).
+  * FP32 mode: iterates and matrix values are rounded to FP32 (unit roundoff
+    6e-8) but accumulate in FP64, so one step from identical FP32-representable
+    inputs agrees with the FP64 oracle to a few FP32 ulps of the operands'
+    magnitude; whole solves are compared on what the method fixes: the oracle's
+    relative KKT of the returned point <= 1e-4 and the objective within 1e-5
+    (relative) of the planted / oracle optimum.
+"""
+import numpy as np
+import pytest
+
+import lpgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pd():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2508_16806_amd as pd
+
+    pd.lib()
+    return pd
+
+
+def _rel(a, b):
+    return abs(a - b) / (1.0 + abs(b))
+
+
+def _cases():
+    return {
+        "c0": lpgen.config0(0),
+        "mixed": lpgen.planted(300, 700, 0.02, 5, ge_frac=0.5),
+        "tinyfree": lpgen.tiny(3, n=8, m=4, free_frac=0.5),
+        "sced_small": lpgen.sced(40, 16, 8, 12, seed=5),
+        "zipf": lpgen.config2(7, m=3000, n=6000, kmax=2000),
+    }
+
+
+# ---------------------------------------------------------------------------
+# KKT of a caller point (FP64 throughout)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["c0", "mixed", "tinyfree", "sced_small", "zipf"])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_kkt_matches_oracle(orc, pd, name, prec):
+    lp = _cases()[name]
+    o = orc.Oracle(lp)
+    s = pd.Solver(lp, precision=prec)
+    rng = np.random.default_rng(1)
+    pts = [(np.clip(rng.standard_normal(lp.n) * 3, lp.l, lp.u), rng.standard_normal(lp.m))]
+    if lp.x_star is not None:
+        pts.append((lp.x_star, lp.y_star))
+    for x, y in pts:
+        g = s.kkt(x, y)
+        c = o.kkt(x, y)
+        for k in ("pres", "dres", "pobj", "dobj"):
+            assert g[k] == pytest.approx(c[k], rel=1e-11, abs=1e-11 * (1 + abs(c["pobj"]))), (k, g[k], c[k])
+        assert g["rel_kkt"] == pytest.approx(c["rel_kkt"], rel=1e-9, abs=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# setup: Ruiz factors, power iteration
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["c0", "mixed", "sced_small", "zipf"])
+def test_ruiz_factors_match_oracle(orc, pd, name):
+    lp = _cases()[name]
+    o = orc.Oracle(lp)
+    for iters in (1, 10):
+        s = pd.Solver(lp, precision="f64", ruiz_iters=iters)
+        rho, kap = s.scaling()
+        rho_o, kap_o = o.ruiz(iters)
+        # same expressions, same order, IEEE sqrt and division: bitwise equal
+        np.testing.assert_array_equal(rho, rho_o)
+        np.testing.assert_array_equal(kap, kap_o)
+
+
+@pytest.mark.parametrize("name", ["c0", "mixed", "sced_small"])
+def test_power_norm_matches_oracle(orc, pd, name):
+    lp = _cases()[name]
+    s = pd.Solver(lp, precision="f64", ruiz_iters=10, power_tol=1e-9, power_max_iters=20000)
+    kn, _ = orc.Oracle(lp).power_norm(10, max_iters=20000, tol=1e-9)
+    assert s.info()["knorm"] == pytest.approx(kn, rel=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# fixed-step trajectory (FP64)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["c0", "mixed", "sced_small", "zipf"])
+def test_fixed_steps_match_oracle_f64(orc, pd, name):
+    lp = _cases()[name]
+    o = orc.Oracle(lp)
+    eta, omega = 0.5, 1.3
+    s = pd.Solver(lp, precision="f64", ruiz_iters=10, step_size=eta, primal_weight=omega)
+    kn = s.info()["knorm"]
+    eta = 0.9 / kn
+    s = pd.Solver(lp, precision="f64", ruiz_iters=10, step_size=eta, primal_weight=omega)
+    rho, kap = o.ruiz(10)
+    x0s = np.clip(np.zeros(lp.n), lp.l / kap, lp.u / kap)
+    y0s = np.zeros(lp.m)
+    done = 0
+    for k in (1, 9, 190):
+        s.iterate(k)
+        done += k
+        xs, ys = o.steps(x0s, y0s, eta / omega, eta * omega, done, ruiz_iters=10)
+        x, y = s.solution(which=pd.SOL_CURRENT)
+        xo, yo = np.clip(kap * xs, lp.l, lp.u), rho * ys
+        tol = 1e-12 if k == 1 else 1e-9
+        np.testing.assert_allclose(x, xo, rtol=tol, atol=tol * (1 + np.abs(xo).max()))
+        np.testing.assert_allclose(y, yo, rtol=tol, atol=tol * (1 + np.abs(yo).max()))
+
+
+def test_iterate_resume_is_exact(pd):
+    lp = _cases()["mixed"]
+    for prec in ("f32", "f64"):
+        a = pd.Solver(lp, precision=prec)
+        b = pd.Solver(lp, precision=prec)
+        a.iterate(37)
+        a.iterate(63)
+        b.iterate(100)
+        xa, ya = a.solution(which=pd.SOL_CURRENT)
+        xb, yb = b.solution(which=pd.SOL_CURRENT)
+        np.testing.assert_array_equal(xa, xb)
+        np.testing.assert_array_equal(ya, yb)
+
+
+def test_one_step_f32_matches_oracle(orc, pd):
+    """FP32 storage, FP64 accumulation: one step agrees to FP32 rounding."""
+    lp = _cases()["sced_small"]
+    o = orc.Oracle(lp)
+    s64 = pd.Solver(lp, precision="f64")
+    eta = 0.9 / s64.info()["knorm"]
+    s = pd.Solver(lp, precision="f32", step_size=eta, primal_weight=1.0)
+    rng = np.random.default_rng(3)
+    rho, kap = o.ruiz(10)
+    # a start point that is exactly representable in FP32 in scaled variables
+    xs = np.clip(rng.uniform(-1, 1, lp.n), lp.l / kap, lp.u / kap).astype(np.float32).astype(np.float64)
+    ys = rng.standard_normal(lp.m).astype(np.float32).astype(np.float64)
+    ys[lp.row_type == 0] = np.abs(ys[lp.row_type == 0])
+    s.set_state(kap * xs, rho * ys)
+    s.iterate(1)
+    x, y = s.solution(which=pd.SOL_CURRENT)
+    xo, yo = o.steps(xs, ys, eta, eta, 1, ruiz_iters=10)
+    # compare in scaled variables against the magnitude of the operands
+    sx = np.abs(xs).max() + 1
+    sy = np.abs(ys).max() + 1
+    np.testing.assert_allclose(x / kap, xo, rtol=0, atol=4e-7 * sx * 10)
+    np.testing.assert_allclose(y / rho, yo, rtol=0, atol=4e-7 * sy * 10)
+
+
+# ---------------------------------------------------------------------------
+# solves
+# ---------------------------------------------------------------------------
+
+def test_solve_c0_plain_f64(orc, pd):
+    lp = _cases()["c0"]
+    opts = dict(precision="f64", ruiz_iters=0, use_restarts=0, use_pw_update=0, eps=1e-6, max_iters=400000)
+    s = pd.Solver(lp, **opts)
+    r = s.solve()[0]
+    ro = orc.Oracle(lp).solve(orc.SolveOpts.plain(eps=1e-6, max_iters=400000))
+    assert r["status"] == 0 and ro.status == 0
+    x, y = s.solution()
+    chk = orc.Oracle(lp).kkt(x, y)
+    assert chk["rel_kkt"] <= 1e-6 * 1.01
+    assert _rel(chk["pobj"], lp.f_star) <= 1e-5
+    # same iteration count: identical algorithm in FP64, same check schedule
+    assert abs(r["iters"] - ro.iters) <= 64
+    assert r["restarts"] == 0
+
+
+@pytest.mark.parametrize("name", ["c0", "mixed", "tinyfree"])
+def test_solve_restarted_f64(orc, pd, name):
+    lp = _cases()[name]
+    s = pd.Solver(lp, precision="f64", eps=1e-6)
+    r = s.solve()[0]
+    ro = orc.Oracle(lp).solve(orc.SolveOpts(eps=1e-6))
+    assert r["status"] == 0, r
+    x, y = s.solution()
+    chk = orc.Oracle(lp).kkt(x, y)
+    assert chk["rel_kkt"] <= 1e-6 * 1.01
+    assert _rel(chk["pobj"], ro.kkt["pobj"]) <= 1e-5
+    if lp.f_star is not None:
+        assert _rel(chk["pobj"], lp.f_star) <= 1e-5
+    assert r["knorm"] == pytest.approx(ro.knorm, rel=1e-5)
+    assert r["omega0"] == pytest.approx(ro.omega0, rel=1e-12)
+
+
+@pytest.mark.parametrize("name", ["c0", "mixed", "sced_small", "zipf"])
+def test_solve_f32_parity(orc, pd, name):
+    lp = _cases()[name]
+    o = orc.Oracle(lp)
+    s = pd.Solver(lp, precision="f32", eps=1e-6, max_iters=200000)
+    r = s.solve()[0]
+    x, y = s.solution()
+    chk = o.kkt(x, y)
+    if lp.f_star is not None:
+        fref = lp.f_star
+    else:
+        fref = o.solve(orc.SolveOpts(eps=1e-7, max_iters=2_000_000)).kkt["pobj"]
+    print(name, r["status_name"], r["iters"], r["restarts"], r["kkt"]["rel_kkt"], chk["rel_kkt"],
+          _rel(chk["pobj"], fref))
+    assert chk["rel_kkt"] <= 1e-4
+    assert _rel(chk["pobj"], fref) <= 1e-5
+
+
+def test_solution_lambda(orc, pd):
+    lp = _cases()["tinyfree"]
+    s = pd.Solver(lp, precision="f64", eps=1e-8)
+    s.solve()
+    x, y, lam = s.solution(lam=True)
+    o = orc.Oracle(lp)
+    d = lp.c - o.spmv_t(y)
+    inf_l, inf_u = ~np.isfinite(lp.l), ~np.isfinite(lp.u)
+    ref = np.where(inf_l & inf_u, 0.0, np.where(inf_l, np.minimum(d, 0), np.where(inf_u, np.maximum(d, 0), d)))
+    np.testing.assert_allclose(lam, ref, rtol=1e-10, atol=1e-10)
+
+
+def test_set_state_roundtrip(pd):
+    lp = _cases()["mixed"]
+    s = pd.Solver(lp, precision="f64")
+    rng = np.random.default_rng(0)
+    x = rng.uniform(0, 1, lp.n) * lp.u
+    y = rng.standard_normal(lp.m)
+    y[lp.row_type == 0] = np.abs(y[lp.row_type == 0])
+    s.set_state(x, y)
+    x2, y2 = s.solution(which=pd.SOL_CURRENT)
+    np.testing.assert_allclose(x2, x, rtol=1e-15, atol=1e-15)
+    np.testing.assert_allclose(y2, y, rtol=1e-15, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# batching
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_batched_equals_solo_bitwise(pd, prec):
+    lps = [lpgen.planted(m, int(2.5 * m), 0.02, 30 + i, ge_frac=0.3) for i, m in enumerate([60, 150, 90, 240])]
+    lps.append(lpgen.sced(20, 8, 4, 6, seed=9))
+    kw = dict(precision=prec, eps=1e-5)
+    b = pd.Solver(lps, **kw)
+    rb = b.solve()
+    for i, lp in enumerate(lps):
+        s = pd.Solver(lp, **kw)
+        rs = s.solve()[0]
+        assert rb[i]["iters"] == rs["iters"] and rb[i]["restarts"] == rs["restarts"], i
+        assert rb[i]["status"] == rs["status"]
+        xb, yb = b.solution(inst=i)
+        xs, ys = s.solution()
+        np.testing.assert_array_equal(xb, xs)
+        np.testing.assert_array_equal(yb, ys)
+
+
+def test_graph_and_eager_agree(pd):
+    lp = _cases()["mixed"]
+    a = pd.Solver(lp, precision="f32", eps=1e-5, use_graph=1)
+    b = pd.Solver(lp, precision="f32", eps=1e-5, use_graph=0)
+    ra, rb = a.solve()[0], b.solve()[0]
+    assert ra["iters"] == rb["iters"]
+    np.testing.assert_array_equal(a.solution()[0], b.solution()[0])
+
+
+def test_iteration_and_time_limits(pd):
+    lp = _cases()["sced_small"]
+    s = pd.Solver(lp, precision="f32", eps=1e-12, max_iters=640)
+    r = s.solve()[0]
+    assert r["status_name"] == "ITERATION_LIMIT" and r["iters"] == 640
+    s = pd.Solver(lp, precision="f32", eps=1e-12, max_iters=10**9, time_limit=0.2)
+    r = s.solve()[0]
+    assert r["status_name"] == "TIME_LIMIT"
+    x, y = s.solution()
+    assert np.isfinite(x).all() and np.isfinite(y).all()
+
+
+def test_huge_step_reports_numerical_error(pd):
+    lp = _cases()["mixed"]
+    s = pd.Solver(lp, precision="f32", step_size=1e6, max_iters=100000, use_restarts=0)
+    r = s.solve()[0]
+    assert r["status_name"] == "NUMERICAL_ERROR"
