@@ -1,0 +1,198 @@
+"""Benchmark of the PDHG hot path on one MI355X.
+
+Workload: the SCED-shaped synthetic LP (5000 generators, 2000 buses, 24
+periods, 125 lines: n = 418,048 variables, m = 298,072 rows, ~15.25M
+nonzeros), FP32 iterates and matrix with FP64 accumulation, FP64 KKT check,
+restart test and primal-weight update.  Inputs are seeded and synthetic and
+are resident in HBM before any timed region.
+
+One step = one chunk of the restarted method: 64 PDHG iterations (fused K~^T y
+sweep + primal update and K~ xbar sweep + dual update, with the epoch
+averages), the FP64 KKT check of the iterate and of the average, the
+per-instance restart / primal-weight / termination decision, and the restart
+copy -- one launch of the captured hipGraph.  value = PDHG iterations per
+second over the K timed steps.
+
+Also reported: per-kernel device times (HIP events, live), the roofline of the
+dominant sweep from its algorithmic bytes, the time to a relative KKT error of
+1e-4 from a cold start, and the FP64 CPU oracle timed on the host on a bounded
+sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "time to 1e-4 rel KKT; PDHG iter/s; HBM GB/s vs peak; batched vs 1-by-1 LPs/s"
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+
+
+def sweep_bytes(info, es=4):
+    """Algorithmic HBM bytes of one launch of each fused sweep.
+
+    primal (rows of K~^T): values + columns (es + 4) per nonzero, int64 row
+    pointers (8 per row), one read of the gathered y (es per dual entry), and
+    per variable: x read+write, xbar write, xavg read+write, c~, l~, u~ reads.
+    dual (rows of K~): values + columns per nonzero, row pointers, one read of
+    the gathered xbar, and per row: y read+write, yavg read+write, q~ read.
+    """
+    n, m, nnz = info["n"], info["m"], info["nnz"]
+    primal = nnz * (es + 4) + 8 * (n + 1) + es * m + es * 8 * n
+    dual = nnz * (es + 4) + 8 * (m + 1) + es * n + es * 5 * m
+    return primal, dual
+
+
+def cpu_baseline(lp, budget_s=15.0):
+    """FP64 CPU oracle iterations/s on this host: two restarted solves that
+    differ only in their iteration limit; the rate is the difference of
+    iterations over the difference of wall time, so setup cancels.  The
+    extra iteration count is sized from a 3-step probe to take ~budget_s."""
+    import numpy as np
+
+    import oracle
+
+    oracle.build(force=False)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    o = oracle.Oracle(lp)
+    sc = o.scaled(10)
+    x, y = np.zeros(lp.n), np.zeros(lp.m)
+    t = time.perf_counter()
+    o.lib.orc_steps(sc.h, 1e-3, 1e-3, x, y, 3)
+    t_step = (time.perf_counter() - t) / 3
+    del sc
+    k = 64 * max(1, int(round(budget_s / (64 * t_step))))
+    opts = oracle.SolveOpts(eps=1e-12, power_max_iters=20, max_iters=64)
+    t0 = time.perf_counter()
+    r1 = o.solve(opts)
+    t1 = time.perf_counter()
+    opts.max_iters = 64 + k
+    r2 = o.solve(opts)
+    t2 = time.perf_counter()
+    rate = (r2.iters - r1.iters) / max((t2 - t1) - (t1 - t0), 1e-9)
+    return {"value": rate, "unit": "PDHG iter/s", "cores": cores, "kind": "oracle",
+            "sample": f"restarted FP64 oracle solve of the same LP: rate from the difference of two "
+                      f"solves capped at {r1.iters} and {r2.iters} iterations (power iteration capped "
+                      f"at 20 passes in both; setup cancels)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance solve")
+    ap.add_argument("--small", action="store_true", help="reduced SCED size (for profiling tests)")
+    ap.add_argument("--no-tuning", action="store_true", help="default bins instead of the tuned ones")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of the "
+              f"PDHG path is a design note, not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import lpgen
+    import paper_2508_16806_amd as pd
+
+    if not torch.cuda.is_available():
+        print("bench.py needs the GPU", file=sys.stderr)
+        sys.exit(1)
+    t = time.perf_counter()
+    lp = lpgen.sced(500, 200, 24, 125, seed=1) if args.small else lpgen.config1()
+    gen_s = time.perf_counter() - t
+    print(f"[bench] generated {lp.name}: n={lp.n} m={lp.m} nnz={lp.nnz} in {gen_s:.1f}s", file=sys.stderr,
+          flush=True)
+    CE = 64
+    tune = {}
+    if not args.small and not args.no_tuning:
+        from paper_2508_16806_amd import autotune
+
+        tune = autotune.load(os.path.join(ROOT, "paper_2508_16806_amd", "tuning", "sced_c1_f32.json"))
+    s = pd.Solver(lp, precision="f32", eps=1e-12, max_iters=CE * max(args.warmup, 1), **tune)
+    info = s.info()
+    print(f"[bench] setup {info['setup_seconds']:.2f}s knorm={info['knorm']:.6g} "
+          f"blocks primal={info['nblk_primal']} dual={info['nblk_dual']}", file=sys.stderr, flush=True)
+    # warmup: W steps
+    if args.warmup > 0:
+        s.solve()
+    # timed: exactly K steps (the iteration limit caps the enqueued chunks)
+    s.set_opts(max_iters=CE * args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = s.solve()[0]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert r["iters"] == CE * args.steps, r
+    ips = r["iters"] / dt
+    print(f"[bench] {args.steps} steps of {CE} iterations in {dt*1e3:.1f} ms: {ips:.1f} iter/s",
+          file=sys.stderr, flush=True)
+
+    kt = s.time_kernels(reps=20)
+    pb, db = sweep_bytes(info, 4)
+    pg, dg = pb / (kt["ms_primal"] * 1e-3) / 1e9, db / (kt["ms_dual"] * 1e-3) / 1e9
+    dom = "dual" if kt["ms_dual"] >= kt["ms_primal"] else "primal"
+    ach = dg if dom == "dual" else pg
+    print(f"[bench] kernels (ms): {json.dumps({k: round(v, 4) for k, v in kt.items() if k != 'reps'})} "
+          f"primal {pg:.0f} GB/s dual {dg:.0f} GB/s", file=sys.stderr, flush=True)
+
+    ttt = None
+    if not args.no_ttt:
+        s.set_opts(eps=1e-4, max_iters=2_000_000, time_limit=120.0)
+        s.set_state(np.zeros(lp.n), np.zeros(lp.m))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rt = s.solve()[0]
+        tsec = time.perf_counter() - t0
+        x, y = s.solution()
+        ttt = {"seconds": tsec, "status": rt["status_name"], "iters": rt["iters"],
+               "restarts": rt["restarts"], "rel_kkt_gpu": rt["kkt"]["rel_kkt"], "pobj": rt["kkt"]["pobj"],
+               "setup_seconds": info["setup_seconds"]}
+        # the library's own FP64 KKT of the returned point on the original LP
+        ttt["rel_kkt_fp64_recheck"] = s.kkt(x, y)["rel_kkt"]
+        print(f"[bench] time to 1e-4: {tsec:.2f}s {rt['status_name']} iters={rt['iters']} "
+              f"restarts={rt['restarts']}", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(lp)
+        print(f"[bench] cpu baseline {cpu['value']:.2f} iter/s on {cpu['cores']} threads", file=sys.stderr,
+              flush=True)
+
+    out = {
+        "metric": METRIC,
+        "value": ips,
+        "unit": "PDHG iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"SCED-shaped LP {lp.name}: n={lp.n}, m={lp.m}, nnz={lp.nnz}; "
+                               f"FP32 iterates, FP64 accumulation and check; step = {CE} iterations + check",
+                   "n": lp.n, "m": lp.m, "nnz": lp.nnz, "iters_per_step": CE, "precision": "f32+f64acc",
+                   "bins": tune or "default"},
+        "roofline": {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": ach / PEAK_HBM_GBS, "traffic": None, "kernel": f"k_{dom}",
+                     "algorithmic_bytes": db if dom == "dual" else pb,
+                     "ms_per_launch": kt["ms_dual" if dom == "dual" else "ms_primal"]},
+        "kernels_ms": {k: v for k, v in kt.items() if k != "reps"},
+        "sweep_gbs": {"primal": pg, "dual": dg},
+        "time_to_tol": ttt,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -115,7 +115,12 @@ typedef struct {
     int32_t unroll_checkpoint; /* checkpoint spacing C for the adjoint replay       */
     int32_t use_graph;         /* capture iteration chunks in a hipGraph            */
     int32_t xcd_remap;         /* XCD-contiguous workgroup numbering                */
-    int32_t bin_max_len[8];    /* row-length bin limits (autotuner output); 0: default */
+    /* Row-length bins (autotuner output).  Bin k takes rows of length
+     * <= bin_len[k] (and above bin k-1's limit) and sweeps each with 2^k lanes
+     * (k = 0..6) or a whole 256-lane workgroup (k = 7).  0 keeps the default
+     * 4, 8, 16, 32, 64, 128, 512, inf. */
+    int32_t bin_len_dual[8];   /* rows of K   (dual sweep)                        */
+    int32_t bin_len_primal[8]; /* rows of K^T (primal sweep)                      */
 } pdhg_opts;
 
 /* Relative KKT error terms (Section 2.3.2, conditions term1-term3) on the
@@ -154,6 +159,16 @@ typedef struct {
     int64_t nblk_primal, nblk_dual; /* workgroups per primal / dual sweep         */
 } pdhg_info;
 
+/* Average device time per launch of each phase kernel (milliseconds). */
+typedef struct {
+    double ms_primal;   /* fused K~^T y sweep + primal update + averaging      */
+    double ms_dual;     /* fused K~ xbar sweep + dual update + averaging       */
+    double ms_check;    /* FP64 KKT partial sums of iterate and average        */
+    double ms_control;  /* per-instance reduction + restart / stop decisions  */
+    double ms_restart;  /* restart copy (0 when restarts are off)              */
+    int32_t reps;
+} pdhg_kernel_times;
+
 typedef struct pdhg_handle pdhg_handle;
 
 /* Fills *o with the defaults listed above. */
@@ -175,6 +190,12 @@ size_t pdhg_workspace_bytes(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o
  * _NONFINITE, _NOMEM, _HIP. */
 int pdhg_setup(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, void *ws, size_t ws_bytes,
                hipStream_t stream, pdhg_handle **out);
+
+/* Changes the run-time options of a handle: use_restarts, use_pw_update,
+ * check_every, max_iters, eps, time_limit, beta_*, eps_zero, use_graph.  The
+ * other fields of *o (precision, scaling, step, power iteration, unroll
+ * capacity, bins) are fixed at setup and ignored here. */
+int pdhg_set_opts(pdhg_handle *h, const pdhg_opts *o);
 
 /* Runs k fixed-step PDHG iterations (Algorithm 1, theta = 1) from the
  * handle's current iterate with the current tau and sigma: no averaging,
@@ -216,6 +237,12 @@ int pdhg_kkt(pdhg_handle *h, int32_t inst, const double *x, const double *y, int
 int pdhg_backward(pdhg_handle *h, const double *gx, const double *gy, double *gc, double *grhs,
                   double *gl, double *gu, double *gx0, double *gy0, int32_t mem,
                   hipStream_t stream);
+
+/* Phase timers: launches each phase kernel `reps` times back to back on
+ * `stream`, bracketed by HIP events, and reports the average time per launch.
+ * The sweeps advance the iterate (fixed steps); solver counters are restored.
+ * Synchronous. */
+int pdhg_time_kernels(pdhg_handle *h, int32_t reps, pdhg_kernel_times *out, hipStream_t stream);
 
 /* Ruiz factors of instance `inst` (Algorithm 3): the scaled problem is
  * K~ = diag(rho) K diag(kappa), x = kappa x~, y = rho y~.  rho has m entries

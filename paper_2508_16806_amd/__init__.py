@@ -49,7 +49,8 @@ class Opts(C.Structure):
                 ("primal_weight", C.c_double), ("power_tol", C.c_double), ("beta_suff", C.c_double),
                 ("beta_nec", C.c_double), ("beta_art", C.c_double), ("eps_zero", C.c_double),
                 ("unroll_capacity", C.c_int32), ("unroll_checkpoint", C.c_int32),
-                ("use_graph", C.c_int32), ("xcd_remap", C.c_int32), ("bin_max_len", C.c_int32 * 8)]
+                ("use_graph", C.c_int32), ("xcd_remap", C.c_int32), ("bin_len_dual", C.c_int32 * 8),
+                ("bin_len_primal", C.c_int32 * 8)]
 
 
 class KKTOut(C.Structure):
@@ -73,6 +74,14 @@ class Result(C.Structure):
         return d
 
 
+class KernelTimes(C.Structure):
+    _fields_ = [("ms_primal", C.c_double), ("ms_dual", C.c_double), ("ms_check", C.c_double),
+                ("ms_control", C.c_double), ("ms_restart", C.c_double), ("reps", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Info(C.Structure):
     _fields_ = [("n", C.c_int64), ("m", C.c_int64), ("m_ineq", C.c_int64), ("nnz", C.c_int64),
                 ("knorm", C.c_double), ("eta", C.c_double), ("omega", C.c_double), ("tau", C.c_double),
@@ -86,7 +95,7 @@ class Info(C.Structure):
 
 EXPORTS = ["pdhg_default_opts", "pdhg_workspace_bytes", "pdhg_setup", "pdhg_iterate", "pdhg_solve",
            "pdhg_get_solution", "pdhg_set_state", "pdhg_kkt", "pdhg_backward", "pdhg_get_scaling",
-           "pdhg_get_info",
+           "pdhg_get_info", "pdhg_time_kernels", "pdhg_set_opts",
            "pdhg_destroy", "pdhg_last_error"]
 
 _lib = None
@@ -112,6 +121,8 @@ def lib():
         L.pdhg_backward.argtypes = [P, P, P, P, P, P, P, P, P, I32, S]
         L.pdhg_get_scaling.argtypes = [P, I32, P, P, I32, S]
         L.pdhg_get_info.argtypes = [P, C.POINTER(Info)]
+        L.pdhg_set_opts.argtypes = [P, C.POINTER(Opts)]
+        L.pdhg_time_kernels.argtypes = [P, I32, C.POINTER(KernelTimes), S]
         L.pdhg_destroy.argtypes = [P]
         L.pdhg_last_error.restype = C.c_char_p
         _lib = L
@@ -129,9 +140,8 @@ def default_opts(**kw) -> Opts:
     for k, v in kw.items():
         if k == "precision" and isinstance(v, str):
             v = {"f32": PREC_F32, "f64": PREC_F64}[v]
-        if k == "bin_max_len":
-            arr = (C.c_int32 * 8)(*v)
-            o.bin_max_len = arr
+        if k in ("bin_len_dual", "bin_len_primal"):
+            setattr(o, k, (C.c_int32 * 8)(*v))
             continue
         if not hasattr(o, k):
             raise TypeError(f"unknown option {k}")
@@ -227,6 +237,14 @@ class Solver:
             pass
 
     # ------------------------------------------------------------------ calls
+    def set_opts(self, **kw):
+        """Change run-time options (eps, max_iters, time_limit, restarts, ...)."""
+        for k, v in kw.items():
+            if not hasattr(self.opts, k):
+                raise TypeError(f"unknown option {k}")
+            setattr(self.opts, k, v)
+        _check(lib().pdhg_set_opts(self.h, C.byref(self.opts)))
+
     def solve(self, stream=None) -> list:
         res = (Result * self.batch)()
         _check(lib().pdhg_solve(self.h, C.cast(res, C.c_void_p), _stream(stream)))
@@ -282,6 +300,12 @@ class Solver:
         _check(lib().pdhg_get_scaling(self.h, inst, rho.ctypes.data, kap.ctypes.data, MEM_HOST,
                                       _stream(stream)))
         return rho, kap
+
+    def time_kernels(self, reps: int = 20, stream=None) -> dict:
+        """Average per-launch device time of each phase kernel (ms), HIP events."""
+        t = KernelTimes()
+        _check(lib().pdhg_time_kernels(self.h, int(reps), C.byref(t), _stream(stream)))
+        return t.as_dict()
 
     def info(self) -> dict:
         i = Info()

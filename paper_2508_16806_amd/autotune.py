@@ -1,0 +1,84 @@
+"""Autotuner for the row-length bins of the two fused sweeps.
+
+A bin sweeps each row with a fixed number of lanes (1, 2, 4, ..., 64 lanes of
+a wavefront, or a whole 256-lane workgroup).  The tuner tries bin limits
+
+    limit_k = f * 2^k  (k = 0..5),   limit_6 = w,   bin 7 = rows longer than w
+
+for a grid of elements-per-lane f and whole-workgroup thresholds w, times the
+primal and the dual sweep of each candidate on the GPU with the library's
+event timers (pdhg_time_kernels), and keeps the fastest limits for each
+operator separately.  The result is a small JSON tuning file that Solver and
+bench.py load (``tuning=``).
+
+    python -m paper_2508_16806_amd.autotune --workload sced --out tuning.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+
+def limits(f: int, w: int):
+    lim = [f * (1 << k) for k in range(6)] + [max(w, 64 * f), 0]
+    return lim
+
+
+def autotune(lp, precision: str = "f32", factors=(1, 2, 4, 8), wg_thresholds=(256, 512, 2048),
+             reps: int = 20, verbose: bool = True) -> dict:
+    import paper_2508_16806_amd as pd
+
+    trials = []
+    for f in factors:
+        for w in wg_thresholds:
+            if w < 64 * f:
+                continue
+            lim = limits(f, w)
+            s = pd.Solver(lp, precision=precision, bin_len_dual=lim, bin_len_primal=lim)
+            s.time_kernels(reps=3)  # warm caches and clocks
+            t = s.time_kernels(reps=reps)
+            trials.append({"f": f, "w": w, "limits": lim, "ms_primal": t["ms_primal"], "ms_dual": t["ms_dual"]})
+            if verbose:
+                print(f"[autotune] f={f} w={w}: primal {t['ms_primal']*1e3:.1f} us, dual "
+                      f"{t['ms_dual']*1e3:.1f} us", file=sys.stderr, flush=True)
+            s.close()
+    bp = min(trials, key=lambda r: r["ms_primal"])
+    bd = min(trials, key=lambda r: r["ms_dual"])
+    return {"n": int(lp.n), "m": int(lp.m), "nnz": int(lp.nnz), "precision": precision,
+            "bin_len_primal": bp["limits"], "bin_len_dual": bd["limits"],
+            "ms_primal": bp["ms_primal"], "ms_dual": bd["ms_dual"], "trials": trials,
+            "time": time.strftime("%Y-%m-%d %H:%M:%S")}
+
+
+def load(path: str) -> dict:
+    with open(path) as f:
+        t = json.load(f)
+    return {"bin_len_primal": t["bin_len_primal"], "bin_len_dual": t["bin_len_dual"]}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="sced", choices=["sced", "sced_small", "zipf", "zipf_small"])
+    ap.add_argument("--precision", default="f32")
+    ap.add_argument("--out", required=True)
+    args = ap.parse_args()
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    import lpgen
+
+    lp = {"sced": lambda: lpgen.config1(), "sced_small": lambda: lpgen.sced(500, 200, 24, 125, seed=1),
+          "zipf": lambda: lpgen.config2(), "zipf_small": lambda: lpgen.config2(m=100000, n=200000)}[
+        args.workload]()
+    res = autotune(lp, precision=args.precision)
+    res["workload"] = args.workload
+    with open(args.out, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps({k: res[k] for k in ("bin_len_primal", "bin_len_dual", "ms_primal", "ms_dual")}))
+
+
+if __name__ == "__main__":
+    main()

@@ -179,13 +179,14 @@ struct Bins {
     int32_t lanes_log2[NBIN];
 };
 
-static Bins make_bins(const pdhg_opts *o)
+static Bins make_bins(const int32_t *lim)
 {
     static const int32_t def_len[NBIN] = {4, 8, 16, 32, 64, 128, 512, INT32_MAX};
     static const int32_t lanes[NBIN] = {0, 1, 2, 3, 4, 5, 6, 8};
     Bins b;
     for (int k = 0; k < NBIN; ++k) {
-        b.max_len[k] = (o && o->bin_max_len[k] > 0) ? o->bin_max_len[k] : def_len[k];
+        b.max_len[k] = (lim && lim[k] > 0) ? lim[k] : def_len[k];
+        if (k > 0 && b.max_len[k] < b.max_len[k - 1]) b.max_len[k] = b.max_len[k - 1];
         b.lanes_log2[k] = lanes[k];
     }
     b.max_len[NBIN - 1] = INT32_MAX;
@@ -201,7 +202,7 @@ static int bin_of(const Bins &b, int64_t len)
 
 static int seg_group(int lanes_log2) { return lanes_log2 >= 8 ? 1 : (WG >> lanes_log2); }
 
-static void plan_instance(const HostLP &h, const Bins &bins, InstPlan &p)
+static void plan_instance(const HostLP &h, const Bins &bins, const Bins &tbins, InstPlan &p)
 {
     p.n = h.n;
     p.m = h.m;
@@ -227,13 +228,13 @@ static void plan_instance(const HostLP &h, const Bins &bins, InstPlan &p)
     std::vector<int64_t> cnt(h.n, 0);
     for (int64_t k = 0; k < h.nnz; ++k) cnt[h.ci[k]]++;
     std::vector<std::vector<int32_t>> cb(NBIN);
-    for (int64_t j = 0; j < h.n; ++j) cb[bin_of(bins, cnt[j])].push_back((int32_t)j);
+    for (int64_t j = 0; j < h.n; ++j) cb[bin_of(tbins, cnt[j])].push_back((int32_t)j);
     p.col_order.clear();
     p.col_order.reserve(h.n);
     p.segT.clear();
     for (int b = 0; b < NBIN; ++b) {
         if (cb[b].empty()) continue;
-        p.segT.push_back({(int64_t)p.col_order.size(), (int32_t)cb[b].size(), bins.lanes_log2[b], 0});
+        p.segT.push_back({(int64_t)p.col_order.size(), (int32_t)cb[b].size(), tbins.lanes_log2[b], 0});
         p.col_order.insert(p.col_order.end(), cb[b].begin(), cb[b].end());
     }
 }
@@ -257,7 +258,7 @@ struct Carve {
 
 struct Sizes {
     int64_t N = 0, M = 0, NNZ = 0;
-    int64_t nsegK = 0, nsegT = 0, nblkK = 0, nblkT = 0;
+    int64_t nsegK = 0, nsegT = 0, nblkK = 0, nblkT = 0, nl2 = 0;
     int32_t batch = 0;
 };
 
@@ -273,6 +274,7 @@ struct Buffers {
     uint8_t *maskx, *masky;
     double *ax, *ay, *aw, *av, *axb, *ac, *al, *au, *aq;
     double *vecN64c;
+    int32_t *l2inst;
 };
 
 struct pdhg_handle {
@@ -343,6 +345,8 @@ static void carve(Carve &cv, const Sizes &sz, int prec, const pdhg_opts &o, Dev 
     *info = cv.take<InstInfo>(sz.batch);
     *st = cv.take<InstState>(sz.batch);
     d.partials = cv.take<double>((size_t)(sz.nblkK + sz.nblkT) * NCAND * NSUM + 1);
+    d.partials2 = cv.take<double>((size_t)sz.nl2 * NCAND * NSUM + 1);
+    b.l2inst = cv.take<int32_t>(sz.nl2 + 1);
     d.vecN64 = cv.take<double>(N);
     d.vecN64b = cv.take<double>(N);
     b.vecN64c = cv.take<double>(N);
@@ -391,7 +395,7 @@ static int plan_all(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, std::v
     if (rc) return rc;
     hosts.resize(batch);
     plans.resize(batch);
-    const Bins bins = make_bins(o);
+    const Bins bins = make_bins(o->bin_len_dual), tbins = make_bins(o->bin_len_primal);
     sz = Sizes{};
     sz.batch = batch;
     for (int b = 0; b < batch; ++b) {
@@ -402,12 +406,17 @@ static int plan_all(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, std::v
             }
             return rc;
         }
-        plan_instance(hosts[b], bins, plans[b]);
+        plan_instance(hosts[b], bins, tbins, plans[b]);
         sz.N += hosts[b].n;
         sz.M += hosts[b].m;
         sz.NNZ += hosts[b].nnz;
-        for (auto &s : plans[b].segK) sz.nblkK += (s.nrows + seg_group(s.lanes_log2) - 1) / seg_group(s.lanes_log2);
-        for (auto &s : plans[b].segT) sz.nblkT += (s.nrows + seg_group(s.lanes_log2) - 1) / seg_group(s.lanes_log2);
+        int64_t pb = 0;
+        for (auto &s : plans[b].segK) pb += (s.nrows + seg_group(s.lanes_log2) - 1) / seg_group(s.lanes_log2);
+        sz.nblkK += pb;
+        int64_t pt = 0;
+        for (auto &s : plans[b].segT) pt += (s.nrows + seg_group(s.lanes_log2) - 1) / seg_group(s.lanes_log2);
+        sz.nblkT += pt;
+        sz.nl2 += (pb + pt + L2CH - 1) / L2CH;
         sz.nsegK += plans[b].segK.size();
         sz.nsegT += plans[b].segT.size();
     }
@@ -457,6 +466,7 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
     std::vector<int32_t> Kci(sz.NNZ), Ktci(sz.NNZ), Kbs(sz.nblkK), Ktbs(sz.nblkT);
     std::vector<double> Kv(sz.NNZ), Ktv(sz.NNZ);
     std::vector<Seg> Kseg, Ktseg;
+    std::vector<int32_t> l2inst;
     std::vector<double> craw(sz.N), lraw(sz.N), uraw(sz.N), qraw(sz.M);
     std::vector<int32_t> col_orig(sz.N), row_orig(sz.M), inst_col(sz.N), inst_row(sz.M);
     h->info.assign(h->batch, InstInfo{});
@@ -541,6 +551,9 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
             Ktseg.push_back(sg);
         }
         in.blkT1 = blkT;
+        in.l2off = (int32_t)l2inst.size();
+        in.l2cnt = (int32_t)((in.blkK1 - in.blkK0 + in.blkT1 - in.blkT0 + L2CH - 1) / L2CH);
+        for (int t = 0; t < in.l2cnt; ++t) l2inst.push_back(bi);
         double cn = 0, qn = 0;
         for (int64_t j = 0; j < p.n; ++j) cn += lp.c[j] * lp.c[j];
         for (int64_t i = 0; i < p.m; ++i) qn += lp.rhs[i] * lp.rhs[i];
@@ -562,7 +575,8 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
         (rc = h2d(d.row_orig, row_orig.data(), row_orig.size(), s)) ||
         (rc = h2d(d.inst_of_col, inst_col.data(), inst_col.size(), s)) ||
         (rc = h2d(d.inst_of_row, inst_row.data(), inst_row.size(), s)) ||
-        (rc = h2d((InstInfo *)d.info, h->info.data(), h->info.size(), s)))
+        (rc = h2d((InstInfo *)d.info, h->info.data(), h->info.size(), s)) ||
+        (rc = h2d(b.l2inst, l2inst.data(), l2inst.size(), s)))
         return rc;
     // the host images die with this scope: wait for the copies
     HIPCHK(hipStreamSynchronize(s));
@@ -714,6 +728,8 @@ extern "C" int pdhg_setup(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, 
     d.M = h->sz.M;
     d.info = info;
     d.st = st;
+    d.l2_inst = h->buf.l2inst;
+    d.nl2 = (int32_t)h->sz.nl2;
     Buffers &b = h->buf;
     d.K = OpDev{h->sz.M, b.Krp, b.Kci, b.Kv32, b.Kv64, b.Kseg, b.Kbs, (int32_t)h->sz.nsegK, (int32_t)h->sz.nblkK};
     d.Kt = OpDev{h->sz.N, b.Ktrp, b.Ktci, b.Ktv32, b.Ktv64, b.Ktseg, b.Ktbs, (int32_t)h->sz.nsegT,
@@ -846,8 +862,10 @@ static int solve_impl(pdhg_handle *h, pdhg_result *res, hipStream_t s)
     const double tl = h->opts.time_limit;
     bool timed_out = false;
     int rc = PDHG_OK;
+    // no instance can run past max_iters, so never enqueue more chunks than that
+    const int64_t max_chunks = (h->opts.max_iters + h->opts.check_every - 1) / h->opts.check_every;
     if (!all_done()) {
-        for (int64_t chunk = 0;; ++chunk) {
+        for (int64_t chunk = 0; chunk < max_chunks; ++chunk) {
             if (h->opts.use_graph) {
                 if (hipGraphLaunch(h->graph, s) != hipSuccess) {
                     rc = fail(PDHG_ERR_HIP, "hipGraphLaunch failed");
@@ -1055,6 +1073,90 @@ extern "C" int pdhg_backward(pdhg_handle *h, const double *gx, const double *gy,
     (void)gx; (void)gy; (void)gc; (void)grhs; (void)gl; (void)gu; (void)gx0; (void)gy0; (void)mem; (void)s;
     if (!h) return fail(PDHG_ERR_INVALID_ARG, "NULL handle");
     return fail(PDHG_ERR_STATE, "no recorded pdhg_iterate to differentiate");
+}
+
+template <typename T>
+static int time_impl(pdhg_handle *h, int32_t reps, pdhg_kernel_times *out, hipStream_t s)
+{
+    const Dev &d = h->d;
+    const int avg = h->opts.use_restarts;
+    std::vector<InstState> st = h->st0;
+    for (auto &x : st) x.done = 0;
+    HIPCHK(hipMemcpyAsync(d.st, st.data(), h->batch * sizeof(InstState), hipMemcpyHostToDevice, s));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    double ms[5] = {0, 0, 0, 0, 0};
+    const CtlParams P = ctl_params(h);
+    for (int phase = 0; phase < 5; ++phase) {
+        if (phase == 4 && !avg) break;
+        hipEventRecord(e0, s);
+        for (int r = 0; r < reps; ++r) {
+            switch (phase) {
+                case 0: launch_primal<T>(d, r, avg, nullptr, s); break;
+                case 1: launch_dual<T>(d, r, avg, nullptr, s); break;
+                case 2: launch_check<T>(d, avg, s); break;
+                case 3: launch_control(d, P, 0, s); break;
+                default: launch_restart<T>(d, s); break;
+            }
+        }
+        hipEventRecord(e1, s);
+        hipEventSynchronize(e1);
+        float t = 0.f;
+        hipEventElapsedTime(&t, e0, e1);
+        ms[phase] = (double)t / reps;
+        if (phase == 3) {
+            // the control kernel may have stopped an instance: restore the state
+            HIPCHK(hipMemcpyAsync(d.st, st.data(), h->batch * sizeof(InstState), hipMemcpyHostToDevice, s));
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    out->ms_primal = ms[0];
+    out->ms_dual = ms[1];
+    out->ms_check = ms[2];
+    out->ms_control = ms[3];
+    out->ms_restart = ms[4];
+    out->reps = reps;
+    return PDHG_OK;
+}
+
+extern "C" int pdhg_time_kernels(pdhg_handle *h, int32_t reps, pdhg_kernel_times *out, hipStream_t s)
+{
+    if (!h || !out || reps < 1) return fail(PDHG_ERR_INVALID_ARG, "bad arguments");
+    return h->prec == PDHG_PREC_F32 ? time_impl<float>(h, reps, out, s) : time_impl<double>(h, reps, out, s);
+}
+
+extern "C" int pdhg_set_opts(pdhg_handle *h, const pdhg_opts *o)
+{
+    if (!h || !o) return fail(PDHG_ERR_INVALID_ARG, "NULL argument");
+    pdhg_opts t = h->opts;
+    t.use_restarts = o->use_restarts;
+    t.use_pw_update = o->use_pw_update;
+    t.check_every = o->check_every;
+    t.max_iters = o->max_iters;
+    t.eps = o->eps;
+    t.time_limit = o->time_limit;
+    t.beta_suff = o->beta_suff;
+    t.beta_nec = o->beta_nec;
+    t.beta_art = o->beta_art;
+    t.eps_zero = o->eps_zero;
+    t.use_graph = o->use_graph;
+    int rc = check_opts(&t);
+    if (rc) return rc;
+    const bool regraph = t.use_restarts != h->opts.use_restarts || t.check_every != h->opts.check_every ||
+                         t.use_pw_update != h->opts.use_pw_update || t.eps != h->opts.eps ||
+                         t.max_iters != h->opts.max_iters || t.beta_suff != h->opts.beta_suff ||
+                         t.beta_nec != h->opts.beta_nec || t.beta_art != h->opts.beta_art ||
+                         t.eps_zero != h->opts.eps_zero;
+    if (regraph && h->graph) {
+        hipGraphExecDestroy(h->graph);
+        h->graph = nullptr;
+    }
+    h->opts = t;
+    return PDHG_OK;
 }
 
 extern "C" int pdhg_get_scaling(pdhg_handle *h, int32_t inst, double *rho, double *kappa, int32_t mem,

@@ -188,17 +188,45 @@ __global__ __launch_bounds__(WG) void k_check(Dev d, const V *__restrict__ xa0, 
     }
 }
 
-// Sums the instance's partials (fixed order) into tot[NCAND * NSUM] in LDS.
+// Second level of the check reduction: block t sums up to L2CH consecutive
+// first-level rows of its instance (K blocks first, then K^T blocks), in a
+// fixed order, so the sums of one instance do not depend on the batch.
+__global__ __launch_bounds__(WG) void k_reduce_l2(Dev d, int skip_done)
+{
+    __shared__ double lds[NCAND * NSUM * 4];
+    const int t = blockIdx.x;
+    const int b = d.l2_inst[t];
+    if (skip_done && d.st[b].done) return;
+    const InstInfo in = d.info[b];
+    const int nK = in.blkK1 - in.blkK0, nT = in.blkT1 - in.blkT0;
+    const int r0 = (t - in.l2off) * L2CH;
+    const int r1 = min(r0 + L2CH, nK + nT);
+    double v[NCAND * NSUM];
+#pragma unroll
+    for (int k = 0; k < NCAND * NSUM; ++k) v[k] = 0.0;
+    for (int r = r0 + (int)threadIdx.x; r < r1; r += WG) {
+        const int lbc = r < nK ? in.blkK0 + r : d.K.nblk + in.blkT0 + (r - nK);
+        const double *p = d.partials + (size_t)lbc * (NCAND * NSUM);
+#pragma unroll
+        for (int k = 0; k < NCAND * NSUM; ++k) v[k] += p[k];
+    }
+    block_sum<NCAND * NSUM>(v, lds);
+    if (threadIdx.x == 0) {
+        double *o = d.partials2 + (size_t)t * (NCAND * NSUM);
+#pragma unroll
+        for (int k = 0; k < NCAND * NSUM; ++k) o[k] = v[k];
+    }
+}
+
+// Sums the instance's second-level rows (fixed order) into tot[NCAND * NSUM].
 __device__ void reduce_instance(const Dev &d, const InstInfo &in, double *tot)
 {
     __shared__ double lds[NCAND * NSUM * 4];
     double v[NCAND * NSUM];
 #pragma unroll
     for (int k = 0; k < NCAND * NSUM; ++k) v[k] = 0.0;
-    const int nK = in.blkK1 - in.blkK0, nT = in.blkT1 - in.blkT0;
-    for (int t = threadIdx.x; t < nK + nT; t += WG) {
-        const int lbc = t < nK ? in.blkK0 + t : d.K.nblk + in.blkT0 + (t - nK);
-        const double *p = d.partials + (size_t)lbc * (NCAND * NSUM);
+    for (int t = threadIdx.x; t < in.l2cnt; t += WG) {
+        const double *p = d.partials2 + (size_t)(in.l2off + t) * (NCAND * NSUM);
 #pragma unroll
         for (int k = 0; k < NCAND * NSUM; ++k) v[k] += p[k];
     }
@@ -699,6 +727,7 @@ void launch_check64(const Dev &d, const double *xs, const double *ys, hipStream_
 
 void launch_control(const Dev &d, const CtlParams &P, int iters_done, hipStream_t s)
 {
+    LAUNCH(k_reduce_l2, (unsigned)d.nl2, d, 1);
     LAUNCH(k_control, (unsigned)d.batch, d, P, iters_done);
 }
 
@@ -818,6 +847,7 @@ void launch_set_point(const Dev &d, int64_t xoff, int64_t n, int64_t yoff, int64
 
 void launch_kkt_final(const Dev &d, int inst, double *out9, hipStream_t s)
 {
+    LAUNCH(k_reduce_l2, (unsigned)d.nl2, d, 0);
     hipLaunchKernelGGL(k_kkt_final, dim3(1), dim3(WG), 0, s, d, inst, out9);
 }
 

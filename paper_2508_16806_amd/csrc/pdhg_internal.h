@@ -28,6 +28,7 @@ constexpr int WG = 256;   // workgroup size of every sweep (4 wave64)
 constexpr int NBIN = 8;   // row-length bins
 constexpr int NSUM = 9;   // partial sums per candidate in the check
 constexpr int NCAND = 2;  // candidates: current iterate, epoch average
+constexpr int L2CH = 512; // first-level partial rows summed by one second-level block
 
 struct Seg {
     int64_t row0;       // first row (global internal index)
@@ -57,6 +58,7 @@ struct InstInfo {
     int32_t n, m, m1;
     int32_t blkK0, blkK1;  // logical block range of K-sweeps
     int32_t blkT0, blkT1;  // logical block range of K^T-sweeps
+    int32_t l2off, l2cnt;  // second-level partial rows of this instance
     double cnorm, qnorm;   // ||c||_2 and ||q||_2 of the ORIGINAL LP
     double cnorm_s, qnorm_s;  // of the scaled LP
 };
@@ -112,6 +114,9 @@ struct Dev {
     int32_t *hdone;               // host-mapped copy of done flags
     // scratch
     double *partials;             // (K.nblk + Kt.nblk) * NCAND * NSUM
+    double *partials2;            // nl2 * NCAND * NSUM (second level)
+    const int32_t *l2_inst;       // instance of each second-level row
+    int32_t nl2;
     double *vecN64, *vecN64b;     // FP64 scratch vectors (N)
     double *vecM64, *vecM64b;     // FP64 scratch vectors (M)
     double *inst_scratch;         // batch * 16

@@ -82,28 +82,35 @@ struct RowSweep {
                     acc[0] = fmax(acc[0], fabs(t));
                 }
             } else {
-                int64_t p = b + lane;
-                // four independent gathers in flight per lane on long rows
-                for (; p + 3 * L < e; p += 4 * L) {
-                    const int32_t c0 = ci[p], c1 = ci[p + L], c2 = ci[p + 2 * L], c3 = ci[p + 3 * L];
-                    const double a0 = ld(va, p), a1 = ld(va, p + L), a2 = ld(va, p + 2 * L),
-                                 a3 = ld(va, p + 3 * L);
-                    acc[0] += a0 * ld(g0, c0);
-                    acc[0] += a1 * ld(g0, c1);
-                    acc[0] += a2 * ld(g0, c2);
-                    acc[0] += a3 * ld(g0, c3);
-                    if constexpr (NR > 1) {
-                        acc[1] += a0 * ld(g1, c0);
-                        acc[1] += a1 * ld(g1, c1);
-                        acc[1] += a2 * ld(g1, c2);
-                        acc[1] += a3 * ld(g1, c3);
+                // U-deep unroll with clamped addresses: every lane issues U
+                // column and U value loads, then U independent gathers, with
+                // no branches (a slot past the row end reloads the lane's
+                // first entry, which is in range, and contributes zero)
+                constexpr int U = (L >= WG) ? 8 : 4;
+                for (int64_t p0 = b + lane; p0 < e; p0 += U * L) {
+                    int32_t c[U];
+                    MV raw[U];
+#pragma unroll
+                    for (int k = 0; k < U; ++k) {
+                        const int64_t p = p0 + (int64_t)k * L;
+                        const int64_t q = p < e ? p : p0;
+                        c[k] = ci[q];
+                        raw[k] = va[q];
                     }
-                }
-                for (; p < e; p += L) {
-                    const int32_t c0 = ci[p];
-                    const double a0 = ld(va, p);
-                    acc[0] += a0 * ld(g0, c0);
-                    if constexpr (NR > 1) acc[1] += a0 * ld(g1, c0);
+                    double a[U];
+#pragma unroll
+                    for (int k = 0; k < U; ++k) a[k] = (p0 + (int64_t)k * L < e) ? (double)raw[k] : 0.0;
+                    double g[U];
+#pragma unroll
+                    for (int k = 0; k < U; ++k) g[k] = ld(g0, c[k]);
+#pragma unroll
+                    for (int k = 0; k < U; ++k) acc[0] += a[k] * g[k];
+                    if constexpr (NR > 1) {
+#pragma unroll
+                        for (int k = 0; k < U; ++k) g[k] = ld(g1, c[k]);
+#pragma unroll
+                        for (int k = 0; k < U; ++k) acc[1] += a[k] * g[k];
+                    }
                 }
             }
         }

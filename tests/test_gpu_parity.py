@@ -152,11 +152,19 @@ def test_one_step_f32_matches_oracle(orc, pd):
     s.iterate(1)
     x, y = s.solution(which=pd.SOL_CURRENT)
     xo, yo = o.steps(xs, ys, eta, eta, 1, ruiz_iters=10)
-    # compare in scaled variables against the magnitude of the operands
-    sx = np.abs(xs).max() + 1
-    sy = np.abs(ys).max() + 1
-    np.testing.assert_allclose(x / kap, xo, rtol=0, atol=4e-7 * sx * 10)
-    np.testing.assert_allclose(y / rho, yo, rtol=0, atol=4e-7 * sy * 10)
+    # error bound of the FP32 path, per element: every FP32 rounding (matrix
+    # entry, data entry, xbar, output) is at most u = 2^-24 relative, and the
+    # FP64 accumulation adds nothing at this scale, so
+    #   |dx_j| <= 4u (|x+_j| + |x_j| + tau (|c~_j| + (|K~^T| |y|)_j))
+    #   |dy_i| <= 4u (|y+_i| + |y_i| + sigma (|q~_i| + (|K~| |xbar|)_i))
+    u = 2.0 ** -24
+    Ks = abs(lp.scipy().multiply(o.ruiz(10)[0][:, None]).multiply(kap[None, :])).tocsr()
+    cs, qs = kap * lp.c, o.ruiz(10)[0] * lp.rhs
+    xb = 2 * xo - xs
+    bx = 4 * u * (np.abs(xo) + np.abs(xs) + eta * (np.abs(cs) + Ks.T @ np.abs(ys)))
+    by = 4 * u * (np.abs(yo) + np.abs(ys) + eta * (np.abs(qs) + Ks @ np.abs(xb)))
+    assert np.all(np.abs(x / kap - xo) <= bx + 1e-30)
+    assert np.all(np.abs(y / rho - yo) <= by + 1e-30)
 
 
 # ---------------------------------------------------------------------------
@@ -283,7 +291,11 @@ def test_iteration_and_time_limits(pd):
 
 
 def test_huge_step_reports_numerical_error(pd):
-    lp = _cases()["mixed"]
-    s = pd.Solver(lp, precision="f32", step_size=1e6, max_iters=100000, use_restarts=0)
+    """A step far above 1/||K|| makes the iterates of free variables grow
+    geometrically; the check's FP64 sums overflow and the control kernel
+    stops the instance with NUMERICAL_ERROR."""
+    lp = _cases()["tinyfree"]
+    assert np.isinf(lp.l).any()
+    s = pd.Solver(lp, precision="f32", step_size=1e4, max_iters=100000, use_restarts=0)
     r = s.solve()[0]
     assert r["status_name"] == "NUMERICAL_ERROR"
