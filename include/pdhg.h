@@ -223,6 +223,13 @@ int pdhg_get_solution(pdhg_handle *h, int32_t inst, int32_t which, double *x, do
 int pdhg_set_state(pdhg_handle *h, int32_t inst, const double *x, const double *y, int32_t mem,
                    hipStream_t stream);
 
+/* Replaces the cost, right-hand side and bounds of every instance (arrays
+ * concatenated over the batch in the caller's layout; NULL keeps a vector).
+ * The matrix, the Ruiz factors and the step parameters stay those of setup.
+ * Host arrays are validated like pdhg_setup's; device arrays are trusted. */
+int pdhg_set_data(pdhg_handle *h, const double *c, const double *rhs, const double *l, const double *u,
+                  int32_t mem, hipStream_t stream);
+
 /* Relative KKT error of a caller point (x, y) on instance `inst`'s original
  * LP (y in caller row order).  FP64 throughout; synchronous. */
 int pdhg_kkt(pdhg_handle *h, int32_t inst, const double *x, const double *y, int32_t mem,

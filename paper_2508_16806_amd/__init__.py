@@ -95,7 +95,7 @@ class Info(C.Structure):
 
 EXPORTS = ["pdhg_default_opts", "pdhg_workspace_bytes", "pdhg_setup", "pdhg_iterate", "pdhg_solve",
            "pdhg_get_solution", "pdhg_set_state", "pdhg_kkt", "pdhg_backward", "pdhg_get_scaling",
-           "pdhg_get_info", "pdhg_time_kernels", "pdhg_set_opts",
+           "pdhg_get_info", "pdhg_time_kernels", "pdhg_set_opts", "pdhg_set_data",
            "pdhg_destroy", "pdhg_last_error"]
 
 _lib = None
@@ -122,6 +122,7 @@ def lib():
         L.pdhg_get_scaling.argtypes = [P, I32, P, P, I32, S]
         L.pdhg_get_info.argtypes = [P, C.POINTER(Info)]
         L.pdhg_set_opts.argtypes = [P, C.POINTER(Opts)]
+        L.pdhg_set_data.argtypes = [P, P, P, P, P, I32, S]
         L.pdhg_time_kernels.argtypes = [P, I32, C.POINTER(KernelTimes), S]
         L.pdhg_destroy.argtypes = [P]
         L.pdhg_last_error.restype = C.c_char_p
@@ -267,6 +268,12 @@ class Solver:
         x = np.ascontiguousarray(x, dtype=np.float64)
         y = np.ascontiguousarray(y, dtype=np.float64)
         _check(lib().pdhg_set_state(self.h, inst, x.ctypes.data, y.ctypes.data, MEM_HOST, _stream(stream)))
+
+    def set_data(self, c=None, rhs=None, l=None, u=None, stream=None):
+        """New cost / right-hand side / bounds (concatenated over the batch)."""
+        arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in (c, rhs, l, u)]
+        ptrs = [None if a is None else a.ctypes.data for a in arrs]
+        _check(lib().pdhg_set_data(self.h, *ptrs, MEM_HOST, _stream(stream)))
 
     def kkt(self, x, y, inst: int = 0, stream=None) -> dict:
         if _is_torch_cuda(x):

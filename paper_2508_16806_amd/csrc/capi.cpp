@@ -296,6 +296,7 @@ struct pdhg_handle {
     hipStream_t cap_stream = nullptr;
     int64_t rec_steps = 0;  // steps recorded by the last recording pdhg_iterate
     int rec_valid = 0;
+    std::vector<InstState> rec_st;  // step parameters of the recorded steps
 };
 
 static size_t elem_size(int prec) { return prec == PDHG_PREC_F64 ? sizeof(double) : sizeof(float); }
@@ -936,16 +937,91 @@ static int iterate_impl(pdhg_handle *h, int64_t k, int32_t record, hipStream_t s
     Dev d = h->d;
     // fixed steps use the handle's tau / sigma and ignore done flags
     std::vector<InstState> st = h->st0;
-    HIPCHK(hipMemcpyAsync(d.st, st.data(), h->batch * sizeof(InstState), hipMemcpyHostToDevice, s));
+    for (auto &x : st) x.done = 0;
     if (record) {
-        (void)record;
-        return fail(PDHG_ERR_STATE, "recording is not available in this build");
+        if (h->opts.unroll_capacity <= 0)
+            return fail(PDHG_ERR_STATE, "recording needs opts.unroll_capacity > 0 at setup");
+        if (k > h->opts.unroll_capacity)
+            return fail(PDHG_ERR_INVALID_ARG, "k = %lld exceeds unroll_capacity = %d", (long long)k,
+                        h->opts.unroll_capacity);
     }
+    HIPCHK(hipMemcpyAsync(d.st, st.data(), h->batch * sizeof(InstState), hipMemcpyHostToDevice, s));
+    const int64_t C = std::max(1, h->opts.unroll_checkpoint);
+    const size_t es = elem_size(h->prec);
     for (int64_t t = 0; t < k; ++t) {
+        if (record && t % C == 0) {
+            const int64_t slot = t / C;
+            HIPCHK(hipMemcpyAsync((char *)h->buf.ckx + slot * d.N * es, d.x, d.N * es, hipMemcpyDeviceToDevice, s));
+            HIPCHK(hipMemcpyAsync((char *)h->buf.cky + slot * d.M * es, d.y, d.M * es, hipMemcpyDeviceToDevice, s));
+        }
         launch_primal<T>(d, 0, 0, nullptr, s);
         launch_dual<T>(d, 0, 0, nullptr, s);
     }
     HIPCHK(hipGetLastError());
+    if (record) {
+        h->rec_steps = k;
+        h->rec_valid = 1;
+        h->rec_st = st;
+    }
+    return PDHG_OK;
+}
+
+template <typename T>
+static int backward_impl(pdhg_handle *h, const double *gx, const double *gy, double *gc, double *grhs,
+                         double *gl, double *gu, double *gx0, double *gy0, int32_t mem, hipStream_t s)
+{
+    if (!h->rec_valid) return fail(PDHG_ERR_STATE, "no recorded pdhg_iterate to differentiate");
+    Dev d = h->d;
+    Buffers &b = h->buf;
+    AdjBufs a{b.ax, b.av, b.ac, b.al, b.au, b.ay, b.aw, b.aq};
+    const int64_t K = h->rec_steps, C = std::max(1, h->opts.unroll_checkpoint);
+    const int64_t nseg = (K + C - 1) / C;
+    const size_t es = elem_size(h->prec);
+    const int64_t N = d.N, M = d.M;
+    const double *gxd = gx, *gyd = gy;
+    if (mem == PDHG_MEM_HOST) {
+        HIPCHK(hipMemcpyAsync(d.vecN64b, gx, N * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(d.vecM64b, gy, M * sizeof(double), hipMemcpyHostToDevice, s));
+        gxd = d.vecN64b;
+        gyd = d.vecM64b;
+    }
+    HIPCHK(hipMemcpyAsync(d.st, h->rec_st.data(), h->batch * sizeof(InstState), hipMemcpyHostToDevice, s));
+    // keep the live iterate: the replay runs in the iterate buffers
+    char *bx = (char *)b.ckx + nseg * N * es, *by = (char *)b.cky + nseg * M * es;
+    HIPCHK(hipMemcpyAsync(bx, d.x, N * es, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(by, d.y, M * es, hipMemcpyDeviceToDevice, s));
+    launch_adj_init(d, a, gxd, gyd, s);
+    for (int64_t sg = nseg - 1; sg >= 0; --sg) {
+        const int64_t len = std::min(C, K - sg * C);
+        HIPCHK(hipMemcpyAsync(d.x, (char *)b.ckx + sg * N * es, N * es, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(d.y, (char *)b.cky + sg * M * es, M * es, hipMemcpyDeviceToDevice, s));
+        for (int64_t t = 0; t < len; ++t) {
+            launch_primal<T>(d, 0, 0, b.maskx + t * N, s);
+            launch_dual<T>(d, 0, 0, b.masky + t * M, s);
+        }
+        for (int64_t t = len - 1; t >= 0; --t) {
+            launch_adj_w(d, a, b.masky + t * M, s);
+            launch_rev_primal<T>(d, a, b.maskx + t * N, s);
+            launch_rev_dual<T>(d, a, s);
+        }
+    }
+    HIPCHK(hipMemcpyAsync(d.x, bx, N * es, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(d.y, by, M * es, hipMemcpyDeviceToDevice, s));
+    if (mem == PDHG_MEM_HOST) {
+        double *o[6] = {d.vecN64, d.vecN64b, b.vecN64c, b.axb, d.vecM64, d.vecM64b};
+        launch_adj_out(d, a, gc ? o[0] : nullptr, grhs ? o[4] : nullptr, gl ? o[1] : nullptr,
+                       gu ? o[2] : nullptr, gx0 ? o[3] : nullptr, gy0 ? o[5] : nullptr, s);
+        double *dst[6] = {gc, gl, gu, gx0, grhs, gy0};
+        const double *src[6] = {o[0], o[1], o[2], o[3], o[4], o[5]};
+        const int64_t cnt[6] = {N, N, N, N, M, M};
+        for (int q = 0; q < 6; ++q)
+            if (dst[q] && cnt[q])
+                HIPCHK(hipMemcpyAsync(dst[q], src[q], cnt[q] * sizeof(double), hipMemcpyDeviceToHost, s));
+    } else {
+        launch_adj_out(d, a, gc, grhs, gl, gu, gx0, gy0, s);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
     return PDHG_OK;
 }
 
@@ -1070,9 +1146,74 @@ extern "C" int pdhg_kkt(pdhg_handle *h, int32_t inst, const double *x, const dou
 extern "C" int pdhg_backward(pdhg_handle *h, const double *gx, const double *gy, double *gc, double *grhs,
                              double *gl, double *gu, double *gx0, double *gy0, int32_t mem, hipStream_t s)
 {
-    (void)gx; (void)gy; (void)gc; (void)grhs; (void)gl; (void)gu; (void)gx0; (void)gy0; (void)mem; (void)s;
+    if (!h || !gx || !gy) return fail(PDHG_ERR_INVALID_ARG, "NULL handle or input gradient");
+    if (mem != PDHG_MEM_HOST && mem != PDHG_MEM_DEVICE) return fail(PDHG_ERR_INVALID_ARG, "bad mem");
+    return h->prec == PDHG_PREC_F32 ? backward_impl<float>(h, gx, gy, gc, grhs, gl, gu, gx0, gy0, mem, s)
+                                    : backward_impl<double>(h, gx, gy, gc, grhs, gl, gu, gx0, gy0, mem, s);
+}
+
+extern "C" int pdhg_set_data(pdhg_handle *h, const double *c, const double *rhs, const double *l,
+                             const double *u, int32_t mem, hipStream_t s)
+{
     if (!h) return fail(PDHG_ERR_INVALID_ARG, "NULL handle");
-    return fail(PDHG_ERR_STATE, "no recorded pdhg_iterate to differentiate");
+    if (mem != PDHG_MEM_HOST && mem != PDHG_MEM_DEVICE) return fail(PDHG_ERR_INVALID_ARG, "bad mem");
+    Dev &d = h->d;
+    const int64_t N = d.N, M = d.M;
+    if (mem == PDHG_MEM_HOST) {
+        for (int64_t j = 0; c && j < N; ++j)
+            if (!std::isfinite(c[j])) return fail(PDHG_ERR_NONFINITE, "c[%lld] is not finite", (long long)j);
+        for (int64_t i = 0; rhs && i < M; ++i)
+            if (!std::isfinite(rhs[i])) return fail(PDHG_ERR_NONFINITE, "rhs[%lld] is not finite", (long long)i);
+        std::vector<double> lh(N), uh(N);
+        if (l || u) {
+            HIPCHK(hipMemcpy(lh.data(), d.lraw, N * sizeof(double), hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(uh.data(), d.uraw, N * sizeof(double), hipMemcpyDeviceToHost));
+        }
+        // bounds are checked per variable in the caller's layout
+        for (int bi = 0; (l || u) && bi < h->batch; ++bi) {
+            const InstInfo &in = h->info[bi];
+            const InstPlan &p = h->plan[bi];
+            for (int64_t j = 0; j < in.n; ++j) {
+                const int64_t o = in.xoff + p.col_order[j];
+                const double lo = l ? l[o] : lh[in.xoff + j], hi = u ? u[o] : uh[in.xoff + j];
+                if (std::isnan(lo) || std::isnan(hi)) return fail(PDHG_ERR_NONFINITE, "bound %lld is NaN", (long long)o);
+                if (lo > hi || lo == INFINITY || hi == -INFINITY)
+                    return fail(PDHG_ERR_BOUNDS, "inconsistent bounds at variable %lld", (long long)o);
+            }
+        }
+    }
+    const double *cd = c, *qd = rhs, *ld = l, *ud = u;
+    if (mem == PDHG_MEM_HOST) {
+        double *st[4] = {d.vecN64, d.vecM64, d.vecN64b, h->buf.vecN64c};
+        const double *src[4] = {c, rhs, l, u};
+        const int64_t cnt[4] = {N, M, N, N};
+        const double **dd[4] = {&cd, &qd, &ld, &ud};
+        for (int q = 0; q < 4; ++q)
+            if (src[q]) {
+                if (cnt[q]) HIPCHK(hipMemcpyAsync(st[q], src[q], cnt[q] * sizeof(double), hipMemcpyHostToDevice, s));
+                *dd[q] = st[q];
+            }
+    }
+    launch_set_raw(d, cd, qd, ld, ud, s);
+    if (h->prec == PDHG_PREC_F32)
+        launch_scale_data<float>(d, s);
+    else
+        launch_scale_data<double>(d, s);
+    // relative KKT terms use the norms of the original c and q
+    const int B = h->batch;
+    std::vector<double> n2(2 * B);
+    launch_inst_nrm2(d, 1, d.craw, d.inst_scratch, s);
+    launch_inst_nrm2(d, 0, d.qraw, d.inst_scratch + B, s);
+    HIPCHK(hipMemcpyAsync(n2.data(), d.inst_scratch, 2 * B * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int bi = 0; bi < B; ++bi) {
+        h->info[bi].cnorm = std::sqrt(n2[bi]);
+        h->info[bi].qnorm = std::sqrt(n2[B + bi]);
+    }
+    HIPCHK(hipMemcpyAsync((InstInfo *)d.info, h->info.data(), B * sizeof(InstInfo), hipMemcpyHostToDevice, s));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    return PDHG_OK;
 }
 
 template <typename T>

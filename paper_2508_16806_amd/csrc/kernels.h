@@ -48,4 +48,15 @@ void launch_set_point(const Dev &d, int64_t xoff, int64_t n, int64_t yoff, int64
                       const double *xs, const double *ys, hipStream_t s);
 void launch_kkt_final(const Dev &d, int inst, double *out9, hipStream_t s);
 
+void launch_adj_init(const Dev &d, const AdjBufs &a, const double *gx, const double *gy, hipStream_t s);
+void launch_adj_w(const Dev &d, const AdjBufs &a, const uint8_t *mask_y, hipStream_t s);
+template <typename T>
+void launch_rev_primal(const Dev &d, const AdjBufs &a, const uint8_t *mask_x, hipStream_t s);
+template <typename T>
+void launch_rev_dual(const Dev &d, const AdjBufs &a, hipStream_t s);
+void launch_adj_out(const Dev &d, const AdjBufs &a, double *gc, double *gq, double *gl, double *gu,
+                    double *gx0, double *gy0, hipStream_t s);
+void launch_set_raw(const Dev &d, const double *c, const double *q, const double *l, const double *u,
+                    hipStream_t s);
+
 }  // namespace pdhg

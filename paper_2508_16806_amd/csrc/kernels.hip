@@ -669,6 +669,137 @@ __global__ __launch_bounds__(WG) void k_kkt_final(Dev d, int inst, double *out9)
     for (int k = 0; k < 9; ++k) out9[k] = m.kkt[k];
 }
 
+
+// ---------------------------------------------------------------------------
+// adjoint of fixed-step PDHG (reverse mode, scaled variables)
+//   forward step:  v = x - tau (c - K^T y), x+ = clip(v, l, u), xbar = 2x+ - x,
+//                  w = y + sigma (q - K xbar), y+ = proj_Y(w)
+//   reverse step, given ax = dL/dx+, ay = dL/dy+:
+//     aw = [row is "=" or w > 0] ay,          aq += sigma aw
+//     axb = -sigma K^T aw,  g = ax + 2 axb
+//     av = g where l < v < u (else g goes to al or au),  ac -= tau av
+//     ax <- av - axb,       ay <- aw + tau K av
+// ---------------------------------------------------------------------------
+
+// ax = kap * gx, ay = rho * gy (caller layout -> internal), accumulators = 0
+__global__ void k_adj_init(Dev d, AdjBufs a, const double *gx, const double *gy)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < d.N) {
+        const InstInfo &in = d.info[d.inst_of_col[t]];
+        a.ax[t] = d.kap[t] * gx[in.xoff + d.col_orig[t]];
+        a.ac[t] = 0.0;
+        a.al[t] = 0.0;
+        a.au[t] = 0.0;
+    }
+    if (t < d.M) {
+        const InstInfo &in = d.info[d.inst_of_row[t]];
+        a.ay[t] = d.rho[t] * gy[in.yoff + d.row_orig[t]];
+        a.aq[t] = 0.0;
+    }
+}
+
+// aw = mask_y * ay ; aq += sigma * aw
+__global__ void k_adj_w(Dev d, AdjBufs a, const uint8_t *__restrict__ mask_y)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.M) return;
+    const double sigma = d.st[d.inst_of_row[i]].sigma;
+    const double w = mask_y[i] ? a.ay[i] : 0.0;
+    a.aw[i] = w;
+    a.aq[i] += sigma * w;
+}
+
+template <typename T>
+__global__ __launch_bounds__(WG) void k_rev_primal(Dev d, AdjBufs a, const uint8_t *__restrict__ mask_x)
+{
+    __shared__ double red[8];
+    const int lb = logical_block(d.remap);
+    const OpDev &op = d.Kt;
+    const Seg s = op.seg[op.blk_seg[lb]];
+    const InstState *st = d.st + s.inst;
+    const double tau = st->tau, sigma = st->sigma;
+    const int bi = lb - s.blk0;
+    dispatch_lanes(s.lanes_log2, [&](auto tag) {
+        constexpr int L = decltype(tag)::value;
+        int64_t j;
+        double acc[1];
+        if (RowSweep<L, 1, T, double>::run(op, s, bi, a.aw, nullptr, nullptr, red, j, acc)) {
+            const double axb = -sigma * acc[0];
+            const double g = a.ax[j] + 2.0 * axb;
+            const uint8_t code = mask_x[j];
+            double av = 0.0;
+            if (code == 1)
+                a.al[j] += g;
+            else if (code == 2)
+                a.au[j] += g;
+            else
+                av = g;
+            a.av[j] = av;
+            a.ac[j] -= tau * av;
+            a.ax[j] = av - axb;
+        }
+    });
+}
+
+template <typename T>
+__global__ __launch_bounds__(WG) void k_rev_dual(Dev d, AdjBufs a)
+{
+    __shared__ double red[8];
+    const int lb = logical_block(d.remap);
+    const OpDev &op = d.K;
+    const Seg s = op.seg[op.blk_seg[lb]];
+    const double tau = d.st[s.inst].tau;
+    const int bi = lb - s.blk0;
+    dispatch_lanes(s.lanes_log2, [&](auto tag) {
+        constexpr int L = decltype(tag)::value;
+        int64_t i;
+        double acc[1];
+        if (RowSweep<L, 1, T, double>::run(op, s, bi, a.av, nullptr, nullptr, red, i, acc))
+            a.ay[i] = a.aw[i] + tau * acc[0];
+    });
+}
+
+// gradients in the caller's variables and layout (concatenated over the batch)
+__global__ void k_adj_out(Dev d, AdjBufs a, double *gc, double *gq, double *gl, double *gu, double *gx0,
+                          double *gy0)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < d.N) {
+        const InstInfo &in = d.info[d.inst_of_col[t]];
+        const int64_t o = in.xoff + d.col_orig[t];
+        const double k = d.kap[t];
+        if (gc) gc[o] = k * a.ac[t];
+        if (gl) gl[o] = a.al[t] / k;
+        if (gu) gu[o] = a.au[t] / k;
+        if (gx0) gx0[o] = a.ax[t] / k;
+    }
+    if (t < d.M) {
+        const InstInfo &in = d.info[d.inst_of_row[t]];
+        const int64_t o = in.yoff + d.row_orig[t];
+        const double r = d.rho[t];
+        if (gq) gq[o] = r * a.aq[t];
+        if (gy0) gy0[o] = a.ay[t] / r;
+    }
+}
+
+// caller-layout FP64 data of all instances -> raw internal copies
+__global__ void k_set_raw(Dev d, const double *c, const double *q, const double *l, const double *u)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < d.N) {
+        const InstInfo &in = d.info[d.inst_of_col[t]];
+        const int64_t o = in.xoff + d.col_orig[t];
+        if (c) d.craw[t] = c[o];
+        if (l) d.lraw[t] = l[o];
+        if (u) d.uraw[t] = u[o];
+    }
+    if (t < d.M && q) {
+        const InstInfo &in = d.info[d.inst_of_row[t]];
+        d.qraw[t] = q[in.yoff + d.row_orig[t]];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------
@@ -851,6 +982,40 @@ void launch_kkt_final(const Dev &d, int inst, double *out9, hipStream_t s)
     hipLaunchKernelGGL(k_kkt_final, dim3(1), dim3(WG), 0, s, d, inst, out9);
 }
 
+void launch_adj_init(const Dev &d, const AdjBufs &a, const double *gx, const double *gy, hipStream_t s)
+{
+    LAUNCH(k_adj_init, nblk_elem(d.N > d.M ? d.N : d.M), d, a, gx, gy);
+}
+
+void launch_adj_w(const Dev &d, const AdjBufs &a, const uint8_t *mask_y, hipStream_t s)
+{
+    LAUNCH(k_adj_w, nblk_elem(d.M), d, a, mask_y);
+}
+
+template <typename T>
+void launch_rev_primal(const Dev &d, const AdjBufs &a, const uint8_t *mask_x, hipStream_t s)
+{
+    LAUNCH(k_rev_primal<T>, (unsigned)d.Kt.nblk, d, a, mask_x);
+}
+
+template <typename T>
+void launch_rev_dual(const Dev &d, const AdjBufs &a, hipStream_t s)
+{
+    LAUNCH(k_rev_dual<T>, (unsigned)d.K.nblk, d, a);
+}
+
+void launch_adj_out(const Dev &d, const AdjBufs &a, double *gc, double *gq, double *gl, double *gu,
+                    double *gx0, double *gy0, hipStream_t s)
+{
+    LAUNCH(k_adj_out, nblk_elem(d.N > d.M ? d.N : d.M), d, a, gc, gq, gl, gu, gx0, gy0);
+}
+
+void launch_set_raw(const Dev &d, const double *c, const double *q, const double *l, const double *u,
+                    hipStream_t s)
+{
+    LAUNCH(k_set_raw, nblk_elem(d.N > d.M ? d.N : d.M), d, c, q, l, u);
+}
+
 #define INST(T)                                                                              \
     template void launch_primal<T>(const Dev &, int, int, uint8_t *, hipStream_t);           \
     template void launch_dual<T>(const Dev &, int, int, uint8_t *, hipStream_t);             \
@@ -861,7 +1026,9 @@ void launch_kkt_final(const Dev &d, int inst, double *out9, hipStream_t s)
     template void launch_epoch_start<T>(const Dev &, hipStream_t);                           \
     template void launch_point_to64<T>(const Dev &, int, double *, double *, hipStream_t);   \
     template void launch_set_point<T>(const Dev &, int64_t, int64_t, int64_t, int64_t, int64_t, \
-                                      const double *, const double *, hipStream_t);
+                                      const double *, const double *, hipStream_t);                 \
+    template void launch_rev_primal<T>(const Dev &, const AdjBufs &, const uint8_t *, hipStream_t); \
+    template void launch_rev_dual<T>(const Dev &, const AdjBufs &, hipStream_t);
 INST(float)
 INST(double)
 

@@ -122,4 +122,10 @@ struct Dev {
     double *inst_scratch;         // batch * 16
 };
 
+// FP64 adjoint vectors of the unrolled-step backward pass.
+struct AdjBufs {
+    double *ax, *av, *ac, *al, *au;  // length N
+    double *ay, *aw, *aq;            // length M
+};
+
 }  // namespace pdhg
