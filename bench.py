@@ -80,6 +80,111 @@ def cpu_baseline(lp, budget_s=15.0):
                       f"at 20 passes in both; setup cancels)"}
 
 
+def bench_batched(args):
+    """256 planted LPs (C3 recipe, m ~ U{1000..m_max}): one batched solve vs the
+    same LPs solved one at a time with the same library on the same GPU."""
+    import numpy as np
+    import torch
+
+    import lpgen
+    import paper_2508_16806_amd as pd
+
+    B = args.batch
+    t = time.perf_counter()
+    lps = [lpgen.config3_instance(i, m_range=(1000, args.m_max)) for i in range(B)]
+    gen_s = time.perf_counter() - t
+    nnz = sum(lp.nnz for lp in lps)
+    print(f"[bench] generated {B} LPs (m <= {args.m_max}), nnz {nnz} in {gen_s:.1f}s", file=sys.stderr, flush=True)
+    kw = dict(precision="f32", eps=1e-4, max_iters=200000, time_limit=300.0)
+    sb = pd.Solver(lps, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rb = sb.solve()
+    tb = time.perf_counter() - t0
+    print(f"[bench] batched: {tb:.2f}s, iters max {max(r['iters'] for r in rb)}", file=sys.stderr, flush=True)
+    solo = []
+    for i, lp in enumerate(lps):
+        s = pd.Solver(lp, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = s.solve()[0]
+        solo.append((time.perf_counter() - t0, r, lp.m, lp.nnz))
+        s.close()
+    ts = sum(x[0] for x in solo)
+    same = all(rb[i]["iters"] == solo[i][1]["iters"] for i in range(B))
+    gaps = [abs(r["kkt"]["pobj"] - lp.f_star) / (1 + abs(lp.f_star)) for r, lp in zip(rb, lps)]
+    buckets = {}
+    for (dt, r, m, z) in solo:
+        k = f"m<{((m - 1) // 2500 + 1) * 2500}"
+        b = buckets.setdefault(k, {"lps": 0, "solo_s": 0.0, "iters": 0})
+        b["lps"] += 1
+        b["solo_s"] += dt
+        b["iters"] += r["iters"]
+    out = {"metric": METRIC, "value": B / tb, "unit": "LPs/s (batched)", "n_gpus": 1, "steps": 1,
+           "warmup": 0, "ms_per_step": tb * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{B} planted LPs, m ~ U{{1000..{args.m_max}}}, n = 2.5m, density "
+                                  f"U(0.001, 0.01); total nnz {nnz}; eps 1e-4",
+                      "batch": B, "nnz_total": nnz},
+           "batched": {"seconds": tb, "lps_per_s": B / tb,
+                       "status": {k: sum(1 for r in rb if r["status_name"] == k) for k in set(r["status_name"] for r in rb)}},
+           "one_by_one": {"seconds": ts, "lps_per_s": B / ts, "buckets": buckets},
+           "speedup": ts / tb, "iterations_identical": same, "max_rel_obj_gap_vs_planted": max(gaps)}
+    print(json.dumps(out), flush=True)
+
+
+def bench_adjoint(args):
+    """64 SCED-shaped LPs at 1/10 of C1: warm start from a batched solve at 1e-4,
+    then K = 500 recorded fixed-step iterations (checkpoint every 50) and the
+    adjoint of L = sum_i c_i' x_K,i."""
+    import numpy as np
+    import torch
+
+    import lpgen
+    import paper_2508_16806_amd as pd
+
+    B, K, C = args.batch, 500, 50
+    t = time.perf_counter()
+    lps = [lpgen.config4_instance(i) for i in range(B)]
+    print(f"[bench] generated {B} SCED/10 LPs in {time.perf_counter() - t:.1f}s", file=sys.stderr, flush=True)
+    s = pd.Solver(lps, precision="f32", eps=1e-4, max_iters=200000, unroll_capacity=K, unroll_checkpoint=C)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rs = s.solve()
+    tsolve = time.perf_counter() - t0
+    xs, ys = [], []
+    for i in range(B):
+        x, y = s.solution(inst=i)
+        xs.append(x)
+        ys.append(y)
+    for i in range(B):
+        s.set_state(xs[i], ys[i], inst=i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.iterate(K, record=True)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    c = np.concatenate([lp.c for lp in lps])
+    t0 = time.perf_counter()
+    g = s.backward(c, np.zeros(sum(lp.m for lp in lps)))
+    tbw = time.perf_counter() - t0
+    # envelope comparison (reported, not gated): d(c'x_K)/dc = x_K + (dx_K/dc)' c  vs  x*
+    xk = np.concatenate([s.solution(inst=i, which=pd.SOL_CURRENT)[0] for i in range(B)])
+    xstar = np.concatenate(xs)
+    total = xk + g["c"]
+    env = float(np.linalg.norm(total - xstar) / np.linalg.norm(xstar))
+    nnz = sum(lp.nnz for lp in lps)
+    out = {"metric": METRIC, "value": B * K / tf, "unit": "LP-steps/s (recorded forward)", "n_gpus": 1,
+           "steps": K, "warmup": 0, "ms_per_step": tf * 1e3 / K, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{B} SCED-shaped LPs at 1/10 of C1 (n={lps[0].n}, m={lps[0].m}), "
+                                  f"K={K} unrolled steps, checkpoint every {C}", "nnz_total": nnz},
+           "solve_seconds": tsolve, "solve_iters_max": max(r["iters"] for r in rs),
+           "forward_seconds": tf, "backward_seconds": tbw, "backward_over_forward": tbw / tf,
+           "envelope_rel_diff_dobj_dc_vs_xstar": env}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +194,10 @@ def main():
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance solve")
     ap.add_argument("--small", action="store_true", help="reduced SCED size (for profiling tests)")
     ap.add_argument("--no-tuning", action="store_true", help="default bins instead of the tuned ones")
+    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "c4"],
+                    help="c1: SCED-shaped LP (default); c3: batched vs one-by-one; c4: unrolled adjoint")
+    ap.add_argument("--batch", type=int, default=0)
+    ap.add_argument("--m-max", type=int, default=10000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of the "
@@ -104,6 +213,12 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs the GPU", file=sys.stderr)
         sys.exit(1)
+    if args.workload == "c3":
+        args.batch = args.batch or 256
+        return bench_batched(args)
+    if args.workload == "c4":
+        args.batch = args.batch or 64
+        return bench_adjoint(args)
     t = time.perf_counter()
     lp = lpgen.sced(500, 200, 24, 125, seed=1) if args.small else lpgen.config1()
     gen_s = time.perf_counter() - t

@@ -121,6 +121,9 @@ typedef struct {
      * 4, 8, 16, 32, 64, 128, 512, inf. */
     int32_t bin_len_dual[8];   /* rows of K   (dual sweep)                        */
     int32_t bin_len_primal[8]; /* rows of K^T (primal sweep)                      */
+    int32_t max_grid;          /* workgroups per solve-time sweep launch (0: 8192);  */
+                               /* a launch walks the row blocks of the instances   */
+                               /* still running                                    */
 } pdhg_opts;
 
 /* Relative KKT error terms (Section 2.3.2, conditions term1-term3) on the

@@ -50,7 +50,7 @@ class Opts(C.Structure):
                 ("beta_nec", C.c_double), ("beta_art", C.c_double), ("eps_zero", C.c_double),
                 ("unroll_capacity", C.c_int32), ("unroll_checkpoint", C.c_int32),
                 ("use_graph", C.c_int32), ("xcd_remap", C.c_int32), ("bin_len_dual", C.c_int32 * 8),
-                ("bin_len_primal", C.c_int32 * 8)]
+                ("bin_len_primal", C.c_int32 * 8), ("max_grid", C.c_int32)]
 
 
 class KKTOut(C.Structure):

@@ -1,5 +1,8 @@
 """Autotuner for the row-length bins of the two fused sweeps.
 
+The launch shape is tuned after the bins: XCD-contiguous workgroup
+numbering on or off and the cap on workgroups per sweep launch.
+
 A bin sweeps each row with a fixed number of lanes (1, 2, 4, ..., 64 lanes of
 a wavefront, or a whole 256-lane workgroup).  The tuner tries bin limits
 
@@ -28,7 +31,7 @@ def limits(f: int, w: int):
 
 
 def autotune(lp, precision: str = "f32", factors=(1, 2, 4, 8), wg_thresholds=(256, 512, 2048),
-             reps: int = 20, verbose: bool = True) -> dict:
+             grid_caps=(4096, 8192, 16384, 65536), reps: int = 20, verbose: bool = True) -> dict:
     import paper_2508_16806_amd as pd
 
     trials = []
@@ -47,16 +50,37 @@ def autotune(lp, precision: str = "f32", factors=(1, 2, 4, 8), wg_thresholds=(25
             s.close()
     bp = min(trials, key=lambda r: r["ms_primal"])
     bd = min(trials, key=lambda r: r["ms_dual"])
+    # launch shape: XCD-contiguous numbering on/off, sweep grid cap
+    shapes = []
+    for remap in (0, 1):
+        for grid in grid_caps:
+            s = pd.Solver(lp, precision=precision, bin_len_dual=bd["limits"], bin_len_primal=bp["limits"],
+                          xcd_remap=remap, max_grid=grid)
+            s.time_kernels(reps=3)
+            t = s.time_kernels(reps=reps)
+            tot = t["ms_primal"] + t["ms_dual"] + t["ms_check"] / 64.0
+            shapes.append({"xcd_remap": remap, "max_grid": grid, "ms_primal": t["ms_primal"],
+                           "ms_dual": t["ms_dual"], "ms_check": t["ms_check"], "ms_iter": tot})
+            if verbose:
+                print(f"[autotune] remap={remap} grid={grid}: primal {t['ms_primal']*1e3:.1f} us, dual "
+                      f"{t['ms_dual']*1e3:.1f} us, check {t['ms_check']*1e3:.1f} us", file=sys.stderr, flush=True)
+            s.close()
+    bs = min(shapes, key=lambda r: r["ms_iter"])
     return {"n": int(lp.n), "m": int(lp.m), "nnz": int(lp.nnz), "precision": precision,
             "bin_len_primal": bp["limits"], "bin_len_dual": bd["limits"],
-            "ms_primal": bp["ms_primal"], "ms_dual": bd["ms_dual"], "trials": trials,
+            "xcd_remap": bs["xcd_remap"], "max_grid": bs["max_grid"],
+            "ms_primal": bs["ms_primal"], "ms_dual": bs["ms_dual"], "trials": trials, "shapes": shapes,
             "time": time.strftime("%Y-%m-%d %H:%M:%S")}
 
 
 def load(path: str) -> dict:
     with open(path) as f:
         t = json.load(f)
-    return {"bin_len_primal": t["bin_len_primal"], "bin_len_dual": t["bin_len_dual"]}
+    out = {"bin_len_primal": t["bin_len_primal"], "bin_len_dual": t["bin_len_dual"]}
+    for k in ("xcd_remap", "max_grid"):
+        if k in t:
+            out[k] = t[k]
+    return out
 
 
 def main():
@@ -77,7 +101,8 @@ def main():
     res["workload"] = args.workload
     with open(args.out, "w") as f:
         json.dump(res, f, indent=1)
-    print(json.dumps({k: res[k] for k in ("bin_len_primal", "bin_len_dual", "ms_primal", "ms_dual")}))
+    print(json.dumps({k: res[k] for k in ("bin_len_primal", "bin_len_dual", "xcd_remap", "max_grid",
+                                          "ms_primal", "ms_dual")}))
 
 
 if __name__ == "__main__":

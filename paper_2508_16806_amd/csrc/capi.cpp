@@ -72,6 +72,7 @@ extern "C" void pdhg_default_opts(pdhg_opts *o)
     o->unroll_checkpoint = 50;
     o->use_graph = 1;
     o->xcd_remap = 1;
+    o->max_grid = 8192;
 }
 
 // ---------------------------------------------------------------------------
@@ -347,6 +348,10 @@ static void carve(Carve &cv, const Sizes &sz, int prec, const pdhg_opts &o, Dev 
     *st = cv.take<InstState>(sz.batch);
     d.partials = cv.take<double>((size_t)(sz.nblkK + sz.nblkT) * NCAND * NSUM + 1);
     d.partials2 = cv.take<double>((size_t)sz.nl2 * NCAND * NSUM + 1);
+    d.actK = cv.take<int32_t>(sz.nblkK + 1);
+    d.actT = cv.take<int32_t>(sz.nblkT + 1);
+    d.act_cnt = cv.take<int32_t>(2);
+    d.act_off = cv.take<int32_t>(2 * (size_t)sz.batch);
     b.l2inst = cv.take<int32_t>(sz.nl2 + 1);
     d.vecN64 = cv.take<double>(N);
     d.vecN64b = cv.take<double>(N);
@@ -522,8 +527,18 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
             uraw[xoff + j] = lp.u[cj];
         }
         // segments and block maps (instance-major, so an instance's blocks are contiguous)
+        // block numbering: segments of long rows first (the dispatcher starts
+        // the expensive workgroups early and short-row workgroups fill the
+        // tail); the rows keep their internal order
+        auto by_lanes = [](const std::vector<SegH> &v) {
+            std::vector<int> o(v.size());
+            for (size_t k = 0; k < v.size(); ++k) o[k] = (int)k;
+            std::stable_sort(o.begin(), o.end(), [&](int a, int b) { return v[a].lanes_log2 > v[b].lanes_log2; });
+            return o;
+        };
         in.blkK0 = blkK;
-        for (const SegH &sh : p.segK) {
+        for (int si : by_lanes(p.segK)) {
+            const SegH &sh = p.segK[si];
             Seg sg{};
             sg.row0 = yoff + sh.row0;
             sg.nrows = sh.nrows;
@@ -538,7 +553,8 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
         }
         in.blkK1 = blkK;
         in.blkT0 = blkT;
-        for (const SegH &sh : p.segT) {
+        for (int si : by_lanes(p.segT)) {
+            const SegH &sh = p.segT[si];
             Seg sg{};
             sg.row0 = xoff + sh.row0;
             sg.nrows = sh.nrows;
@@ -731,6 +747,7 @@ extern "C" int pdhg_setup(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, 
     d.st = st;
     d.l2_inst = h->buf.l2inst;
     d.nl2 = (int32_t)h->sz.nl2;
+    d.grid_cap = o->max_grid > 0 ? o->max_grid : 8192;
     Buffers &b = h->buf;
     d.K = OpDev{h->sz.M, b.Krp, b.Kci, b.Kv32, b.Kv64, b.Kseg, b.Kbs, (int32_t)h->sz.nsegK, (int32_t)h->sz.nblkK};
     d.Kt = OpDev{h->sz.N, b.Ktrp, b.Ktci, b.Ktv32, b.Ktv64, b.Ktseg, b.Ktbs, (int32_t)h->sz.nsegT,
@@ -802,6 +819,7 @@ static void enqueue_chunk(const pdhg_handle *h, hipStream_t s)
     launch_check<T>(d, avg, s);
     launch_control(d, ctl_params(h), h->opts.check_every, s);
     if (avg) launch_restart<T>(d, s);
+    launch_active(d, s);
 }
 
 template <typename T>
@@ -845,9 +863,11 @@ static int solve_impl(pdhg_handle *h, pdhg_result *res, hipStream_t s)
     }
     std::memset(h->hdone_host, 0, sizeof(int32_t) * B);
     HIPCHK(hipMemcpyAsync(d.st, st.data(), B * sizeof(InstState), hipMemcpyHostToDevice, s));
+    launch_active(d, s);
     launch_epoch_start<T>(d, s);
     launch_check<T>(d, 0, s);
     launch_control(d, ctl_params(h), 0, s);
+    launch_active(d, s);
     HIPCHK(hipGetLastError());
 
     const int DEPTH = 4;
@@ -946,6 +966,7 @@ static int iterate_impl(pdhg_handle *h, int64_t k, int32_t record, hipStream_t s
                         h->opts.unroll_capacity);
     }
     HIPCHK(hipMemcpyAsync(d.st, st.data(), h->batch * sizeof(InstState), hipMemcpyHostToDevice, s));
+    launch_active(d, s);
     const int64_t C = std::max(1, h->opts.unroll_checkpoint);
     const size_t es = elem_size(h->prec);
     for (int64_t t = 0; t < k; ++t) {
@@ -986,6 +1007,7 @@ static int backward_impl(pdhg_handle *h, const double *gx, const double *gy, dou
         gyd = d.vecM64b;
     }
     HIPCHK(hipMemcpyAsync(d.st, h->rec_st.data(), h->batch * sizeof(InstState), hipMemcpyHostToDevice, s));
+    launch_active(d, s);
     // keep the live iterate: the replay runs in the iterate buffers
     char *bx = (char *)b.ckx + nseg * N * es, *by = (char *)b.cky + nseg * M * es;
     HIPCHK(hipMemcpyAsync(bx, d.x, N * es, hipMemcpyDeviceToDevice, s));
@@ -1224,6 +1246,7 @@ static int time_impl(pdhg_handle *h, int32_t reps, pdhg_kernel_times *out, hipSt
     std::vector<InstState> st = h->st0;
     for (auto &x : st) x.done = 0;
     HIPCHK(hipMemcpyAsync(d.st, st.data(), h->batch * sizeof(InstState), hipMemcpyHostToDevice, s));
+    launch_active(d, s);
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -1249,6 +1272,7 @@ static int time_impl(pdhg_handle *h, int32_t reps, pdhg_kernel_times *out, hipSt
         if (phase == 3) {
             // the control kernel may have stopped an instance: restore the state
             HIPCHK(hipMemcpyAsync(d.st, st.data(), h->batch * sizeof(InstState), hipMemcpyHostToDevice, s));
+            launch_active(d, s);
         }
     }
     hipEventDestroy(e0);

@@ -14,6 +14,7 @@ template <typename T>
 void launch_check(const Dev &d, int avg, hipStream_t s);
 void launch_check64(const Dev &d, const double *xs, const double *ys, hipStream_t s);
 void launch_control(const Dev &d, const CtlParams &P, int iters_done, hipStream_t s);
+void launch_active(const Dev &d, hipStream_t s);
 template <typename T>
 void launch_restart(const Dev &d, hipStream_t s);
 

@@ -25,19 +25,18 @@ namespace pdhg {
 // hot path: fused SpMV + update sweeps
 // ---------------------------------------------------------------------------
 
+// The solve-time sweeps run a bounded grid that walks the compacted list of
+// logical blocks of instances still running (see k_act_fill), so finished
+// instances of a batch cost nothing.  Each logical block computes exactly what
+// it would in a full launch.
+
 // MASK: also record the clip region of x (0 interior, 1 at l, 2 at u) for the
 // adjoint replay.
 template <typename T, int AVG, int MASK>
 __global__ __launch_bounds__(WG) void k_primal(Dev d, int j_in_chunk, uint8_t *__restrict__ mask)
 {
     __shared__ double red[8];
-    const int lb = logical_block(d.remap);
     const OpDev &op = d.Kt;
-    const Seg s = op.seg[op.blk_seg[lb]];
-    const InstState *st = d.st + s.inst;
-    if (st->done) return;
-    const double tau = st->tau;
-    const double w = AVG ? 1.0 / (double)(st->t_inner + j_in_chunk + 1) : 0.0;
     T *__restrict__ x = (T *)d.x;
     T *__restrict__ xb = (T *)d.xbar;
     T *__restrict__ xa = (T *)d.xavg;
@@ -45,25 +44,40 @@ __global__ __launch_bounds__(WG) void k_primal(Dev d, int j_in_chunk, uint8_t *_
     const T *__restrict__ l = (const T *)d.l;
     const T *__restrict__ u = (const T *)d.u;
     const T *__restrict__ y = (const T *)d.y;
-    const int bi = lb - s.blk0;
-    dispatch_lanes(s.lanes_log2, [&](auto tag) {
-        constexpr int L = decltype(tag)::value;
-        int64_t j;
-        double acc[1];
-        if (RowSweep<L, 1, T, T>::run(op, s, bi, y, nullptr, nullptr, red, j, acc)) {
-            const double xo = (double)x[j];
-            const double v = xo - tau * ((double)c[j] - acc[0]);
-            const double lo = (double)l[j], hi = (double)u[j];
-            const double xn = v < lo ? lo : (v > hi ? hi : v);
-            const T xnT = (T)xn;
-            x[j] = xnT;
-            xb[j] = (T)(2.0 * (double)xnT - xo);
-            if (AVG) {
-                const double a = (double)xa[j];
-                xa[j] = (T)(a + ((double)xnT - a) * w);
+    const int cnt = d.act_cnt[1];
+    const bool full = cnt == op.nblk;  // every block active: the list is the identity
+    for_each_item(cnt, d.remap, [&](int it) {
+        const int lb = full ? it : d.actT[it];
+        const Seg s = op.seg[op.blk_seg[lb]];
+        const InstState *st = d.st + s.inst;
+        const double tau = st->tau;
+        const double w = AVG ? 1.0 / (double)(st->t_inner + j_in_chunk + 1) : 0.0;
+        const int bi = lb - s.blk0;
+        dispatch_lanes(s.lanes_log2, [&](auto tag) {
+            constexpr int L = decltype(tag)::value;
+            using RS = RowSweep<L, 1, T, T>;
+            const typename RS::Pos ps = RS::locate(s, bi);
+            const int64_t j = ps.row;
+            // the update's operands are loaded before the dot product so their
+            // latency overlaps the streaming of the row
+            // (unconditional loads from a clamped row: no branch forces a wait)
+            const int64_t jj = ps.valid ? j : s.row0;
+            const T r_x = x[jj], r_c = c[jj], r_l = l[jj], r_u = u[jj];
+            const T r_a = AVG ? xa[jj] : T(0);
+            double acc[1];
+            RS::dot(op, ps, y, nullptr, nullptr, red, acc);
+            if (ps.leader) {
+                const double xo = (double)r_x, cj = (double)r_c, lo = (double)r_l, hi = (double)r_u;
+                const double xav = (double)r_a;
+                const double v = xo - tau * (cj - acc[0]);
+                const double xn = v < lo ? lo : (v > hi ? hi : v);
+                const T xnT = (T)xn;
+                x[j] = xnT;
+                xb[j] = (T)(2.0 * (double)xnT - xo);
+                if (AVG) xa[j] = (T)(xav + ((double)xnT - xav) * w);
+                if (MASK) mask[j] = (uint8_t)(v <= lo ? 1 : (v >= hi ? 2 : 0));
             }
-            if (MASK) mask[j] = (uint8_t)(v <= lo ? 1 : (v >= hi ? 2 : 0));
-        }
+        });
     });
 }
 
@@ -71,34 +85,41 @@ template <typename T, int AVG, int MASK>
 __global__ __launch_bounds__(WG) void k_dual(Dev d, int j_in_chunk, uint8_t *__restrict__ mask)
 {
     __shared__ double red[8];
-    const int lb = logical_block(d.remap);
     const OpDev &op = d.K;
-    const Seg s = op.seg[op.blk_seg[lb]];
-    const InstState *st = d.st + s.inst;
-    if (st->done) return;
-    const double sigma = st->sigma;
-    const double w = AVG ? 1.0 / (double)(st->t_inner + j_in_chunk + 1) : 0.0;
     T *__restrict__ y = (T *)d.y;
     T *__restrict__ ya = (T *)d.yavg;
     const T *__restrict__ q = (const T *)d.q;
     const T *__restrict__ xb = (const T *)d.xbar;
-    const bool ineq = s.ineq != 0;
-    const int bi = lb - s.blk0;
-    dispatch_lanes(s.lanes_log2, [&](auto tag) {
-        constexpr int L = decltype(tag)::value;
-        int64_t i;
-        double acc[1];
-        if (RowSweep<L, 1, T, T>::run(op, s, bi, xb, nullptr, nullptr, red, i, acc)) {
-            const double wv = (double)y[i] + sigma * ((double)q[i] - acc[0]);
-            const double yn = (ineq && wv < 0.0) ? 0.0 : wv;
-            const T ynT = (T)yn;
-            y[i] = ynT;
-            if (AVG) {
-                const double a = (double)ya[i];
-                ya[i] = (T)(a + ((double)ynT - a) * w);
+    const int cnt = d.act_cnt[0];
+    const bool full = cnt == op.nblk;
+    for_each_item(cnt, d.remap, [&](int it) {
+        const int lb = full ? it : d.actK[it];
+        const Seg s = op.seg[op.blk_seg[lb]];
+        const InstState *st = d.st + s.inst;
+        const double sigma = st->sigma;
+        const double w = AVG ? 1.0 / (double)(st->t_inner + j_in_chunk + 1) : 0.0;
+        const bool ineq = s.ineq != 0;
+        const int bi = lb - s.blk0;
+        dispatch_lanes(s.lanes_log2, [&](auto tag) {
+            constexpr int L = decltype(tag)::value;
+            using RS = RowSweep<L, 1, T, T>;
+            const typename RS::Pos ps = RS::locate(s, bi);
+            const int64_t i = ps.row;
+            const int64_t ii = ps.valid ? i : s.row0;
+            const T r_y = y[ii], r_q = q[ii];
+            const T r_a = AVG ? ya[ii] : T(0);
+            double acc[1];
+            RS::dot(op, ps, xb, nullptr, nullptr, red, acc);
+            if (ps.leader) {
+                const double yo = (double)r_y, qi = (double)r_q, yav = (double)r_a;
+                const double wv = yo + sigma * (qi - acc[0]);
+                const double yn = (ineq && wv < 0.0) ? 0.0 : wv;
+                const T ynT = (T)yn;
+                y[i] = ynT;
+                if (AVG) ya[i] = (T)(yav + ((double)ynT - yav) * w);
+                if (MASK) mask[i] = (uint8_t)((!ineq || wv > 0.0) ? 1 : 0);
             }
-            if (MASK) mask[i] = (uint8_t)((!ineq || wv > 0.0) ? 1 : 0);
-        }
+        });
     });
 }
 
@@ -122,70 +143,76 @@ __device__ __forceinline__ double proj_lambda(double v, double l, double u)
     return v;
 }
 
+// use_list: walk the active lists (solve); otherwise every block (caller KKT).
 template <typename V, int NC>
 __global__ __launch_bounds__(WG) void k_check(Dev d, const V *__restrict__ xa0, const V *__restrict__ xa1,
                                               const V *__restrict__ ya0, const V *__restrict__ ya1,
                                               const V *__restrict__ xs, const V *__restrict__ ys,
-                                              int skip_done)
+                                              int use_list)
 {
     __shared__ double red[NCAND * NSUM * 4];
-    const int lbc = logical_block(d.remap);
-    const bool onK = lbc < d.K.nblk;
-    const OpDev &op = onK ? d.K : d.Kt;
-    const int lb = onK ? lbc : lbc - d.K.nblk;
-    const Seg s = op.seg[op.blk_seg[lb]];
-    if (skip_done && d.st[s.inst].done) return;
-    double sum[NC * NSUM];
+    const int nK = use_list ? d.act_cnt[0] : d.K.nblk;
+    const int nT = use_list ? d.act_cnt[1] : d.Kt.nblk;
+    const bool fullK = nK == d.K.nblk, fullT = nT == d.Kt.nblk;
+    for_each_item(nK + nT, d.remap, [&](int it) {
+        const bool onK = it < nK;
+        const int lb = onK ? (fullK ? it : d.actK[it]) : (fullT ? it - nK : d.actT[it - nK]);
+        const int lbc = onK ? lb : d.K.nblk + lb;
+        const OpDev &op = onK ? d.K : d.Kt;
+        const Seg s = op.seg[op.blk_seg[lb]];
+        double sum[NC * NSUM];
 #pragma unroll
-    for (int k = 0; k < NC * NSUM; ++k) sum[k] = 0.0;
-    const int bi = lb - s.blk0;
-    const bool ineq = s.ineq != 0;
-    dispatch_lanes(s.lanes_log2, [&](auto tag) {
-        constexpr int L = decltype(tag)::value;
-        int64_t r;
-        double acc[NC];
-        if (onK) {
-            if (RowSweep<L, NC, double, V>::run(op, s, bi, xa0, xa1, nullptr, red, r, acc)) {
-                const double qi = d.q64[r], rh = d.rho[r];
+        for (int k = 0; k < NC * NSUM; ++k) sum[k] = 0.0;
+        const int bi = lb - s.blk0;
+        const bool ineq = s.ineq != 0;
+        dispatch_lanes(s.lanes_log2, [&](auto tag) {
+            constexpr int L = decltype(tag)::value;
+            int64_t r;
+            double acc[NC];
+            if (onK) {
+                if (RowSweep<L, NC, double, V>::run(op, s, bi, xa0, xa1, nullptr, red, r, acc)) {
+                    const double qi = d.q64[r], rh = d.rho[r];
 #pragma unroll
-                for (int a = 0; a < NC; ++a) {
-                    double e = qi - acc[a];
-                    if (ineq && e < 0.0) e = 0.0;
-                    const double eu = e / rh;
-                    const double ya = (double)(a == 0 ? ya0 : ya1)[r];
-                    const double dy = ya - (double)ys[r];
-                    sum[a * NSUM + 0] += e * e;
-                    sum[a * NSUM + 1] += eu * eu;
-                    sum[a * NSUM + 2] += qi * ya;
-                    sum[a * NSUM + 3] += dy * dy;
+                    for (int a = 0; a < NC; ++a) {
+                        double e = qi - acc[a];
+                        if (ineq && e < 0.0) e = 0.0;
+                        const double eu = e / rh;
+                        const double ya = (double)(a == 0 ? ya0 : ya1)[r];
+                        const double dy = ya - (double)ys[r];
+                        sum[a * NSUM + 0] += e * e;
+                        sum[a * NSUM + 1] += eu * eu;
+                        sum[a * NSUM + 2] += qi * ya;
+                        sum[a * NSUM + 3] += dy * dy;
+                    }
+                }
+            } else {
+                if (RowSweep<L, NC, double, V>::run(op, s, bi, ya0, ya1, nullptr, red, r, acc)) {
+                    const double cj = d.c64[r], lj = d.l64[r], uj = d.u64[r], kj = d.kap[r];
+#pragma unroll
+                    for (int a = 0; a < NC; ++a) {
+                        const double dd = cj - acc[a];
+                        const double lam = proj_lambda(dd, lj, uj);
+                        const double rd = dd - lam;
+                        const double rdu = rd / kj;
+                        const double xv = (double)(a == 0 ? xa0 : xa1)[r];
+                        const double dx = xv - (double)xs[r];
+                        sum[a * NSUM + 4] += rd * rd;
+                        sum[a * NSUM + 5] += rdu * rdu;
+                        sum[a * NSUM + 6] += cj * xv;
+                        sum[a * NSUM + 7] += lam > 0.0 ? lj * lam : (lam < 0.0 ? uj * lam : 0.0);
+                        sum[a * NSUM + 8] += dx * dx;
+                    }
                 }
             }
-        } else {
-            if (RowSweep<L, NC, double, V>::run(op, s, bi, ya0, ya1, nullptr, red, r, acc)) {
-                const double cj = d.c64[r], lj = d.l64[r], uj = d.u64[r], kj = d.kap[r];
+        });
+        block_sum<NC * NSUM>(sum, red);
+        if (threadIdx.x == 0) {
+            double *out = d.partials + (size_t)lbc * (NCAND * NSUM);
 #pragma unroll
-                for (int a = 0; a < NC; ++a) {
-                    const double dd = cj - acc[a];
-                    const double lam = proj_lambda(dd, lj, uj);
-                    const double rd = dd - lam;
-                    const double rdu = rd / kj;
-                    const double xv = (double)(a == 0 ? xa0 : xa1)[r];
-                    const double dx = xv - (double)xs[r];
-                    sum[a * NSUM + 4] += rd * rd;
-                    sum[a * NSUM + 5] += rdu * rdu;
-                    sum[a * NSUM + 6] += cj * xv;
-                    sum[a * NSUM + 7] += lam > 0.0 ? lj * lam : (lam < 0.0 ? uj * lam : 0.0);
-                    sum[a * NSUM + 8] += dx * dx;
-                }
-            }
+            for (int k = 0; k < NCAND * NSUM; ++k) out[k] = k < NC * NSUM ? sum[k] : 0.0;
         }
+        __syncthreads();
     });
-    block_sum<NC * NSUM>(sum, red);
-    if (threadIdx.x == 0) {
-        double *out = d.partials + (size_t)lbc * (NCAND * NSUM);
-#pragma unroll
-        for (int k = 0; k < NCAND * NSUM; ++k) out[k] = k < NC * NSUM ? sum[k] : 0.0;
-    }
 }
 
 // Second level of the check reduction: block t sums up to L2CH consecutive
@@ -358,28 +385,66 @@ __global__ __launch_bounds__(WG) void k_control(Dev d, CtlParams P, int iters_do
     }
 }
 
-// On restart: z <- candidate, epoch start <- z.  Grid: K^T blocks then K blocks.
+// On restart: z <- candidate, epoch start <- z.  Walks K^T blocks then K blocks
+// of the running instances.
 template <typename T>
 __global__ __launch_bounds__(WG) void k_restart(Dev d)
 {
-    const int lbc = logical_block(d.remap);
-    const bool onT = lbc < d.Kt.nblk;
-    const OpDev &op = onT ? d.Kt : d.K;
-    const int lb = onT ? lbc : lbc - d.Kt.nblk;
-    const Seg s = op.seg[op.blk_seg[lb]];
-    const InstState &st = d.st[s.inst];
-    if (st.done || !st.restart) return;
-    const int L = s.lanes_log2 >= 8 ? WG : (1 << s.lanes_log2);
-    const int G = WG / L;
-    const int64_t r0 = s.row0 + (int64_t)(lb - s.blk0) * G;
-    const int64_t r1 = min(r0 + G, s.row0 + s.nrows);
-    T *z = (T *)(onT ? d.x : d.y);
-    T *za = (T *)(onT ? d.xavg : d.yavg);
-    T *z0 = (T *)(onT ? d.x0 : d.y0);
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += WG) {
-        const T v = st.cand_avg ? za[r] : z[r];
-        z[r] = v;
-        z0[r] = v;
+    const int nT = d.act_cnt[1], nK = d.act_cnt[0];
+    const bool fullK = nK == d.K.nblk, fullT = nT == d.Kt.nblk;
+    for_each_item(nT + nK, d.remap, [&](int it) {
+        const bool onT = it < nT;
+        const int lb = onT ? (fullT ? it : d.actT[it]) : (fullK ? it - nT : d.actK[it - nT]);
+        const OpDev &op = onT ? d.Kt : d.K;
+        const Seg s = op.seg[op.blk_seg[lb]];
+        const InstState &st = d.st[s.inst];
+        if (!st.restart) return;
+        const int L = s.lanes_log2 >= 8 ? WG : (1 << s.lanes_log2);
+        const int G = WG / L;
+        const int64_t r0 = s.row0 + (int64_t)(lb - s.blk0) * G;
+        const int64_t r1 = min(r0 + G, s.row0 + s.nrows);
+        T *z = (T *)(onT ? d.x : d.y);
+        T *za = (T *)(onT ? d.xavg : d.yavg);
+        T *z0 = (T *)(onT ? d.x0 : d.y0);
+        for (int64_t r = r0 + threadIdx.x; r < r1; r += WG) {
+            const T v = st.cand_avg ? za[r] : z[r];
+            z[r] = v;
+            z0[r] = v;
+        }
+    });
+}
+
+// Active lists: exclusive scan of the running instances' block counts (one
+// workgroup, sequential over the batch: O(batch) per check) ...
+__global__ void k_act_scan(Dev d)
+{
+    if (threadIdx.x != 0) return;
+    int oK = 0, oT = 0;
+    for (int b = 0; b < d.batch; ++b) {
+        const InstInfo &in = d.info[b];
+        d.act_off[2 * b] = oK;
+        d.act_off[2 * b + 1] = oT;
+        if (!d.st[b].done) {
+            oK += in.blkK1 - in.blkK0;
+            oT += in.blkT1 - in.blkT0;
+        }
+    }
+    d.act_cnt[0] = oK;
+    d.act_cnt[1] = oT;
+}
+
+// ... then every logical block of a running instance writes itself into place
+// (instance order, block order: the lists are deterministic).
+__global__ void k_act_fill(Dev d)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < d.K.nblk) {
+        const int b = d.K.seg[d.K.blk_seg[t]].inst;
+        if (!d.st[b].done) d.actK[d.act_off[2 * b] + (t - d.info[b].blkK0)] = t;
+    }
+    if (t < d.Kt.nblk) {
+        const int b = d.Kt.seg[d.Kt.blk_seg[t]].inst;
+        if (!d.st[b].done) d.actT[d.act_off[2 * b + 1] + (t - d.info[b].blkT0)] = t;
     }
 }
 
@@ -811,10 +876,16 @@ static inline unsigned nblk_elem(int64_t n) { return (unsigned)((n + WG - 1) / W
         if ((grid) > 0) hipLaunchKernelGGL(kern, dim3(grid), dim3(WG), 0, s, __VA_ARGS__); \
     } while (0)
 
+static inline unsigned sweep_grid(const Dev &d, int64_t nitems)
+{
+    const int64_t g = nitems < d.grid_cap ? nitems : d.grid_cap;
+    return (unsigned)(g > 0 ? g : 0);
+}
+
 template <typename T>
 void launch_primal(const Dev &d, int j, int avg, uint8_t *mask, hipStream_t s)
 {
-    const unsigned g = (unsigned)d.Kt.nblk;
+    const unsigned g = sweep_grid(d, d.Kt.nblk);
     if (mask) {
         LAUNCH((k_primal<T, 0, 1>), g, d, j, mask);
     } else if (avg) {
@@ -827,7 +898,7 @@ void launch_primal(const Dev &d, int j, int avg, uint8_t *mask, hipStream_t s)
 template <typename T>
 void launch_dual(const Dev &d, int j, int avg, uint8_t *mask, hipStream_t s)
 {
-    const unsigned g = (unsigned)d.K.nblk;
+    const unsigned g = sweep_grid(d, d.K.nblk);
     if (mask) {
         LAUNCH((k_dual<T, 0, 1>), g, d, j, mask);
     } else if (avg) {
@@ -840,7 +911,7 @@ void launch_dual(const Dev &d, int j, int avg, uint8_t *mask, hipStream_t s)
 template <typename T>
 void launch_check(const Dev &d, int avg, hipStream_t s)
 {
-    const unsigned g = (unsigned)(d.K.nblk + d.Kt.nblk);
+    const unsigned g = sweep_grid(d, d.K.nblk + d.Kt.nblk);
     const T *x = (const T *)d.x, *xa = (const T *)d.xavg, *x0 = (const T *)d.x0;
     const T *y = (const T *)d.y, *ya = (const T *)d.yavg, *y0 = (const T *)d.y0;
     if (avg) {
@@ -852,8 +923,15 @@ void launch_check(const Dev &d, int avg, hipStream_t s)
 
 void launch_check64(const Dev &d, const double *xs, const double *ys, hipStream_t s)
 {
-    const unsigned g = (unsigned)(d.K.nblk + d.Kt.nblk);
+    const unsigned g = sweep_grid(d, d.K.nblk + d.Kt.nblk);
     LAUNCH((k_check<double, 1>), g, d, xs, xs, ys, ys, xs, ys, 0);
+}
+
+void launch_active(const Dev &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_act_scan, dim3(1), dim3(64), 0, s, d);
+    const int64_t n = d.K.nblk > d.Kt.nblk ? d.K.nblk : d.Kt.nblk;
+    LAUNCH(k_act_fill, nblk_elem(n), d);
 }
 
 void launch_control(const Dev &d, const CtlParams &P, int iters_done, hipStream_t s)
@@ -865,7 +943,7 @@ void launch_control(const Dev &d, const CtlParams &P, int iters_done, hipStream_
 template <typename T>
 void launch_restart(const Dev &d, hipStream_t s)
 {
-    LAUNCH(k_restart<T>, (unsigned)(d.K.nblk + d.Kt.nblk), d);
+    LAUNCH(k_restart<T>, sweep_grid(d, d.K.nblk + d.Kt.nblk), d);
 }
 
 void launch_fill(double *p, int64_t n, double v, hipStream_t s) { LAUNCH(k_fill, nblk_elem(n), p, n, v); }

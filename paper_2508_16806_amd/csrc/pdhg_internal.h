@@ -117,6 +117,10 @@ struct Dev {
     double *partials2;            // nl2 * NCAND * NSUM (second level)
     const int32_t *l2_inst;       // instance of each second-level row
     int32_t nl2;
+    int32_t *actK, *actT;         // logical blocks of running instances (K, K^T sweeps)
+    int32_t *act_cnt;             // [2]: lengths of actK, actT
+    int32_t *act_off;             // [2 * batch]: list offsets per instance
+    int32_t grid_cap;             // workgroups of a solve-time sweep launch
     double *vecN64, *vecN64b;     // FP64 scratch vectors (N)
     double *vecM64, *vecM64b;     // FP64 scratch vectors (M)
     double *inst_scratch;         // batch * 16

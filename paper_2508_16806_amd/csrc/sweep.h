@@ -26,6 +26,27 @@ __device__ __forceinline__ int logical_block(int remap)
     return xcd * q + (xcd < r ? xcd : r) + (b >> 3);
 }
 
+// Work items [0, cnt) of a bounded grid.  With `remap`, XCD x (the hardware
+// places workgroup b on XCD b mod 8) takes the contiguous item range
+// [x * ceil(cnt/8), (x + 1) * ceil(cnt/8)) and its workgroups stride through
+// it, so neighbouring rows share one XCD's L2.  The loop is uniform across a
+// workgroup (f may use __syncthreads).
+template <typename F>
+__device__ __forceinline__ void for_each_item(int cnt, int remap, F &&f)
+{
+    const int G = gridDim.x, b = blockIdx.x;
+    if (!remap || G < 8) {
+        for (int it = b; it < cnt; it += G) f(it);
+        return;
+    }
+    const int xcd = b & 7, loc = b >> 3;
+    const int nloc = (G - xcd + 7) >> 3;
+    const int per = (cnt + 7) >> 3;
+    const int i0 = xcd * per;
+    const int i1 = min(cnt, i0 + per);
+    for (int it = i0 + loc; it < i1; it += nloc) f(it);
+}
+
 template <typename V>
 __device__ __forceinline__ const V *op_vals(const OpDev &op);
 template <>
@@ -55,21 +76,38 @@ template <int L, int NR, typename MV, typename GV, bool MAXABS = false, bool FAC
 struct RowSweep {
     static constexpr int G = (L >= WG) ? 1 : WG / L;
 
-    // Returns, for this lane, whether it leads a valid row, and that row.
-    __device__ __forceinline__ static bool run(const OpDev &op, const Seg &s, int bi,
-                                               const GV *__restrict__ g0, const GV *__restrict__ g1,
-                                               const double *__restrict__ rowfac,
-                                               double *red_lds, int64_t &row, double (&acc)[NR])
+    // Position of this lane: the row its group handles, whether that row
+    // exists, and whether this lane leads the group (receives the dot product).
+    struct Pos {
+        int64_t row;
+        int lane;
+        bool valid;
+        bool leader;
+    };
+
+    __device__ __forceinline__ static Pos locate(const Seg &s, int bi)
     {
         const int tid = threadIdx.x;
         const int grp = (L >= WG) ? 0 : tid / L;
         const int lane = (L >= WG) ? tid : (tid & (L - 1));
         const int64_t rloc = (int64_t)bi * G + grp;
         const bool valid = rloc < s.nrows;
-        row = s.row0 + rloc;
+        return {s.row0 + rloc, lane, valid, valid && lane == 0};
+    }
+
+    // Dot product(s) of the row at p with the gathered vector(s); the result
+    // is valid in the leader lane.  Every lane of the workgroup must call it.
+    __device__ __forceinline__ static void dot(const OpDev &op, const Pos &ps,
+                                               const GV *__restrict__ g0, const GV *__restrict__ g1,
+                                               const double *__restrict__ rowfac, double *red_lds,
+                                               double (&acc)[NR])
+    {
+        const int tid = threadIdx.x;
+        const int lane = ps.lane;
+        const int64_t row = ps.row;
 #pragma unroll
         for (int k = 0; k < NR; ++k) acc[k] = 0.0;
-        if (valid) {
+        if (ps.valid) {
             const int64_t b = op.rp[row], e = op.rp[row + 1];
             const MV *__restrict__ va = op_vals<MV>(op);
             const int32_t *__restrict__ ci = op.ci;
@@ -133,12 +171,22 @@ struct RowSweep {
                 }
             }
             __syncthreads();
-            return valid && tid == 0;
         } else {
 #pragma unroll
             for (int k = 0; k < NR; ++k) acc[k] = group_reduce<L, MAXABS>(acc[k]);
-            return valid && lane == 0;
         }
+    }
+
+    // locate + dot; returns whether this lane leads a valid row.
+    __device__ __forceinline__ static bool run(const OpDev &op, const Seg &s, int bi,
+                                               const GV *__restrict__ g0, const GV *__restrict__ g1,
+                                               const double *__restrict__ rowfac,
+                                               double *red_lds, int64_t &row, double (&acc)[NR])
+    {
+        const Pos ps = locate(s, bi);
+        row = ps.row;
+        dot(op, ps, g0, g1, rowfac, red_lds, acc);
+        return ps.leader;
     }
 };
 
