@@ -198,6 +198,8 @@ def main():
                     help="c1: SCED-shaped LP (default); c3: batched vs one-by-one; c4: unrolled adjoint")
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--m-max", type=int, default=10000)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run plain 256 MiB device copies (counter calibration under rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of the "
@@ -249,6 +251,13 @@ def main():
     print(f"[bench] {args.steps} steps of {CE} iterations in {dt*1e3:.1f} ms: {ips:.1f} iter/s",
           file=sys.stderr, flush=True)
 
+    if args.calib_copy:
+        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     kt = s.time_kernels(reps=20)
     pb, db = sweep_bytes(info, 4)
     pg, dg = pb / (kt["ms_primal"] * 1e-3) / 1e9, db / (kt["ms_dual"] * 1e-3) / 1e9

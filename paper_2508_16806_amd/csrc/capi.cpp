@@ -270,6 +270,7 @@ struct Buffers {
     double *Kv64, *Ktv64;
     float *Kv32, *Ktv32;
     Seg *Kseg, *Ktseg;
+    int4 *Kbd, *Ktbd;
     // record / adjoint
     void *ckx, *cky;
     uint8_t *maskx, *masky;
@@ -313,12 +314,14 @@ static void carve(Carve &cv, const Sizes &sz, int prec, const pdhg_opts &o, Dev 
     b.Kv32 = prec == PDHG_PREC_F32 ? cv.take<float>(NNZ) : nullptr;
     b.Kseg = cv.take<Seg>(sz.nsegK);
     b.Kbs = cv.take<int32_t>(sz.nblkK);
+    b.Kbd = cv.take<int4>(sz.nblkK);
     b.Ktrp = cv.take<int64_t>(N + 1);
     b.Ktci = cv.take<int32_t>(NNZ);
     b.Ktv64 = cv.take<double>(NNZ);
     b.Ktv32 = prec == PDHG_PREC_F32 ? cv.take<float>(NNZ) : nullptr;
     b.Ktseg = cv.take<Seg>(sz.nsegT);
     b.Ktbs = cv.take<int32_t>(sz.nblkT);
+    b.Ktbd = cv.take<int4>(sz.nblkT);
     d.x = cv.take<char>(N * es);
     d.xbar = cv.take<char>(N * es);
     d.xavg = cv.take<char>(N * es);
@@ -426,7 +429,9 @@ static int plan_all(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, std::v
         sz.nsegK += plans[b].segK.size();
         sz.nsegT += plans[b].segT.size();
     }
-    if (sz.N >= INT32_MAX || sz.M >= INT32_MAX) return fail(PDHG_ERR_SHAPE, "total n and m must be < 2^31");
+    // sweeps address the gathered vectors with 32-bit byte offsets
+    if (sz.N >= (int64_t(1) << 29) || sz.M >= (int64_t(1) << 29))
+        return fail(PDHG_ERR_SHAPE, "total n and m over the batch must be < 2^29");
     if (sz.nblkK + sz.nblkT >= INT32_MAX) return fail(PDHG_ERR_SHAPE, "too many workgroups");
     return PDHG_OK;
 }
@@ -470,6 +475,7 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
     Dev &d = h->d;
     std::vector<int64_t> Krp(sz.M + 1), Ktrp(sz.N + 1);
     std::vector<int32_t> Kci(sz.NNZ), Ktci(sz.NNZ), Kbs(sz.nblkK), Ktbs(sz.nblkT);
+    std::vector<int4> Kbd(sz.nblkK), Ktbd(sz.nblkT);
     std::vector<double> Kv(sz.NNZ), Ktv(sz.NNZ);
     std::vector<Seg> Kseg, Ktseg;
     std::vector<int32_t> l2inst;
@@ -547,7 +553,13 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
             sg.lanes_log2 = sh.lanes_log2;
             sg.inst = bi;
             sg.ineq = sh.ineq;
-            for (int t = 0; t < sg.nblk; ++t) Kbs[blkK + t] = (int32_t)Kseg.size();
+            for (int t = 0; t < sg.nblk; ++t) {
+                Kbs[blkK + t] = (int32_t)Kseg.size();
+                const int G = seg_group(sg.lanes_log2);
+                const int64_t r0 = sg.row0 + (int64_t)t * G;
+                const int nr = (int)std::min<int64_t>(G, sg.row0 + sg.nrows - r0);
+                Kbd[blkK + t] = make_int4((int)r0, nr, bi, sg.lanes_log2 | (sg.ineq << 8));
+            }
             blkK += sg.nblk;
             Kseg.push_back(sg);
         }
@@ -563,7 +575,13 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
             sg.lanes_log2 = sh.lanes_log2;
             sg.inst = bi;
             sg.ineq = 0;
-            for (int t = 0; t < sg.nblk; ++t) Ktbs[blkT + t] = (int32_t)Ktseg.size();
+            for (int t = 0; t < sg.nblk; ++t) {
+                Ktbs[blkT + t] = (int32_t)Ktseg.size();
+                const int G = seg_group(sg.lanes_log2);
+                const int64_t r0 = sg.row0 + (int64_t)t * G;
+                const int nr = (int)std::min<int64_t>(G, sg.row0 + sg.nrows - r0);
+                Ktbd[blkT + t] = make_int4((int)r0, nr, bi, sg.lanes_log2);
+            }
             blkT += sg.nblk;
             Ktseg.push_back(sg);
         }
@@ -584,6 +602,7 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
     if ((rc = h2d(b.Krp, Krp.data(), Krp.size(), s)) || (rc = h2d(b.Kci, Kci.data(), Kci.size(), s)) ||
         (rc = h2d(b.Kv64, Kv.data(), Kv.size(), s)) || (rc = h2d(b.Kseg, Kseg.data(), Kseg.size(), s)) ||
         (rc = h2d(b.Kbs, Kbs.data(), Kbs.size(), s)) || (rc = h2d(b.Ktrp, Ktrp.data(), Ktrp.size(), s)) ||
+        (rc = h2d(b.Kbd, Kbd.data(), Kbd.size(), s)) || (rc = h2d(b.Ktbd, Ktbd.data(), Ktbd.size(), s)) ||
         (rc = h2d(b.Ktci, Ktci.data(), Ktci.size(), s)) || (rc = h2d(b.Ktv64, Ktv.data(), Ktv.size(), s)) ||
         (rc = h2d(b.Ktseg, Ktseg.data(), Ktseg.size(), s)) || (rc = h2d(b.Ktbs, Ktbs.data(), Ktbs.size(), s)) ||
         (rc = h2d(d.craw, craw.data(), craw.size(), s)) || (rc = h2d(d.lraw, lraw.data(), lraw.size(), s)) ||
@@ -749,8 +768,9 @@ extern "C" int pdhg_setup(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, 
     d.nl2 = (int32_t)h->sz.nl2;
     d.grid_cap = o->max_grid > 0 ? o->max_grid : 8192;
     Buffers &b = h->buf;
-    d.K = OpDev{h->sz.M, b.Krp, b.Kci, b.Kv32, b.Kv64, b.Kseg, b.Kbs, (int32_t)h->sz.nsegK, (int32_t)h->sz.nblkK};
-    d.Kt = OpDev{h->sz.N, b.Ktrp, b.Ktci, b.Ktv32, b.Ktv64, b.Ktseg, b.Ktbs, (int32_t)h->sz.nsegT,
+    d.K = OpDev{h->sz.M, b.Krp, b.Kci, b.Kv32, b.Kv64, b.Kseg, b.Kbs, b.Kbd, (int32_t)h->sz.nsegK,
+                (int32_t)h->sz.nblkK};
+    d.Kt = OpDev{h->sz.N, b.Ktrp, b.Ktci, b.Ktv32, b.Ktv64, b.Ktseg, b.Ktbs, b.Ktbd, (int32_t)h->sz.nsegT,
                  (int32_t)h->sz.nblkT};
     if (hipHostMalloc((void **)&h->hdone_host, sizeof(int32_t) * batch, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
         delete h;

@@ -48,7 +48,7 @@ __global__ __launch_bounds__(WG) void k_primal(Dev d, int j_in_chunk, uint8_t *_
     const bool full = cnt == op.nblk;  // every block active: the list is the identity
     for_each_item(cnt, d.remap, [&](int it) {
         const int lb = full ? it : d.actT[it];
-        const Seg s = op.seg[op.blk_seg[lb]];
+        const Seg s = block_seg(op, lb);
         const InstState *st = d.st + s.inst;
         const double tau = st->tau;
         const double w = AVG ? 1.0 / (double)(st->t_inner + j_in_chunk + 1) : 0.0;
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(WG) void k_dual(Dev d, int j_in_chunk, uint8_t *__r
     const bool full = cnt == op.nblk;
     for_each_item(cnt, d.remap, [&](int it) {
         const int lb = full ? it : d.actK[it];
-        const Seg s = op.seg[op.blk_seg[lb]];
+        const Seg s = block_seg(op, lb);
         const InstState *st = d.st + s.inst;
         const double sigma = st->sigma;
         const double w = AVG ? 1.0 / (double)(st->t_inner + j_in_chunk + 1) : 0.0;
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(WG) void k_check(Dev d, const V *__restrict__ xa0, 
         const int lb = onK ? (fullK ? it : d.actK[it]) : (fullT ? it - nK : d.actT[it - nK]);
         const int lbc = onK ? lb : d.K.nblk + lb;
         const OpDev &op = onK ? d.K : d.Kt;
-        const Seg s = op.seg[op.blk_seg[lb]];
+        const Seg s = block_seg(op, lb);
         double sum[NC * NSUM];
 #pragma unroll
         for (int k = 0; k < NC * NSUM; ++k) sum[k] = 0.0;
@@ -396,7 +396,7 @@ __global__ __launch_bounds__(WG) void k_restart(Dev d)
         const bool onT = it < nT;
         const int lb = onT ? (fullT ? it : d.actT[it]) : (fullK ? it - nT : d.actK[it - nT]);
         const OpDev &op = onT ? d.Kt : d.K;
-        const Seg s = op.seg[op.blk_seg[lb]];
+        const Seg s = block_seg(op, lb);
         const InstState &st = d.st[s.inst];
         if (!st.restart) return;
         const int L = s.lanes_log2 >= 8 ? WG : (1 << s.lanes_log2);
@@ -439,11 +439,11 @@ __global__ void k_act_fill(Dev d)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < d.K.nblk) {
-        const int b = d.K.seg[d.K.blk_seg[t]].inst;
+        const int b = block_seg(d.K, t).inst;
         if (!d.st[b].done) d.actK[d.act_off[2 * b] + (t - d.info[b].blkK0)] = t;
     }
     if (t < d.Kt.nblk) {
-        const int b = d.Kt.seg[d.Kt.blk_seg[t]].inst;
+        const int b = block_seg(d.Kt, t).inst;
         if (!d.st[b].done) d.actT[d.act_off[2 * b + 1] + (t - d.info[b].blkT0)] = t;
     }
 }
@@ -467,7 +467,7 @@ __global__ __launch_bounds__(WG) void k_rowmax(OpDev op, int remap, const double
 {
     __shared__ double red[8];
     const int lb = logical_block(remap);
-    const Seg s = op.seg[op.blk_seg[lb]];
+    const Seg s = block_seg(op, lb);
     const int bi = lb - s.blk0;
     dispatch_lanes(s.lanes_log2, [&](auto tag) {
         constexpr int L = decltype(tag)::value;
@@ -533,7 +533,7 @@ __global__ __launch_bounds__(WG) void k_spmv64(OpDev op, int remap, const double
 {
     __shared__ double red[8];
     const int lb = logical_block(remap);
-    const Seg s = op.seg[op.blk_seg[lb]];
+    const Seg s = block_seg(op, lb);
     const int bi = lb - s.blk0;
     double sq[1] = {0.0};
     dispatch_lanes(s.lanes_log2, [&](auto tag) {
@@ -660,7 +660,7 @@ __global__ __launch_bounds__(WG) void k_lambda(Dev d, const double *ys, double *
     __shared__ double red[8];
     const int lb = logical_block(d.remap);
     const OpDev &op = d.Kt;
-    const Seg s = op.seg[op.blk_seg[lb]];
+    const Seg s = block_seg(op, lb);
     const int bi = lb - s.blk0;
     dispatch_lanes(s.lanes_log2, [&](auto tag) {
         constexpr int L = decltype(tag)::value;
@@ -781,7 +781,7 @@ __global__ __launch_bounds__(WG) void k_rev_primal(Dev d, AdjBufs a, const uint8
     __shared__ double red[8];
     const int lb = logical_block(d.remap);
     const OpDev &op = d.Kt;
-    const Seg s = op.seg[op.blk_seg[lb]];
+    const Seg s = block_seg(op, lb);
     const InstState *st = d.st + s.inst;
     const double tau = st->tau, sigma = st->sigma;
     const int bi = lb - s.blk0;
@@ -813,7 +813,7 @@ __global__ __launch_bounds__(WG) void k_rev_dual(Dev d, AdjBufs a)
     __shared__ double red[8];
     const int lb = logical_block(d.remap);
     const OpDev &op = d.K;
-    const Seg s = op.seg[op.blk_seg[lb]];
+    const Seg s = block_seg(op, lb);
     const double tau = d.st[s.inst].tau;
     const int bi = lb - s.blk0;
     dispatch_lanes(s.lanes_log2, [&](auto tag) {

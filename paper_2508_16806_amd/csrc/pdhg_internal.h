@@ -20,6 +20,7 @@
 //    of one instance are contiguous, so per-instance reductions read a fixed
 //    contiguous range of per-block partial sums (deterministic, no atomics).
 #pragma once
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace pdhg {
@@ -48,6 +49,7 @@ struct OpDev {
     const double *v64;   // scaled values, FP64 (after setup)
     const Seg *seg;
     const int32_t *blk_seg;
+    const int4 *bdesc;   // per logical block: {first row, rows, instance, lanes_log2 | ineq << 8}
     int32_t nseg;
     int32_t nblk;
 };

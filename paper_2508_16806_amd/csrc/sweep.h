@@ -47,6 +47,22 @@ __device__ __forceinline__ void for_each_item(int cnt, int remap, F &&f)
     for (int it = i0 + loc; it < i1; it += nloc) f(it);
 }
 
+// The rows of logical block lb as a one-block segment (one 16-byte load):
+// rows [row0, row0 + nrows) of one instance and one length bin.
+__device__ __forceinline__ Seg block_seg(const OpDev &op, int lb)
+{
+    const int4 v = op.bdesc[lb];
+    Seg s;
+    s.row0 = v.x;
+    s.nrows = v.y;
+    s.blk0 = lb;
+    s.nblk = 1;
+    s.inst = v.z;
+    s.lanes_log2 = v.w & 0xff;
+    s.ineq = v.w >> 8;
+    return s;
+}
+
 template <typename V>
 __device__ __forceinline__ const V *op_vals(const OpDev &op);
 template <>
@@ -56,6 +72,14 @@ __device__ __forceinline__ const double *op_vals<double>(const OpDev &op) { retu
 
 template <typename V>
 __device__ __forceinline__ double ld(const V *p, int64_t i) { return (double)p[i]; }
+
+// Load with a 32-bit byte offset from a workgroup-uniform base: the compiler
+// emits the scalar-base + 32-bit-offset global load (one VGPR per address).
+template <typename V>
+__device__ __forceinline__ V ldo(const V *base, uint32_t idx)
+{
+    return *(const V *)((const char *)base + idx * (uint32_t)sizeof(V));
+}
 
 // Sum (or max when MAXABS) of a value across the L lanes of a group.
 template <int L, bool MAXABS>
@@ -80,6 +104,7 @@ struct RowSweep {
     // exists, and whether this lane leads the group (receives the dot product).
     struct Pos {
         int64_t row;
+        int64_t blk_row0;  // first row of the workgroup (uniform)
         int lane;
         bool valid;
         bool leader;
@@ -92,7 +117,7 @@ struct RowSweep {
         const int lane = (L >= WG) ? tid : (tid & (L - 1));
         const int64_t rloc = (int64_t)bi * G + grp;
         const bool valid = rloc < s.nrows;
-        return {s.row0 + rloc, lane, valid, valid && lane == 0};
+        return {s.row0 + rloc, s.row0 + (int64_t)bi * G, lane, valid, valid && lane == 0};
     }
 
     // Dot product(s) of the row at p with the gathered vector(s); the result
@@ -109,9 +134,9 @@ struct RowSweep {
         for (int k = 0; k < NR; ++k) acc[k] = 0.0;
         if (ps.valid) {
             const int64_t b = op.rp[row], e = op.rp[row + 1];
-            const MV *__restrict__ va = op_vals<MV>(op);
-            const int32_t *__restrict__ ci = op.ci;
             if constexpr (MAXABS) {
+                const MV *__restrict__ va = op_vals<MV>(op);
+                const int32_t *__restrict__ ci = op.ci;
                 const double rf = rowfac[row];
                 for (int64_t p = b + lane; p < e; p += L) {
                     const double cf = ld(g0, ci[p]);
@@ -120,32 +145,38 @@ struct RowSweep {
                     acc[0] = fmax(acc[0], fabs(t));
                 }
             } else {
-                // U-deep unroll with clamped addresses: every lane issues U
-                // column and U value loads, then U independent gathers, with
-                // no branches (a slot past the row end reloads the lane's
-                // first entry, which is in range, and contributes zero)
-                constexpr int U = (L >= WG) ? 8 : 4;
-                for (int64_t p0 = b + lane; p0 < e; p0 += U * L) {
-                    int32_t c[U];
+                // Entries are addressed relative to the workgroup's first entry
+                // (a uniform base) with 32-bit offsets.  U-deep unroll with
+                // clamped offsets: every lane issues U column and U value
+                // loads, then U independent gathers, with no branches (a slot
+                // past the row end reloads the lane's first entry, which is in
+                // range, and contributes zero).
+                constexpr int U = 4;
+                const int64_t base = op.rp[ps.blk_row0];
+                const int32_t *__restrict__ cib = op.ci + base;
+                const MV *__restrict__ vab = op_vals<MV>(op) + base;
+                const uint32_t ob = (uint32_t)(b - base), oe = (uint32_t)(e - base);
+                for (uint32_t p0 = ob + lane; p0 < oe; p0 += U * L) {
+                    uint32_t c[U];
                     MV raw[U];
 #pragma unroll
                     for (int k = 0; k < U; ++k) {
-                        const int64_t p = p0 + (int64_t)k * L;
-                        const int64_t q = p < e ? p : p0;
-                        c[k] = ci[q];
-                        raw[k] = va[q];
+                        const uint32_t p = p0 + (uint32_t)(k * L);
+                        const uint32_t q = p < oe ? p : p0;
+                        c[k] = (uint32_t)ldo(cib, q);
+                        raw[k] = ldo(vab, q);
                     }
                     double a[U];
 #pragma unroll
-                    for (int k = 0; k < U; ++k) a[k] = (p0 + (int64_t)k * L < e) ? (double)raw[k] : 0.0;
+                    for (int k = 0; k < U; ++k) a[k] = (p0 + (uint32_t)(k * L) < oe) ? (double)raw[k] : 0.0;
                     double g[U];
 #pragma unroll
-                    for (int k = 0; k < U; ++k) g[k] = ld(g0, c[k]);
+                    for (int k = 0; k < U; ++k) g[k] = (double)ldo(g0, c[k]);
 #pragma unroll
                     for (int k = 0; k < U; ++k) acc[0] += a[k] * g[k];
                     if constexpr (NR > 1) {
 #pragma unroll
-                        for (int k = 0; k < U; ++k) g[k] = ld(g1, c[k]);
+                        for (int k = 0; k < U; ++k) g[k] = (double)ldo(g1, c[k]);
 #pragma unroll
                         for (int k = 0; k < U; ++k) acc[1] += a[k] * g[k];
                     }
