@@ -121,6 +121,10 @@ typedef struct {
      * 4, 8, 16, 32, 64, 128, 512, inf. */
     int32_t bin_len_dual[8];   /* rows of K   (dual sweep)                        */
     int32_t bin_len_primal[8]; /* rows of K^T (primal sweep)                      */
+    /* Rows handled by one lane group in bins 0..4 (1, 2 or 4; 0 means 1): the
+     * group interleaves the loads of its rows. */
+    int32_t bin_rows_dual[8];
+    int32_t bin_rows_primal[8];
     int32_t max_grid;          /* workgroups per solve-time sweep launch (0: 8192);  */
                                /* a launch walks the row blocks of the instances   */
                                /* still running                                    */

@@ -50,7 +50,8 @@ class Opts(C.Structure):
                 ("beta_nec", C.c_double), ("beta_art", C.c_double), ("eps_zero", C.c_double),
                 ("unroll_capacity", C.c_int32), ("unroll_checkpoint", C.c_int32),
                 ("use_graph", C.c_int32), ("xcd_remap", C.c_int32), ("bin_len_dual", C.c_int32 * 8),
-                ("bin_len_primal", C.c_int32 * 8), ("max_grid", C.c_int32)]
+                ("bin_len_primal", C.c_int32 * 8), ("bin_rows_dual", C.c_int32 * 8),
+                ("bin_rows_primal", C.c_int32 * 8), ("max_grid", C.c_int32)]
 
 
 class KKTOut(C.Structure):
@@ -141,7 +142,7 @@ def default_opts(**kw) -> Opts:
     for k, v in kw.items():
         if k == "precision" and isinstance(v, str):
             v = {"f32": PREC_F32, "f64": PREC_F64}[v]
-        if k in ("bin_len_dual", "bin_len_primal"):
+        if k in ("bin_len_dual", "bin_len_primal", "bin_rows_dual", "bin_rows_primal"):
             setattr(o, k, (C.c_int32 * 8)(*v))
             continue
         if not hasattr(o, k):

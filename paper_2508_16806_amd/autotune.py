@@ -1,6 +1,7 @@
 """Autotuner for the row-length bins of the two fused sweeps.
 
-The launch shape is tuned after the bins: XCD-contiguous workgroup
+After the bins it tunes the rows handled by one lane group (1, 2 or 4 in
+the bins of at most 16 lanes) and the launch shape: XCD-contiguous workgroup
 numbering on or off and the cap on workgroups per sweep launch.
 
 A bin sweeps each row with a fixed number of lanes (1, 2, 4, ..., 64 lanes of
@@ -30,7 +31,7 @@ def limits(f: int, w: int):
     return lim
 
 
-def autotune(lp, precision: str = "f32", factors=(1, 2, 4, 8), wg_thresholds=(256, 512, 2048),
+def autotune(lp, precision: str = "f32", factors=(2, 4, 8, 16), wg_thresholds=(512, 2048),
              grid_caps=(4096, 8192, 16384, 65536), reps: int = 20, verbose: bool = True) -> dict:
     import paper_2508_16806_amd as pd
 
@@ -50,12 +51,27 @@ def autotune(lp, precision: str = "f32", factors=(1, 2, 4, 8), wg_thresholds=(25
             s.close()
     bp = min(trials, key=lambda r: r["ms_primal"])
     bd = min(trials, key=lambda r: r["ms_dual"])
+    # rows per lane group in the bins of at most 16 lanes
+    rtrials = []
+    for rows in (1, 2, 4):
+        rr = [rows] * 5 + [1, 1, 1]
+        s = pd.Solver(lp, precision=precision, bin_len_dual=bd["limits"], bin_len_primal=bp["limits"],
+                      bin_rows_dual=rr, bin_rows_primal=rr)
+        s.time_kernels(reps=3)
+        t = s.time_kernels(reps=reps)
+        rtrials.append({"rows": rr, "ms_primal": t["ms_primal"], "ms_dual": t["ms_dual"]})
+        if verbose:
+            print(f"[autotune] rows/group={rows}: primal {t['ms_primal']*1e3:.1f} us, dual "
+                  f"{t['ms_dual']*1e3:.1f} us", file=sys.stderr, flush=True)
+        s.close()
+    rp_ = min(rtrials, key=lambda r: r["ms_primal"])["rows"]
+    rd_ = min(rtrials, key=lambda r: r["ms_dual"])["rows"]
     # launch shape: XCD-contiguous numbering on/off, sweep grid cap
     shapes = []
     for remap in (0, 1):
         for grid in grid_caps:
             s = pd.Solver(lp, precision=precision, bin_len_dual=bd["limits"], bin_len_primal=bp["limits"],
-                          xcd_remap=remap, max_grid=grid)
+                          bin_rows_dual=rd_, bin_rows_primal=rp_, xcd_remap=remap, max_grid=grid)
             s.time_kernels(reps=3)
             t = s.time_kernels(reps=reps)
             tot = t["ms_primal"] + t["ms_dual"] + t["ms_check"] / 64.0
@@ -68,6 +84,7 @@ def autotune(lp, precision: str = "f32", factors=(1, 2, 4, 8), wg_thresholds=(25
     bs = min(shapes, key=lambda r: r["ms_iter"])
     return {"n": int(lp.n), "m": int(lp.m), "nnz": int(lp.nnz), "precision": precision,
             "bin_len_primal": bp["limits"], "bin_len_dual": bd["limits"],
+            "bin_rows_primal": rp_, "bin_rows_dual": rd_, "rows_trials": rtrials,
             "xcd_remap": bs["xcd_remap"], "max_grid": bs["max_grid"],
             "ms_primal": bs["ms_primal"], "ms_dual": bs["ms_dual"], "trials": trials, "shapes": shapes,
             "time": time.strftime("%Y-%m-%d %H:%M:%S")}
@@ -77,7 +94,7 @@ def load(path: str) -> dict:
     with open(path) as f:
         t = json.load(f)
     out = {"bin_len_primal": t["bin_len_primal"], "bin_len_dual": t["bin_len_dual"]}
-    for k in ("xcd_remap", "max_grid"):
+    for k in ("xcd_remap", "max_grid", "bin_rows_primal", "bin_rows_dual"):
         if k in t:
             out[k] = t[k]
     return out
@@ -101,8 +118,8 @@ def main():
     res["workload"] = args.workload
     with open(args.out, "w") as f:
         json.dump(res, f, indent=1)
-    print(json.dumps({k: res[k] for k in ("bin_len_primal", "bin_len_dual", "xcd_remap", "max_grid",
-                                          "ms_primal", "ms_dual")}))
+    print(json.dumps({k: res[k] for k in ("bin_len_primal", "bin_len_dual", "bin_rows_primal", "bin_rows_dual",
+                                          "xcd_remap", "max_grid", "ms_primal", "ms_dual")}))
 
 
 if __name__ == "__main__":

@@ -177,10 +177,12 @@ struct InstPlan {
 
 struct Bins {
     int32_t max_len[NBIN];
-    int32_t lanes_log2[NBIN];
+    int32_t code[NBIN];  // lanes_log2 | rows_log2 << 4
 };
 
-static Bins make_bins(const int32_t *lim)
+// lim: row-length limits; rows: rows per lane group (1, 2, 4; only for bins
+// of at most 16 lanes)
+static Bins make_bins(const int32_t *lim, const int32_t *rows)
 {
     static const int32_t def_len[NBIN] = {4, 8, 16, 32, 64, 128, 512, INT32_MAX};
     static const int32_t lanes[NBIN] = {0, 1, 2, 3, 4, 5, 6, 8};
@@ -188,7 +190,9 @@ static Bins make_bins(const int32_t *lim)
     for (int k = 0; k < NBIN; ++k) {
         b.max_len[k] = (lim && lim[k] > 0) ? lim[k] : def_len[k];
         if (k > 0 && b.max_len[k] < b.max_len[k - 1]) b.max_len[k] = b.max_len[k - 1];
-        b.lanes_log2[k] = lanes[k];
+        int rl = 0;
+        if (rows && k <= 4) rl = rows[k] >= 4 ? 2 : (rows[k] >= 2 ? 1 : 0);
+        b.code[k] = lanes[k] | (rl << 4);
     }
     b.max_len[NBIN - 1] = INT32_MAX;
     return b;
@@ -201,7 +205,12 @@ static int bin_of(const Bins &b, int64_t len)
     return NBIN - 1;
 }
 
-static int seg_group(int lanes_log2) { return lanes_log2 >= 8 ? 1 : (WG >> lanes_log2); }
+// rows per logical block of a segment with this lanes / rows code
+static int seg_group(int code)
+{
+    const int lanes_log2 = code & 15, rows_log2 = (code >> 4) & 3;
+    return (lanes_log2 >= 8 ? 1 : (WG >> lanes_log2)) << rows_log2;
+}
 
 static void plan_instance(const HostLP &h, const Bins &bins, const Bins &tbins, InstPlan &p)
 {
@@ -222,7 +231,7 @@ static void plan_instance(const HostLP &h, const Bins &bins, const Bins &tbins, 
         for (int b = 0; b < NBIN; ++b) {
             auto &v = buck[g * NBIN + b];
             if (v.empty()) continue;
-            p.segK.push_back({(int64_t)p.row_order.size(), (int32_t)v.size(), bins.lanes_log2[b], g == 0});
+            p.segK.push_back({(int64_t)p.row_order.size(), (int32_t)v.size(), bins.code[b], g == 0});
             p.row_order.insert(p.row_order.end(), v.begin(), v.end());
         }
     // columns: ordered by bin of their entry count, stable
@@ -235,7 +244,7 @@ static void plan_instance(const HostLP &h, const Bins &bins, const Bins &tbins, 
     p.segT.clear();
     for (int b = 0; b < NBIN; ++b) {
         if (cb[b].empty()) continue;
-        p.segT.push_back({(int64_t)p.col_order.size(), (int32_t)cb[b].size(), tbins.lanes_log2[b], 0});
+        p.segT.push_back({(int64_t)p.col_order.size(), (int32_t)cb[b].size(), tbins.code[b], 0});
         p.col_order.insert(p.col_order.end(), cb[b].begin(), cb[b].end());
     }
 }
@@ -404,7 +413,8 @@ static int plan_all(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, std::v
     if (rc) return rc;
     hosts.resize(batch);
     plans.resize(batch);
-    const Bins bins = make_bins(o->bin_len_dual), tbins = make_bins(o->bin_len_primal);
+    const Bins bins = make_bins(o->bin_len_dual, o->bin_rows_dual);
+    const Bins tbins = make_bins(o->bin_len_primal, o->bin_rows_primal);
     sz = Sizes{};
     sz.batch = batch;
     for (int b = 0; b < batch; ++b) {
@@ -539,7 +549,8 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
         auto by_lanes = [](const std::vector<SegH> &v) {
             std::vector<int> o(v.size());
             for (size_t k = 0; k < v.size(); ++k) o[k] = (int)k;
-            std::stable_sort(o.begin(), o.end(), [&](int a, int b) { return v[a].lanes_log2 > v[b].lanes_log2; });
+            std::stable_sort(o.begin(), o.end(),
+                             [&](int a, int b) { return (v[a].lanes_log2 & 15) > (v[b].lanes_log2 & 15); });
             return o;
         };
         in.blkK0 = blkK;
@@ -768,10 +779,15 @@ extern "C" int pdhg_setup(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, 
     d.nl2 = (int32_t)h->sz.nl2;
     d.grid_cap = o->max_grid > 0 ? o->max_grid : 8192;
     Buffers &b = h->buf;
+    int rmK = 1, rmT = 1;
+    for (const InstPlan &p : h->plan) {
+        for (const SegH &sg : p.segK) rmK = std::max(rmK, 1 << ((sg.lanes_log2 >> 4) & 3));
+        for (const SegH &sg : p.segT) rmT = std::max(rmT, 1 << ((sg.lanes_log2 >> 4) & 3));
+    }
     d.K = OpDev{h->sz.M, b.Krp, b.Kci, b.Kv32, b.Kv64, b.Kseg, b.Kbs, b.Kbd, (int32_t)h->sz.nsegK,
-                (int32_t)h->sz.nblkK};
+                (int32_t)h->sz.nblkK, rmK};
     d.Kt = OpDev{h->sz.N, b.Ktrp, b.Ktci, b.Ktv32, b.Ktv64, b.Ktseg, b.Ktbs, b.Ktbd, (int32_t)h->sz.nsegT,
-                 (int32_t)h->sz.nblkT};
+                 (int32_t)h->sz.nblkT, rmT};
     if (hipHostMalloc((void **)&h->hdone_host, sizeof(int32_t) * batch, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
         delete h;
         return fail(PDHG_ERR_HIP, "hipHostMalloc failed");

@@ -32,7 +32,7 @@ namespace pdhg {
 
 // MASK: also record the clip region of x (0 interior, 1 at l, 2 at u) for the
 // adjoint replay.
-template <typename T, int AVG, int MASK>
+template <typename T, int AVG, int MASK, int RM>
 __global__ __launch_bounds__(WG) void k_primal(Dev d, int j_in_chunk, uint8_t *__restrict__ mask)
 {
     __shared__ double red[8];
@@ -53,35 +53,46 @@ __global__ __launch_bounds__(WG) void k_primal(Dev d, int j_in_chunk, uint8_t *_
         const double tau = st->tau;
         const double w = AVG ? 1.0 / (double)(st->t_inner + j_in_chunk + 1) : 0.0;
         const int bi = lb - s.blk0;
-        dispatch_lanes(s.lanes_log2, [&](auto tag) {
-            constexpr int L = decltype(tag)::value;
-            using RS = RowSweep<L, 1, T, T>;
+        dispatch_lanes<RM>(s.lanes_log2, [&](auto tag, auto rtag) {
+            constexpr int L = decltype(tag)::value, R = decltype(rtag)::value;
+            using RS = RowSweep<L, 1, T, T, R>;
             const typename RS::Pos ps = RS::locate(s, bi);
-            const int64_t j = ps.row;
-            // the update's operands are loaded before the dot product so their
-            // latency overlaps the streaming of the row
-            // (unconditional loads from a clamped row: no branch forces a wait)
-            const int64_t jj = ps.valid ? j : s.row0;
-            const T r_x = x[jj], r_c = c[jj], r_l = l[jj], r_u = u[jj];
-            const T r_a = AVG ? xa[jj] : T(0);
-            double acc[1];
+            // the update's operands are loaded before the dot products so their
+            // latency overlaps the streaming of the rows (unconditional loads
+            // from clamped rows: no branch forces a wait)
+            T r_x[R], r_c[R], r_l[R], r_u[R], r_a[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t jj = r < ps.nvalid ? ps.row0 + r : ps.blk_row0;
+                r_x[r] = x[jj];
+                r_c[r] = c[jj];
+                r_l[r] = l[jj];
+                r_u[r] = u[jj];
+                r_a[r] = AVG ? xa[jj] : T(0);
+            }
+            double acc[R][1];
             RS::dot(op, ps, y, nullptr, nullptr, red, acc);
             if (ps.leader) {
-                const double xo = (double)r_x, cj = (double)r_c, lo = (double)r_l, hi = (double)r_u;
-                const double xav = (double)r_a;
-                const double v = xo - tau * (cj - acc[0]);
-                const double xn = v < lo ? lo : (v > hi ? hi : v);
-                const T xnT = (T)xn;
-                x[j] = xnT;
-                xb[j] = (T)(2.0 * (double)xnT - xo);
-                if (AVG) xa[j] = (T)(xav + ((double)xnT - xav) * w);
-                if (MASK) mask[j] = (uint8_t)(v <= lo ? 1 : (v >= hi ? 2 : 0));
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (r >= ps.nvalid) break;
+                    const int64_t j = ps.row0 + r;
+                    const double xo = (double)r_x[r], cj = (double)r_c[r], lo = (double)r_l[r];
+                    const double hi = (double)r_u[r], xav = (double)r_a[r];
+                    const double v = xo - tau * (cj - acc[r][0]);
+                    const double xn = v < lo ? lo : (v > hi ? hi : v);
+                    const T xnT = (T)xn;
+                    x[j] = xnT;
+                    xb[j] = (T)(2.0 * (double)xnT - xo);
+                    if (AVG) xa[j] = (T)(xav + ((double)xnT - xav) * w);
+                    if (MASK) mask[j] = (uint8_t)(v <= lo ? 1 : (v >= hi ? 2 : 0));
+                }
             }
         });
     });
 }
 
-template <typename T, int AVG, int MASK>
+template <typename T, int AVG, int MASK, int RM>
 __global__ __launch_bounds__(WG) void k_dual(Dev d, int j_in_chunk, uint8_t *__restrict__ mask)
 {
     __shared__ double red[8];
@@ -100,24 +111,33 @@ __global__ __launch_bounds__(WG) void k_dual(Dev d, int j_in_chunk, uint8_t *__r
         const double w = AVG ? 1.0 / (double)(st->t_inner + j_in_chunk + 1) : 0.0;
         const bool ineq = s.ineq != 0;
         const int bi = lb - s.blk0;
-        dispatch_lanes(s.lanes_log2, [&](auto tag) {
-            constexpr int L = decltype(tag)::value;
-            using RS = RowSweep<L, 1, T, T>;
+        dispatch_lanes<RM>(s.lanes_log2, [&](auto tag, auto rtag) {
+            constexpr int L = decltype(tag)::value, R = decltype(rtag)::value;
+            using RS = RowSweep<L, 1, T, T, R>;
             const typename RS::Pos ps = RS::locate(s, bi);
-            const int64_t i = ps.row;
-            const int64_t ii = ps.valid ? i : s.row0;
-            const T r_y = y[ii], r_q = q[ii];
-            const T r_a = AVG ? ya[ii] : T(0);
-            double acc[1];
+            T r_y[R], r_q[R], r_a[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t ii = r < ps.nvalid ? ps.row0 + r : ps.blk_row0;
+                r_y[r] = y[ii];
+                r_q[r] = q[ii];
+                r_a[r] = AVG ? ya[ii] : T(0);
+            }
+            double acc[R][1];
             RS::dot(op, ps, xb, nullptr, nullptr, red, acc);
             if (ps.leader) {
-                const double yo = (double)r_y, qi = (double)r_q, yav = (double)r_a;
-                const double wv = yo + sigma * (qi - acc[0]);
-                const double yn = (ineq && wv < 0.0) ? 0.0 : wv;
-                const T ynT = (T)yn;
-                y[i] = ynT;
-                if (AVG) ya[i] = (T)(yav + ((double)ynT - yav) * w);
-                if (MASK) mask[i] = (uint8_t)((!ineq || wv > 0.0) ? 1 : 0);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (r >= ps.nvalid) break;
+                    const int64_t i = ps.row0 + r;
+                    const double yo = (double)r_y[r], qi = (double)r_q[r], yav = (double)r_a[r];
+                    const double wv = yo + sigma * (qi - acc[r][0]);
+                    const double yn = (ineq && wv < 0.0) ? 0.0 : wv;
+                    const T ynT = (T)yn;
+                    y[i] = ynT;
+                    if (AVG) ya[i] = (T)(yav + ((double)ynT - yav) * w);
+                    if (MASK) mask[i] = (uint8_t)((!ineq || wv > 0.0) ? 1 : 0);
+                }
             }
         });
     });
@@ -144,7 +164,7 @@ __device__ __forceinline__ double proj_lambda(double v, double l, double u)
 }
 
 // use_list: walk the active lists (solve); otherwise every block (caller KKT).
-template <typename V, int NC>
+template <typename V, int NC, int RM>
 __global__ __launch_bounds__(WG) void k_check(Dev d, const V *__restrict__ xa0, const V *__restrict__ xa1,
                                               const V *__restrict__ ya0, const V *__restrict__ ya1,
                                               const V *__restrict__ xs, const V *__restrict__ ys,
@@ -165,12 +185,10 @@ __global__ __launch_bounds__(WG) void k_check(Dev d, const V *__restrict__ xa0, 
         for (int k = 0; k < NC * NSUM; ++k) sum[k] = 0.0;
         const int bi = lb - s.blk0;
         const bool ineq = s.ineq != 0;
-        dispatch_lanes(s.lanes_log2, [&](auto tag) {
-            constexpr int L = decltype(tag)::value;
-            int64_t r;
-            double acc[NC];
+        dispatch_lanes<RM>(s.lanes_log2, [&](auto tag, auto rtag) {
+            constexpr int L = decltype(tag)::value, R = decltype(rtag)::value;
             if (onK) {
-                if (RowSweep<L, NC, double, V>::run(op, s, bi, xa0, xa1, nullptr, red, r, acc)) {
+                sweep_rows<L, NC, double, V, R>(op, s, bi, xa0, xa1, nullptr, red, [&](int64_t r, const double *acc) {
                     const double qi = d.q64[r], rh = d.rho[r];
 #pragma unroll
                     for (int a = 0; a < NC; ++a) {
@@ -184,9 +202,9 @@ __global__ __launch_bounds__(WG) void k_check(Dev d, const V *__restrict__ xa0, 
                         sum[a * NSUM + 2] += qi * ya;
                         sum[a * NSUM + 3] += dy * dy;
                     }
-                }
+                });
             } else {
-                if (RowSweep<L, NC, double, V>::run(op, s, bi, ya0, ya1, nullptr, red, r, acc)) {
+                sweep_rows<L, NC, double, V, R>(op, s, bi, ya0, ya1, nullptr, red, [&](int64_t r, const double *acc) {
                     const double cj = d.c64[r], lj = d.l64[r], uj = d.u64[r], kj = d.kap[r];
 #pragma unroll
                     for (int a = 0; a < NC; ++a) {
@@ -202,7 +220,7 @@ __global__ __launch_bounds__(WG) void k_check(Dev d, const V *__restrict__ xa0, 
                         sum[a * NSUM + 7] += lam > 0.0 ? lj * lam : (lam < 0.0 ? uj * lam : 0.0);
                         sum[a * NSUM + 8] += dx * dx;
                     }
-                }
+                });
             }
         });
         block_sum<NC * NSUM>(sum, red);
@@ -399,10 +417,8 @@ __global__ __launch_bounds__(WG) void k_restart(Dev d)
         const Seg s = block_seg(op, lb);
         const InstState &st = d.st[s.inst];
         if (!st.restart) return;
-        const int L = s.lanes_log2 >= 8 ? WG : (1 << s.lanes_log2);
-        const int G = WG / L;
-        const int64_t r0 = s.row0 + (int64_t)(lb - s.blk0) * G;
-        const int64_t r1 = min(r0 + G, s.row0 + s.nrows);
+        const int64_t r0 = s.row0;  // one logical block = rows [row0, row0 + nrows)
+        const int64_t r1 = s.row0 + s.nrows;
         T *z = (T *)(onT ? d.x : d.y);
         T *za = (T *)(onT ? d.xavg : d.yavg);
         T *z0 = (T *)(onT ? d.x0 : d.y0);
@@ -469,13 +485,10 @@ __global__ __launch_bounds__(WG) void k_rowmax(OpDev op, int remap, const double
     const int lb = logical_block(remap);
     const Seg s = block_seg(op, lb);
     const int bi = lb - s.blk0;
-    dispatch_lanes(s.lanes_log2, [&](auto tag) {
-        constexpr int L = decltype(tag)::value;
-        int64_t r;
-        double acc[1];
-        if (RowSweep<L, 1, double, double, true, ROW_FIRST>::run(op, s, bi, colfac, nullptr, rowfac,
-                                                                  red, r, acc))
-            out[r] = acc[0];
+    dispatch_lanes<4>(s.lanes_log2, [&](auto tag, auto rtag) {
+        constexpr int L = decltype(tag)::value, R = decltype(rtag)::value;
+        sweep_rows<L, 1, double, double, R, true, ROW_FIRST>(op, s, bi, colfac, nullptr, rowfac, red,
+                                                              [&](int64_t r, const double *acc) { out[r] = acc[0]; });
     });
 }
 
@@ -536,14 +549,12 @@ __global__ __launch_bounds__(WG) void k_spmv64(OpDev op, int remap, const double
     const Seg s = block_seg(op, lb);
     const int bi = lb - s.blk0;
     double sq[1] = {0.0};
-    dispatch_lanes(s.lanes_log2, [&](auto tag) {
-        constexpr int L = decltype(tag)::value;
-        int64_t r;
-        double acc[1];
-        if (RowSweep<L, 1, double, double>::run(op, s, bi, v, nullptr, nullptr, red, r, acc)) {
+    dispatch_lanes<4>(s.lanes_log2, [&](auto tag, auto rtag) {
+        constexpr int L = decltype(tag)::value, R = decltype(rtag)::value;
+        sweep_rows<L, 1, double, double, R>(op, s, bi, v, nullptr, nullptr, red, [&](int64_t r, const double *acc) {
             out[r] = acc[0];
             sq[0] += acc[0] * acc[0];
-        }
+        });
     });
     block_sum<1>(sq, red);
     if (threadIdx.x == 0 && partials) partials[lb] = sq[0];
@@ -662,14 +673,12 @@ __global__ __launch_bounds__(WG) void k_lambda(Dev d, const double *ys, double *
     const OpDev &op = d.Kt;
     const Seg s = block_seg(op, lb);
     const int bi = lb - s.blk0;
-    dispatch_lanes(s.lanes_log2, [&](auto tag) {
-        constexpr int L = decltype(tag)::value;
-        int64_t j;
-        double acc[1];
-        if (RowSweep<L, 1, double, double>::run(op, s, bi, ys, nullptr, nullptr, red, j, acc)) {
+    dispatch_lanes<4>(s.lanes_log2, [&](auto tag, auto rtag) {
+        constexpr int L = decltype(tag)::value, R = decltype(rtag)::value;
+        sweep_rows<L, 1, double, double, R>(op, s, bi, ys, nullptr, nullptr, red, [&](int64_t j, const double *acc) {
             const double dd = d.c64[j] - acc[0];
             lam_s[j] = proj_lambda(dd, d.l64[j], d.u64[j]) / d.kap[j];
-        }
+        });
     });
 }
 
@@ -775,7 +784,7 @@ __global__ void k_adj_w(Dev d, AdjBufs a, const uint8_t *__restrict__ mask_y)
     a.aq[i] += sigma * w;
 }
 
-template <typename T>
+template <typename T, int RM>
 __global__ __launch_bounds__(WG) void k_rev_primal(Dev d, AdjBufs a, const uint8_t *__restrict__ mask_x)
 {
     __shared__ double red[8];
@@ -785,11 +794,9 @@ __global__ __launch_bounds__(WG) void k_rev_primal(Dev d, AdjBufs a, const uint8
     const InstState *st = d.st + s.inst;
     const double tau = st->tau, sigma = st->sigma;
     const int bi = lb - s.blk0;
-    dispatch_lanes(s.lanes_log2, [&](auto tag) {
-        constexpr int L = decltype(tag)::value;
-        int64_t j;
-        double acc[1];
-        if (RowSweep<L, 1, T, double>::run(op, s, bi, a.aw, nullptr, nullptr, red, j, acc)) {
+    dispatch_lanes<RM>(s.lanes_log2, [&](auto tag, auto rtag) {
+        constexpr int L = decltype(tag)::value, R = decltype(rtag)::value;
+        sweep_rows<L, 1, T, double, R>(op, s, bi, a.aw, nullptr, nullptr, red, [&](int64_t j, const double *acc) {
             const double axb = -sigma * acc[0];
             const double g = a.ax[j] + 2.0 * axb;
             const uint8_t code = mask_x[j];
@@ -803,11 +810,11 @@ __global__ __launch_bounds__(WG) void k_rev_primal(Dev d, AdjBufs a, const uint8
             a.av[j] = av;
             a.ac[j] -= tau * av;
             a.ax[j] = av - axb;
-        }
+        });
     });
 }
 
-template <typename T>
+template <typename T, int RM>
 __global__ __launch_bounds__(WG) void k_rev_dual(Dev d, AdjBufs a)
 {
     __shared__ double red[8];
@@ -816,12 +823,10 @@ __global__ __launch_bounds__(WG) void k_rev_dual(Dev d, AdjBufs a)
     const Seg s = block_seg(op, lb);
     const double tau = d.st[s.inst].tau;
     const int bi = lb - s.blk0;
-    dispatch_lanes(s.lanes_log2, [&](auto tag) {
-        constexpr int L = decltype(tag)::value;
-        int64_t i;
-        double acc[1];
-        if (RowSweep<L, 1, T, double>::run(op, s, bi, a.av, nullptr, nullptr, red, i, acc))
-            a.ay[i] = a.aw[i] + tau * acc[0];
+    dispatch_lanes<RM>(s.lanes_log2, [&](auto tag, auto rtag) {
+        constexpr int L = decltype(tag)::value, R = decltype(rtag)::value;
+        sweep_rows<L, 1, T, double, R>(op, s, bi, a.av, nullptr, nullptr, red,
+                                       [&](int64_t i, const double *acc) { a.ay[i] = a.aw[i] + tau * acc[0]; });
     });
 }
 
@@ -882,30 +887,49 @@ static inline unsigned sweep_grid(const Dev &d, int64_t nitems)
     return (unsigned)(g > 0 ? g : 0);
 }
 
+// kernel variant for the largest rows-per-group of the operator(s)
+#define RM_SWITCH(rmax, BODY)                 \
+    do {                                      \
+        if ((rmax) >= 4) {                    \
+            constexpr int RMV = 4;            \
+            BODY;                             \
+        } else if ((rmax) >= 2) {             \
+            constexpr int RMV = 2;            \
+            BODY;                             \
+        } else {                              \
+            constexpr int RMV = 1;            \
+            BODY;                             \
+        }                                     \
+    } while (0)
+
 template <typename T>
 void launch_primal(const Dev &d, int j, int avg, uint8_t *mask, hipStream_t s)
 {
     const unsigned g = sweep_grid(d, d.Kt.nblk);
-    if (mask) {
-        LAUNCH((k_primal<T, 0, 1>), g, d, j, mask);
-    } else if (avg) {
-        LAUNCH((k_primal<T, 1, 0>), g, d, j, mask);
-    } else {
-        LAUNCH((k_primal<T, 0, 0>), g, d, j, mask);
-    }
+    RM_SWITCH(d.Kt.rmax, {
+        if (mask) {
+            LAUNCH((k_primal<T, 0, 1, RMV>), g, d, j, mask);
+        } else if (avg) {
+            LAUNCH((k_primal<T, 1, 0, RMV>), g, d, j, mask);
+        } else {
+            LAUNCH((k_primal<T, 0, 0, RMV>), g, d, j, mask);
+        }
+    });
 }
 
 template <typename T>
 void launch_dual(const Dev &d, int j, int avg, uint8_t *mask, hipStream_t s)
 {
     const unsigned g = sweep_grid(d, d.K.nblk);
-    if (mask) {
-        LAUNCH((k_dual<T, 0, 1>), g, d, j, mask);
-    } else if (avg) {
-        LAUNCH((k_dual<T, 1, 0>), g, d, j, mask);
-    } else {
-        LAUNCH((k_dual<T, 0, 0>), g, d, j, mask);
-    }
+    RM_SWITCH(d.K.rmax, {
+        if (mask) {
+            LAUNCH((k_dual<T, 0, 1, RMV>), g, d, j, mask);
+        } else if (avg) {
+            LAUNCH((k_dual<T, 1, 0, RMV>), g, d, j, mask);
+        } else {
+            LAUNCH((k_dual<T, 0, 0, RMV>), g, d, j, mask);
+        }
+    });
 }
 
 template <typename T>
@@ -914,17 +938,21 @@ void launch_check(const Dev &d, int avg, hipStream_t s)
     const unsigned g = sweep_grid(d, d.K.nblk + d.Kt.nblk);
     const T *x = (const T *)d.x, *xa = (const T *)d.xavg, *x0 = (const T *)d.x0;
     const T *y = (const T *)d.y, *ya = (const T *)d.yavg, *y0 = (const T *)d.y0;
-    if (avg) {
-        LAUNCH((k_check<T, 2>), g, d, x, xa, y, ya, x0, y0, 1);
-    } else {
-        LAUNCH((k_check<T, 1>), g, d, x, x, y, y, x0, y0, 1);
-    }
+    const int rm = d.K.rmax > d.Kt.rmax ? d.K.rmax : d.Kt.rmax;
+    RM_SWITCH(rm, {
+        if (avg) {
+            LAUNCH((k_check<T, 2, RMV>), g, d, x, xa, y, ya, x0, y0, 1);
+        } else {
+            LAUNCH((k_check<T, 1, RMV>), g, d, x, x, y, y, x0, y0, 1);
+        }
+    });
 }
 
 void launch_check64(const Dev &d, const double *xs, const double *ys, hipStream_t s)
 {
     const unsigned g = sweep_grid(d, d.K.nblk + d.Kt.nblk);
-    LAUNCH((k_check<double, 1>), g, d, xs, xs, ys, ys, xs, ys, 0);
+    const int rm = d.K.rmax > d.Kt.rmax ? d.K.rmax : d.Kt.rmax;
+    RM_SWITCH(rm, { LAUNCH((k_check<double, 1, RMV>), g, d, xs, xs, ys, ys, xs, ys, 0); });
 }
 
 void launch_active(const Dev &d, hipStream_t s)
@@ -1073,13 +1101,13 @@ void launch_adj_w(const Dev &d, const AdjBufs &a, const uint8_t *mask_y, hipStre
 template <typename T>
 void launch_rev_primal(const Dev &d, const AdjBufs &a, const uint8_t *mask_x, hipStream_t s)
 {
-    LAUNCH(k_rev_primal<T>, (unsigned)d.Kt.nblk, d, a, mask_x);
+    RM_SWITCH(d.Kt.rmax, { LAUNCH((k_rev_primal<T, RMV>), (unsigned)d.Kt.nblk, d, a, mask_x); });
 }
 
 template <typename T>
 void launch_rev_dual(const Dev &d, const AdjBufs &a, hipStream_t s)
 {
-    LAUNCH(k_rev_dual<T>, (unsigned)d.K.nblk, d, a);
+    RM_SWITCH(d.K.rmax, { LAUNCH((k_rev_dual<T, RMV>), (unsigned)d.K.nblk, d, a); });
 }
 
 void launch_adj_out(const Dev &d, const AdjBufs &a, double *gc, double *gq, double *gl, double *gu,

@@ -52,6 +52,7 @@ struct OpDev {
     const int4 *bdesc;   // per logical block: {first row, rows, instance, lanes_log2 | ineq << 8}
     int32_t nseg;
     int32_t nblk;
+    int32_t rmax;        // largest rows per lane group in any block (1, 2, 4)
 };
 
 // Immutable per-instance facts.

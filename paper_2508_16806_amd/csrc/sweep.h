@@ -58,7 +58,7 @@ __device__ __forceinline__ Seg block_seg(const OpDev &op, int lb)
     s.blk0 = lb;
     s.nblk = 1;
     s.inst = v.z;
-    s.lanes_log2 = v.w & 0xff;
+    s.lanes_log2 = v.w & 0xff;  // lanes (bits 0-3) and rows per group (bits 4-5)
     s.ineq = v.w >> 8;
     return s;
 }
@@ -94,19 +94,22 @@ __device__ __forceinline__ double group_reduce(double v)
 }
 
 // Per-row dot products of one workgroup's rows.  NR gathered vectors (1 or 2).
-// MAXABS: instead of a dot product, max over the row of |(a * v) * b| where
-// the products use the factor vectors (Ruiz pass).
-template <int L, int NR, typename MV, typename GV, bool MAXABS = false, bool FAC_ROW_FIRST = true>
+// A group of L lanes handles R consecutive rows (R = 1 for whole-workgroup
+// rows); their loads are interleaved so one chain of memory latencies moves
+// R rows.  MAXABS: instead of a dot product, the max over the row of
+// |(a * v) * b| with the factor vectors (Ruiz pass).
+template <int L, int NR, typename MV, typename GV, int R = 1, bool MAXABS = false, bool FAC_ROW_FIRST = true>
 struct RowSweep {
     static constexpr int G = (L >= WG) ? 1 : WG / L;
+    static constexpr int U = (L >= WG) ? 4 : (R >= 4 ? 1 : (R == 2 ? 2 : 4));
 
-    // Position of this lane: the row its group handles, whether that row
-    // exists, and whether this lane leads the group (receives the dot product).
+    // Position of this lane: the first of its group's R rows, how many of them
+    // exist, and whether this lane leads the group (receives the products).
     struct Pos {
-        int64_t row;
+        int64_t row0;
         int64_t blk_row0;  // first row of the workgroup (uniform)
         int lane;
-        bool valid;
+        int nvalid;
         bool leader;
     };
 
@@ -115,70 +118,100 @@ struct RowSweep {
         const int tid = threadIdx.x;
         const int grp = (L >= WG) ? 0 : tid / L;
         const int lane = (L >= WG) ? tid : (tid & (L - 1));
-        const int64_t rloc = (int64_t)bi * G + grp;
-        const bool valid = rloc < s.nrows;
-        return {s.row0 + rloc, s.row0 + (int64_t)bi * G, lane, valid, valid && lane == 0};
+        const int64_t first = (int64_t)bi * G * R;
+        const int64_t rloc = first + (int64_t)grp * R;
+        int64_t nv = s.nrows - rloc;
+        nv = nv < 0 ? 0 : (nv > R ? R : nv);
+        return {s.row0 + rloc, s.row0 + first, lane, (int)nv, nv > 0 && lane == 0};
     }
 
-    // Dot product(s) of the row at p with the gathered vector(s); the result
-    // is valid in the leader lane.  Every lane of the workgroup must call it.
+    // Dot products of the group's rows with the gathered vector(s); valid in
+    // the leader lane.  Every lane of the workgroup must call it.
     __device__ __forceinline__ static void dot(const OpDev &op, const Pos &ps,
                                                const GV *__restrict__ g0, const GV *__restrict__ g1,
                                                const double *__restrict__ rowfac, double *red_lds,
-                                               double (&acc)[NR])
+                                               double (&acc)[R][NR])
     {
         const int tid = threadIdx.x;
         const int lane = ps.lane;
-        const int64_t row = ps.row;
 #pragma unroll
-        for (int k = 0; k < NR; ++k) acc[k] = 0.0;
-        if (ps.valid) {
-            const int64_t b = op.rp[row], e = op.rp[row + 1];
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int k = 0; k < NR; ++k) acc[r][k] = 0.0;
+        if (ps.nvalid > 0) {
             if constexpr (MAXABS) {
                 const MV *__restrict__ va = op_vals<MV>(op);
                 const int32_t *__restrict__ ci = op.ci;
-                const double rf = rowfac[row];
-                for (int64_t p = b + lane; p < e; p += L) {
-                    const double cf = ld(g0, ci[p]);
-                    const double a = ld(va, p);
-                    const double t = FAC_ROW_FIRST ? (rf * a) * cf : (cf * a) * rf;
-                    acc[0] = fmax(acc[0], fabs(t));
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (r >= ps.nvalid) break;
+                    const int64_t row = ps.row0 + r;
+                    const int64_t b = op.rp[row], e = op.rp[row + 1];
+                    const double rf = rowfac[row];
+                    for (int64_t p = b + lane; p < e; p += L) {
+                        const double cf = ld(g0, ci[p]);
+                        const double a = ld(va, p);
+                        const double t = FAC_ROW_FIRST ? (rf * a) * cf : (cf * a) * rf;
+                        acc[r][0] = fmax(acc[r][0], fabs(t));
+                    }
                 }
             } else {
                 // Entries are addressed relative to the workgroup's first entry
-                // (a uniform base) with 32-bit offsets.  U-deep unroll with
-                // clamped offsets: every lane issues U column and U value
-                // loads, then U independent gathers, with no branches (a slot
-                // past the row end reloads the lane's first entry, which is in
-                // range, and contributes zero).
-                constexpr int U = 4;
+                // (a uniform base) with 32-bit offsets.  Each round issues, per
+                // row, U column and U value loads and then the U independent
+                // gathers, with no branches: a slot past its row's end reloads
+                // the workgroup's first entry (in range: the loop only runs when
+                // the group's rows hold entries) and contributes zero.
                 const int64_t base = op.rp[ps.blk_row0];
                 const int32_t *__restrict__ cib = op.ci + base;
                 const MV *__restrict__ vab = op_vals<MV>(op) + base;
-                const uint32_t ob = (uint32_t)(b - base), oe = (uint32_t)(e - base);
-                for (uint32_t p0 = ob + lane; p0 < oe; p0 += U * L) {
-                    uint32_t c[U];
-                    MV raw[U];
+                uint32_t ob[R], oe[R];
+                uint32_t maxlen = 0;
 #pragma unroll
-                    for (int k = 0; k < U; ++k) {
-                        const uint32_t p = p0 + (uint32_t)(k * L);
-                        const uint32_t q = p < oe ? p : p0;
-                        c[k] = (uint32_t)ldo(cib, q);
-                        raw[k] = ldo(vab, q);
-                    }
-                    double a[U];
+                for (int r = 0; r < R; ++r) {
+                    const int64_t row = ps.row0 + (r < ps.nvalid ? r : ps.nvalid - 1);
+                    const int64_t b = op.rp[row], e = op.rp[row + 1];
+                    ob[r] = (uint32_t)(b - base);
+                    oe[r] = r < ps.nvalid ? (uint32_t)(e - base) : ob[r];
+                    maxlen = max(maxlen, oe[r] - ob[r]);
+                }
+                for (uint32_t off = lane; off < maxlen; off += U * L) {
+                    uint32_t c[R][U];
+                    MV raw[R][U];
 #pragma unroll
-                    for (int k = 0; k < U; ++k) a[k] = (p0 + (uint32_t)(k * L) < oe) ? (double)raw[k] : 0.0;
-                    double g[U];
+                    for (int r = 0; r < R; ++r)
 #pragma unroll
-                    for (int k = 0; k < U; ++k) g[k] = (double)ldo(g0, c[k]);
+                        for (int k = 0; k < U; ++k) {
+                            const uint32_t p = ob[r] + off + (uint32_t)(k * L);
+                            const uint32_t q = p < oe[r] ? p : 0u;
+                            c[r][k] = (uint32_t)ldo(cib, q);
+                            raw[r][k] = ldo(vab, q);
+                        }
+                    double g[R][U];
 #pragma unroll
-                    for (int k = 0; k < U; ++k) acc[0] += a[k] * g[k];
+                    for (int r = 0; r < R; ++r)
+#pragma unroll
+                        for (int k = 0; k < U; ++k) g[r][k] = (double)ldo(g0, c[r][k]);
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+#pragma unroll
+                        for (int k = 0; k < U; ++k) {
+                            const double a = (ob[r] + off + (uint32_t)(k * L) < oe[r]) ? (double)raw[r][k] : 0.0;
+                            acc[r][0] += a * g[r][k];
+                        }
                     if constexpr (NR > 1) {
 #pragma unroll
-                        for (int k = 0; k < U; ++k) g[k] = (double)ldo(g1, c[k]);
+                        for (int r = 0; r < R; ++r)
 #pragma unroll
-                        for (int k = 0; k < U; ++k) acc[1] += a[k] * g[k];
+                            for (int k = 0; k < U; ++k) g[r][k] = (double)ldo(g1, c[r][k]);
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+#pragma unroll
+                            for (int k = 0; k < U; ++k) {
+                                const double a =
+                                    (ob[r] + off + (uint32_t)(k * L) < oe[r]) ? (double)raw[r][k] : 0.0;
+                                acc[r][1] += a * g[r][k];
+                            }
                     }
                 }
             }
@@ -186,61 +219,96 @@ struct RowSweep {
         if constexpr (L >= WG) {
             // wavefront reduce, then the four wavefront totals in LDS, fixed order
 #pragma unroll
-            for (int k = 0; k < NR; ++k) acc[k] = group_reduce<64, MAXABS>(acc[k]);
+            for (int k = 0; k < NR; ++k) acc[0][k] = group_reduce<64, MAXABS>(acc[0][k]);
             const int wave = tid >> 6;
             if ((tid & 63) == 0) {
 #pragma unroll
-                for (int k = 0; k < NR; ++k) red_lds[k * 4 + wave] = acc[k];
+                for (int k = 0; k < NR; ++k) red_lds[k * 4 + wave] = acc[0][k];
             }
             __syncthreads();
             if (tid == 0) {
 #pragma unroll
                 for (int k = 0; k < NR; ++k) {
-                    const double *r = red_lds + k * 4;
-                    acc[k] = MAXABS ? fmax(fmax(r[0], r[1]), fmax(r[2], r[3]))
-                                    : (r[0] + r[1]) + (r[2] + r[3]);
+                    const double *rr = red_lds + k * 4;
+                    acc[0][k] = MAXABS ? fmax(fmax(rr[0], rr[1]), fmax(rr[2], rr[3]))
+                                       : (rr[0] + rr[1]) + (rr[2] + rr[3]);
                 }
             }
             __syncthreads();
         } else {
 #pragma unroll
-            for (int k = 0; k < NR; ++k) acc[k] = group_reduce<L, MAXABS>(acc[k]);
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int k = 0; k < NR; ++k) acc[r][k] = group_reduce<L, MAXABS>(acc[r][k]);
         }
-    }
-
-    // locate + dot; returns whether this lane leads a valid row.
-    __device__ __forceinline__ static bool run(const OpDev &op, const Seg &s, int bi,
-                                               const GV *__restrict__ g0, const GV *__restrict__ g1,
-                                               const double *__restrict__ rowfac,
-                                               double *red_lds, int64_t &row, double (&acc)[NR])
-    {
-        const Pos ps = locate(s, bi);
-        row = ps.row;
-        dot(op, ps, g0, g1, rowfac, red_lds, acc);
-        return ps.leader;
     }
 };
 
-// Dispatch on the segment's lanes-per-row (uniform across the workgroup).
-// F is called as f(std::integral_constant<int, L>{}).
+// locate + dot, then f(row, products) for each of the group's rows, in the
+// leader lane.
+template <int L, int NR, typename MV, typename GV, int R, bool MAXABS = false, bool FRF = true, typename F>
+__device__ __forceinline__ void sweep_rows(const OpDev &op, const Seg &s, int bi, const GV *g0, const GV *g1,
+                                           const double *rowfac, double *red, F &&f)
+{
+    using RS = RowSweep<L, NR, MV, GV, R, MAXABS, FRF>;
+    const typename RS::Pos ps = RS::locate(s, bi);
+    double acc[R][NR];
+    RS::dot(op, ps, g0, g1, rowfac, red, acc);
+    if (ps.leader) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (r < ps.nvalid) f(ps.row0 + r, acc[r]);
+    }
+}
+
+// Dispatch on the block's lanes per row and rows per group (uniform across
+// the workgroup).  f is called as f(LaneTag<L>{}, LaneTag<R>{}).
 template <int L>
 struct LaneTag {
     static constexpr int value = L;
 };
 
-template <typename F>
-__device__ __forceinline__ void dispatch_lanes(int lanes_log2, F &&f)
+// RM: the largest rows-per-group the launch supports (the host picks the
+// kernel variant from the operator's bins, so kernels over R = 1 layouts keep
+// the register footprint of the single-row path).
+template <int RM = 1, typename F>
+__device__ __forceinline__ void dispatch_lanes(int code, F &&f)
 {
+    const int lanes_log2 = code & 15, rows_log2 = (code >> 4) & 3;
     switch (lanes_log2) {
-        case 0: f(LaneTag<1>{}); break;
-        case 1: f(LaneTag<2>{}); break;
-        case 2: f(LaneTag<4>{}); break;
-        case 3: f(LaneTag<8>{}); break;
-        case 4: f(LaneTag<16>{}); break;
-        case 5: f(LaneTag<32>{}); break;
-        case 6: f(LaneTag<64>{}); break;
-        default: f(LaneTag<WG>{}); break;
+#define PDHG_LR(LL, LV)                                                   \
+    case LL:                                                            \
+        if constexpr (RM >= 4) {                                        \
+            if (rows_log2 == 2) {                                       \
+                f(LaneTag<LV>{}, LaneTag<4>{});                         \
+                break;                                                  \
+            }                                                           \
+        }                                                               \
+        if constexpr (RM >= 2) {                                        \
+            if (rows_log2 >= 1) {                                       \
+                f(LaneTag<LV>{}, LaneTag<(RM >= 2 ? 2 : 1)>{});         \
+                break;                                                  \
+            }                                                           \
+        }                                                               \
+        f(LaneTag<LV>{}, LaneTag<1>{});                                 \
+        break;
+        PDHG_LR(0, 1)
+        PDHG_LR(1, 2)
+        PDHG_LR(2, 4)
+        PDHG_LR(3, 8)
+        PDHG_LR(4, 16)
+#undef PDHG_LR
+        case 5: f(LaneTag<32>{}, LaneTag<1>{}); break;
+        case 6: f(LaneTag<64>{}, LaneTag<1>{}); break;
+        default: f(LaneTag<WG>{}, LaneTag<1>{}); break;
     }
+}
+
+// Rows of one logical block of a segment with this lanes / rows code.
+__host__ __device__ __forceinline__ int block_rows(int code)
+{
+    const int lanes_log2 = code & 15, rows_log2 = (code >> 4) & 3;
+    return (lanes_log2 >= 8 ? 1 : (WG >> lanes_log2)) << rows_log2;
 }
 
 // Block-wide sum of NV per-thread values, fixed reduction order; result valid

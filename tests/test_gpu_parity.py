@@ -299,3 +299,60 @@ def test_huge_step_reports_numerical_error(pd):
     s = pd.Solver(lp, precision="f32", step_size=1e4, max_iters=100000, use_restarts=0)
     r = s.solve()[0]
     assert r["status_name"] == "NUMERICAL_ERROR"
+
+
+# ---------------------------------------------------------------------------
+# launch layouts: rows per lane group, bin limits, XCD numbering, grid cap
+# ---------------------------------------------------------------------------
+
+LAYOUTS = [
+    dict(bin_rows_dual=[4] * 5 + [1] * 3, bin_rows_primal=[4] * 5 + [1] * 3),
+    dict(bin_rows_dual=[2] * 5 + [1] * 3, bin_rows_primal=[2] * 5 + [1] * 3, xcd_remap=0, max_grid=64),
+    dict(bin_len_dual=[16, 32, 64, 128, 256, 512, 2048, 0], bin_len_primal=[1, 2, 4, 8, 16, 32, 64, 0],
+         xcd_remap=1, max_grid=100000),
+]
+
+
+@pytest.mark.parametrize("li", range(len(LAYOUTS)))
+@pytest.mark.parametrize("name", ["mixed", "zipf", "sced_small"])
+def test_layouts_fixed_steps_f64(orc, pd, li, name):
+    lp = _cases()[name]
+    o = orc.Oracle(lp)
+    s0 = pd.Solver(lp, precision="f64")
+    eta, omega = 0.9 / s0.info()["knorm"], 1.1
+    s = pd.Solver(lp, precision="f64", step_size=eta, primal_weight=omega, **LAYOUTS[li])
+    rho, kap = o.ruiz(10)
+    s.iterate(50)
+    xs, ys = o.steps(np.clip(np.zeros(lp.n), lp.l / kap, lp.u / kap), np.zeros(lp.m), eta / omega, eta * omega,
+                     50, ruiz_iters=10)
+    x, y = s.solution(which=pd.SOL_CURRENT)
+    xo, yo = np.clip(kap * xs, lp.l, lp.u), rho * ys
+    np.testing.assert_allclose(x, xo, rtol=1e-9, atol=1e-9 * (1 + np.abs(xo).max()))
+    np.testing.assert_allclose(y, yo, rtol=1e-9, atol=1e-9 * (1 + np.abs(yo).max()))
+    # the caller-point KKT uses the same layout
+    g = s.kkt(x, y)
+    c = o.kkt(x, y)
+    assert g["rel_kkt"] == pytest.approx(c["rel_kkt"], rel=1e-9, abs=1e-13)
+
+
+@pytest.mark.parametrize("li", range(len(LAYOUTS)))
+def test_layouts_solve_f32(orc, pd, li):
+    lp = _cases()["zipf"]
+    s = pd.Solver(lp, precision="f32", eps=1e-5, max_iters=200000, **LAYOUTS[li])
+    r = s.solve()[0]
+    x, y = s.solution()
+    chk = orc.Oracle(lp).kkt(x, y)
+    assert chk["rel_kkt"] <= 1e-4, (r["status_name"], chk)
+    assert _rel(chk["pobj"], lp.f_star) <= 1e-5
+
+
+def test_layouts_batched_bitwise(pd):
+    lps = [lpgen.planted(m, int(2.5 * m), 0.02, 60 + i, ge_frac=0.3) for i, m in enumerate([70, 160, 110])]
+    kw = dict(precision="f32", eps=1e-5, **LAYOUTS[0])
+    b = pd.Solver(lps, **kw)
+    rb = b.solve()
+    for i, lp in enumerate(lps):
+        s = pd.Solver(lp, **kw)
+        rs = s.solve()[0]
+        assert rb[i]["iters"] == rs["iters"]
+        np.testing.assert_array_equal(b.solution(inst=i)[0], s.solution()[0])
