@@ -29,6 +29,32 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "time to 1e-4 rel KKT; PDHG iter/s; HBM GB/s vs peak; batched vs 1-by-1 LPs/s"
+KERNEL_SOURCES = ["paper_2508_16806_amd/csrc/kernels.hip", "paper_2508_16806_amd/csrc/sweep.h",
+                  "paper_2508_16806_amd/csrc/pdhg_internal.h"]
+TRAFFIC_FILE = "profiles/c1_sced_hbm_traffic.json"
+
+
+def kernel_src_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when the kernel sources changed since it was taken."""
+    try:
+        with open(os.path.join(ROOT, TRAFFIC_FILE)) as f:
+            t = json.load(f)
+    except OSError:
+        return None
+    if t.get("kernel_src_sha") != kernel_src_hash() or kernel not in t.get("per_launch_bytes", {}):
+        return None
+    return t["per_launch_bytes"][kernel]
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 
 
@@ -307,10 +333,11 @@ def main():
                    "n": lp.n, "m": lp.m, "nnz": lp.nnz, "iters_per_step": CE, "precision": "f32+f64acc",
                    "bins": tune or "default"},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": ach / PEAK_HBM_GBS, "traffic": None, "kernel": f"k_{dom}",
+                     "frac": ach / PEAK_HBM_GBS, "traffic": measured_traffic(f"k_{dom}"), "kernel": f"k_{dom}",
                      "algorithmic_bytes": db if dom == "dual" else pb,
                      "ms_per_launch": kt["ms_dual" if dom == "dual" else "ms_primal"]},
         "kernels_ms": {k: v for k, v in kt.items() if k != "reps"},
+        "kernel_src_sha": kernel_src_hash(),
         "sweep_gbs": {"primal": pg, "dual": dg},
         "time_to_tol": ttt,
         "cpu_baseline": cpu,
