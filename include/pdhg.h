@@ -90,7 +90,7 @@ typedef struct {
 } pdhg_lp;
 
 /* Solver options.  pdhg_default_opts fills the paper's constants:
- * eps = 1e-4 (Section 2.3.2), step = 0.9 / ||K~||_2 (Section 3.2),
+ * eps = 1e-4 (Section 2.3.2), step = 0.9 / ||K~||_2 (Sections 4.1-4.2),
  * restart constants 0.2 / 0.8 / 0.36 (Section 2.4.2), eps_zero = 1e-6
  * (Section 2.4.3), and the choices the paper leaves open: 10 Ruiz passes,
  * a KKT check every 64 iterations, power iteration to a 1e-6 relative change

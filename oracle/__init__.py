@@ -109,7 +109,7 @@ def _f64(a):
 class SolveOpts:
     """Options of the restarted solve; defaults are the paper's constants.
 
-    eps 1e-4 (Section 2.3.2), step 0.9/||K||_2 (Section 3.2), restart
+    eps 1e-4 (Section 2.3.2), step 0.9/||K||_2 (Sections 4.1-4.2), restart
     constants 0.2 / 0.8 / 0.36 (Section 2.4.2), eps_zero 1e-6 (Section 2.4.3).
     Choices the paper leaves open: 10 Ruiz passes, a check every 64 iterations,
     power iteration to 1e-6 relative change or 1000 passes.
