@@ -50,20 +50,22 @@ class Opts(C.Structure):
                 ("check_every", C.c_int), ("max_iters", C.c_longlong), ("eps", C.c_double),
                 ("step_size", C.c_double), ("step_frac", C.c_double), ("primal_weight", C.c_double),
                 ("power_max_iters", C.c_int), ("power_tol", C.c_double), ("beta_suff", C.c_double),
-                ("beta_nec", C.c_double), ("beta_art", C.c_double), ("eps_zero", C.c_double)]
+                ("beta_nec", C.c_double), ("beta_art", C.c_double), ("eps_zero", C.c_double),
+                ("adaptive_step", C.c_int)]
 
 
 class Result(C.Structure):
     _fields_ = [("status", C.c_int), ("from_avg", C.c_int), ("iters", C.c_longlong),
                 ("restarts", C.c_int), ("power_iters", C.c_int), ("knorm", C.c_double),
                 ("eta", C.c_double), ("omega0", C.c_double), ("omega", C.c_double),
-                ("tau", C.c_double), ("sigma", C.c_double), ("kkt", KKT), ("trace_len", C.c_int)]
+                ("tau", C.c_double), ("sigma", C.c_double), ("kkt", KKT), ("trace_len", C.c_int),
+                ("accepted", C.c_longlong), ("eta_next", C.c_double)]
 
 
 class TraceRec(C.Structure):
     _fields_ = [("iter", C.c_longlong), ("restarted", C.c_int), ("cand_avg", C.c_int),
                 ("kkt_cand", C.c_double), ("omega", C.c_double), ("rel_kkt_cur", C.c_double),
-                ("rel_kkt_avg", C.c_double)]
+                ("rel_kkt_avg", C.c_double), ("eta_next", C.c_double), ("accepted", C.c_longlong)]
 
 
 _lib = None
@@ -93,6 +95,9 @@ def _load():
         L.orc_steps.argtypes = [P, C.c_double, C.c_double, D, D, C.c_longlong]
         L.orc_solve.restype = C.c_int
         L.orc_solve.argtypes = [P, C.POINTER(Opts), D, D, C.POINTER(Result), C.c_void_p, C.c_int]
+        L.orc_adaptive_attempt.restype = C.c_int
+        L.orc_adaptive_attempt.argtypes = [P, C.c_double, C.c_double, C.c_longlong, D, D, D, D,
+                                           C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.orc_unrolled.argtypes = [P, D, D, C.c_double, C.c_double, D, D, D, D, D, D,
                                    C.c_longlong, D, D]
         L.orc_unrolled_vjp.argtypes = [P, D, D, C.c_double, C.c_double, D, D, D, D, D, D,
@@ -112,7 +117,9 @@ class SolveOpts:
     eps 1e-4 (Section 2.3.2), step 0.9/||K||_2 (Sections 4.1-4.2), restart
     constants 0.2 / 0.8 / 0.36 (Section 2.4.2), eps_zero 1e-6 (Section 2.4.3).
     Choices the paper leaves open: 10 Ruiz passes, a check every 64 iterations,
-    power iteration to 1e-6 relative change or 1000 passes.
+    power iteration to 1e-6 relative change or 1000 passes.  adaptive_step
+    turns on the backtracking step size of Algorithm 5 (Section 2.4.4); the
+    first attempt tries the fixed step.
     """
 
     ruiz_iters: int = 10
@@ -130,6 +137,7 @@ class SolveOpts:
     beta_nec: float = 0.8
     beta_art: float = 0.36
     eps_zero: float = 1e-6
+    adaptive_step: bool = False
 
     @staticmethod
     def plain(**kw) -> "SolveOpts":
@@ -143,7 +151,7 @@ class SolveOpts:
         return Opts(self.ruiz_iters, int(self.use_restarts), int(self.use_pw_update),
                     self.check_every, self.max_iters, self.eps, self.step_size, self.step_frac,
                     self.primal_weight, self.power_max_iters, self.power_tol, self.beta_suff,
-                    self.beta_nec, self.beta_art, self.eps_zero)
+                    self.beta_nec, self.beta_art, self.eps_zero, int(self.adaptive_step))
 
 
 @dataclass
@@ -161,6 +169,8 @@ class SolveResult:
     kkt: dict
     power_iters: int
     trace: list = field(default_factory=list)
+    accepted: int = 0
+    eta_next: float = 0.0
 
 
 class Oracle:
@@ -255,9 +265,22 @@ class Oracle:
                            trace_cap)
         trace = [dict(iter=t.iter, restarted=t.restarted, cand_avg=t.cand_avg,
                       kkt_cand=t.kkt_cand, omega=t.omega, rel_kkt_cur=t.rel_kkt_cur,
-                      rel_kkt_avg=t.rel_kkt_avg) for t in tr[:r.trace_len]]
+                      rel_kkt_avg=t.rel_kkt_avg, eta_next=t.eta_next, accepted=t.accepted)
+                 for t in tr[:r.trace_len]]
         return SolveResult(r.status, x, self.to_user_rows(y), r.iters, r.restarts, bool(r.from_avg),
-                           r.knorm, r.eta, r.omega0, r.omega, r.kkt.as_dict(), r.power_iters, trace)
+                           r.knorm, r.eta, r.omega0, r.omega, r.kkt.as_dict(), r.power_iters, trace,
+                           r.accepted, r.eta_next)
+
+    def adaptive_attempt(self, x, y, omega, eta, k, ruiz_iters: int = 0):
+        """One attempt of Algorithm 5 on the scaled problem from (x, y) (scaled
+        variables, y in user row order) with step eta, primal weight omega and
+        attempt count k (k >= 1).  Returns (accepted, x', y', etabar, eta')."""
+        s = self.scaled(ruiz_iters)
+        xn, yn = np.empty(self.n), np.empty(self.m)
+        eb, en = C.c_double(0.0), C.c_double(0.0)
+        acc = self.lib.orc_adaptive_attempt(s.h, omega, eta, k, _f64(x), self.to_internal_rows(y), xn, yn,
+                                            C.byref(eb), C.byref(en))
+        return bool(acc), xn, self.to_user_rows(yn), eb.value, en.value
 
     def unrolled(self, ruiz_iters, tau, sigma, c, q, l, u, x0, y0, K):
         """K fixed PDHG steps with inputs and outputs in original variables (q, y user order)."""

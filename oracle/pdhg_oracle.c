@@ -24,6 +24,10 @@
  *   orc_solve .................... pinned (planted f*, HiGHS, vertex enumeration);
  *                                  the restart/primal-weight trace itself is
  *                                  parity unpinned: the paper prints no trace.
+ *   orc_adaptive_attempt ......... pinned (hand-worked 1x1 cases, the bound
+ *                                  etabar >= 1/||K||_2 from Cauchy-Schwarz)
+ *   orc_solve, adaptive steps .... pinned (planted f*, HiGHS); the sequence of
+ *                                  accepted steps is parity unpinned.
  *   orc_unrolled_vjp ............. pinned (central finite differences)
  */
 #include <math.h>
@@ -379,6 +383,65 @@ void orc_steps(const orc_prob *p, double tau, double sigma, double *x, double *y
 }
 
 /* ------------------------------------------------------------------------- */
+/* adaptive step size (Section 2.4.4, Algorithm 5): one attempt              */
+/* ------------------------------------------------------------------------- */
+
+/* One pass of the retry loop of Algorithm 5 from (x, y) with step eta and
+ * primal weight omega: the PDHG candidate
+ *   x' = proj_X(x - (eta/omega)(c - K^T y)),
+ *   y' = proj_Y(y + eta omega (q - K(2x' - x))),
+ * the largest step the candidate certifies
+ *   etabar = (omega ||x'-x||^2 + ||y'-y||^2 / omega) / |2 (y'-y)^T K (x'-x)|
+ * (+inf when the interaction term is 0), and the step to try next
+ *   eta' = min((1 - (k+1)^-0.3) etabar, (1 + (k+1)^-0.6) eta).
+ * k counts the attempts of the solve including this one (k >= 1).  Returns 1
+ * when the candidate is accepted (eta <= etabar).  K(x'-x) is a product with
+ * the difference vector (no cached products). */
+int orc_adaptive_attempt(const orc_prob *p, double omega, double eta, long long k, const double *x,
+                         const double *y, double *xn, double *yn, double *etabar_out,
+                         double *eta_next_out)
+{
+    int64_t n = p->n, m = p->m;
+    double tau = eta / omega, sigma = eta * omega;
+    double *kty = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+    double *dv = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+    double *kv = (double *)malloc((size_t)(m ? m : 1) * sizeof(double));
+    orc_spmv_t(p, y, kty);
+    for (int64_t j = 0; j < n; ++j) {
+        xn[j] = clip(x[j] - tau * (p->c[j] - kty[j]), p->l[j], p->u[j]);
+        dv[j] = 2.0 * xn[j] - x[j];
+    }
+    orc_spmv(p, dv, kv); /* K xbar */
+    for (int64_t i = 0; i < m; ++i) {
+        double v = y[i] + sigma * (p->q[i] - kv[i]);
+        if (i < p->m1 && v < 0.0) v = 0.0;
+        yn[i] = v;
+    }
+    double dx2 = 0.0, dy2 = 0.0, inter = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        dv[j] = xn[j] - x[j];
+        dx2 += dv[j] * dv[j];
+    }
+    orc_spmv(p, dv, kv); /* K (x' - x) */
+    for (int64_t i = 0; i < m; ++i) {
+        double d = yn[i] - y[i];
+        dy2 += d * d;
+        inter += d * kv[i];
+    }
+    double den = fabs(2.0 * inter);
+    double etabar = den > 0.0 ? (omega * dx2 + dy2 / omega) / den : INFINITY;
+    double kk = (double)k + 1.0;
+    double shrink = (1.0 - pow(kk, -0.3)) * etabar;
+    double grow = (1.0 + pow(kk, -0.6)) * eta;
+    *etabar_out = etabar;
+    *eta_next_out = shrink < grow ? shrink : grow;
+    free(kty);
+    free(dv);
+    free(kv);
+    return eta <= etabar;
+}
+
+/* ------------------------------------------------------------------------- */
 /* restarted PDHG solve (Sections 2.3-2.4: Algorithms 1-4, restarts)          */
 /* ------------------------------------------------------------------------- */
 
@@ -396,6 +459,7 @@ typedef struct {
     double power_tol;      /* power-iteration relative change tolerance        */
     double beta_suff, beta_nec, beta_art; /* restart constants 0.2 0.8 0.36   */
     double eps_zero;       /* 1e-6                                             */
+    int adaptive_step;     /* backtracking step size, Algorithm 5              */
 } orc_opts;
 
 typedef struct {
@@ -407,6 +471,8 @@ typedef struct {
     double knorm, eta, omega0, omega, tau, sigma;
     orc_kkt_t kkt;         /* relative KKT of the returned point, original LP  */
     int trace_len;
+    long long accepted;    /* accepted steps (= iters without adaptive steps)  */
+    double eta_next;       /* step the next attempt would try                  */
 } orc_result;
 
 /* one restart (or check) record */
@@ -417,6 +483,8 @@ typedef struct {
     double kkt_cand;       /* KKT_omega of the candidate                       */
     double omega;          /* primal weight after the check                    */
     double rel_kkt_cur, rel_kkt_avg;
+    double eta_next;       /* step the next attempt would try                  */
+    long long accepted;    /* accepted steps so far                            */
 } orc_trace_rec;
 
 /* Solves the LP (rows already ordered [G; A]).  x_out / y_out receive the
@@ -460,10 +528,19 @@ int orc_solve(const orc_prob *p, const orc_opts *o, double *x_out, double *y_out
     for (int64_t j = 0; j < n; ++j) x[j] = clip(0.0, s->l[j], s->u[j]);
     memcpy(x0, x, (size_t)n * sizeof(double));
     memcpy(y0, y, (size_t)m * sizeof(double));
+    double *xn = NULL, *yn = NULL; /* candidates of the adaptive step */
+    if (o->adaptive_step) {
+        xn = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+        yn = (double *)malloc((size_t)(m ? m : 1) * sizeof(double));
+    }
     orc_work w;
     work_alloc(s, &w);
 
-    long long k_total = 0, t_inner = 0;
+    /* Averages are weighted by the step of each accepted iterate (Section
+     * 2.4.2): wsum = sum of the weights of the current epoch.  With fixed steps
+     * every weight is 1.  Iteration counters count attempts. */
+    long long k_total = 0, t_inner = 0, k_att = 0, n_acc = 0;
+    double wsum = 0.0, eta_try = eta;
     int restarts = 0, tl = 0;
     double kkt0, kkt_prev = INFINITY;
     orc_kkt_t kc, ka, ksc, ksa;
@@ -484,12 +561,30 @@ int orc_solve(const orc_prob *p, const orc_opts *o, double *x_out, double *y_out
 
     for (;;) {
         for (int it = 0; it < o->check_every; ++it) {
-            step(s, eta / omega, eta * omega, x, y, &w);
+            double wgt = 1.0;
+            int accepted = 1;
+            if (o->adaptive_step) {
+                double etabar, etan;
+                ++k_att;
+                accepted = orc_adaptive_attempt(s, omega, eta_try, k_att, x, y, xn, yn, &etabar, &etan);
+                wgt = eta_try;
+                if (accepted) {
+                    memcpy(x, xn, (size_t)n * sizeof(double));
+                    memcpy(y, yn, (size_t)m * sizeof(double));
+                }
+                eta_try = etan;
+            } else {
+                step(s, eta / omega, eta * omega, x, y, &w);
+            }
             ++k_total;
             ++t_inner;
-            if (o->use_restarts) {
-                for (int64_t j = 0; j < n; ++j) xs[j] += x[j];
-                for (int64_t i = 0; i < m; ++i) ys[i] += y[i];
+            if (accepted) {
+                ++n_acc;
+                if (o->use_restarts) {
+                    for (int64_t j = 0; j < n; ++j) xs[j] += wgt * x[j];
+                    for (int64_t i = 0; i < m; ++i) ys[i] += wgt * y[i];
+                    wsum += wgt;
+                }
             }
         }
         /* termination metric on the original LP, restart metric on the scaled one */
@@ -499,8 +594,13 @@ int orc_solve(const orc_prob *p, const orc_opts *o, double *x_out, double *y_out
         orc_kkt(s, x, y, &ksc);
         double kw_c = kkt_omega(&ksc, omega), kw_a = INFINITY;
         if (o->use_restarts) {
-            for (int64_t j = 0; j < n; ++j) xa[j] = xs[j] / (double)t_inner;
-            for (int64_t i = 0; i < m; ++i) ya[i] = ys[i] / (double)t_inner;
+            if (wsum > 0.0) {
+                for (int64_t j = 0; j < n; ++j) xa[j] = xs[j] / wsum;
+                for (int64_t i = 0; i < m; ++i) ya[i] = ys[i] / wsum;
+            } else { /* no accepted step this epoch: the average is the iterate */
+                memcpy(xa, x, (size_t)n * sizeof(double));
+                memcpy(ya, y, (size_t)m * sizeof(double));
+            }
             for (int64_t j = 0; j < n; ++j) xu[j] = kap[j] * xa[j];
             for (int64_t i = 0; i < m; ++i) yu[i] = rho[i] * ya[i];
             orc_kkt(p, xu, yu, &ka);
@@ -513,7 +613,8 @@ int orc_solve(const orc_prob *p, const orc_opts *o, double *x_out, double *y_out
         const orc_kkt_t *k_cand = cand_avg ? &ka : &kc;
         const orc_kkt_t *k_other = cand_avg ? &kc : &ka;
         orc_trace_rec rec = {k_total, 0, cand_avg, kw_cand, omega, kc.rel_kkt,
-                             o->use_restarts ? ka.rel_kkt : INFINITY};
+                             o->use_restarts ? ka.rel_kkt : INFINITY,
+                             o->adaptive_step ? eta_try : eta, n_acc};
 
         /* termination (Section 2.3.2): candidate first, then the other point */
         if (k_cand->rel_kkt <= o->eps) {
@@ -557,6 +658,7 @@ int orc_solve(const orc_prob *p, const orc_opts *o, double *x_out, double *y_out
                 kkt0 = kkt_omega(cand_avg ? &ksa : &ksc, omega);
                 kkt_prev = INFINITY;
                 t_inner = 0;
+                wsum = 0.0;
                 memset(xs, 0, (size_t)n * sizeof(double));
                 memset(ys, 0, (size_t)m * sizeof(double));
                 ++restarts;
@@ -580,7 +682,11 @@ done:
     res->tau = eta / omega;
     res->sigma = eta * omega;
     res->trace_len = tl;
+    res->accepted = n_acc;
+    res->eta_next = o->adaptive_step ? eta_try : eta;
     work_free(&w);
+    free(xn);
+    free(yn);
     free(x); free(y); free(xs); free(ys); free(xa); free(ya);
     free(x0); free(y0); free(xu); free(yu);
     free(rho); free(kap);

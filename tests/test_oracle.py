@@ -441,3 +441,118 @@ def test_unrolled_zero_steps_is_identity(orc):
     xk, yk = o.unrolled(3, tau, sigma, lp.c, lp.rhs, lp.l, lp.u, x0, y0, 0)
     np.testing.assert_allclose(xk, x0, rtol=1e-15)
     np.testing.assert_allclose(yk, y0, rtol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# adaptive step size (Section 2.4.4, Algorithm 5)
+# ---------------------------------------------------------------------------
+
+def test_adaptive_attempt_golden_1x1(orc):
+    """Hand-worked attempts: a rejection, an acceptance and the zero-interaction case."""
+    with open(os.path.join(GOLD, "adaptive_1x1.json")) as f:
+        g = json.load(f)
+    for cs in g["cases"]:
+        lo = -np.inf if cs["l"] is None else cs["l"]
+        hi = np.inf if cs["u"] is None else cs["u"]
+        lp = lpgen.from_dense(np.array([[1.0]]), [cs["row_type"]], [cs["q"]], [cs["c"]], [lo], [hi])
+        acc, xn, yn, eb, en = orc.Oracle(lp).adaptive_attempt([0.0], [0.0], cs["omega"], cs["eta"], cs["k"])
+        assert acc == cs["accepted"], cs["name"]
+        if cs["etabar"] == "inf":
+            assert eb == np.inf
+        else:
+            assert eb == pytest.approx(cs["etabar"], rel=1e-14), cs["name"]
+        assert en == pytest.approx(cs["eta_next"], rel=1e-14), cs["name"]
+        assert xn[0] == pytest.approx(cs["x"], rel=1e-14, abs=1e-300), cs["name"]
+        assert yn[0] == pytest.approx(cs["y"], rel=1e-14, abs=1e-300), cs["name"]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_adaptive_etabar_at_least_inverse_norm(orc, seed):
+    """2|dy' K dx| <= ||K||_2 (w ||dx||^2 + ||dy||^2 / w) (Cauchy-Schwarz and
+    AM-GM), so etabar >= 1/||K||_2 and every step up to 1/||K||_2 is accepted;
+    the candidate is one fixed PDHG step with tau = eta/w, sigma = eta w."""
+    lp = lpgen.planted(40, 90, 0.08, 30 + seed, ge_frac=0.5)
+    o = orc.Oracle(lp)
+    kn = np.linalg.norm(lp.scipy().toarray(), 2)
+    rng = np.random.default_rng(seed)
+    lo = np.where(np.isfinite(lp.l), lp.l, -3.0)
+    hi = np.where(np.isfinite(lp.u), lp.u, lo + 6.0)
+    for trial in range(6):
+        x = lo + rng.uniform(0, 1, lp.n) * (hi - lo)
+        y = rng.standard_normal(lp.m)
+        y[lp.row_type == 0] = np.abs(y[lp.row_type == 0])
+        w = [0.3, 1.0, 4.0][trial % 3]
+        for f in (0.5, 0.999, 3.0, 30.0):
+            eta = f / kn
+            acc, xn, yn, eb, en = o.adaptive_attempt(x, y, w, eta, trial + 1)
+            assert eb >= (1.0 / kn) * (1.0 - 1e-12)
+            assert acc == (eta <= eb)
+            if f < 1.0:
+                assert acc
+            xo, yo = o.steps(x, y, eta / w, eta * w, 1)
+            np.testing.assert_allclose(xn, xo, rtol=1e-14, atol=1e-14)
+            np.testing.assert_allclose(yn, yo, rtol=1e-14, atol=1e-14)
+            assert 0.0 < en <= (1.0 + (trial + 2) ** -0.6) * eta * (1 + 1e-15)
+
+
+@pytest.mark.parametrize("maker", [lambda: lpgen.config0(0), lambda: lpgen.config0(1, unique=True),
+                                   lambda: lpgen.planted(150, 400, 0.03, 8, ge_frac=0.5)])
+def test_adaptive_solve_matches_planted(orc, maker):
+    lp = maker()
+    o = orc.Oracle(lp)
+    r = o.solve(orc.SolveOpts(eps=1e-6, adaptive_step=True))
+    assert r.status == 0
+    chk = o.kkt(r.x, r.y)
+    assert chk["rel_kkt"] <= 1e-6 * 1.0001
+    assert _rel(chk["pobj"], lp.f_star) <= 1e-5
+    assert 0 < r.accepted <= r.iters
+    assert r.eta_next > 0.0
+
+
+def test_adaptive_solve_matches_highs(orc):
+    from scipy.optimize import linprog
+
+    lp = lpgen.planted(120, 260, 0.05, 21, ge_frac=0.6)
+    A = lp.scipy().toarray()
+    ge, eq = lp.row_type == 0, lp.row_type == 1
+    ref = linprog(lp.c, A_ub=-A[ge], b_ub=-lp.rhs[ge], A_eq=A[eq], b_eq=lp.rhs[eq],
+                  bounds=list(zip(lp.l, lp.u)), method="highs")
+    r = orc.Oracle(lp).solve(orc.SolveOpts(eps=1e-7, adaptive_step=True))
+    assert r.status == 0
+    assert _rel(r.kkt["pobj"], ref.fun) <= 1e-6
+
+
+def test_adaptive_first_check_weighted_average(orc):
+    """Replays the first check period attempt by attempt with the pinned single
+    attempt and forms the step-weighted average sum(eta_i z_i) / sum(eta_i)
+    (Section 2.4.2) in numpy: the solve's first check must report its KKT."""
+    lp = lpgen.planted(60, 150, 0.05, 1, ge_frac=0.5)
+    o = orc.Oracle(lp)
+    r = o.solve(orc.SolveOpts(eps=1e-12, adaptive_step=True, max_iters=64))
+    rho, kap = o.ruiz(10)
+    x = np.clip(np.zeros(lp.n), lp.l / kap, lp.u / kap)
+    y = np.zeros(lp.m)
+    eta, w = r.eta, r.omega0
+    sx, sy, ws, acc_n = np.zeros(lp.n), np.zeros(lp.m), 0.0, 0
+    ux, uy = np.zeros(lp.n), np.zeros(lp.m)
+    for k in range(1, 65):
+        acc, xn, yn, eb, en = o.adaptive_attempt(x, y, w, eta, k, ruiz_iters=10)
+        if acc:
+            x, y = xn, yn
+            sx += eta * x
+            sy += eta * y
+            ws += eta
+            ux += x
+            uy += y
+            acc_n += 1
+        eta = en
+    t0 = r.trace[0]
+    assert t0["accepted"] == acc_n
+    assert t0["eta_next"] == pytest.approx(eta, rel=1e-12)
+    avg = o.kkt(kap * sx / ws, rho * sy / ws)
+    cur = o.kkt(kap * x, rho * y)
+    assert t0["rel_kkt_avg"] == pytest.approx(avg["rel_kkt"], rel=1e-10)
+    assert t0["rel_kkt_cur"] == pytest.approx(cur["rel_kkt"], rel=1e-10)
+    # the plain mean of the same iterates is measurably different (the weights matter)
+    plain = o.kkt(kap * ux / acc_n, rho * uy / acc_n)
+    assert abs(plain["rel_kkt"] - avg["rel_kkt"]) > 1e3 * abs(t0["rel_kkt_avg"] - avg["rel_kkt"])
