@@ -128,6 +128,18 @@ typedef struct {
     int32_t max_grid;          /* workgroups per solve-time sweep launch (0: 8192);  */
                                /* a launch walks the row blocks of the instances   */
                                /* still running                                    */
+    /* Adaptive step size (Section 2.4.4, Algorithm 5), 0 or 1.  Each attempt
+     * takes the PDHG step with the instance's trial step eta from the current
+     * iterate, forms etabar = ||(x'-x, y'-y)||_w^2 / |2 (y'-y)' K~ (x'-x)|
+     * with ||(a, b)||_w^2 = w ||a||^2 + ||b||^2 / w (+inf when the product
+     * is 0) and the next trial step eta' = min((1 - (k+1)^-0.3) etabar,
+     * (1 + (k+1)^-0.6) eta), k = attempts of this solve including this one;
+     * the candidate becomes the iterate when eta <= etabar.  The first
+     * attempt of every pdhg_solve tries the fixed step above.  Averages are
+     * weighted by the accepted steps (Section 2.4.2).  Iteration counts,
+     * check_every and max_iters count attempts.  pdhg_iterate always takes
+     * fixed steps. */
+    int32_t adaptive_step;
 } pdhg_opts;
 
 /* Relative KKT error terms (Section 2.3.2, conditions term1-term3) on the
@@ -154,6 +166,8 @@ typedef struct {
     double eta, omega0, omega, tau, sigma;
     pdhg_kkt_out kkt;    /* of the returned point (last check)                      */
     double seconds;      /* wall time of pdhg_solve                                 */
+    int64_t accepted;    /* accepted steps (= iters without adaptive steps)         */
+    double eta_next;     /* trial step of the next attempt (= eta without them)     */
 } pdhg_result;
 
 typedef struct {
@@ -174,6 +188,9 @@ typedef struct {
     double ms_control;  /* per-instance reduction + restart / stop decisions  */
     double ms_restart;  /* restart copy (0 when restarts are off)              */
     int32_t reps;
+    double ms_primal_ad; /* adaptive step: K~^T y sweep + candidate x' + sums   */
+    double ms_dual_ad;   /* adaptive step: K~ x' sweep + candidate y' + sums    */
+    double ms_step_ad;   /* adaptive step: per-instance accept / reject         */
 } pdhg_kernel_times;
 
 typedef struct pdhg_handle pdhg_handle;

@@ -51,7 +51,7 @@ class Opts(C.Structure):
                 ("unroll_capacity", C.c_int32), ("unroll_checkpoint", C.c_int32),
                 ("use_graph", C.c_int32), ("xcd_remap", C.c_int32), ("bin_len_dual", C.c_int32 * 8),
                 ("bin_len_primal", C.c_int32 * 8), ("bin_rows_dual", C.c_int32 * 8),
-                ("bin_rows_primal", C.c_int32 * 8), ("max_grid", C.c_int32)]
+                ("bin_rows_primal", C.c_int32 * 8), ("max_grid", C.c_int32), ("adaptive_step", C.c_int32)]
 
 
 class KKTOut(C.Structure):
@@ -66,7 +66,8 @@ class Result(C.Structure):
     _fields_ = [("status", C.c_int32), ("from_avg", C.c_int32), ("iters", C.c_int64),
                 ("restarts", C.c_int32), ("power_iters", C.c_int32), ("knorm", C.c_double),
                 ("eta", C.c_double), ("omega0", C.c_double), ("omega", C.c_double),
-                ("tau", C.c_double), ("sigma", C.c_double), ("kkt", KKTOut), ("seconds", C.c_double)]
+                ("tau", C.c_double), ("sigma", C.c_double), ("kkt", KKTOut), ("seconds", C.c_double),
+                ("accepted", C.c_int64), ("eta_next", C.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "kkt"}
@@ -77,7 +78,8 @@ class Result(C.Structure):
 
 class KernelTimes(C.Structure):
     _fields_ = [("ms_primal", C.c_double), ("ms_dual", C.c_double), ("ms_check", C.c_double),
-                ("ms_control", C.c_double), ("ms_restart", C.c_double), ("reps", C.c_int32)]
+                ("ms_control", C.c_double), ("ms_restart", C.c_double), ("reps", C.c_int32),
+                ("ms_primal_ad", C.c_double), ("ms_dual_ad", C.c_double), ("ms_step_ad", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -73,6 +73,7 @@ extern "C" void pdhg_default_opts(pdhg_opts *o)
     o->use_graph = 1;
     o->xcd_remap = 1;
     o->max_grid = 8192;
+    o->adaptive_step = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -360,6 +361,13 @@ static void carve(Carve &cv, const Sizes &sz, int prec, const pdhg_opts &o, Dev 
     *st = cv.take<InstState>(sz.batch);
     d.partials = cv.take<double>((size_t)(sz.nblkK + sz.nblkT) * NCAND * NSUM + 1);
     d.partials2 = cv.take<double>((size_t)sz.nl2 * NCAND * NSUM + 1);
+    d.adp = cv.take<double>(2 * (size_t)sz.nblkK + sz.nblkT + 1);
+    // second buffers of the adaptive step size
+    d.xavg1 = cv.take<char>(N * es);
+    d.y1 = cv.take<char>(M * es);
+    d.yavg1 = cv.take<char>(M * es);
+    d.kx0 = cv.take<double>(M);
+    d.kx1 = cv.take<double>(M);
     d.actK = cv.take<int32_t>(sz.nblkK + 1);
     d.actT = cv.take<int32_t>(sz.nblkT + 1);
     d.act_cnt = cv.take<int32_t>(2);
@@ -402,6 +410,7 @@ static int check_opts(const pdhg_opts *o)
     if (o->unroll_capacity < 0 || (o->unroll_capacity > 0 && o->unroll_checkpoint < 1))
         return fail(PDHG_ERR_INVALID_ARG, "bad unroll capacity / checkpoint");
     if (!(o->step_frac > 0.0) && !(o->step_size > 0.0)) return fail(PDHG_ERR_INVALID_ARG, "step_frac must be > 0");
+    if (o->adaptive_step != 0 && o->adaptive_step != 1) return fail(PDHG_ERR_INVALID_ARG, "adaptive_step must be 0 or 1");
     return PDHG_OK;
 }
 
@@ -726,10 +735,20 @@ static int device_setup(pdhg_handle *h, hipStream_t s)
         st.kkt0 = INFINITY;
         st.kkt_prev = INFINITY;
         st.power_iters = its[b];
+        st.eta_try = eta;
     }
     HIPCHK(hipMemcpyAsync(d.st, h->st0.data(), B * sizeof(InstState), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync((InstInfo *)d.info, h->info.data(), B * sizeof(InstInfo), hipMemcpyHostToDevice, s));
     launch_init_point<T>(d, s);
+    // the adaptive step's second buffers start defined (they are overwritten
+    // before they are read)
+    const size_t es = sizeof(T);
+    HIPCHK(hipMemsetAsync(d.xbar, 0, d.N * es, s));
+    HIPCHK(hipMemsetAsync(d.xavg1, 0, d.N * es, s));
+    HIPCHK(hipMemsetAsync(d.y1, 0, d.M * es, s));
+    HIPCHK(hipMemsetAsync(d.yavg1, 0, d.M * es, s));
+    HIPCHK(hipMemsetAsync(d.kx0, 0, d.M * sizeof(double), s));
+    HIPCHK(hipMemsetAsync(d.kx1, 0, d.M * sizeof(double), s));
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
     return PDHG_OK;
@@ -839,6 +858,7 @@ static CtlParams ctl_params(const pdhg_handle *h)
     P.use_restarts = o.use_restarts;
     P.use_pw = o.use_pw_update;
     P.batch = h->batch;
+    P.adaptive = o.adaptive_step;
     return P;
 }
 
@@ -848,13 +868,26 @@ static void enqueue_chunk(const pdhg_handle *h, hipStream_t s)
 {
     const Dev &d = h->d;
     const int avg = h->opts.use_restarts;
-    for (int j = 0; j < h->opts.check_every; ++j) {
-        launch_primal<T>(d, j, avg, nullptr, s);
-        launch_dual<T>(d, j, avg, nullptr, s);
+    if (h->opts.adaptive_step) {
+        // Algorithm 5: check_every attempts, then the current buffers move to 0
+        for (int j = 0; j < h->opts.check_every; ++j) {
+            launch_primal_ad<T>(d, s);
+            launch_dual_ad<T>(d, s);
+            launch_step_ad(d, s);
+        }
+        launch_commit_ad<T>(d, s);
+    } else {
+        for (int j = 0; j < h->opts.check_every; ++j) {
+            launch_primal<T>(d, j, avg, nullptr, s);
+            launch_dual<T>(d, j, avg, nullptr, s);
+        }
     }
     launch_check<T>(d, avg, s);
     launch_control(d, ctl_params(h), h->opts.check_every, s);
-    if (avg) launch_restart<T>(d, s);
+    if (avg) {
+        launch_restart<T>(d, s);
+        if (h->opts.adaptive_step) launch_kx_ad<T>(d, 0, s);  // K~x of the restarted iterates
+    }
     launch_active(d, s);
 }
 
@@ -896,6 +929,11 @@ static int solve_impl(pdhg_handle *h, pdhg_result *res, hipStream_t s)
         x.nrestarts = 0;
         x.kkt0 = INFINITY;
         x.kkt_prev = INFINITY;
+        x.par = 0;
+        x.eta_try = x.eta;
+        x.eta_sum = 0.0;
+        x.k_att = 0;
+        x.n_acc = 0;
     }
     std::memset(h->hdone_host, 0, sizeof(int32_t) * B);
     HIPCHK(hipMemcpyAsync(d.st, st.data(), B * sizeof(InstState), hipMemcpyHostToDevice, s));
@@ -904,6 +942,7 @@ static int solve_impl(pdhg_handle *h, pdhg_result *res, hipStream_t s)
     launch_check<T>(d, 0, s);
     launch_control(d, ctl_params(h), 0, s);
     launch_active(d, s);
+    if (h->opts.adaptive_step) launch_kx_ad<T>(d, 1, s);
     HIPCHK(hipGetLastError());
 
     const int DEPTH = 4;
@@ -966,6 +1005,8 @@ static int solve_impl(pdhg_handle *h, pdhg_result *res, hipStream_t s)
         r.sigma = x.sigma;
         std::memcpy(&r.kkt, x.kkt, sizeof(double) * 9);
         r.seconds = secs;
+        r.accepted = h->opts.adaptive_step ? x.n_acc : x.k_total;
+        r.eta_next = h->opts.adaptive_step ? x.eta_try : x.eta;
         h->sol_avg[b] = x.sol_avg;
     }
     // keep tau / sigma / omega of the end of the solve for later fixed-step calls
@@ -1286,10 +1327,11 @@ static int time_impl(pdhg_handle *h, int32_t reps, pdhg_kernel_times *out, hipSt
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    double ms[5] = {0, 0, 0, 0, 0};
+    double ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     const CtlParams P = ctl_params(h);
-    for (int phase = 0; phase < 5; ++phase) {
-        if (phase == 4 && !avg) break;
+    for (int phase = 0; phase < 8; ++phase) {
+        if (phase == 4 && !avg) continue;
+        if (phase == 5) launch_kx_ad<T>(d, 1, s);
         hipEventRecord(e0, s);
         for (int r = 0; r < reps; ++r) {
             switch (phase) {
@@ -1297,7 +1339,10 @@ static int time_impl(pdhg_handle *h, int32_t reps, pdhg_kernel_times *out, hipSt
                 case 1: launch_dual<T>(d, r, avg, nullptr, s); break;
                 case 2: launch_check<T>(d, avg, s); break;
                 case 3: launch_control(d, P, 0, s); break;
-                default: launch_restart<T>(d, s); break;
+                case 4: launch_restart<T>(d, s); break;
+                case 5: launch_primal_ad<T>(d, s); break;
+                case 6: launch_dual_ad<T>(d, s); break;
+                default: launch_step_ad(d, s); break;
             }
         }
         hipEventRecord(e1, s);
@@ -1305,8 +1350,9 @@ static int time_impl(pdhg_handle *h, int32_t reps, pdhg_kernel_times *out, hipSt
         float t = 0.f;
         hipEventElapsedTime(&t, e0, e1);
         ms[phase] = (double)t / reps;
-        if (phase == 3) {
-            // the control kernel may have stopped an instance: restore the state
+        if (phase == 3 || phase == 7) {
+            // the control kernel may have stopped an instance and the step
+            // kernel flips buffers: restore the state
             HIPCHK(hipMemcpyAsync(d.st, st.data(), h->batch * sizeof(InstState), hipMemcpyHostToDevice, s));
             launch_active(d, s);
         }
@@ -1320,6 +1366,9 @@ static int time_impl(pdhg_handle *h, int32_t reps, pdhg_kernel_times *out, hipSt
     out->ms_check = ms[2];
     out->ms_control = ms[3];
     out->ms_restart = ms[4];
+    out->ms_primal_ad = ms[5];
+    out->ms_dual_ad = ms[6];
+    out->ms_step_ad = ms[7];
     out->reps = reps;
     return PDHG_OK;
 }
@@ -1345,13 +1394,14 @@ extern "C" int pdhg_set_opts(pdhg_handle *h, const pdhg_opts *o)
     t.beta_art = o->beta_art;
     t.eps_zero = o->eps_zero;
     t.use_graph = o->use_graph;
+    t.adaptive_step = o->adaptive_step;
     int rc = check_opts(&t);
     if (rc) return rc;
     const bool regraph = t.use_restarts != h->opts.use_restarts || t.check_every != h->opts.check_every ||
                          t.use_pw_update != h->opts.use_pw_update || t.eps != h->opts.eps ||
                          t.max_iters != h->opts.max_iters || t.beta_suff != h->opts.beta_suff ||
                          t.beta_nec != h->opts.beta_nec || t.beta_art != h->opts.beta_art ||
-                         t.eps_zero != h->opts.eps_zero;
+                         t.eps_zero != h->opts.eps_zero || t.adaptive_step != h->opts.adaptive_step;
     if (regraph && h->graph) {
         hipGraphExecDestroy(h->graph);
         h->graph = nullptr;

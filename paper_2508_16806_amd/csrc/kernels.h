@@ -11,6 +11,15 @@ void launch_primal(const Dev &d, int j, int avg, uint8_t *mask, hipStream_t s);
 template <typename T>
 void launch_dual(const Dev &d, int j, int avg, uint8_t *mask, hipStream_t s);
 template <typename T>
+void launch_primal_ad(const Dev &d, hipStream_t s);
+template <typename T>
+void launch_dual_ad(const Dev &d, hipStream_t s);
+void launch_step_ad(const Dev &d, hipStream_t s);
+template <typename T>
+void launch_commit_ad(const Dev &d, hipStream_t s);
+template <typename T>
+void launch_kx_ad(const Dev &d, int all, hipStream_t s);
+template <typename T>
 void launch_check(const Dev &d, int avg, hipStream_t s);
 void launch_check64(const Dev &d, const double *xs, const double *ys, hipStream_t s);
 void launch_control(const Dev &d, const CtlParams &P, int iters_done, hipStream_t s);

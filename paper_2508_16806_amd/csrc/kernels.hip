@@ -144,6 +144,256 @@ __global__ __launch_bounds__(WG) void k_dual(Dev d, int j_in_chunk, uint8_t *__r
 }
 
 // ---------------------------------------------------------------------------
+// adaptive step size (Section 2.4.4, Algorithm 5)
+//
+// One attempt = k_primal_ad, k_dual_ad, k_step_ad.  The sweeps read the
+// instance's current buffer `par` and write the candidate into the other one:
+//   x' = clip(x - (eta/omega)(c~ - K~^T y)),  a = K~ x' (FP64 sums),
+//   K~ xbar = 2a - K~ x  (K~ x is cached per buffer: kx0 / kx1),
+//   y' = proj_Y(y + eta omega (q~ - K~ xbar)),  K~ (x' - x) = a - K~ x,
+// together with the step-weighted averages of the candidate,
+//   zavg' = zavg + (z' - zavg) eta / (eta_sum + eta),
+// and per-block FP64 sums of ||x'-x||^2, ||y'-y||^2 and (y'-y)'K~(x'-x).  The
+// step kernel reduces them per instance, forms etabar and eta' and accepts the
+// candidate (flips `par`) when eta <= etabar; a rejected candidate is simply
+// overwritten by the next attempt.  Before each check k_commit_ad moves every
+// instance's current buffer to buffer 0, so the check, the restart and the
+// solution readers see the usual layout.
+// ---------------------------------------------------------------------------
+
+template <typename T, int RM>
+__global__ __launch_bounds__(WG) void k_primal_ad(Dev d)
+{
+    __shared__ double red[8];
+    __shared__ double lds[4];
+    const OpDev &op = d.Kt;
+    const T *__restrict__ c = (const T *)d.c;
+    const T *__restrict__ l = (const T *)d.l;
+    const T *__restrict__ u = (const T *)d.u;
+    const int cnt = d.act_cnt[1];
+    const bool full = cnt == op.nblk;
+    for_each_item(cnt, d.remap, [&](int it) {
+        const int lb = full ? it : d.actT[it];
+        const Seg s = block_seg(op, lb);
+        const InstState *st = d.st + s.inst;
+        const int par = st->par;
+        const double eta = st->eta_try, tau = eta / st->omega;
+        const bool first = !(st->eta_sum > 0.0);
+        const double wa = eta / (st->eta_sum + eta);
+        const T *__restrict__ x = (const T *)(par ? d.xbar : d.x);
+        T *__restrict__ xn = (T *)(par ? d.x : d.xbar);
+        const T *__restrict__ xa = (const T *)(par ? d.xavg1 : d.xavg);
+        T *__restrict__ xan = (T *)(par ? d.xavg : d.xavg1);
+        const T *__restrict__ y = (const T *)(par ? d.y1 : d.y);
+        const int bi = lb - s.blk0;
+        double part[1] = {0.0};
+        dispatch_lanes<RM>(s.lanes_log2, [&](auto tag, auto rtag) {
+            constexpr int L = decltype(tag)::value, R = decltype(rtag)::value;
+            using RS = RowSweep<L, 1, T, T, R>;
+            const typename RS::Pos ps = RS::locate(s, bi);
+            T r_x[R], r_c[R], r_l[R], r_u[R], r_a[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t jj = r < ps.nvalid ? ps.row0 + r : ps.blk_row0;
+                r_x[r] = x[jj];
+                r_c[r] = c[jj];
+                r_l[r] = l[jj];
+                r_u[r] = u[jj];
+                r_a[r] = xa[jj];
+            }
+            double acc[R][1];
+            RS::dot(op, ps, y, nullptr, nullptr, red, acc);
+            if (ps.leader) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (r >= ps.nvalid) break;
+                    const int64_t j = ps.row0 + r;
+                    const double xo = (double)r_x[r], cj = (double)r_c[r], lo = (double)r_l[r];
+                    const double hi = (double)r_u[r], xav = (double)r_a[r];
+                    const double v = xo - tau * (cj - acc[r][0]);
+                    const double xv = v < lo ? lo : (v > hi ? hi : v);
+                    const T xnT = (T)xv;
+                    xn[j] = xnT;
+                    xan[j] = first ? xnT : (T)(xav + ((double)xnT - xav) * wa);
+                    const double dx = (double)xnT - xo;
+                    part[0] += dx * dx;
+                }
+            }
+        });
+        block_sum<1>(part, lds);
+        if (threadIdx.x == 0) d.adp[2 * (size_t)d.K.nblk + lb] = part[0];
+    });
+}
+
+template <typename T, int RM>
+__global__ __launch_bounds__(WG) void k_dual_ad(Dev d)
+{
+    __shared__ double red[8];
+    __shared__ double lds[8];
+    const OpDev &op = d.K;
+    const T *__restrict__ q = (const T *)d.q;
+    const int cnt = d.act_cnt[0];
+    const bool full = cnt == op.nblk;
+    for_each_item(cnt, d.remap, [&](int it) {
+        const int lb = full ? it : d.actK[it];
+        const Seg s = block_seg(op, lb);
+        const InstState *st = d.st + s.inst;
+        const int par = st->par;
+        const double eta = st->eta_try, sigma = eta * st->omega;
+        const bool first = !(st->eta_sum > 0.0);
+        const double wa = eta / (st->eta_sum + eta);
+        const T *__restrict__ xc = (const T *)(par ? d.x : d.xbar);  // candidate x'
+        const T *__restrict__ y = (const T *)(par ? d.y1 : d.y);
+        T *__restrict__ yn = (T *)(par ? d.y : d.y1);
+        const T *__restrict__ ya = (const T *)(par ? d.yavg1 : d.yavg);
+        T *__restrict__ yan = (T *)(par ? d.yavg : d.yavg1);
+        const double *__restrict__ kx = par ? d.kx1 : d.kx0;
+        double *__restrict__ kxn = par ? d.kx0 : d.kx1;
+        const bool ineq = s.ineq != 0;
+        const int bi = lb - s.blk0;
+        double part[2] = {0.0, 0.0};
+        dispatch_lanes<RM>(s.lanes_log2, [&](auto tag, auto rtag) {
+            constexpr int L = decltype(tag)::value, R = decltype(rtag)::value;
+            using RS = RowSweep<L, 1, T, T, R>;
+            const typename RS::Pos ps = RS::locate(s, bi);
+            T r_y[R], r_q[R], r_a[R];
+            double r_k[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t ii = r < ps.nvalid ? ps.row0 + r : ps.blk_row0;
+                r_y[r] = y[ii];
+                r_q[r] = q[ii];
+                r_a[r] = ya[ii];
+                r_k[r] = kx[ii];
+            }
+            double acc[R][1];
+            RS::dot(op, ps, xc, nullptr, nullptr, red, acc);
+            if (ps.leader) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (r >= ps.nvalid) break;
+                    const int64_t i = ps.row0 + r;
+                    const double a = acc[r][0], kxo = r_k[r];
+                    const double yo = (double)r_y[r], qi = (double)r_q[r], yav = (double)r_a[r];
+                    const double wv = yo + sigma * (qi - (2.0 * a - kxo));
+                    const double yv = (ineq && wv < 0.0) ? 0.0 : wv;
+                    const T ynT = (T)yv;
+                    yn[i] = ynT;
+                    kxn[i] = a;
+                    yan[i] = first ? ynT : (T)(yav + ((double)ynT - yav) * wa);
+                    const double dy = (double)ynT - yo;
+                    part[0] += dy * dy;
+                    part[1] += dy * (a - kxo);
+                }
+            }
+        });
+        block_sum<2>(part, lds);
+        if (threadIdx.x == 0) {
+            d.adp[2 * (size_t)lb] = part[0];
+            d.adp[2 * (size_t)lb + 1] = part[1];
+        }
+    });
+}
+
+// One workgroup per instance: the accept / reject decision of the attempt.
+// k counts the attempts of the solve including this one.
+__global__ __launch_bounds__(WG) void k_step_ad(Dev d)
+{
+    __shared__ double lds[12];
+    const int b = blockIdx.x;
+    InstState &st = d.st[b];
+    if (st.done) return;
+    const InstInfo in = d.info[b];
+    const int nT = in.blkT1 - in.blkT0, nK = in.blkK1 - in.blkK0;
+    const double *pT = d.adp + 2 * (size_t)d.K.nblk + in.blkT0;
+    const double *pK = d.adp + 2 * (size_t)in.blkK0;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int r = threadIdx.x; r < nT; r += WG) v[0] += pT[r];
+    for (int r = threadIdx.x; r < nK; r += WG) {
+        v[1] += pK[2 * r];
+        v[2] += pK[2 * r + 1];
+    }
+    block_sum<3>(v, lds);
+    if (threadIdx.x != 0) return;
+    const double w = st.omega, eta = st.eta_try;
+    const long long k = st.k_att + 1;
+    const double den = fabs(2.0 * v[2]);
+    const double etabar = den > 0.0 ? (w * v[0] + v[1] / w) / den : INFINITY;
+    const double kk = (double)k + 1.0;
+    const double shrink = (1.0 - pow(kk, -0.3)) * etabar;
+    const double grow = (1.0 + pow(kk, -0.6)) * eta;
+    st.k_att = k;
+    if (eta <= etabar) {
+        st.par ^= 1;
+        st.eta_sum += eta;
+        st.n_acc += 1;
+    }
+    st.eta_try = shrink < grow ? shrink : grow;
+}
+
+// Before a check: every running instance's current iterate, its average and
+// K~ x move to buffer 0.  An epoch without an accepted step has no average:
+// the average is set to the iterate.  (k_control then resets par.)
+template <typename T>
+__global__ __launch_bounds__(WG) void k_commit_ad(Dev d)
+{
+    const int nT = d.act_cnt[1], nK = d.act_cnt[0];
+    const bool fullK = nK == d.K.nblk, fullT = nT == d.Kt.nblk;
+    for_each_item(nT + nK, d.remap, [&](int it) {
+        const bool onT = it < nT;
+        const int lb = onT ? (fullT ? it : d.actT[it]) : (fullK ? it - nT : d.actK[it - nT]);
+        const OpDev &op = onT ? d.Kt : d.K;
+        const Seg s = block_seg(op, lb);
+        const InstState &st = d.st[s.inst];
+        const bool flip = st.par != 0, noavg = !(st.eta_sum > 0.0);
+        if (!flip && !noavg) return;
+        T *z0 = (T *)(onT ? d.x : d.y);
+        const T *z1 = (const T *)(onT ? d.xbar : d.y1);
+        T *za0 = (T *)(onT ? d.xavg : d.yavg);
+        const T *za1 = (const T *)(onT ? d.xavg1 : d.yavg1);
+        const int64_t r1 = s.row0 + s.nrows;
+        for (int64_t r = s.row0 + threadIdx.x; r < r1; r += WG) {
+            const T v = flip ? z1[r] : z0[r];
+            if (flip) z0[r] = v;
+            za0[r] = noavg ? v : za1[r];
+            if (!onT && flip) d.kx0[r] = d.kx1[r];
+        }
+    });
+}
+
+// kx0 = K~ x (buffer 0) with the sweep's own values and summation, for every
+// running instance (all = 1: solve start) or those that just restarted.
+template <typename T, int RM>
+__global__ __launch_bounds__(WG) void k_kx_ad(Dev d, int all)
+{
+    __shared__ double red[8];
+    const OpDev &op = d.K;
+    const T *__restrict__ x = (const T *)d.x;
+    const int cnt = d.act_cnt[0];
+    const bool full = cnt == op.nblk;
+    for_each_item(cnt, d.remap, [&](int it) {
+        const int lb = full ? it : d.actK[it];
+        const Seg s = block_seg(op, lb);
+        if (!all && !d.st[s.inst].restart) return;
+        const int bi = lb - s.blk0;
+        dispatch_lanes<RM>(s.lanes_log2, [&](auto tag, auto rtag) {
+            constexpr int L = decltype(tag)::value, R = decltype(rtag)::value;
+            using RS = RowSweep<L, 1, T, T, R>;
+            const typename RS::Pos ps = RS::locate(s, bi);
+            double acc[R][1];
+            RS::dot(op, ps, x, nullptr, nullptr, red, acc);
+            if (ps.leader) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (r >= ps.nvalid) break;
+                    d.kx0[ps.row0 + r] = acc[r][0];
+                }
+            }
+        });
+    });
+}
+
+// ---------------------------------------------------------------------------
 // check: per-workgroup FP64 partial sums for NC candidates
 //   K rows i   : s0 += e^2 (e = q~ - K~x, clipped at 0 on ">=" rows),
 //                s1 += (e / rho_i)^2, s2 += q~_i y_i, s3 += (y_i - y0_i)^2
@@ -323,6 +573,7 @@ __global__ __launch_bounds__(WG) void k_control(Dev d, CtlParams P, int iters_do
     const InstInfo in = d.info[b];
     reduce_instance(d, in, tot);
     if (threadIdx.x != 0) return;
+    if (P.adaptive) st.par = 0;  // k_commit_ad moved the current iterate to buffer 0
 
     st.k_total += iters_done;
     st.t_inner += iters_done;
@@ -396,6 +647,7 @@ __global__ __launch_bounds__(WG) void k_control(Dev d, CtlParams P, int iters_do
         st.kkt0 = kkt_omega(mt[cand], w);
         st.kkt_prev = INFINITY;
         st.t_inner = 0;
+        st.eta_sum = 0.0;
         st.restart = 1;
         st.nrestarts += 1;
     } else {
@@ -933,6 +1185,35 @@ void launch_dual(const Dev &d, int j, int avg, uint8_t *mask, hipStream_t s)
 }
 
 template <typename T>
+void launch_primal_ad(const Dev &d, hipStream_t s)
+{
+    const unsigned g = sweep_grid(d, d.Kt.nblk);
+    RM_SWITCH(d.Kt.rmax, { LAUNCH((k_primal_ad<T, RMV>), g, d); });
+}
+
+template <typename T>
+void launch_dual_ad(const Dev &d, hipStream_t s)
+{
+    const unsigned g = sweep_grid(d, d.K.nblk);
+    RM_SWITCH(d.K.rmax, { LAUNCH((k_dual_ad<T, RMV>), g, d); });
+}
+
+void launch_step_ad(const Dev &d, hipStream_t s) { LAUNCH(k_step_ad, (unsigned)d.batch, d); }
+
+template <typename T>
+void launch_commit_ad(const Dev &d, hipStream_t s)
+{
+    LAUNCH(k_commit_ad<T>, sweep_grid(d, d.K.nblk + d.Kt.nblk), d);
+}
+
+template <typename T>
+void launch_kx_ad(const Dev &d, int all, hipStream_t s)
+{
+    const unsigned g = sweep_grid(d, d.K.nblk);
+    RM_SWITCH(d.K.rmax, { LAUNCH((k_kx_ad<T, RMV>), g, d, all); });
+}
+
+template <typename T>
 void launch_check(const Dev &d, int avg, hipStream_t s)
 {
     const unsigned g = sweep_grid(d, d.K.nblk + d.Kt.nblk);
@@ -1125,6 +1406,10 @@ void launch_set_raw(const Dev &d, const double *c, const double *q, const double
 #define INST(T)                                                                              \
     template void launch_primal<T>(const Dev &, int, int, uint8_t *, hipStream_t);           \
     template void launch_dual<T>(const Dev &, int, int, uint8_t *, hipStream_t);             \
+    template void launch_primal_ad<T>(const Dev &, hipStream_t);                             \
+    template void launch_dual_ad<T>(const Dev &, hipStream_t);                               \
+    template void launch_commit_ad<T>(const Dev &, hipStream_t);                             \
+    template void launch_kx_ad<T>(const Dev &, int, hipStream_t);                            \
     template void launch_check<T>(const Dev &, int, hipStream_t);                            \
     template void launch_restart<T>(const Dev &, hipStream_t);                               \
     template void launch_scale_data<T>(const Dev &, hipStream_t);                            \

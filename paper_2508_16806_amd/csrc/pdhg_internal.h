@@ -80,8 +80,13 @@ struct InstState {
     int32_t sol_avg;   // the returned point is the average
     int32_t nrestarts;
     int32_t power_iters;
-    int32_t pad;
+    int32_t par;       // adaptive steps: buffer (0 or 1) holding the current iterate
     double kkt[9];     // pres, dres, pobj, dobj, gap, rel_pres, rel_dres, rel_gap, rel_kkt
+    // adaptive step size (Algorithm 5)
+    double eta_try;    // step the next attempt tries
+    double eta_sum;    // sum of the accepted steps of the current epoch (average weights)
+    long long k_att;   // attempts of this solve
+    long long n_acc;   // accepted steps of this solve
 };
 
 struct CtlParams {
@@ -90,6 +95,7 @@ struct CtlParams {
     int32_t check_every;
     int32_t use_restarts, use_pw;
     int32_t batch;
+    int32_t adaptive;  // adaptive step size: the check follows a commit to buffer 0
 };
 
 // Device pointers and sizes of one handle (passed by value to kernels).
@@ -98,8 +104,11 @@ struct Dev {
     int32_t remap;       // XCD-contiguous workgroup numbering
     int64_t N, M;        // total primal / dual length
     OpDev K, Kt;
-    // primal vectors (length N)
+    // primal vectors (length N).  With adaptive steps the iterate and its
+    // average are double-buffered per instance: buffer 0 = (x, xavg), buffer 1
+    // = (xbar, xavg1); likewise (y, yavg, kx0) / (y1, yavg1, kx1) for the dual.
     void *x, *xbar, *xavg, *x0;   // iterate type T
+    void *xavg1;
     void *c, *l, *u;              // scaled data, type T
     double *c64, *l64, *u64;      // scaled data, FP64
     double *kap;                  // column factors (x = kap * x~)
@@ -108,6 +117,8 @@ struct Dev {
     int32_t *inst_of_col;
     // dual vectors (length M)
     void *y, *yavg, *y0, *q;      // type T
+    void *y1, *yavg1;
+    double *kx0, *kx1;            // K~ x of the buffer's iterate (sweep precision, FP64 sums)
     double *q64, *rho, *qraw;
     int32_t *row_orig;            // internal row -> caller row (per instance)
     int32_t *inst_of_row;
@@ -118,6 +129,7 @@ struct Dev {
     // scratch
     double *partials;             // (K.nblk + Kt.nblk) * NCAND * NSUM
     double *partials2;            // nl2 * NCAND * NSUM (second level)
+    double *adp;                  // adaptive step: 2 per K block, then 1 per K^T block
     const int32_t *l2_inst;       // instance of each second-level row
     int32_t nl2;
     int32_t *actK, *actT;         // logical blocks of running instances (K, K^T sweeps)
