@@ -73,6 +73,20 @@ def sweep_bytes(info, es=4):
     return primal, dual
 
 
+def sweep_bytes_ad(info, es=4):
+    """Algorithmic HBM bytes of one launch of each adaptive-step sweep.
+
+    primal: as the fixed sweep without the xbar write (x read, x' write,
+    xavg read+write, c~, l~, u~: 7 per variable).  dual: values + columns,
+    row pointers, one read of the gathered x', and per row y read, y' write,
+    yavg read+write, q~ read, plus the FP64 K~x read and K~x' write.
+    """
+    n, m, nnz = info["n"], info["m"], info["nnz"]
+    primal = nnz * (es + 4) + 8 * (n + 1) + es * m + es * 7 * n
+    dual = nnz * (es + 4) + 8 * (m + 1) + es * n + es * 5 * m + 16 * m
+    return primal, dual
+
+
 def cpu_baseline(lp, budget_s=15.0):
     """FP64 CPU oracle iterations/s on this host: two restarted solves that
     differ only in their iteration limit; the rate is the difference of
@@ -309,6 +323,29 @@ def main():
         print(f"[bench] time to 1e-4: {tsec:.2f}s {rt['status_name']} iters={rt['iters']} "
               f"restarts={rt['restarts']}", file=sys.stderr, flush=True)
 
+    # adaptive step size (Algorithm 5): its sweeps' device time and the time
+    # to the same tolerance from the same cold start
+    pba, dba = sweep_bytes_ad(info, 4)
+    adaptive = {"ms_primal_ad": kt["ms_primal_ad"], "ms_dual_ad": kt["ms_dual_ad"],
+                "ms_step_ad": kt["ms_step_ad"],
+                "gbs_primal_ad": pba / (kt["ms_primal_ad"] * 1e-3) / 1e9,
+                "gbs_dual_ad": dba / (kt["ms_dual_ad"] * 1e-3) / 1e9}
+    if not args.no_ttt:
+        s.set_opts(adaptive_step=1)
+        s.set_state(np.zeros(lp.n), np.zeros(lp.m))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ra = s.solve()[0]
+        tsa = time.perf_counter() - t0
+        x, y = s.solution()
+        adaptive["time_to_tol"] = {"seconds": tsa, "status": ra["status_name"], "iters": ra["iters"],
+                                   "accepted": ra["accepted"], "restarts": ra["restarts"],
+                                   "rel_kkt_fp64_recheck": s.kkt(x, y)["rel_kkt"],
+                                   "pobj": ra["kkt"]["pobj"]}
+        s.set_opts(adaptive_step=0)
+        print(f"[bench] adaptive steps: time to 1e-4: {tsa:.2f}s {ra['status_name']} iters={ra['iters']} "
+              f"accepted={ra['accepted']} restarts={ra['restarts']}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(lp)
@@ -340,6 +377,7 @@ def main():
         "kernel_src_sha": kernel_src_hash(),
         "sweep_gbs": {"primal": pg, "dual": dg},
         "time_to_tol": ttt,
+        "adaptive_step": adaptive,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -176,10 +176,13 @@ __global__ __launch_bounds__(WG) void k_primal_ad(Dev d)
         const int lb = full ? it : d.actT[it];
         const Seg s = block_seg(op, lb);
         const InstState *st = d.st + s.inst;
-        const int par = st->par;
-        const double eta = st->eta_try, tau = eta / st->omega;
-        const bool first = !(st->eta_sum > 0.0);
-        const double wa = eta / (st->eta_sum + eta);
+        // the state is uniform per block: keep it (and the pointers the buffer
+        // flag selects) in scalar registers
+        const int par = uniform_i(st->par);
+        const double eta = uniform_d(st->eta_try), esum = uniform_d(st->eta_sum);
+        const double tau = uniform_d(eta / uniform_d(st->omega));
+        const bool first = !(esum > 0.0);
+        const double wa = uniform_d(eta / (esum + eta));
         const T *__restrict__ x = (const T *)(par ? d.xbar : d.x);
         T *__restrict__ xn = (T *)(par ? d.x : d.xbar);
         const T *__restrict__ xa = (const T *)(par ? d.xavg1 : d.xavg);
@@ -191,15 +194,16 @@ __global__ __launch_bounds__(WG) void k_primal_ad(Dev d)
             constexpr int L = decltype(tag)::value, R = decltype(rtag)::value;
             using RS = RowSweep<L, 1, T, T, R>;
             const typename RS::Pos ps = RS::locate(s, bi);
+            // rows are < 2^29: 32-bit offsets from the scalar bases
             T r_x[R], r_c[R], r_l[R], r_u[R], r_a[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const int64_t jj = r < ps.nvalid ? ps.row0 + r : ps.blk_row0;
-                r_x[r] = x[jj];
-                r_c[r] = c[jj];
-                r_l[r] = l[jj];
-                r_u[r] = u[jj];
-                r_a[r] = xa[jj];
+                const uint32_t jj = (uint32_t)(r < ps.nvalid ? ps.row0 + r : ps.blk_row0);
+                r_x[r] = ldo(x, jj);
+                r_c[r] = ldo(c, jj);
+                r_l[r] = ldo(l, jj);
+                r_u[r] = ldo(u, jj);
+                r_a[r] = ldo(xa, jj);
             }
             double acc[R][1];
             RS::dot(op, ps, y, nullptr, nullptr, red, acc);
@@ -207,14 +211,14 @@ __global__ __launch_bounds__(WG) void k_primal_ad(Dev d)
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     if (r >= ps.nvalid) break;
-                    const int64_t j = ps.row0 + r;
+                    const uint32_t j = (uint32_t)(ps.row0 + r);
                     const double xo = (double)r_x[r], cj = (double)r_c[r], lo = (double)r_l[r];
                     const double hi = (double)r_u[r], xav = (double)r_a[r];
                     const double v = xo - tau * (cj - acc[r][0]);
                     const double xv = v < lo ? lo : (v > hi ? hi : v);
                     const T xnT = (T)xv;
-                    xn[j] = xnT;
-                    xan[j] = first ? xnT : (T)(xav + ((double)xnT - xav) * wa);
+                    sto(xn, j, xnT);
+                    sto(xan, j, first ? xnT : (T)(xav + ((double)xnT - xav) * wa));
                     const double dx = (double)xnT - xo;
                     part[0] += dx * dx;
                 }
@@ -238,10 +242,11 @@ __global__ __launch_bounds__(WG) void k_dual_ad(Dev d)
         const int lb = full ? it : d.actK[it];
         const Seg s = block_seg(op, lb);
         const InstState *st = d.st + s.inst;
-        const int par = st->par;
-        const double eta = st->eta_try, sigma = eta * st->omega;
-        const bool first = !(st->eta_sum > 0.0);
-        const double wa = eta / (st->eta_sum + eta);
+        const int par = uniform_i(st->par);
+        const double eta = uniform_d(st->eta_try), esum = uniform_d(st->eta_sum);
+        const double sigma = uniform_d(eta * uniform_d(st->omega));
+        const bool first = !(esum > 0.0);
+        const double wa = uniform_d(eta / (esum + eta));
         const T *__restrict__ xc = (const T *)(par ? d.x : d.xbar);  // candidate x'
         const T *__restrict__ y = (const T *)(par ? d.y1 : d.y);
         T *__restrict__ yn = (T *)(par ? d.y : d.y1);
@@ -260,11 +265,11 @@ __global__ __launch_bounds__(WG) void k_dual_ad(Dev d)
             double r_k[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const int64_t ii = r < ps.nvalid ? ps.row0 + r : ps.blk_row0;
-                r_y[r] = y[ii];
-                r_q[r] = q[ii];
-                r_a[r] = ya[ii];
-                r_k[r] = kx[ii];
+                const uint32_t ii = (uint32_t)(r < ps.nvalid ? ps.row0 + r : ps.blk_row0);
+                r_y[r] = ldo(y, ii);
+                r_q[r] = ldo(q, ii);
+                r_a[r] = ldo(ya, ii);
+                r_k[r] = ldo(kx, ii);
             }
             double acc[R][1];
             RS::dot(op, ps, xc, nullptr, nullptr, red, acc);
@@ -272,15 +277,15 @@ __global__ __launch_bounds__(WG) void k_dual_ad(Dev d)
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     if (r >= ps.nvalid) break;
-                    const int64_t i = ps.row0 + r;
+                    const uint32_t i = (uint32_t)(ps.row0 + r);
                     const double a = acc[r][0], kxo = r_k[r];
                     const double yo = (double)r_y[r], qi = (double)r_q[r], yav = (double)r_a[r];
                     const double wv = yo + sigma * (qi - (2.0 * a - kxo));
                     const double yv = (ineq && wv < 0.0) ? 0.0 : wv;
                     const T ynT = (T)yv;
-                    yn[i] = ynT;
-                    kxn[i] = a;
-                    yan[i] = first ? ynT : (T)(yav + ((double)ynT - yav) * wa);
+                    sto(yn, i, ynT);
+                    sto(kxn, i, a);
+                    sto(yan, i, first ? ynT : (T)(yav + ((double)ynT - yav) * wa));
                     const double dy = (double)ynT - yo;
                     part[0] += dy * dy;
                     part[1] += dy * (a - kxo);
@@ -295,11 +300,16 @@ __global__ __launch_bounds__(WG) void k_dual_ad(Dev d)
     });
 }
 
-// One workgroup per instance: the accept / reject decision of the attempt.
+// One 1024-lane workgroup per instance: the accept / reject decision of the
+// attempt.  The per-block sums are read 8 per lane in flight (the kernel is
+// bound by the latency of these loads), then reduced in a fixed order.
 // k counts the attempts of the solve including this one.
-__global__ __launch_bounds__(WG) void k_step_ad(Dev d)
+constexpr int STEP_WG = 1024;
+constexpr int STEP_U = 8;
+
+__global__ __launch_bounds__(STEP_WG) void k_step_ad(Dev d)
 {
-    __shared__ double lds[12];
+    __shared__ double lds[3 * (STEP_WG / 64)];
     const int b = blockIdx.x;
     InstState &st = d.st[b];
     if (st.done) return;
@@ -307,14 +317,47 @@ __global__ __launch_bounds__(WG) void k_step_ad(Dev d)
     const int nT = in.blkT1 - in.blkT0, nK = in.blkK1 - in.blkK0;
     const double *pT = d.adp + 2 * (size_t)d.K.nblk + in.blkT0;
     const double *pK = d.adp + 2 * (size_t)in.blkK0;
+    const int tid = threadIdx.x;
     double v[3] = {0.0, 0.0, 0.0};
-    for (int r = threadIdx.x; r < nT; r += WG) v[0] += pT[r];
-    for (int r = threadIdx.x; r < nK; r += WG) {
-        v[1] += pK[2 * r];
-        v[2] += pK[2 * r + 1];
+    for (int r0 = tid; r0 < nT; r0 += STEP_U * STEP_WG) {
+        double a[STEP_U];
+#pragma unroll
+        for (int k = 0; k < STEP_U; ++k) {
+            const int r = r0 + k * STEP_WG;
+            a[k] = r < nT ? pT[r] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < STEP_U; ++k) v[0] += a[k];
     }
-    block_sum<3>(v, lds);
-    if (threadIdx.x != 0) return;
+    for (int r0 = tid; r0 < nK; r0 += STEP_U * STEP_WG) {
+        double a[STEP_U], c[STEP_U];
+#pragma unroll
+        for (int k = 0; k < STEP_U; ++k) {
+            const int r = r0 + k * STEP_WG;
+            a[k] = r < nK ? pK[2 * r] : 0.0;
+            c[k] = r < nK ? pK[2 * r + 1] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < STEP_U; ++k) {
+            v[1] += a[k];
+            v[2] += c[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = group_reduce<64, false>(v[k]);
+    const int wave = tid >> 6;
+    if ((tid & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) lds[k * (STEP_WG / 64) + wave] = v[k];
+    }
+    __syncthreads();
+    if (tid != 0) return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double t = 0.0;
+        for (int w = 0; w < STEP_WG / 64; ++w) t += lds[k * (STEP_WG / 64) + w];
+        v[k] = t;
+    }
     const double w = st.omega, eta = st.eta_try;
     const long long k = st.k_att + 1;
     const double den = fabs(2.0 * v[2]);
@@ -1198,7 +1241,10 @@ void launch_dual_ad(const Dev &d, hipStream_t s)
     RM_SWITCH(d.K.rmax, { LAUNCH((k_dual_ad<T, RMV>), g, d); });
 }
 
-void launch_step_ad(const Dev &d, hipStream_t s) { LAUNCH(k_step_ad, (unsigned)d.batch, d); }
+void launch_step_ad(const Dev &d, hipStream_t s)
+{
+    if (d.batch > 0) hipLaunchKernelGGL(k_step_ad, dim3(d.batch), dim3(STEP_WG), 0, s, d);
+}
 
 template <typename T>
 void launch_commit_ad(const Dev &d, hipStream_t s)

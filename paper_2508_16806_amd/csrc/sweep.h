@@ -26,6 +26,18 @@ __device__ __forceinline__ int logical_block(int remap)
     return xcd * q + (xcd < r ? xcd : r) + (b >> 3);
 }
 
+// A value the caller knows to be the same in every lane (read from per-
+// instance state at a uniform address), moved to scalar registers so it costs
+// no vector registers.
+__device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uniform_d(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Work items [0, cnt) of a bounded grid.  With `remap`, XCD x (the hardware
 // places workgroup b on XCD b mod 8) takes the contiguous item range
 // [x * ceil(cnt/8), (x + 1) * ceil(cnt/8)) and its workgroups stride through
@@ -79,6 +91,13 @@ template <typename V>
 __device__ __forceinline__ V ldo(const V *base, uint32_t idx)
 {
     return *(const V *)((const char *)base + idx * (uint32_t)sizeof(V));
+}
+
+// Store with a 32-bit byte offset from a workgroup-uniform base (as ldo).
+template <typename V>
+__device__ __forceinline__ void sto(V *base, uint32_t idx, V v)
+{
+    *(V *)((char *)base + idx * (uint32_t)sizeof(V)) = v;
 }
 
 // Sum (or max when MAXABS) of a value across the L lanes of a group.
