@@ -167,7 +167,7 @@ def _plant(rng, n, rowptr, col, val, row_type, u, frac_zero=0.5, frac_int=0.4,
 
 def planted(m: int, n: int, density: float, seed: int, ge_frac: float = 0.0,
             u_range=(1.0, 10.0), unique: bool = False, name: str = "planted") -> LP:
-    """Random sparse LP with a planted optimal pair (BASELINE config 0 recipe).
+    """Random sparse LP with a planted optimal pair (the recipe of C0 and C3).
 
     Entries of K are nonzero with probability ``density`` and N(0,1) valued,
     0 <= x <= u with u ~ U(u_range), x* half at 0, 40% interior, 10% at u,
@@ -444,3 +444,65 @@ def from_dense(a: np.ndarray, row_type, rhs, c, l, u, name="dense") -> LP:
     return LP(n, m, rowptr, col, val, np.asarray(row_type, dtype=np.uint8),
               np.asarray(rhs, dtype=np.float64), np.asarray(c, dtype=np.float64),
               np.asarray(l, dtype=np.float64), np.asarray(u, dtype=np.float64), name=name)
+
+
+# ---------------------------------------------------------------------------
+# infeasible and unbounded LPs (Section 2.4.5 test cases)
+# ---------------------------------------------------------------------------
+
+def _append(lp: LP, rows, cols, vals, row_type, rhs, n_new: int = 0, c_new=(), l_new=(), u_new=(),
+            name: str = "") -> LP:
+    """lp with extra rows (COO entries with row indices counted from lp.m) and
+    n_new extra columns (indices from lp.n)."""
+    r0 = np.repeat(np.arange(lp.m, dtype=np.int64), np.diff(lp.rowptr))
+    r = np.concatenate([r0, np.asarray(rows, dtype=np.int64)])
+    cc = np.concatenate([np.asarray(lp.col, dtype=np.int64), np.asarray(cols, dtype=np.int64)])
+    v = np.concatenate([np.asarray(lp.val), np.asarray(vals, dtype=np.float64)])
+    m = lp.m + len(row_type)
+    n = lp.n + n_new
+    rowptr, col, val = _csr_from_coo(m, r, cc, v)
+    return LP(n, m, rowptr, col, val,
+              np.concatenate([lp.row_type, np.asarray(row_type, dtype=np.uint8)]),
+              np.concatenate([lp.rhs, np.asarray(rhs, dtype=np.float64)]),
+              np.concatenate([lp.c, np.asarray(c_new, dtype=np.float64)]),
+              np.concatenate([lp.l, np.asarray(l_new, dtype=np.float64)]),
+              np.concatenate([lp.u, np.asarray(u_new, dtype=np.float64)]), name=name or lp.name)
+
+
+def primal_infeasible(m: int, n: int, density: float, seed: int, kind: str = "bound") -> LP:
+    """A planted LP made infeasible.  kind "bound": one more ">=" row
+    x_j >= u_j + 1 on a boxed variable j; kind "pair": a random sparse row a
+    twice, as a x >= h and -a x >= 1 - h (so a x <= h - 1)."""
+    base = planted(m, n, density, seed, ge_frac=0.5)
+    rng = np.random.default_rng(seed + 7919)
+    if kind == "bound":
+        j = int(rng.integers(n))
+        return _append(base, [m], [j], [1.0], [GE], [base.u[j] + 1.0], name=f"infeas-bound({m}x{n})")
+    k = max(2, int(density * n))
+    cols = rng.choice(n, size=k, replace=False)
+    a = rng.standard_normal(k)
+    h = float(rng.standard_normal())
+    return _append(base, [m] * k + [m + 1] * k, list(cols) * 2, list(a) + list(-a), [GE, GE],
+                   [h, 1.0 - h], name=f"infeas-pair({m}x{n})")
+
+
+def dual_infeasible(m: int, n: int, density: float, seed: int) -> LP:
+    """A planted LP made unbounded: one more variable t >= 0 (no upper bound)
+    with cost -1 that appears only in ">=" rows, with positive coefficients,
+    so x* + s e_t is feasible for every s >= 0 and the objective falls without
+    bound."""
+    base = planted(m, n, density, seed, ge_frac=0.5)
+    rng = np.random.default_rng(seed + 104729)
+    ge = np.nonzero(base.row_type == GE)[0]
+    k = max(1, min(len(ge), int(round(density * m)) + 1))
+    rows = rng.choice(ge, size=k, replace=False) if len(ge) else np.zeros(0, dtype=np.int64)
+    vals = rng.uniform(0.5, 2.0, size=len(rows))
+    out = _append(base, [], [], [], [], [], name=f"unbounded({m}x{n})")
+    # the new column: rebuild with its entries
+    r0 = np.repeat(np.arange(out.m, dtype=np.int64), np.diff(out.rowptr))
+    r = np.concatenate([r0, rows.astype(np.int64)])
+    cc = np.concatenate([np.asarray(out.col, dtype=np.int64), np.full(len(rows), n, dtype=np.int64)])
+    v = np.concatenate([np.asarray(out.val), vals])
+    rowptr, col, val = _csr_from_coo(out.m, r, cc, v)
+    return LP(n + 1, out.m, rowptr, col, val, out.row_type, out.rhs, np.append(out.c, -1.0),
+              np.append(out.l, 0.0), np.append(out.u, np.inf), name=out.name)

@@ -51,7 +51,16 @@ class Opts(C.Structure):
                 ("step_size", C.c_double), ("step_frac", C.c_double), ("primal_weight", C.c_double),
                 ("power_max_iters", C.c_int), ("power_tol", C.c_double), ("beta_suff", C.c_double),
                 ("beta_nec", C.c_double), ("beta_art", C.c_double), ("eps_zero", C.c_double),
-                ("adaptive_step", C.c_int)]
+                ("adaptive_step", C.c_int), ("detect_infeas", C.c_int), ("infeas_tol", C.c_double)]
+
+
+class InfeasOut(C.Structure):
+    _fields_ = [("eq_norm", C.c_double), ("ineq_min", C.c_double), ("c_dx", C.c_double),
+                ("v_viol", C.c_double), ("res_norm", C.c_double), ("dy_min", C.c_double),
+                ("psi", C.c_double), ("verdict", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class Result(C.Structure):
@@ -95,6 +104,8 @@ def _load():
         L.orc_steps.argtypes = [P, C.c_double, C.c_double, D, D, C.c_longlong]
         L.orc_solve.restype = C.c_int
         L.orc_solve.argtypes = [P, C.POINTER(Opts), D, D, C.POINTER(Result), C.c_void_p, C.c_int]
+        L.orc_infeas_test.restype = C.c_int
+        L.orc_infeas_test.argtypes = [P, D, D, D, D, C.c_double, C.POINTER(InfeasOut)]
         L.orc_adaptive_attempt.restype = C.c_int
         L.orc_adaptive_attempt.argtypes = [P, C.c_double, C.c_double, C.c_longlong, D, D, D, D,
                                            C.POINTER(C.c_double), C.POINTER(C.c_double)]
@@ -119,7 +130,9 @@ class SolveOpts:
     Choices the paper leaves open: 10 Ruiz passes, a check every 64 iterations,
     power iteration to 1e-6 relative change or 1000 passes.  adaptive_step
     turns on the backtracking step size of Algorithm 5 (Section 2.4.4); the
-    first attempt tries the fixed step.
+    first attempt tries the fixed step.  detect_infeas turns on the
+    infeasibility tests of Algorithm 6 (Section 2.4.5) at every check, on the
+    difference of the last step, with tolerance infeas_tol (1e-4, Section 4).
     """
 
     ruiz_iters: int = 10
@@ -138,6 +151,8 @@ class SolveOpts:
     beta_art: float = 0.36
     eps_zero: float = 1e-6
     adaptive_step: bool = False
+    detect_infeas: bool = False
+    infeas_tol: float = 1e-4
 
     @staticmethod
     def plain(**kw) -> "SolveOpts":
@@ -151,7 +166,8 @@ class SolveOpts:
         return Opts(self.ruiz_iters, int(self.use_restarts), int(self.use_pw_update),
                     self.check_every, self.max_iters, self.eps, self.step_size, self.step_frac,
                     self.primal_weight, self.power_max_iters, self.power_tol, self.beta_suff,
-                    self.beta_nec, self.beta_art, self.eps_zero, int(self.adaptive_step))
+                    self.beta_nec, self.beta_art, self.eps_zero, int(self.adaptive_step),
+                    int(self.detect_infeas), self.infeas_tol)
 
 
 @dataclass
@@ -270,6 +286,15 @@ class Oracle:
         return SolveResult(r.status, x, self.to_user_rows(y), r.iters, r.restarts, bool(r.from_avg),
                            r.knorm, r.eta, r.omega0, r.omega, r.kkt.as_dict(), r.power_iters, trace,
                            r.accepted, r.eta_next)
+
+    def infeas_test(self, x, y, xp, yp, tol: float = 1e-4) -> dict:
+        """Algorithm 6's tests on the original LP for dx = x - xp, dy = y - yp
+        (original variables, y in user row order); verdict 0 none, 1 primal
+        infeasible, 2 dual infeasible."""
+        out = InfeasOut()
+        self.lib.orc_infeas_test(self.h, _f64(x), self.to_internal_rows(y), _f64(xp), self.to_internal_rows(yp),
+                                 tol, C.byref(out))
+        return out.as_dict()
 
     def adaptive_attempt(self, x, y, omega, eta, k, ruiz_iters: int = 0):
         """One attempt of Algorithm 5 on the scaled problem from (x, y) (scaled

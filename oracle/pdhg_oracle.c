@@ -28,6 +28,8 @@
  *                                  etabar >= 1/||K||_2 from Cauchy-Schwarz)
  *   orc_solve, adaptive steps .... pinned (planted f*, HiGHS); the sequence of
  *                                  accepted steps is parity unpinned.
+ *   orc_infeas_test .............. pinned (hand-worked Farkas rays, HiGHS
+ *                                  infeasible / unbounded verdicts)
  *   orc_unrolled_vjp ............. pinned (central finite differences)
  */
 #include <math.h>
@@ -442,6 +444,108 @@ int orc_adaptive_attempt(const orc_prob *p, double omega, double eta, long long 
 }
 
 /* ------------------------------------------------------------------------- */
+/* infeasibility detection (Section 2.4.5, Algorithm 6)                       */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    double eq_norm;      /* ||A dx||_2                                          */
+    double ineq_min;     /* min_i (G dx)_i (+inf without inequality rows)       */
+    double c_dx;         /* c' dx                                               */
+    double v_viol;       /* largest violation of dx_j in V_j                    */
+    double res_norm;     /* ||K' dy + dlambda||_2                               */
+    double dy_min;       /* min_i dy_i over inequality rows (+inf without)      */
+    double psi;          /* q' dy + l' dlambda^+ + u' dlambda^- (-inf when an   */
+                         /* infinite bound meets a nonzero multiplier)          */
+    int verdict;         /* 0 none, 1 primal infeasible, 2 dual infeasible      */
+} orc_infeas_t;
+
+/* The tests of Algorithm 6 on the ORIGINAL LP p for the difference of two
+ * iterates given in original variables: dx = x - xp, dy = y - yp, and
+ * dlambda = lambda(y) - lambda(yp) with lambda(y) = proj_Lambda(c - K'y).
+ * A certificate is a ray that improves its objective; each test measures the
+ * ray in units of that improvement (the ray scaled to improve it by one):
+ * dual infeasibility (dx is a primal ray): c'dx < 0 and, relative to |c'dx|,
+ * ||A dx|| <= tol, min(G dx) >= -tol and dx_j in V_j (the recession cone of
+ * [l_j, u_j]: R, R^-, R^+ or {0}) to within tol.  Primal infeasibility
+ * ((dy, dlambda) is a dual ray): psi > 0 and, relative to psi,
+ * ||K'dy + dlambda|| <= tol (lambda = c - K'y moves opposite to K'y) and
+ * min(dy_ineq) >= -tol.  The dual test is taken first. */
+int orc_infeas_test(const orc_prob *p, const double *x, const double *y, const double *xp,
+                    const double *yp, double tol, orc_infeas_t *out)
+{
+    int64_t n = p->n, m = p->m;
+    double *dx = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+    double *dy = (double *)malloc((size_t)(m ? m : 1) * sizeof(double));
+    double *kv = (double *)malloc((size_t)(m ? m : 1) * sizeof(double));
+    double *g1 = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+    double *g0 = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+    double *gd = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+    for (int64_t j = 0; j < n; ++j) dx[j] = x[j] - xp[j];
+    for (int64_t i = 0; i < m; ++i) dy[i] = y[i] - yp[i];
+
+    /* dual-infeasibility quantities */
+    orc_spmv(p, dx, kv);
+    double eq2 = 0.0, imin = INFINITY, cdx = 0.0, viol = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+        if (i < p->m1) {
+            if (kv[i] < imin) imin = kv[i];
+        } else {
+            eq2 += kv[i] * kv[i];
+        }
+    }
+    for (int64_t j = 0; j < n; ++j) {
+        cdx += p->c[j] * dx[j];
+        int lf = isfinite(p->l[j]), uf = isfinite(p->u[j]);
+        double v = 0.0;
+        if (lf && uf) v = fabs(dx[j]);          /* {0}  */
+        else if (lf) v = -dx[j];                /* R^+  */
+        else if (uf) v = dx[j];                 /* R^-  */
+        if (v > viol) viol = v;
+    }
+
+    /* primal-infeasibility quantities */
+    orc_spmv_t(p, y, g1);
+    orc_spmv_t(p, yp, g0);
+    orc_spmv_t(p, dy, gd);
+    double r2 = 0.0, psi = 0.0, dymin = INFINITY;
+    int inf_term = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        double dl = proj_lambda(p->c[j] - g1[j], p->l[j], p->u[j]) -
+                    proj_lambda(p->c[j] - g0[j], p->l[j], p->u[j]);
+        double r = gd[j] + dl;
+        r2 += r * r;
+        if (dl > 0.0) {
+            if (isfinite(p->l[j])) psi += p->l[j] * dl;
+            else inf_term = 1;
+        } else if (dl < 0.0) {
+            if (isfinite(p->u[j])) psi += p->u[j] * dl;
+            else inf_term = 1;
+        }
+    }
+    for (int64_t i = 0; i < m; ++i) {
+        psi += p->q[i] * dy[i];
+        if (i < p->m1 && dy[i] < dymin) dymin = dy[i];
+    }
+    if (inf_term) psi = -INFINITY;
+
+    out->eq_norm = sqrt(eq2);
+    out->ineq_min = imin;
+    out->c_dx = cdx;
+    out->v_viol = viol;
+    out->res_norm = sqrt(r2);
+    out->dy_min = dymin;
+    out->psi = psi;
+    out->verdict = 0;
+    const double sd = -cdx, sp = psi; /* objective improvements along the rays */
+    if (sd > 0.0 && out->eq_norm <= tol * sd && imin >= -tol * sd && viol <= tol * sd)
+        out->verdict = 2;
+    else if (sp > 0.0 && out->res_norm <= tol * sp && dymin >= -tol * sp)
+        out->verdict = 1;
+    free(dx); free(dy); free(kv); free(g1); free(g0); free(gd);
+    return out->verdict;
+}
+
+/* ------------------------------------------------------------------------- */
 /* restarted PDHG solve (Sections 2.3-2.4: Algorithms 1-4, restarts)          */
 /* ------------------------------------------------------------------------- */
 
@@ -460,10 +564,13 @@ typedef struct {
     double beta_suff, beta_nec, beta_art; /* restart constants 0.2 0.8 0.36   */
     double eps_zero;       /* 1e-6                                             */
     int adaptive_step;     /* backtracking step size, Algorithm 5              */
+    int detect_infeas;     /* infeasibility detection, Algorithm 6             */
+    double infeas_tol;     /* its tolerance (1e-4)                             */
 } orc_opts;
 
 typedef struct {
-    int status;            /* 0 optimal, 1 iteration limit                     */
+    int status;            /* 0 optimal, 1 iteration limit, 4 primal           */
+                           /* infeasible, 5 dual infeasible                    */
     int from_avg;          /* returned point is the average (1) or iterate (0) */
     long long iters;
     int restarts;
@@ -533,6 +640,12 @@ int orc_solve(const orc_prob *p, const orc_opts *o, double *x_out, double *y_out
         xn = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
         yn = (double *)malloc((size_t)(m ? m : 1) * sizeof(double));
     }
+    /* iterate before the last step of a check period (infeasibility detection) */
+    double *xp = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+    double *yp = (double *)malloc((size_t)(m ? m : 1) * sizeof(double));
+    double *xpu = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+    double *ypu = (double *)malloc((size_t)(m ? m : 1) * sizeof(double));
+    int prev_ok = 0;
     orc_work w;
     work_alloc(s, &w);
 
@@ -569,11 +682,19 @@ int orc_solve(const orc_prob *p, const orc_opts *o, double *x_out, double *y_out
                 accepted = orc_adaptive_attempt(s, omega, eta_try, k_att, x, y, xn, yn, &etabar, &etan);
                 wgt = eta_try;
                 if (accepted) {
+                    memcpy(xp, x, (size_t)n * sizeof(double));
+                    memcpy(yp, y, (size_t)m * sizeof(double));
                     memcpy(x, xn, (size_t)n * sizeof(double));
                     memcpy(y, yn, (size_t)m * sizeof(double));
                 }
+                prev_ok = accepted; /* the difference is one step only if the last attempt moved */
                 eta_try = etan;
             } else {
+                if (it == o->check_every - 1) {
+                    memcpy(xp, x, (size_t)n * sizeof(double));
+                    memcpy(yp, y, (size_t)m * sizeof(double));
+                    prev_ok = 1;
+                }
                 step(s, eta / omega, eta * omega, x, y, &w);
             }
             ++k_total;
@@ -623,6 +744,29 @@ int orc_solve(const orc_prob *p, const orc_opts *o, double *x_out, double *y_out
         } else if (o->use_restarts && k_other->rel_kkt <= o->eps) {
             status = 0;
             from_avg = !cand_avg;
+        }
+        /* infeasibility (Algorithm 6) on the last step's difference, in the
+         * original variables; the returned point is the current iterate */
+        if (status != 0 && o->detect_infeas && prev_ok) {
+            orc_infeas_t inf;
+            for (int64_t j = 0; j < n; ++j) {
+                xu[j] = kap[j] * x[j];
+                xpu[j] = kap[j] * xp[j];
+            }
+            for (int64_t i = 0; i < m; ++i) {
+                yu[i] = rho[i] * y[i];
+                ypu[i] = rho[i] * yp[i];
+            }
+            int v = orc_infeas_test(p, xu, yu, xpu, ypu, o->infeas_tol, &inf);
+            if (v) {
+                status = v == 1 ? 4 : 5;
+                res->kkt = kc;
+                ret_x = x;
+                ret_y = y;
+                from_avg = 0;
+                if (trace && tl < trace_cap) trace[tl++] = rec;
+                break;
+            }
         }
         if (status == 0 || k_total >= o->max_iters) {
             if (status != 0) from_avg = cand_avg;
@@ -687,6 +831,7 @@ done:
     work_free(&w);
     free(xn);
     free(yn);
+    free(xp); free(yp); free(xpu); free(ypu);
     free(x); free(y); free(xs); free(ys); free(xa); free(ya);
     free(x0); free(y0); free(xu); free(yu);
     free(rho); free(kap);

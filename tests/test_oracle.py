@@ -556,3 +556,75 @@ def test_adaptive_first_check_weighted_average(orc):
     # the plain mean of the same iterates is measurably different (the weights matter)
     plain = o.kkt(kap * ux / acc_n, rho * uy / acc_n)
     assert abs(plain["rel_kkt"] - avg["rel_kkt"]) > 1e3 * abs(t0["rel_kkt_avg"] - avg["rel_kkt"])
+
+
+# ---------------------------------------------------------------------------
+# infeasibility detection (Section 2.4.5, Algorithm 6)
+# ---------------------------------------------------------------------------
+
+def _fl(v):
+    return np.array([float(t) for t in v], dtype=np.float64)
+
+
+def test_infeas_golden_cases(orc):
+    with open(os.path.join(GOLD, "infeas_cases.json")) as f:
+        g = json.load(f)
+    for cs in g["cases"]:
+        lp = lpgen.from_dense(np.array(cs["K"]), cs["row_type"], cs["rhs"], cs["c"], _fl(cs["l"]), _fl(cs["u"]))
+        out = orc.Oracle(lp).infeas_test(_fl(cs["x"]), _fl(cs["y"]), _fl(cs["xp"]), _fl(cs["yp"]), g["tol"])
+        assert out["verdict"] == cs["verdict"], (cs["name"], out)
+        for k in ("psi", "res_norm", "c_dx", "ineq_min", "v_viol"):
+            if k in cs:
+                want = float(cs[k])
+                if np.isinf(want):
+                    assert out[k] == want, (cs["name"], k)
+                else:
+                    assert out[k] == pytest.approx(want, rel=1e-9, abs=1e-15), (cs["name"], k, out[k])
+
+
+def _highs_status(lp):
+    from scipy.optimize import linprog
+
+    A = lp.scipy().toarray()
+    ge, eq = lp.row_type == 0, lp.row_type == 1
+    bounds = [(None if not np.isfinite(a) else a, None if not np.isfinite(b) else b) for a, b in zip(lp.l, lp.u)]
+    r = linprog(lp.c, A_ub=-A[ge] if ge.any() else None, b_ub=-lp.rhs[ge] if ge.any() else None,
+                A_eq=A[eq] if eq.any() else None, b_eq=lp.rhs[eq] if eq.any() else None, bounds=bounds,
+                method="highs")
+    return r.status  # 0 optimal, 2 infeasible, 3 unbounded
+
+
+@pytest.mark.parametrize("maker,want,highs", [
+    (lambda: lpgen.primal_infeasible(60, 150, 0.05, 1, "bound"), 4, 2),
+    (lambda: lpgen.primal_infeasible(60, 150, 0.05, 2, "pair"), 4, 2),
+    (lambda: lpgen.primal_infeasible(300, 700, 0.02, 4, "pair"), 4, 2),
+    (lambda: lpgen.dual_infeasible(60, 150, 0.05, 3), 5, 3),
+    (lambda: lpgen.dual_infeasible(300, 700, 0.02, 5), 5, 3),
+])
+@pytest.mark.parametrize("adaptive", [False, True])
+def test_infeas_detected_matches_highs(orc, maker, want, highs, adaptive):
+    lp = maker()
+    assert _highs_status(lp) == highs
+    r = orc.Oracle(lp).solve(orc.SolveOpts(eps=1e-6, detect_infeas=True, adaptive_step=adaptive,
+                                           max_iters=100_000))
+    assert r.status == want, (r.status, r.iters)
+    without = orc.Oracle(lp).solve(orc.SolveOpts(eps=1e-6, adaptive_step=adaptive, max_iters=r.iters + 640))
+    assert without.status == 1  # no optimum exists: only the iteration limit stops it
+
+
+@pytest.mark.parametrize("maker", [lambda: lpgen.config0(1, unique=True),
+                                   lambda: lpgen.planted(300, 700, 0.02, 5, ge_frac=0.5),
+                                   lambda: lpgen.sced(40, 16, 8, 12, seed=5),
+                                   lambda: lpgen.tiny(3, n=8, m=4, free_frac=0.5),
+                                   lambda: lpgen.planted(100, 250, 0.05, 9, ge_frac=0.8)])
+@pytest.mark.parametrize("adaptive", [False, True])
+def test_infeas_no_false_positive(orc, maker, adaptive):
+    """On feasible bounded LPs detection never fires: the solve takes the same
+    path as without it."""
+    lp = maker()
+    o = orc.Oracle(lp)
+    a = o.solve(orc.SolveOpts(eps=1e-8, detect_infeas=True, adaptive_step=adaptive, max_iters=60_000))
+    b = o.solve(orc.SolveOpts(eps=1e-8, adaptive_step=adaptive, max_iters=60_000))
+    assert a.status == b.status and a.status in (0, 1)
+    assert a.iters == b.iters
+    np.testing.assert_array_equal(a.x, b.x)
