@@ -51,6 +51,9 @@ extern "C" {
 #define PDHG_ITERATION_LIMIT 1
 #define PDHG_TIME_LIMIT 2
 #define PDHG_NUMERICAL_ERROR 3  /* a reduction in the check became NaN/inf     */
+#define PDHG_PRIMAL_INFEASIBLE 4 /* a dual ray certifies it (Section 2.4.5)     */
+#define PDHG_DUAL_INFEASIBLE 5   /* a primal ray certifies it: the LP is         */
+                                 /* unbounded if it is feasible                 */
 
 /* ---- enumerations ---------------------------------------------------------- */
 #define PDHG_MEM_HOST 0
@@ -140,6 +143,18 @@ typedef struct {
      * check_every and max_iters count attempts.  pdhg_iterate always takes
      * fixed steps. */
     int32_t adaptive_step;
+    /* Infeasibility detection (Section 2.4.5, Algorithm 6), 0 or 1.  At every
+     * check, on the difference of the last step in the original variables
+     * (dx, dy, dlambda with lambda = proj_Lambda(c - K'y); with adaptive steps
+     * only when the last attempt was accepted): the LP is reported
+     * PDHG_DUAL_INFEASIBLE when c'dx < 0 and ||A dx||, -min(G dx) and the
+     * largest violation of dx_j in the recession cone of [l_j, u_j] are all
+     * <= infeas_tol * |c'dx|; else PDHG_PRIMAL_INFEASIBLE when
+     * psi = q'dy + l'dlambda^+ + u'dlambda^- > 0 (-inf when an infinite bound
+     * meets a nonzero multiplier) and ||K'dy + dlambda|| and -min(dy_ineq)
+     * are <= infeas_tol * psi.  The returned point is the current iterate. */
+    int32_t detect_infeas;
+    double infeas_tol;         /* default 1e-4                                      */
 } pdhg_opts;
 
 /* Relative KKT error terms (Section 2.3.2, conditions term1-term3) on the

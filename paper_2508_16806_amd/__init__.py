@@ -24,7 +24,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpdhg.so"
 MEM_HOST, MEM_DEVICE = 0, 1
 PREC_F64, PREC_F32 = 0, 1
 SOL_RESULT, SOL_CURRENT, SOL_AVERAGE = 0, 1, 2
-STATUS = {0: "OPTIMAL", 1: "ITERATION_LIMIT", 2: "TIME_LIMIT", 3: "NUMERICAL_ERROR"}
+STATUS = {0: "OPTIMAL", 1: "ITERATION_LIMIT", 2: "TIME_LIMIT", 3: "NUMERICAL_ERROR", 4: "PRIMAL_INFEASIBLE",
+          5: "DUAL_INFEASIBLE"}
 ERRORS = {-1: "INVALID_ARG", -2: "SHAPE", -3: "BOUNDS", -4: "NONFINITE", -5: "NOMEM", -6: "HIP",
           -7: "STATE"}
 
@@ -51,7 +52,8 @@ class Opts(C.Structure):
                 ("unroll_capacity", C.c_int32), ("unroll_checkpoint", C.c_int32),
                 ("use_graph", C.c_int32), ("xcd_remap", C.c_int32), ("bin_len_dual", C.c_int32 * 8),
                 ("bin_len_primal", C.c_int32 * 8), ("bin_rows_dual", C.c_int32 * 8),
-                ("bin_rows_primal", C.c_int32 * 8), ("max_grid", C.c_int32), ("adaptive_step", C.c_int32)]
+                ("bin_rows_primal", C.c_int32 * 8), ("max_grid", C.c_int32), ("adaptive_step", C.c_int32),
+                ("detect_infeas", C.c_int32), ("infeas_tol", C.c_double)]
 
 
 class KKTOut(C.Structure):

@@ -74,6 +74,8 @@ extern "C" void pdhg_default_opts(pdhg_opts *o)
     o->xcd_remap = 1;
     o->max_grid = 8192;
     o->adaptive_step = 0;
+    o->detect_infeas = 0;
+    o->infeas_tol = 1e-4;
 }
 
 // ---------------------------------------------------------------------------
@@ -359,8 +361,8 @@ static void carve(Carve &cv, const Sizes &sz, int prec, const pdhg_opts &o, Dev 
     d.inst_of_row = cv.take<int32_t>(M);
     *info = cv.take<InstInfo>(sz.batch);
     *st = cv.take<InstState>(sz.batch);
-    d.partials = cv.take<double>((size_t)(sz.nblkK + sz.nblkT) * NCAND * NSUM + 1);
-    d.partials2 = cv.take<double>((size_t)sz.nl2 * NCAND * NSUM + 1);
+    d.partials = cv.take<double>((size_t)(sz.nblkK + sz.nblkT) * NPART + 1);
+    d.partials2 = cv.take<double>((size_t)sz.nl2 * NPART + 1);
     d.adp = cv.take<double>(2 * (size_t)sz.nblkK + sz.nblkT + 1);
     // second buffers of the adaptive step size
     d.xavg1 = cv.take<char>(N * es);
@@ -411,6 +413,8 @@ static int check_opts(const pdhg_opts *o)
         return fail(PDHG_ERR_INVALID_ARG, "bad unroll capacity / checkpoint");
     if (!(o->step_frac > 0.0) && !(o->step_size > 0.0)) return fail(PDHG_ERR_INVALID_ARG, "step_frac must be > 0");
     if (o->adaptive_step != 0 && o->adaptive_step != 1) return fail(PDHG_ERR_INVALID_ARG, "adaptive_step must be 0 or 1");
+    if (o->detect_infeas != 0 && o->detect_infeas != 1) return fail(PDHG_ERR_INVALID_ARG, "detect_infeas must be 0 or 1");
+    if (o->detect_infeas && !(o->infeas_tol > 0.0)) return fail(PDHG_ERR_INVALID_ARG, "infeas_tol must be > 0");
     return PDHG_OK;
 }
 
@@ -749,6 +753,7 @@ static int device_setup(pdhg_handle *h, hipStream_t s)
     HIPCHK(hipMemsetAsync(d.yavg1, 0, d.M * es, s));
     HIPCHK(hipMemsetAsync(d.kx0, 0, d.M * sizeof(double), s));
     HIPCHK(hipMemsetAsync(d.kx1, 0, d.M * sizeof(double), s));
+    HIPCHK(hipMemsetAsync(d.partials, 0, (size_t)(d.K.nblk + d.Kt.nblk) * NPART * sizeof(double), s));
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
     return PDHG_OK;
@@ -859,6 +864,8 @@ static CtlParams ctl_params(const pdhg_handle *h)
     P.use_pw = o.use_pw_update;
     P.batch = h->batch;
     P.adaptive = o.adaptive_step;
+    P.detect = o.detect_infeas;
+    P.infeas_tol = o.infeas_tol;
     return P;
 }
 
@@ -868,6 +875,7 @@ static void enqueue_chunk(const pdhg_handle *h, hipStream_t s)
 {
     const Dev &d = h->d;
     const int avg = h->opts.use_restarts;
+    const int detect = h->opts.detect_infeas;
     if (h->opts.adaptive_step) {
         // Algorithm 5: check_every attempts, then the current buffers move to 0
         for (int j = 0; j < h->opts.check_every; ++j) {
@@ -878,11 +886,15 @@ static void enqueue_chunk(const pdhg_handle *h, hipStream_t s)
         launch_commit_ad<T>(d, s);
     } else {
         for (int j = 0; j < h->opts.check_every; ++j) {
+            if (detect && j == h->opts.check_every - 1) launch_save_prev<T>(d, s);
             launch_primal<T>(d, j, avg, nullptr, s);
             launch_dual<T>(d, j, avg, nullptr, s);
         }
     }
     launch_check<T>(d, avg, s);
+    // Algorithm 6 on the difference of the last step: the iterate before it is
+    // in (xavg1, y1) with fixed steps, in buffer 1 (xbar, y1) with adaptive ones
+    if (detect) launch_infeas<T>(d, h->opts.adaptive_step ? d.xbar : d.xavg1, d.y1, s);
     launch_control(d, ctl_params(h), h->opts.check_every, s);
     if (avg) {
         launch_restart<T>(d, s);
@@ -934,6 +946,7 @@ static int solve_impl(pdhg_handle *h, pdhg_result *res, hipStream_t s)
         x.eta_sum = 0.0;
         x.k_att = 0;
         x.n_acc = 0;
+        x.prev_ok = 0;
     }
     std::memset(h->hdone_host, 0, sizeof(int32_t) * B);
     HIPCHK(hipMemcpyAsync(d.st, st.data(), B * sizeof(InstState), hipMemcpyHostToDevice, s));
@@ -1395,13 +1408,16 @@ extern "C" int pdhg_set_opts(pdhg_handle *h, const pdhg_opts *o)
     t.eps_zero = o->eps_zero;
     t.use_graph = o->use_graph;
     t.adaptive_step = o->adaptive_step;
+    t.detect_infeas = o->detect_infeas;
+    t.infeas_tol = o->infeas_tol;
     int rc = check_opts(&t);
     if (rc) return rc;
     const bool regraph = t.use_restarts != h->opts.use_restarts || t.check_every != h->opts.check_every ||
                          t.use_pw_update != h->opts.use_pw_update || t.eps != h->opts.eps ||
                          t.max_iters != h->opts.max_iters || t.beta_suff != h->opts.beta_suff ||
                          t.beta_nec != h->opts.beta_nec || t.beta_art != h->opts.beta_art ||
-                         t.eps_zero != h->opts.eps_zero || t.adaptive_step != h->opts.adaptive_step;
+                         t.eps_zero != h->opts.eps_zero || t.adaptive_step != h->opts.adaptive_step ||
+                         t.detect_infeas != h->opts.detect_infeas || t.infeas_tol != h->opts.infeas_tol;
     if (regraph && h->graph) {
         hipGraphExecDestroy(h->graph);
         h->graph = nullptr;

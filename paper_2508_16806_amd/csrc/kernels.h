@@ -20,6 +20,10 @@ void launch_commit_ad(const Dev &d, hipStream_t s);
 template <typename T>
 void launch_kx_ad(const Dev &d, int all, hipStream_t s);
 template <typename T>
+void launch_infeas(const Dev &d, const void *xp, const void *yp, hipStream_t s);
+template <typename T>
+void launch_save_prev(const Dev &d, hipStream_t s);
+template <typename T>
 void launch_check(const Dev &d, int avg, hipStream_t s);
 void launch_check64(const Dev &d, const double *xs, const double *ys, hipStream_t s);
 void launch_control(const Dev &d, const CtlParams &P, int iters_done, hipStream_t s);

@@ -366,6 +366,7 @@ __global__ __launch_bounds__(STEP_WG) void k_step_ad(Dev d)
     const double shrink = (1.0 - pow(kk, -0.3)) * etabar;
     const double grow = (1.0 + pow(kk, -0.6)) * eta;
     st.k_att = k;
+    st.prev_ok = eta <= etabar;
     if (eta <= etabar) {
         st.par ^= 1;
         st.eta_sum += eta;
@@ -375,8 +376,10 @@ __global__ __launch_bounds__(STEP_WG) void k_step_ad(Dev d)
 }
 
 // Before a check: every running instance's current iterate, its average and
-// K~ x move to buffer 0.  An epoch without an accepted step has no average:
-// the average is set to the iterate.  (k_control then resets par.)
+// K~ x move to buffer 0 (the iterates are swapped, so buffer 1 then holds the
+// iterate before the last accepted step).  An epoch without an accepted step
+// has no average: the average is set to the iterate.  (k_control then resets
+// par.)
 template <typename T>
 __global__ __launch_bounds__(WG) void k_commit_ad(Dev d)
 {
@@ -395,9 +398,14 @@ __global__ __launch_bounds__(WG) void k_commit_ad(Dev d)
         T *za0 = (T *)(onT ? d.xavg : d.yavg);
         const T *za1 = (const T *)(onT ? d.xavg1 : d.yavg1);
         const int64_t r1 = s.row0 + s.nrows;
+        T *z1w = (T *)z1;
         for (int64_t r = s.row0 + threadIdx.x; r < r1; r += WG) {
             const T v = flip ? z1[r] : z0[r];
-            if (flip) z0[r] = v;
+            if (flip) {
+                // swap: buffer 1 keeps the iterate before the last accepted step
+                z1w[r] = z0[r];
+                z0[r] = v;
+            }
             za0[r] = noavg ? v : za1[r];
             if (!onT && flip) d.kx0[r] = d.kx1[r];
         }
@@ -518,7 +526,7 @@ __global__ __launch_bounds__(WG) void k_check(Dev d, const V *__restrict__ xa0, 
         });
         block_sum<NC * NSUM>(sum, red);
         if (threadIdx.x == 0) {
-            double *out = d.partials + (size_t)lbc * (NCAND * NSUM);
+            double *out = d.partials + (size_t)lbc * NPART;
 #pragma unroll
             for (int k = 0; k < NCAND * NSUM; ++k) out[k] = k < NC * NSUM ? sum[k] : 0.0;
         }
@@ -526,12 +534,155 @@ __global__ __launch_bounds__(WG) void k_check(Dev d, const V *__restrict__ xa0, 
     });
 }
 
-// Second level of the check reduction: block t sums up to L2CH consecutive
+// ---------------------------------------------------------------------------
+// infeasibility detection (Section 2.4.5, Algorithm 6): per-block terms of
+// the tests on the last step's difference, in ORIGINAL variables
+// (x = kap x~, y = rho y~, (K x)_i = (K~ x~)_i / rho_i,
+// (c - K^T y)_j = (c~ - K~^T y~)_j / kap_j), FP64 matrix:
+//   K rows i   : kd = (K dx)_i, dy_i
+//                s0 += kd^2 ("=" rows), s1 = max(-kd) (">=" rows),
+//                s2 = max(-dy_i) (">=" rows), s3 += q_i dy_i
+//   K^T rows j : dx_j, dlambda_j = lambda_j(y) - lambda_j(yp) with
+//                lambda = proj_Lambda(c - K^T y), r = (K^T dy)_j + dlambda_j,
+//                s4 += c_j dx_j, s5 = max violation of dx_j in V_j,
+//                s6 += r^2, s7 += l_j dlambda^+ + u_j dlambda^- (-inf when an
+//                infinite bound meets a nonzero multiplier)
+// (x, y) is the current iterate, (xp, yp) the one before the last step.
+// ---------------------------------------------------------------------------
+template <typename V, int RM>
+__global__ __launch_bounds__(WG) void k_infeas(Dev d, const V *__restrict__ xp, const V *__restrict__ yp)
+{
+    __shared__ double red[2 * 4];
+    __shared__ double lds[NINF * 4];
+    const V *__restrict__ x = (const V *)d.x;
+    const V *__restrict__ y = (const V *)d.y;
+    const int nK = d.act_cnt[0], nT = d.act_cnt[1];
+    const bool fullK = nK == d.K.nblk, fullT = nT == d.Kt.nblk;
+    for_each_item(nK + nT, d.remap, [&](int it) {
+        const bool onK = it < nK;
+        const int lb = onK ? (fullK ? it : d.actK[it]) : (fullT ? it - nK : d.actT[it - nK]);
+        const int lbc = onK ? lb : d.K.nblk + lb;
+        const OpDev &op = onK ? d.K : d.Kt;
+        const Seg s = block_seg(op, lb);
+        double f[NINF];
+#pragma unroll
+        for (int k = 0; k < NINF; ++k) f[k] = (k == 1 || k == 2 || k == 5) ? -INFINITY : 0.0;
+        const int bi = lb - s.blk0;
+        const bool ineq = s.ineq != 0;
+        dispatch_lanes<RM>(s.lanes_log2, [&](auto tag, auto rtag) {
+            constexpr int L = decltype(tag)::value, R = decltype(rtag)::value;
+            if (onK) {
+                sweep_rows<L, 2, double, V, R>(op, s, bi, x, xp, nullptr, red, [&](int64_t r, const double *acc) {
+                    const double rh = d.rho[r];
+                    const double kd = (acc[0] - acc[1]) / rh;
+                    const double dy = rh * ((double)y[r] - (double)yp[r]);
+                    if (ineq) {
+                        f[1] = fmax(f[1], -kd);
+                        f[2] = fmax(f[2], -dy);
+                    } else {
+                        f[0] += kd * kd;
+                    }
+                    f[3] += d.qraw[r] * dy;
+                });
+            } else {
+                sweep_rows<L, 2, double, V, R>(op, s, bi, y, yp, nullptr, red, [&](int64_t r, const double *acc) {
+                    const double cj = d.c64[r], kj = d.kap[r];
+                    const double ls = d.l64[r], us = d.u64[r];
+                    const double dl = (proj_lambda(cj - acc[0], ls, us) - proj_lambda(cj - acc[1], ls, us)) / kj;
+                    const double res = (acc[0] - acc[1]) / kj + dl;
+                    const double dx = kj * ((double)x[r] - (double)xp[r]);
+                    const double lo = d.lraw[r], hi = d.uraw[r];
+                    const bool lf = isfinite(lo), uf = isfinite(hi);
+                    f[4] += d.craw[r] * dx;
+                    const double v = (lf && uf) ? fabs(dx) : (lf ? -dx : (uf ? dx : 0.0));
+                    f[5] = fmax(f[5], v);
+                    f[6] += res * res;
+                    if (dl > 0.0) f[7] += lf ? lo * dl : -INFINITY;
+                    else if (dl < 0.0) f[7] += uf ? hi * dl : -INFINITY;
+                });
+            }
+        });
+#pragma unroll
+        for (int k = 0; k < NINF; ++k)
+            f[k] = (k == 1 || k == 2 || k == 5) ? group_reduce<64, true>(f[k]) : group_reduce<64, false>(f[k]);
+        const int tid = threadIdx.x, wave = tid >> 6;
+        __syncthreads();
+        if ((tid & 63) == 0) {
+#pragma unroll
+            for (int k = 0; k < NINF; ++k) lds[k * 4 + wave] = f[k];
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double *out = d.partials + (size_t)lbc * NPART + NCAND * NSUM;
+#pragma unroll
+            for (int k = 0; k < NINF; ++k) {
+                const double *q = lds + k * 4;
+                out[k] = (k == 1 || k == 2 || k == 5) ? fmax(fmax(q[0], q[1]), fmax(q[2], q[3]))
+                                                      : (q[0] + q[1]) + (q[2] + q[3]);
+            }
+        }
+    });
+}
+
+// Fixed steps: the iterate before the last step of a check period, saved to
+// (xavg1, y1) for the infeasibility tests.  Walks the running instances' rows.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_save_prev(Dev d)
+{
+    const int nT = d.act_cnt[1], nK = d.act_cnt[0];
+    const bool fullK = nK == d.K.nblk, fullT = nT == d.Kt.nblk;
+    for_each_item(nT + nK, d.remap, [&](int it) {
+        const bool onT = it < nT;
+        const int lb = onT ? (fullT ? it : d.actT[it]) : (fullK ? it - nT : d.actK[it - nT]);
+        const Seg s = block_seg(onT ? d.Kt : d.K, lb);
+        const T *src = (const T *)(onT ? d.x : d.y);
+        T *dst = (T *)(onT ? d.xavg1 : d.y1);
+        const int64_t r1 = s.row0 + s.nrows;
+        for (int64_t r = s.row0 + threadIdx.x; r < r1; r += WG) dst[r] = src[r];
+    });
+}
+
+// Block-wide reduction of the NPART per-thread partials (sums, and maxima in
+// the part_is_max slots), fixed order; result valid in thread 0.
+__device__ __forceinline__ void block_reduce_part(double (&v)[NPART], double *lds)
+{
+#pragma unroll
+    for (int k = 0; k < NPART; ++k)
+        v[k] = part_is_max(k) ? group_reduce<64, true>(v[k]) : group_reduce<64, false>(v[k]);
+    const int tid = threadIdx.x, wave = tid >> 6;
+    __syncthreads();
+    if ((tid & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < NPART; ++k) lds[k * 4 + wave] = v[k];
+    }
+    __syncthreads();
+    if (tid == 0) {
+#pragma unroll
+        for (int k = 0; k < NPART; ++k) {
+            const double *r = lds + k * 4;
+            v[k] = part_is_max(k) ? fmax(fmax(r[0], r[1]), fmax(r[2], r[3])) : (r[0] + r[1]) + (r[2] + r[3]);
+        }
+    }
+}
+
+__device__ __forceinline__ void part_init(double (&v)[NPART])
+{
+#pragma unroll
+    for (int k = 0; k < NPART; ++k) v[k] = part_is_max(k) ? -INFINITY : 0.0;
+}
+
+__device__ __forceinline__ void part_acc(double (&v)[NPART], const double *p)
+{
+#pragma unroll
+    for (int k = 0; k < NPART; ++k) v[k] = part_is_max(k) ? fmax(v[k], p[k]) : v[k] + p[k];
+}
+
+// Second level of the check reduction: block t reduces up to L2CH consecutive
 // first-level rows of its instance (K blocks first, then K^T blocks), in a
-// fixed order, so the sums of one instance do not depend on the batch.
+// fixed order, so the totals of one instance do not depend on the batch.
 __global__ __launch_bounds__(WG) void k_reduce_l2(Dev d, int skip_done)
 {
-    __shared__ double lds[NCAND * NSUM * 4];
+    __shared__ double lds[NPART * 4];
     const int t = blockIdx.x;
     const int b = d.l2_inst[t];
     if (skip_done && d.st[b].done) return;
@@ -539,39 +690,31 @@ __global__ __launch_bounds__(WG) void k_reduce_l2(Dev d, int skip_done)
     const int nK = in.blkK1 - in.blkK0, nT = in.blkT1 - in.blkT0;
     const int r0 = (t - in.l2off) * L2CH;
     const int r1 = min(r0 + L2CH, nK + nT);
-    double v[NCAND * NSUM];
-#pragma unroll
-    for (int k = 0; k < NCAND * NSUM; ++k) v[k] = 0.0;
+    double v[NPART];
+    part_init(v);
     for (int r = r0 + (int)threadIdx.x; r < r1; r += WG) {
         const int lbc = r < nK ? in.blkK0 + r : d.K.nblk + in.blkT0 + (r - nK);
-        const double *p = d.partials + (size_t)lbc * (NCAND * NSUM);
-#pragma unroll
-        for (int k = 0; k < NCAND * NSUM; ++k) v[k] += p[k];
+        part_acc(v, d.partials + (size_t)lbc * NPART);
     }
-    block_sum<NCAND * NSUM>(v, lds);
+    block_reduce_part(v, lds);
     if (threadIdx.x == 0) {
-        double *o = d.partials2 + (size_t)t * (NCAND * NSUM);
+        double *o = d.partials2 + (size_t)t * NPART;
 #pragma unroll
-        for (int k = 0; k < NCAND * NSUM; ++k) o[k] = v[k];
+        for (int k = 0; k < NPART; ++k) o[k] = v[k];
     }
 }
 
-// Sums the instance's second-level rows (fixed order) into tot[NCAND * NSUM].
+// Reduces the instance's second-level rows (fixed order) into tot[NPART].
 __device__ void reduce_instance(const Dev &d, const InstInfo &in, double *tot)
 {
-    __shared__ double lds[NCAND * NSUM * 4];
-    double v[NCAND * NSUM];
-#pragma unroll
-    for (int k = 0; k < NCAND * NSUM; ++k) v[k] = 0.0;
-    for (int t = threadIdx.x; t < in.l2cnt; t += WG) {
-        const double *p = d.partials2 + (size_t)(in.l2off + t) * (NCAND * NSUM);
-#pragma unroll
-        for (int k = 0; k < NCAND * NSUM; ++k) v[k] += p[k];
-    }
-    block_sum<NCAND * NSUM>(v, lds);
+    __shared__ double lds[NPART * 4];
+    double v[NPART];
+    part_init(v);
+    for (int t = threadIdx.x; t < in.l2cnt; t += WG) part_acc(v, d.partials2 + (size_t)(in.l2off + t) * NPART);
+    block_reduce_part(v, lds);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < NCAND * NSUM; ++k) tot[k] = v[k];
+        for (int k = 0; k < NPART; ++k) tot[k] = v[k];
     }
 }
 
@@ -609,7 +752,7 @@ __device__ __forceinline__ double kkt_omega(const Metrics &m, double w)
 // (0 for the check of the starting point).
 __global__ __launch_bounds__(WG) void k_control(Dev d, CtlParams P, int iters_done)
 {
-    __shared__ double tot[NCAND * NSUM];
+    __shared__ double tot[NPART];
     const int b = blockIdx.x;
     InstState &st = d.st[b];
     if (st.done) return;
@@ -663,9 +806,20 @@ __global__ __launch_bounds__(WG) void k_control(Dev d, CtlParams P, int iters_do
     } else if (nc > 1 && mt[1 - cand].kkt[8] <= P.eps) {
         stop = PDHG_OPTIMAL + 1;
         sol = 1 - cand;
-    } else if (st.k_total >= P.max_iters) {
-        stop = PDHG_ITERATION_LIMIT + 1;
+    } else if (P.detect && (!P.adaptive || st.prev_ok)) {
+        // Algorithm 6 on the last step's difference; each test relative to
+        // the ray's objective improvement (dual test first)
+        const double *f = tot + NCAND * NSUM;
+        const double tol = P.infeas_tol, sd = -f[4], sp = f[3] + f[7];
+        if (sd > 0.0 && sqrt(f[0]) <= tol * sd && f[1] <= tol * sd && f[5] <= tol * sd) {
+            stop = PDHG_DUAL_INFEASIBLE + 1;
+            sol = 0;
+        } else if (sp > 0.0 && sqrt(f[6]) <= tol * sp && f[2] <= tol * sp) {
+            stop = PDHG_PRIMAL_INFEASIBLE + 1;
+            sol = 0;
+        }
     }
+    if (!stop && st.k_total >= P.max_iters) stop = PDHG_ITERATION_LIMIT + 1;
     if (stop) {
         st.done = 1;
         st.status = stop - 1;
@@ -1029,7 +1183,7 @@ __global__ void k_set_point(Dev d, int64_t xoff, int64_t n, int64_t yoff, int64_
 // KKT terms of a single candidate for one instance from the check partials
 __global__ __launch_bounds__(WG) void k_kkt_final(Dev d, int inst, double *out9)
 {
-    __shared__ double tot[NCAND * NSUM];
+    __shared__ double tot[NPART];
     const InstInfo in = d.info[inst];
     reduce_instance(d, in, tot);
     if (threadIdx.x != 0) return;
@@ -1260,6 +1414,20 @@ void launch_kx_ad(const Dev &d, int all, hipStream_t s)
 }
 
 template <typename T>
+void launch_infeas(const Dev &d, const void *xp, const void *yp, hipStream_t s)
+{
+    const unsigned g = sweep_grid(d, d.K.nblk + d.Kt.nblk);
+    const int rm = d.K.rmax > d.Kt.rmax ? d.K.rmax : d.Kt.rmax;
+    RM_SWITCH(rm, { LAUNCH((k_infeas<T, RMV>), g, d, (const T *)xp, (const T *)yp); });
+}
+
+template <typename T>
+void launch_save_prev(const Dev &d, hipStream_t s)
+{
+    LAUNCH(k_save_prev<T>, sweep_grid(d, d.K.nblk + d.Kt.nblk), d);
+}
+
+template <typename T>
 void launch_check(const Dev &d, int avg, hipStream_t s)
 {
     const unsigned g = sweep_grid(d, d.K.nblk + d.Kt.nblk);
@@ -1456,6 +1624,8 @@ void launch_set_raw(const Dev &d, const double *c, const double *q, const double
     template void launch_dual_ad<T>(const Dev &, hipStream_t);                               \
     template void launch_commit_ad<T>(const Dev &, hipStream_t);                             \
     template void launch_kx_ad<T>(const Dev &, int, hipStream_t);                            \
+    template void launch_infeas<T>(const Dev &, const void *, const void *, hipStream_t);    \
+    template void launch_save_prev<T>(const Dev &, hipStream_t);                             \
     template void launch_check<T>(const Dev &, int, hipStream_t);                            \
     template void launch_restart<T>(const Dev &, hipStream_t);                               \
     template void launch_scale_data<T>(const Dev &, hipStream_t);                            \

@@ -30,6 +30,14 @@ constexpr int NBIN = 8;   // row-length bins
 constexpr int NSUM = 9;   // partial sums per candidate in the check
 constexpr int NCAND = 2;  // candidates: current iterate, epoch average
 constexpr int L2CH = 512; // first-level partial rows summed by one second-level block
+// Infeasibility detection adds NINF per-block terms after the check's sums:
+// sums, except slots 1, 2 and 5, which are maxima.
+constexpr int NINF = 8;
+constexpr int NPART = NCAND * NSUM + NINF;  // stride of the per-block partials
+__host__ __device__ constexpr bool part_is_max(int k)
+{
+    return k == NCAND * NSUM + 1 || k == NCAND * NSUM + 2 || k == NCAND * NSUM + 5;
+}
 
 struct Seg {
     int64_t row0;       // first row (global internal index)
@@ -87,6 +95,8 @@ struct InstState {
     double eta_sum;    // sum of the accepted steps of the current epoch (average weights)
     long long k_att;   // attempts of this solve
     long long n_acc;   // accepted steps of this solve
+    int32_t prev_ok;   // the last attempt was accepted: buffer 1 holds the iterate before it
+    int32_t pad2;
 };
 
 struct CtlParams {
@@ -96,6 +106,8 @@ struct CtlParams {
     int32_t use_restarts, use_pw;
     int32_t batch;
     int32_t adaptive;  // adaptive step size: the check follows a commit to buffer 0
+    int32_t detect;    // infeasibility detection (Algorithm 6)
+    double infeas_tol;
 };
 
 // Device pointers and sizes of one handle (passed by value to kernels).
@@ -127,8 +139,8 @@ struct Dev {
     InstState *st;
     int32_t *hdone;               // host-mapped copy of done flags
     // scratch
-    double *partials;             // (K.nblk + Kt.nblk) * NCAND * NSUM
-    double *partials2;            // nl2 * NCAND * NSUM (second level)
+    double *partials;             // (K.nblk + Kt.nblk) * NPART
+    double *partials2;            // nl2 * NPART (second level)
     double *adp;                  // adaptive step: 2 per K block, then 1 per K^T block
     const int32_t *l2_inst;       // instance of each second-level row
     int32_t nl2;

@@ -44,9 +44,10 @@ def test_struct_layouts_match_header(pd):
     assert o.precision == 1 and o.ruiz_iters == 10 and o.check_every == 64
     assert o.eps == 1e-4 and o.step_frac == 0.9 and o.beta_art == 0.36
     assert o.adaptive_step == 0 and o.max_grid == 8192
-    # the option struct ends with adaptive_step; the result and timer structs
+    # the option struct ends with the detection fields; the result and timer structs
     # end with the adaptive-step fields
-    assert pd.Opts.adaptive_step.offset + 4 == C.sizeof(pd.Opts)
+    assert pd.Opts.infeas_tol.offset + 8 == C.sizeof(pd.Opts)
+    assert o.detect_infeas == 0 and o.infeas_tol == 1e-4
     assert pd.Result.eta_next.offset + 8 == C.sizeof(pd.Result)
     assert pd.KernelTimes.ms_step_ad.offset + 8 == C.sizeof(pd.KernelTimes)
     assert L.pdhg_last_error() is not None
@@ -116,6 +117,9 @@ def test_rejects_bad_options(pd):
     assert _nbytes(pd, lp, precision=7) == 0
     assert _nbytes(pd, lp, adaptive_step=2) == 0 and "adaptive_step" in _err(pd)
     assert _nbytes(pd, lp, adaptive_step=1) == _nbytes(pd, lp)
+    assert _nbytes(pd, lp, detect_infeas=2) == 0 and "detect_infeas" in _err(pd)
+    assert _nbytes(pd, lp, detect_infeas=1, infeas_tol=0.0) == 0 and "infeas_tol" in _err(pd)
+    assert _nbytes(pd, lp, detect_infeas=1) == _nbytes(pd, lp)
 
 
 def test_infinite_bounds_accepted(pd):
