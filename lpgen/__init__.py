@@ -506,3 +506,15 @@ def dual_infeasible(m: int, n: int, density: float, seed: int) -> LP:
     rowptr, col, val = _csr_from_coo(out.m, r, cc, v)
     return LP(n + 1, out.m, rowptr, col, val, out.row_type, out.rhs, np.append(out.c, -1.0),
               np.append(out.l, 0.0), np.append(out.u, np.inf), name=out.name)
+
+
+# ---------------------------------------------------------------------------
+# random draws of the fishnet multi-start (Section 2.5), passed to both paths
+# ---------------------------------------------------------------------------
+
+def fishnet_draws(n: int, P: int, seed: int):
+    """Standard normal draws for fishnet casting: G (P x n, one row per
+    starting point) and P*P draws for the repopulation weights (more than the
+    rounds of 2^p points consume)."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((P, n)), rng.standard_normal(P * P)

@@ -102,6 +102,12 @@ def _load():
         L.orc_power_norm.restype = C.c_double
         L.orc_power_norm.argtypes = [P, C.c_int, C.c_double, C.POINTER(C.c_int)]
         L.orc_steps.argtypes = [P, C.c_double, C.c_double, D, D, C.c_longlong]
+        L.orc_solve_from.restype = C.c_int
+        L.orc_solve_from.argtypes = [P, C.POINTER(Opts), C.c_void_p, C.c_void_p, D, D, C.POINTER(Result),
+                                     C.c_void_p, C.c_int]
+        L.orc_fishnet.restype = C.c_int
+        L.orc_fishnet.argtypes = [P, C.c_double, C.c_double, C.c_double, C.c_int, C.c_longlong, D, D, D, D,
+                                  C.c_void_p, C.c_void_p]
         L.orc_solve.restype = C.c_int
         L.orc_solve.argtypes = [P, C.POINTER(Opts), D, D, C.POINTER(Result), C.c_void_p, C.c_int]
         L.orc_infeas_test.restype = C.c_int
@@ -271,14 +277,19 @@ class Oracle:
         self.lib.orc_steps(s.h, tau, sigma, xi, yi, k)
         return xi, self.to_user_rows(yi)
 
-    def solve(self, opts: Optional[SolveOpts] = None, trace_cap: int = 4096) -> SolveResult:
+    def solve(self, opts: Optional[SolveOpts] = None, trace_cap: int = 4096, x0=None, y0=None) -> SolveResult:
+        """Restarted solve; (x0, y0) (original variables, y in user row order)
+        replace the default start proj_X(0), 0."""
         opts = opts or SolveOpts()
         x = np.empty(self.n)
         y = np.empty(self.m)
         r = Result()
         tr = (TraceRec * trace_cap)()
-        self.lib.orc_solve(self.h, C.byref(opts.c()), x, y, C.byref(r), C.cast(tr, C.c_void_p),
-                           trace_cap)
+        xs = None if x0 is None else _f64(x0)
+        ys = None if y0 is None else self.to_internal_rows(y0)
+        self.lib.orc_solve_from(self.h, C.byref(opts.c()), None if xs is None else xs.ctypes.data,
+                                None if ys is None else ys.ctypes.data, x, y, C.byref(r),
+                                C.cast(tr, C.c_void_p), trace_cap)
         trace = [dict(iter=t.iter, restarted=t.restarted, cand_avg=t.cand_avg,
                       kkt_cand=t.kkt_cand, omega=t.omega, rel_kkt_cur=t.rel_kkt_cur,
                       rel_kkt_avg=t.rel_kkt_avg, eta_next=t.eta_next, accepted=t.accepted)
@@ -286,6 +297,26 @@ class Oracle:
         return SolveResult(r.status, x, self.to_user_rows(y), r.iters, r.restarts, bool(r.from_avg),
                            r.knorm, r.eta, r.omega0, r.omega, r.kkt.as_dict(), r.power_iters, trace,
                            r.accepted, r.eta_next)
+
+    def fishnet(self, ruiz_iters, eta, omega, knorm, P, k, G, wraw):
+        """Algorithm 7 on the scaled problem (Ruiz passes ruiz_iters) with fixed
+        steps eta, omega, radius knorm, P = 2^p points, k steps per round, the
+        standard normal draws G (P x n, point-major) and wraw (repopulation
+        draws).  Returns the last point in original variables (y in user row
+        order), each round's gaps (rounds x P) and kept indices (rounds x P,
+        -1 past the kept half)."""
+        s = self.scaled(ruiz_iters)
+        x, y = np.empty(self.n), np.empty(self.m)
+        maxr = 2 * 7
+        gaps = np.zeros((maxr, P))
+        keep = np.zeros((maxr, P), dtype=np.int32)
+        G = _f64(np.asarray(G).reshape(-1))
+        w = _f64(np.asarray(wraw).reshape(-1)) if len(wraw) else np.zeros(1)
+        rounds = self.lib.orc_fishnet(s.h, eta, omega, knorm, P, k, G, w, x, y, gaps.ctypes.data,
+                                      keep.ctypes.data)
+        if rounds < 0:
+            raise ValueError("P must be a power of two in 2..64")
+        return s.kap * x, self.to_user_rows(s.rho_i * y), gaps[:rounds], keep[:rounds]
 
     def infeas_test(self, x, y, xp, yp, tol: float = 1e-4) -> dict:
         """Algorithm 6's tests on the original LP for dx = x - xp, dy = y - yp

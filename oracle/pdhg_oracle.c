@@ -28,6 +28,9 @@
  *                                  etabar >= 1/||K||_2 from Cauchy-Schwarz)
  *   orc_solve, adaptive steps .... pinned (planted f*, HiGHS); the sequence of
  *                                  accepted steps is parity unpinned.
+ *   orc_fishnet .................. pinned (P = 2 equals the better of two
+ *                                  pinned step sequences; one-hot weights copy
+ *                                  a survivor; a numpy replay of the rounds)
  *   orc_infeas_test .............. pinned (hand-worked Farkas rays, HiGHS
  *                                  infeasible / unbounded verdicts)
  *   orc_unrolled_vjp ............. pinned (central finite differences)
@@ -546,6 +549,112 @@ int orc_infeas_test(const orc_prob *p, const double *x, const double *y, const d
 }
 
 /* ------------------------------------------------------------------------- */
+/* fishnet casting (Section 2.5, Algorithm 7)                                 */
+/* ------------------------------------------------------------------------- */
+
+/* Duality gap |dobj - pobj| of one point of problem p (Section 2.3.2):
+ * pobj = c'x, dobj = q'y + l'lambda^+ + u'lambda^-, lambda = proj(c - K'y). */
+static double point_gap(const orc_prob *p, const double *x, const double *y, double *work_n)
+{
+    double pobj = 0.0, dobj = 0.0;
+    orc_spmv_t(p, y, work_n);
+    for (int64_t j = 0; j < p->n; ++j) {
+        pobj += p->c[j] * x[j];
+        double lam = proj_lambda(p->c[j] - work_n[j], p->l[j], p->u[j]);
+        if (lam > 0.0) dobj += p->l[j] * lam;
+        else if (lam < 0.0) dobj += p->u[j] * lam;
+    }
+    for (int64_t i = 0; i < p->m; ++i) dobj += p->q[i] * y[i];
+    return fabs(dobj - pobj);
+}
+
+/* Fishnet casting on problem p (the scaled problem of the solve) with fixed
+ * steps tau = eta/omega, sigma = eta*omega:
+ *   X^0 = (r / sqrt(n)) G with r = knorm and G the caller's n x P standard
+ *   normal draws (point-major: G[q*n + j]), Y^0 = K X^0;
+ *   while more than one point is left: k PDHG steps on every point; keep the
+ *   half with the smallest duality gap (ties by index), ordered by gap; in
+ *   odd rounds whose starting count exceeds 2, append as many new points, new
+ *   point a = sum_s w_as (x_s, y_s) with w_as = |g_as| / sum_s |g_as| from
+ *   the caller's draws (consumed row by row from wraw; equal weights when a
+ *   row of draws is all zero).
+ * P = 2^p (2..64).  x_out, y_out receive the last point.  gaps (P * rounds)
+ * and keep (P * rounds) receive each round's gaps and kept indices (may be
+ * NULL).  Returns the number of rounds, or -1 for a bad P. */
+int orc_fishnet(const orc_prob *p, double eta, double omega, double knorm, int P, long long k,
+                const double *G, const double *wraw, double *x_out, double *y_out, double *gaps,
+                int *keep)
+{
+    int64_t n = p->n, m = p->m;
+    if (P < 2 || P > 64 || (P & (P - 1))) return -1;
+    double *X = (double *)malloc((size_t)P * (n ? n : 1) * sizeof(double));
+    double *Y = (double *)malloc((size_t)P * (m ? m : 1) * sizeof(double));
+    double *X2 = (double *)malloc((size_t)P * (n ? n : 1) * sizeof(double));
+    double *Y2 = (double *)malloc((size_t)P * (m ? m : 1) * sizeof(double));
+    double *wn = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+    double gap[64];
+    int idx[64];
+    double sc = n > 0 ? knorm / sqrt((double)n) : 0.0;
+    for (int q = 0; q < P; ++q) {
+        for (int64_t j = 0; j < n; ++j) X[(size_t)q * n + j] = sc * G[(size_t)q * n + j];
+        orc_spmv(p, X + (size_t)q * n, Y + (size_t)q * m);
+    }
+    int j = P, round = 0;
+    size_t wpos = 0;
+    while (j > 1) {
+        for (int q = 0; q < j; ++q) {
+            orc_steps(p, eta / omega, eta * omega, X + (size_t)q * n, Y + (size_t)q * m, k);
+            gap[q] = point_gap(p, X + (size_t)q * n, Y + (size_t)q * m, wn);
+            idx[q] = q;
+        }
+        /* stable order by (gap, index): insertion sort of at most 64 entries */
+        for (int a = 1; a < j; ++a) {
+            int t = idx[a];
+            int b = a - 1;
+            while (b >= 0 && (gap[idx[b]] > gap[t] || (gap[idx[b]] == gap[t] && idx[b] > t))) {
+                idx[b + 1] = idx[b];
+                --b;
+            }
+            idx[b + 1] = t;
+        }
+        if (gaps) for (int q = 0; q < P; ++q) gaps[(size_t)round * P + q] = q < j ? gap[q] : 0.0;
+        int half = j / 2;
+        if (keep) for (int q = 0; q < P; ++q) keep[(size_t)round * P + q] = q < half ? idx[q] : -1;
+        for (int r = 0; r < half; ++r) {
+            memcpy(X2 + (size_t)r * n, X + (size_t)idx[r] * n, (size_t)n * sizeof(double));
+            memcpy(Y2 + (size_t)r * m, Y + (size_t)idx[r] * m, (size_t)m * sizeof(double));
+        }
+        int next = half;
+        if ((round & 1) && j > 2) {
+            for (int a = 0; a < half; ++a) {
+                double ws[64], tot = 0.0;
+                for (int s2 = 0; s2 < half; ++s2) {
+                    ws[s2] = fabs(wraw[wpos++]);
+                    tot += ws[s2];
+                }
+                double *xa = X2 + (size_t)(half + a) * n, *ya = Y2 + (size_t)(half + a) * m;
+                for (int64_t t = 0; t < n; ++t) xa[t] = 0.0;
+                for (int64_t t = 0; t < m; ++t) ya[t] = 0.0;
+                for (int s2 = 0; s2 < half; ++s2) {
+                    double w = tot > 0.0 ? ws[s2] / tot : 1.0 / half; /* all-zero draws: equal weights */
+                    for (int64_t t = 0; t < n; ++t) xa[t] += w * X2[(size_t)s2 * n + t];
+                    for (int64_t t = 0; t < m; ++t) ya[t] += w * Y2[(size_t)s2 * m + t];
+                }
+            }
+            next = 2 * half;
+        }
+        double *tx = X; X = X2; X2 = tx;
+        double *ty = Y; Y = Y2; Y2 = ty;
+        j = next;
+        ++round;
+    }
+    memcpy(x_out, X, (size_t)n * sizeof(double));
+    memcpy(y_out, Y, (size_t)m * sizeof(double));
+    free(X); free(Y); free(X2); free(Y2); free(wn);
+    return round;
+}
+
+/* ------------------------------------------------------------------------- */
 /* restarted PDHG solve (Sections 2.3-2.4: Algorithms 1-4, restarts)          */
 /* ------------------------------------------------------------------------- */
 
@@ -596,9 +705,11 @@ typedef struct {
 
 /* Solves the LP (rows already ordered [G; A]).  x_out / y_out receive the
  * returned point in the original variables.  trace (may be NULL) receives up
- * to trace_cap check records. */
-int orc_solve(const orc_prob *p, const orc_opts *o, double *x_out, double *y_out, orc_result *res,
-              orc_trace_rec *trace, int trace_cap)
+ * to trace_cap check records.  x_start / y_start (original variables, may be
+ * NULL) replace the starting point proj_X(0), 0; they are projected onto
+ * X and Y. */
+int orc_solve_from(const orc_prob *p, const orc_opts *o, const double *x_start, const double *y_start,
+                   double *x_out, double *y_out, orc_result *res, orc_trace_rec *trace, int trace_cap)
 {
     int64_t n = p->n, m = p->m;
     memset(res, 0, sizeof(*res));
@@ -632,7 +743,9 @@ int orc_solve(const orc_prob *p, const orc_opts *o, double *x_out, double *y_out
     double *y0 = (double *)malloc((size_t)(m ? m : 1) * sizeof(double));
     double *xu = (double *)malloc((size_t)(n ? n : 1) * sizeof(double)); /* unscaled */
     double *yu = (double *)malloc((size_t)(m ? m : 1) * sizeof(double));
-    for (int64_t j = 0; j < n; ++j) x[j] = clip(0.0, s->l[j], s->u[j]);
+    for (int64_t j = 0; j < n; ++j) x[j] = clip(x_start ? x_start[j] / kap[j] : 0.0, s->l[j], s->u[j]);
+    if (y_start)
+        for (int64_t i = 0; i < m; ++i) y[i] = (i < s->m1 && y_start[i] < 0.0) ? 0.0 : y_start[i] / rho[i];
     memcpy(x0, x, (size_t)n * sizeof(double));
     memcpy(y0, y, (size_t)m * sizeof(double));
     double *xn = NULL, *yn = NULL; /* candidates of the adaptive step */
@@ -837,6 +950,12 @@ done:
     free(rho); free(kap);
     orc_prob_free(s);
     return status;
+}
+
+int orc_solve(const orc_prob *p, const orc_opts *o, double *x_out, double *y_out, orc_result *res,
+              orc_trace_rec *trace, int trace_cap)
+{
+    return orc_solve_from(p, o, NULL, NULL, x_out, y_out, res, trace, trace_cap);
 }
 
 /* ------------------------------------------------------------------------- */

@@ -628,3 +628,103 @@ def test_infeas_no_false_positive(orc, maker, adaptive):
     assert a.status == b.status and a.status in (0, 1)
     assert a.iters == b.iters
     np.testing.assert_array_equal(a.x, b.x)
+
+
+# ---------------------------------------------------------------------------
+# fishnet casting (Section 2.5, Algorithm 7)
+# ---------------------------------------------------------------------------
+
+def _fish_setup(orc, lp, ruiz=10):
+    o = orc.Oracle(lp)
+    r = o.solve(orc.SolveOpts(max_iters=1, eps=1e-12, ruiz_iters=ruiz))
+    rho, kap = o.ruiz(ruiz)
+    return o, r.eta, r.omega0, r.knorm, rho, kap
+
+
+def _replay(o, lp, eta, w, kn, rho, kap, P, k, G, wraw, ruiz=10):
+    """Algorithm 7 replayed from pinned pieces: the scaled product through
+    orc_spmv, k fixed steps through orc_steps, the gap through orc_kkt."""
+    X = [(kn / np.sqrt(lp.n)) * G[q] for q in range(P)]
+    Y = [rho * o.spmv(kap * x) for x in X]
+    j, rnd, pos, keeps = P, 0, 0, []
+    while j > 1:
+        gaps = []
+        for q in range(j):
+            X[q], Y[q] = o.steps(X[q], Y[q], eta / w, eta * w, k, ruiz_iters=ruiz)
+            gaps.append(o.kkt(kap * X[q], rho * Y[q])["gap"])
+        order = sorted(range(j), key=lambda q: (gaps[q], q))
+        half = j // 2
+        keeps.append(order[:half])
+        X, Y = [X[q] for q in order[:half]], [Y[q] for q in order[:half]]
+        if rnd % 2 == 1 and j > 2:
+            for a in range(half):
+                ws = np.abs(wraw[pos:pos + half])
+                pos += half
+                ws = ws / ws.sum()
+                X.append(sum(ws[s] * X[s] for s in range(half)))
+                Y.append(sum(ws[s] * Y[s] for s in range(half)))
+        j = len(X)
+        rnd += 1
+    return kap * X[0], rho * Y[0], keeps
+
+
+@pytest.mark.parametrize("P,k", [(2, 20), (4, 16), (8, 10), (16, 6)])
+def test_fishnet_replay_from_pinned_pieces(orc, P, k):
+    lp = lpgen.planted(40, 100, 0.06, 17, ge_frac=0.5)
+    o, eta, w, kn, rho, kap = _fish_setup(orc, lp)
+    G, wraw = lpgen.fishnet_draws(lp.n, P, seed=5)
+    x, y, gaps, keep = o.fishnet(10, eta, w, kn, P, k, G, wraw)
+    xr, yr, keeps = _replay(o, lp, eta, w, kn, rho, kap, P, k, G, wraw)
+    p = int(np.log2(P))
+    assert len(keep) == (1 if P == 2 else 2 * p - 2)
+    for r, kr in enumerate(keeps):
+        assert list(keep[r][:len(kr)]) == kr
+    np.testing.assert_allclose(x, xr, rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(y, yr, rtol=1e-10, atol=1e-12)
+
+
+def test_fishnet_one_hot_weights_copy_survivors(orc):
+    """Raw weights that are one-hot make each new point a copy of a survivor,
+    so the next round's gaps come in equal pairs."""
+    lp = lpgen.planted(40, 100, 0.06, 18, ge_frac=0.3)
+    o, eta, w, kn, rho, kap = _fish_setup(orc, lp)
+    P = 8
+    G, _ = lpgen.fishnet_draws(lp.n, P, seed=6)
+    wraw = np.zeros(P * P)
+    # round 0 keeps 4 of 8; round 1 keeps 2 of 4 and appends 2 new points,
+    # point a one-hot on survivor a
+    wraw[0] = 1.0
+    wraw[3] = -1.0  # the sign of a draw does not matter
+    x, y, gaps, keep = o.fishnet(10, eta, w, kn, P, 8, G, wraw)
+    g2 = gaps[2][:4]
+    np.testing.assert_array_equal(g2[:2], g2[2:4])
+    # all-zero draws give equal weights: the replay with equal weights agrees
+    x2, y2, _, _ = o.fishnet(10, eta, w, kn, P, 8, G, np.zeros(P * P))
+    x3, y3, _, _ = o.fishnet(10, eta, w, kn, P, 8, G, np.ones(P * P))
+    np.testing.assert_allclose(x2, x3, rtol=1e-13, atol=1e-15)
+
+
+def test_fishnet_warm_start_solves(orc):
+    lp = lpgen.config0(2)
+    o, eta, w, kn, rho, kap = _fish_setup(orc, lp)
+    G, wraw = lpgen.fishnet_draws(lp.n, 32, seed=7)
+    x0, y0, gaps, keep = o.fishnet(10, eta, w, kn, 32, 64, G, wraw)
+    r = o.solve(orc.SolveOpts(eps=1e-6), x0=x0, y0=y0)
+    assert r.status == 0
+    assert _rel(r.kkt["pobj"], lp.f_star) <= 1e-5
+    # culling keeps the smaller gaps
+    for rr in range(len(keep)):
+        kept = [q for q in keep[rr] if q >= 0]
+        n_live = int(np.count_nonzero(gaps[rr] != 0.0)) or len(kept) * 2
+        dropped = [q for q in range(n_live) if q not in kept]
+        if dropped:
+            assert max(gaps[rr][kept]) <= min(gaps[rr][dropped])
+
+
+def test_solve_from_start_point(orc):
+    """A start point is projected: starting at the planted optimum stops at the
+    first check."""
+    lp = lpgen.config0(0)
+    o = orc.Oracle(lp)
+    r = o.solve(orc.SolveOpts(eps=1e-6), x0=lp.x_star, y0=lp.y_star)
+    assert r.status == 0 and r.iters == 0
