@@ -155,6 +155,9 @@ typedef struct {
      * are <= infeas_tol * psi.  The returned point is the current iterate. */
     int32_t detect_infeas;
     double infeas_tol;         /* default 1e-4                                      */
+    /* Largest point count of pdhg_fishnet (0, or a power of two in 2..64): the
+     * workspace then holds that many interleaved candidate points. */
+    int32_t fishnet_points;
 } pdhg_opts;
 
 /* Relative KKT error terms (Section 2.3.2, conditions term1-term3) on the
@@ -268,6 +271,32 @@ int pdhg_set_state(pdhg_handle *h, int32_t inst, const double *x, const double *
  * Host arrays are validated like pdhg_setup's; device arrays are trusted. */
 int pdhg_set_data(pdhg_handle *h, const double *c, const double *rhs, const double *l, const double *u,
                   int32_t mem, hipStream_t stream);
+
+/* Fishnet casting (Section 2.5, Algorithm 7): a multi-start warm start for a
+ * handle of one LP (batch 1, opts.fishnet_points >= npoints at setup).
+ * npoints = 2^p candidate points (2..64) start at (r / sqrt(n)) g_q with
+ * r = ||K~||_2 (the handle's power-iteration estimate) and g_q the caller's
+ * standard normal draws G (npoints x n, point-major, caller column order,
+ * scaled variables), and y_q = K~ x_q.  Each round runs k fixed PDHG steps
+ * (the handle's tau, sigma) on every live point, keeps the half with the
+ * smallest duality gap |dobj - pobj| (ties by index, best first) and, in odd
+ * rounds that start with more than two points, appends as many new points,
+ * new point a = sum_s w_as (kept point s) with w_as = |g_as| / sum_s |g_as|
+ * from the caller's draws wraw (consumed a row of (kept count) at a time;
+ * equal weights for an all-zero row).  Rounds end when one point is left; it
+ * becomes the current iterate and the start of a restart epoch, so the next
+ * pdhg_solve starts from it.  The rounds and draw count for npoints come from
+ * pdhg_fishnet_rounds.  gaps (rounds x npoints) and keep (rounds x npoints,
+ * kept indices best first, -1 beyond) may be NULL.  G, wraw, gaps and keep
+ * live in memory space `mem`.  All points run together: each sweep reads a
+ * matrix entry once for every point.  Synchronous.  Errors: _INVALID_ARG,
+ * _STATE (batch > 1 or no fishnet workspace), _NONFINITE (host draws). */
+int pdhg_fishnet(pdhg_handle *h, int32_t npoints, int32_t k, const double *G, const double *wraw, int64_t nw,
+                 int32_t mem, double *gaps, int32_t *keep, hipStream_t stream);
+
+/* Rounds of Algorithm 7 for npoints points and the number of repopulation
+ * draws pdhg_fishnet consumes (host only). */
+int pdhg_fishnet_rounds(int32_t npoints, int32_t *rounds, int64_t *draws);
 
 /* Relative KKT error of a caller point (x, y) on instance `inst`'s original
  * LP (y in caller row order).  FP64 throughout; synchronous. */

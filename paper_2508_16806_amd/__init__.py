@@ -53,7 +53,7 @@ class Opts(C.Structure):
                 ("use_graph", C.c_int32), ("xcd_remap", C.c_int32), ("bin_len_dual", C.c_int32 * 8),
                 ("bin_len_primal", C.c_int32 * 8), ("bin_rows_dual", C.c_int32 * 8),
                 ("bin_rows_primal", C.c_int32 * 8), ("max_grid", C.c_int32), ("adaptive_step", C.c_int32),
-                ("detect_infeas", C.c_int32), ("infeas_tol", C.c_double)]
+                ("detect_infeas", C.c_int32), ("infeas_tol", C.c_double), ("fishnet_points", C.c_int32)]
 
 
 class KKTOut(C.Structure):
@@ -101,7 +101,7 @@ class Info(C.Structure):
 EXPORTS = ["pdhg_default_opts", "pdhg_workspace_bytes", "pdhg_setup", "pdhg_iterate", "pdhg_solve",
            "pdhg_get_solution", "pdhg_set_state", "pdhg_kkt", "pdhg_backward", "pdhg_get_scaling",
            "pdhg_get_info", "pdhg_time_kernels", "pdhg_set_opts", "pdhg_set_data",
-           "pdhg_destroy", "pdhg_last_error"]
+           "pdhg_destroy", "pdhg_last_error", "pdhg_fishnet", "pdhg_fishnet_rounds"]
 
 _lib = None
 
@@ -129,6 +129,8 @@ def lib():
         L.pdhg_set_opts.argtypes = [P, C.POINTER(Opts)]
         L.pdhg_set_data.argtypes = [P, P, P, P, P, I32, S]
         L.pdhg_time_kernels.argtypes = [P, I32, C.POINTER(KernelTimes), S]
+        L.pdhg_fishnet.argtypes = [P, I32, I32, P, P, I64, I32, P, P, S]
+        L.pdhg_fishnet_rounds.argtypes = [I32, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
         L.pdhg_destroy.argtypes = [P]
         L.pdhg_last_error.restype = C.c_char_p
         _lib = L
@@ -312,6 +314,28 @@ class Solver:
         _check(lib().pdhg_get_scaling(self.h, inst, rho.ctypes.data, kap.ctypes.data, MEM_HOST,
                                       _stream(stream)))
         return rho, kap
+
+    def fishnet(self, npoints: int = 32, k: int = 64, G=None, wraw=None, seed: int = 0, stream=None) -> dict:
+        """Fishnet casting (Algorithm 7) on a one-LP handle; the surviving point
+        becomes the current iterate.  G (npoints x n) and wraw are standard
+        normal draws; when omitted they are drawn from numpy's PCG64 with
+        `seed`.  Returns {"rounds", "gaps" (rounds x npoints), "keep"}."""
+        r, nd = C.c_int32(0), C.c_int64(0)
+        _check(lib().pdhg_fishnet_rounds(int(npoints), C.byref(r), C.byref(nd)))
+        n = self.sizes[0][0]
+        if G is None or wraw is None:
+            rng = np.random.default_rng(seed)
+            G = rng.standard_normal((npoints, n)) if G is None else G
+            wraw = rng.standard_normal(npoints * npoints) if wraw is None else wraw
+        G = np.ascontiguousarray(G, dtype=np.float64).reshape(-1)
+        wraw = np.ascontiguousarray(wraw, dtype=np.float64).reshape(-1)
+        if G.size != npoints * n:
+            raise ValueError(f"G must hold {npoints} x {n} draws")
+        gaps = np.zeros((r.value, npoints))
+        keep = np.zeros((r.value, npoints), dtype=np.int32)
+        _check(lib().pdhg_fishnet(self.h, int(npoints), int(k), G.ctypes.data, wraw.ctypes.data, wraw.size,
+                                  MEM_HOST, gaps.ctypes.data, keep.ctypes.data, _stream(stream)))
+        return {"rounds": r.value, "gaps": gaps, "keep": keep}
 
     def time_kernels(self, reps: int = 20, stream=None) -> dict:
         """Average per-launch device time of each phase kernel (ms), HIP events."""

@@ -76,6 +76,7 @@ extern "C" void pdhg_default_opts(pdhg_opts *o)
     o->adaptive_step = 0;
     o->detect_infeas = 0;
     o->infeas_tol = 1e-4;
+    o->fishnet_points = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -308,6 +309,8 @@ struct pdhg_handle {
     double setup_seconds = 0;
     hipGraphExec_t graph = nullptr;
     hipStream_t cap_stream = nullptr;
+    FishDev fish{};          // fishnet buffers (opts.fishnet_points > 0)
+    bool fish_rows = false;  // fish.rowK / rowT hold the rows by decreasing length
     int64_t rec_steps = 0;  // steps recorded by the last recording pdhg_iterate
     int rec_valid = 0;
     std::vector<InstState> rec_st;  // step parameters of the recorded steps
@@ -315,8 +318,15 @@ struct pdhg_handle {
 
 static size_t elem_size(int prec) { return prec == PDHG_PREC_F64 ? sizeof(double) : sizeof(float); }
 
+static int ilog2(int v)
+{
+    int r = 0;
+    while ((1 << (r + 1)) <= v) ++r;
+    return r;
+}
+
 static void carve(Carve &cv, const Sizes &sz, int prec, const pdhg_opts &o, Dev &d, Buffers &b,
-                  InstInfo **info, InstState **st)
+                  InstInfo **info, InstState **st, FishDev *fish)
 {
     const size_t es = elem_size(prec);
     const int64_t N = sz.N, M = sz.M, NNZ = sz.NNZ;
@@ -381,6 +391,26 @@ static void carve(Carve &cv, const Sizes &sz, int prec, const pdhg_opts &o, Dev 
     d.vecM64 = cv.take<double>(M);
     d.vecM64b = cv.take<double>(M);
     d.inst_scratch = cv.take<double>((size_t)sz.batch * 16 + 16);
+    // fishnet casting: PS interleaved points
+    if (o.fishnet_points > 0) {
+        const int64_t PS = o.fishnet_points;
+        fish->PS = (int32_t)PS;
+        fish->nrec = 2 * ilog2((int)PS);
+        fish->X = cv.take<char>(N * PS * es);
+        fish->XB = cv.take<char>(N * PS * es);
+        fish->X2 = cv.take<char>(N * PS * es);
+        fish->Y = cv.take<char>(M * PS * es);
+        fish->Y2 = cv.take<char>(M * PS * es);
+        fish->rowK = cv.take<int32_t>(M + 1);
+        fish->rowT = cv.take<int32_t>(N + 1);
+        fish->part = cv.take<double>((size_t)FISH_GRID * PS);
+        fish->wmat = cv.take<double>((size_t)(PS / 2) * (PS / 2) + 1);
+        fish->keep = cv.take<int32_t>(PS);
+        fish->gstage = cv.take<double>(N * PS + 1);
+        fish->wstage = cv.take<double>(PS * PS);
+        fish->rec_gaps = cv.take<double>((size_t)fish->nrec * PS);
+        fish->rec_keep = cv.take<int32_t>((size_t)fish->nrec * PS);
+    }
     // adjoint of unrolled steps
     if (o.unroll_capacity > 0) {
         const int64_t C = std::max(1, o.unroll_checkpoint);
@@ -415,6 +445,9 @@ static int check_opts(const pdhg_opts *o)
     if (o->adaptive_step != 0 && o->adaptive_step != 1) return fail(PDHG_ERR_INVALID_ARG, "adaptive_step must be 0 or 1");
     if (o->detect_infeas != 0 && o->detect_infeas != 1) return fail(PDHG_ERR_INVALID_ARG, "detect_infeas must be 0 or 1");
     if (o->detect_infeas && !(o->infeas_tol > 0.0)) return fail(PDHG_ERR_INVALID_ARG, "infeas_tol must be > 0");
+    if (o->fishnet_points != 0 &&
+        (o->fishnet_points < 2 || o->fishnet_points > 64 || (o->fishnet_points & (o->fishnet_points - 1))))
+        return fail(PDHG_ERR_INVALID_ARG, "fishnet_points must be 0 or a power of two in 2..64");
     return PDHG_OK;
 }
 
@@ -475,7 +508,8 @@ extern "C" size_t pdhg_workspace_bytes(const pdhg_lp *lp, int32_t batch, const p
     Buffers b{};
     InstInfo *info;
     InstState *st;
-    carve(cv, sz, o->precision, *o, d, b, &info, &st);
+    FishDev fish{};
+    carve(cv, sz, o->precision, *o, d, b, &info, &st, &fish);
     return (cv.off + 255) & ~(size_t)255;
 }
 
@@ -786,7 +820,7 @@ extern "C" int pdhg_setup(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, 
     cv.base = (char *)ws;
     InstInfo *info;
     InstState *st;
-    carve(cv, h->sz, h->prec, *o, h->d, h->buf, &info, &st);
+    carve(cv, h->sz, h->prec, *o, h->d, h->buf, &info, &st, &h->fish);
     if (cv.off > ws_bytes) {
         delete h;
         return fail(PDHG_ERR_NOMEM, "workspace too small: need %zu bytes, got %zu", cv.off, ws_bytes);
@@ -1228,6 +1262,146 @@ extern "C" int pdhg_set_state(pdhg_handle *h, int32_t inst, const double *x, con
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
     return PDHG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// fishnet casting (Section 2.5, Algorithm 7)
+// ---------------------------------------------------------------------------
+
+// rows of one operator in order of decreasing length (stable), uploaded once
+static int fish_build_rows(pdhg_handle *h, hipStream_t s)
+{
+    const Dev &d = h->d;
+    for (int op = 0; op < 2; ++op) {
+        const OpDev &o = op == 0 ? d.K : d.Kt;
+        std::vector<int64_t> rp(o.nrows + 1);
+        HIPCHK(hipMemcpyAsync(rp.data(), o.rp, rp.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        std::vector<int32_t> ord(o.nrows);
+        for (int64_t r = 0; r < o.nrows; ++r) ord[r] = (int32_t)r;
+        std::stable_sort(ord.begin(), ord.end(),
+                         [&](int32_t a, int32_t b) { return rp[a + 1] - rp[a] > rp[b + 1] - rp[b]; });
+        int32_t *dst = (int32_t *)(op == 0 ? h->fish.rowK : h->fish.rowT);
+        if (o.nrows) HIPCHK(hipMemcpyAsync(dst, ord.data(), ord.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    h->fish_rows = true;
+    return PDHG_OK;
+}
+
+// rounds of Algorithm 7 for P points and the repopulation draws they consume
+static void fish_plan(int P, int *rounds, int64_t *draws)
+{
+    int j = P, r = 0;
+    int64_t need = 0;
+    while (j > 1) {
+        const int half = j / 2;
+        const bool rep = (r & 1) && j > 2;
+        if (rep) need += (int64_t)half * half;
+        j = rep ? 2 * half : half;
+        ++r;
+    }
+    *rounds = r;
+    *draws = need;
+}
+
+template <typename T>
+static int fishnet_impl(pdhg_handle *h, int P, int32_t k, const double *G, const double *wraw, int mem,
+                        double *gaps, int32_t *keep, hipStream_t s)
+{
+    Dev &d = h->d;
+    FishDev f = h->fish;
+    int rounds;
+    int64_t need;
+    fish_plan(P, &rounds, &need);
+    const size_t ng = (size_t)P * d.N;
+    if (mem == PDHG_MEM_HOST) {
+        for (size_t t = 0; t < ng; ++t)
+            if (!std::isfinite(G[t])) return fail(PDHG_ERR_NONFINITE, "fishnet draws: G[%zu] is not finite", t);
+        for (int64_t t = 0; t < need; ++t)
+            if (!std::isfinite(wraw[t])) return fail(PDHG_ERR_NONFINITE, "fishnet draws: wraw[%lld] is not finite",
+                                                     (long long)t);
+    }
+    const hipMemcpyKind kind = mem == PDHG_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    if (ng) HIPCHK(hipMemcpyAsync(f.gstage, G, ng * sizeof(double), kind, s));
+    if (need) HIPCHK(hipMemcpyAsync(f.wstage, wraw, need * sizeof(double), kind, s));
+    if (!h->fish_rows) {
+        int rc = fish_build_rows(h, s);
+        if (rc) return rc;
+    }
+    const InstState &st = h->st0[0];
+    const InstInfo &in = h->info[0];
+    const double sc = d.N > 0 ? st.knorm / std::sqrt((double)d.N) : 0.0;
+    launch_fish_init<T>(d, f, ilog2(P), sc, s);
+    int j = P, round = 0;
+    int64_t wpos = 0;
+    while (j > 1) {
+        const int lj = ilog2(j);
+        for (int t = 0; t < k; ++t) launch_fish_step<T>(d, f, lj, st.tau, st.sigma, in.m1, s);
+        const int half = j / 2;
+        const int rep = (round & 1) && j > 2;
+        const int next = rep ? 2 * half : half;
+        launch_fish_gap_rank<T>(d, f, lj, round, rep, half, wpos, s);
+        launch_fish_gather<T>(d, f, ilog2(next), half, s);
+        std::swap(f.X, f.X2);
+        std::swap(f.Y, f.Y2);
+        if (rep) wpos += (int64_t)half * half;
+        j = next;
+        ++round;
+    }
+    launch_fish_out<T>(d, f, s);
+    launch_set_point<T>(d, 0, d.N, 0, d.M, in.m1, d.vecN64, d.vecM64, s);
+    HIPCHK(hipGetLastError());
+    // the record, repacked to P columns
+    std::vector<double> rg((size_t)f.nrec * f.PS);
+    std::vector<int32_t> rk((size_t)f.nrec * f.PS);
+    HIPCHK(hipMemcpyAsync(rg.data(), f.rec_gaps, rg.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(rk.data(), f.rec_keep, rk.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<double> og((size_t)rounds * P);
+    std::vector<int32_t> ok((size_t)rounds * P);
+    for (int r = 0; r < rounds; ++r)
+        for (int q = 0; q < P; ++q) {
+            og[(size_t)r * P + q] = rg[(size_t)r * f.PS + q];
+            ok[(size_t)r * P + q] = rk[(size_t)r * f.PS + q];
+        }
+    const hipMemcpyKind back = mem == PDHG_MEM_HOST ? hipMemcpyHostToHost : hipMemcpyHostToDevice;
+    if (gaps) HIPCHK(hipMemcpy(gaps, og.data(), og.size() * sizeof(double), back));
+    if (keep) HIPCHK(hipMemcpy(keep, ok.data(), ok.size() * sizeof(int32_t), back));
+    return PDHG_OK;
+}
+
+extern "C" int pdhg_fishnet_rounds(int32_t npoints, int32_t *rounds, int64_t *draws)
+{
+    if (npoints < 2 || npoints > 64 || (npoints & (npoints - 1)) || !rounds || !draws)
+        return fail(PDHG_ERR_INVALID_ARG, "npoints must be a power of two in 2..64");
+    int r;
+    int64_t n;
+    fish_plan(npoints, &r, &n);
+    *rounds = r;
+    *draws = n;
+    return PDHG_OK;
+}
+
+extern "C" int pdhg_fishnet(pdhg_handle *h, int32_t npoints, int32_t k, const double *G, const double *wraw,
+                            int64_t nw, int32_t mem, double *gaps, int32_t *keep, hipStream_t s)
+{
+    if (!h || !G) return fail(PDHG_ERR_INVALID_ARG, "NULL handle or draws");
+    if (h->batch != 1) return fail(PDHG_ERR_STATE, "fishnet casting runs on a handle of one LP");
+    if (h->opts.fishnet_points <= 0)
+        return fail(PDHG_ERR_STATE, "fishnet casting needs opts.fishnet_points > 0 at setup");
+    if (npoints < 2 || npoints > h->opts.fishnet_points || (npoints & (npoints - 1)))
+        return fail(PDHG_ERR_INVALID_ARG, "npoints must be a power of two in 2..%d", h->opts.fishnet_points);
+    if (k < 1) return fail(PDHG_ERR_INVALID_ARG, "k must be >= 1");
+    if (mem != PDHG_MEM_HOST && mem != PDHG_MEM_DEVICE) return fail(PDHG_ERR_INVALID_ARG, "bad mem");
+    int rounds;
+    int64_t need;
+    fish_plan(npoints, &rounds, &need);
+    if (need > 0 && (!wraw || nw < need))
+        return fail(PDHG_ERR_INVALID_ARG, "%d points need %lld repopulation draws, got %lld", npoints,
+                    (long long)need, (long long)(wraw ? nw : 0));
+    return h->prec == PDHG_PREC_F32 ? fishnet_impl<float>(h, npoints, k, G, wraw, mem, gaps, keep, s)
+                                    : fishnet_impl<double>(h, npoints, k, G, wraw, mem, gaps, keep, s);
 }
 
 extern "C" int pdhg_kkt(pdhg_handle *h, int32_t inst, const double *x, const double *y, int32_t mem,

@@ -62,6 +62,18 @@ void launch_set_point(const Dev &d, int64_t xoff, int64_t n, int64_t yoff, int64
                       const double *xs, const double *ys, hipStream_t s);
 void launch_kkt_final(const Dev &d, int inst, double *out9, hipStream_t s);
 
+template <typename T>
+void launch_fish_step(const Dev &d, const FishDev &f, int lj, double tau, double sigma, int64_t m1, hipStream_t s);
+template <typename T>
+void launch_fish_init(const Dev &d, const FishDev &f, int lp, double sc, hipStream_t s);
+template <typename T>
+int launch_fish_gap_rank(const Dev &d, const FishDev &f, int lj, int round, int repop, int half, int64_t wpos,
+                         hipStream_t s);
+template <typename T>
+void launch_fish_gather(const Dev &d, const FishDev &f, int lnext, int half, hipStream_t s);
+template <typename T>
+void launch_fish_out(const Dev &d, const FishDev &f, hipStream_t s);
+
 void launch_adj_init(const Dev &d, const AdjBufs &a, const double *gx, const double *gy, hipStream_t s);
 void launch_adj_w(const Dev &d, const AdjBufs &a, const uint8_t *mask_y, hipStream_t s);
 template <typename T>

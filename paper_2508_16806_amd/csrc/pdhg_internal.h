@@ -153,6 +153,25 @@ struct Dev {
     double *inst_scratch;         // batch * 16
 };
 
+// Fishnet casting (Algorithm 7): up to PS candidate points, interleaved
+// (entry r of point q at [r * PS + q]) so that one gather of a matrix entry
+// serves every point with a contiguous load.
+struct FishDev {
+    int32_t PS;                 // point capacity (stride), a power of two <= 64
+    int32_t nrec;               // rounds the record arrays hold
+    void *X, *XB, *Y;           // current points (type T): N x PS, N x PS, M x PS
+    void *X2, *Y2;              // next round's points
+    const int32_t *rowK, *rowT; // rows of K / K^T by decreasing length
+    double *part;               // per-workgroup gap partials, FISH_GRID x PS
+    double *wmat;               // repopulation weights, (PS/2) x (PS/2)
+    int32_t *keep;              // kept point indices of the current round (PS)
+    double *gstage;             // caller's normal draws, PS x N (FP64)
+    double *wstage;             // caller's repopulation draws (PS * PS)
+    double *rec_gaps;           // nrec x PS
+    int32_t *rec_keep;          // nrec x PS
+};
+constexpr int FISH_GRID = 512;  // workgroups of the gap pass
+
 // FP64 adjoint vectors of the unrolled-step backward pass.
 struct AdjBufs {
     double *ax, *av, *ac, *al, *au;  // length N

@@ -46,7 +46,8 @@ def test_struct_layouts_match_header(pd):
     assert o.adaptive_step == 0 and o.max_grid == 8192
     # the option struct ends with the detection fields; the result and timer structs
     # end with the adaptive-step fields
-    assert pd.Opts.infeas_tol.offset + 8 == C.sizeof(pd.Opts)
+    assert pd.Opts.fishnet_points.offset == pd.Opts.infeas_tol.offset + 8
+    assert o.fishnet_points == 0
     assert o.detect_infeas == 0 and o.infeas_tol == 1e-4
     assert pd.Result.eta_next.offset + 8 == C.sizeof(pd.Result)
     assert pd.KernelTimes.ms_step_ad.offset + 8 == C.sizeof(pd.KernelTimes)
@@ -120,6 +121,20 @@ def test_rejects_bad_options(pd):
     assert _nbytes(pd, lp, detect_infeas=2) == 0 and "detect_infeas" in _err(pd)
     assert _nbytes(pd, lp, detect_infeas=1, infeas_tol=0.0) == 0 and "infeas_tol" in _err(pd)
     assert _nbytes(pd, lp, detect_infeas=1) == _nbytes(pd, lp)
+    assert _nbytes(pd, lp, fishnet_points=3) == 0 and "fishnet_points" in _err(pd)
+    assert _nbytes(pd, lp, fishnet_points=128) == 0
+    assert _nbytes(pd, lp, fishnet_points=32) > _nbytes(pd, lp)
+
+
+def test_fishnet_rounds_and_draws(pd):
+    L = pd.lib()
+    r, n = C.c_int32(0), C.c_int64(0)
+    # 2^p points: 2p - 2 rounds (one for two points); the repopulating rounds
+    # keep 2^(p-2), ..., 2 points and draw (kept)^2 weights each
+    for P, rounds, draws in ((2, 1, 0), (4, 2, 0), (8, 4, 4), (16, 6, 20), (32, 8, 84), (64, 10, 340)):
+        assert L.pdhg_fishnet_rounds(P, C.byref(r), C.byref(n)) == 0
+        assert (r.value, n.value) == (rounds, draws), P
+    assert L.pdhg_fishnet_rounds(6, C.byref(r), C.byref(n)) != 0
 
 
 def test_infinite_bounds_accepted(pd):
