@@ -346,6 +346,35 @@ def main():
         print(f"[bench] adaptive steps: time to 1e-4: {tsa:.2f}s {ra['status_name']} iters={ra['iters']} "
               f"accepted={ra['accepted']} restarts={ra['restarts']}", file=sys.stderr, flush=True)
 
+    # fishnet casting (Algorithm 7): 32 points, 64 steps per round, then the
+    # restarted solve from the surviving point
+    fish = None
+    if not args.no_ttt:
+        sf = pd.Solver(lp, precision="f32", eps=1e-4, max_iters=2_000_000, time_limit=120.0, fishnet_points=32,
+                       **tune)
+        sf.fishnet(32, 64, seed=0)  # first call: row orders and kernel loads
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fo = sf.fishnet(32, 64, seed=1)
+        tfn = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        rf = sf.solve()[0]
+        tfs = time.perf_counter() - t0
+        x, y = sf.solution()
+        pts = 0
+        j = 32
+        for r in range(fo["rounds"]):  # live points per round
+            pts += j * 64
+            half = j // 2
+            j = 2 * half if (r % 2 == 1 and j > 2) else half
+        fish = {"points": 32, "k": 64, "rounds": fo["rounds"], "seconds_fishnet": tfn, "point_iters": pts,
+                "point_iters_per_s": pts / tfn, "seconds_solve_after": tfs, "status": rf["status_name"],
+                "iters_after": rf["iters"], "restarts_after": rf["restarts"],
+                "rel_kkt_fp64_recheck": sf.kkt(x, y)["rel_kkt"], "seconds_total": tfn + tfs}
+        sf.close()
+        print(f"[bench] fishnet 32 x 64: {tfn:.3f}s ({pts / tfn:.0f} point-iter/s), then solve to 1e-4 in "
+              f"{tfs:.3f}s {rf['status_name']} iters={rf['iters']}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(lp)
@@ -378,6 +407,7 @@ def main():
         "sweep_gbs": {"primal": pg, "dual": dg},
         "time_to_tol": ttt,
         "adaptive_step": adaptive,
+        "fishnet": fish,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
