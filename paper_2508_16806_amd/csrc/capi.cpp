@@ -403,6 +403,12 @@ static void carve(Carve &cv, const Sizes &sz, int prec, const pdhg_opts &o, Dev 
         fish->Y2 = cv.take<char>(M * PS * es);
         fish->rowK = cv.take<int32_t>(M + 1);
         fish->rowT = cv.take<int32_t>(N + 1);
+        const int64_t chunks = NNZ / FISH_CHUNK + 1;
+        fish->taskK = cv.take<int4>(M + chunks + 1);
+        fish->taskT = cv.take<int4>(N + chunks + 1);
+        fish->splitK = cv.take<int4>(std::min<int64_t>(M, chunks) + 1);
+        fish->splitT = cv.take<int4>(std::min<int64_t>(N, chunks) + 1);
+        fish->cpart = cv.take<double>((2 * chunks + 2) * PS);
         fish->part = cv.take<double>((size_t)FISH_GRID * PS);
         fish->wmat = cv.take<double>((size_t)(PS / 2) * (PS / 2) + 1);
         fish->keep = cv.take<int32_t>(PS);
@@ -1268,22 +1274,53 @@ extern "C" int pdhg_set_state(pdhg_handle *h, int32_t inst, const double *x, con
 // fishnet casting (Section 2.5, Algorithm 7)
 // ---------------------------------------------------------------------------
 
-// rows of one operator in order of decreasing length (stable), uploaded once
-static int fish_build_rows(pdhg_handle *h, hipStream_t s)
+// Once per handle: the rows of each operator by decreasing length (stable)
+// for the gap pass, and the sweep tasks: whole rows, or FISH_CHUNK-entry
+// chunks of longer rows (with one partial slot each), longest first.
+static int fish_build_tables(pdhg_handle *h, hipStream_t s)
 {
     const Dev &d = h->d;
+    FishDev &f = h->fish;
     for (int op = 0; op < 2; ++op) {
         const OpDev &o = op == 0 ? d.K : d.Kt;
         std::vector<int64_t> rp(o.nrows + 1);
         HIPCHK(hipMemcpyAsync(rp.data(), o.rp, rp.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        if (rp[o.nrows] >= INT32_MAX) return fail(PDHG_ERR_SHAPE, "fishnet casting needs fewer than 2^31 nonzeros");
         std::vector<int32_t> ord(o.nrows);
         for (int64_t r = 0; r < o.nrows; ++r) ord[r] = (int32_t)r;
         std::stable_sort(ord.begin(), ord.end(),
                          [&](int32_t a, int32_t b) { return rp[a + 1] - rp[a] > rp[b + 1] - rp[b]; });
-        int32_t *dst = (int32_t *)(op == 0 ? h->fish.rowK : h->fish.rowT);
-        if (o.nrows) HIPCHK(hipMemcpyAsync(dst, ord.data(), ord.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        std::vector<int4> tasks, splits;
+        int32_t slot = 0;
+        for (int64_t r = 0; r < o.nrows; ++r) {
+            const int32_t b = (int32_t)rp[r], e = (int32_t)rp[r + 1];
+            if (e - b <= FISH_CHUNK) {
+                tasks.push_back(make_int4((int32_t)r, b, e, -1));
+                continue;
+            }
+            const int32_t nch = (e - b + FISH_CHUNK - 1) / FISH_CHUNK;
+            splits.push_back(make_int4((int32_t)r, slot, nch, 0));
+            for (int32_t c = 0; c < nch; ++c)
+                tasks.push_back(make_int4((int32_t)r, b + c * FISH_CHUNK, std::min(e, b + (c + 1) * FISH_CHUNK), slot + c));
+            slot += nch;
+        }
+        std::stable_sort(tasks.begin(), tasks.end(), [](const int4 &a, const int4 &b) { return a.z - a.y > b.z - b.y; });
+        std::stable_sort(splits.begin(), splits.end(), [](const int4 &a, const int4 &b) { return a.z > b.z; });
+        int32_t *rows = (int32_t *)(op == 0 ? f.rowK : f.rowT);
+        int4 *tk = (int4 *)(op == 0 ? f.taskK : f.taskT);
+        int4 *sp = (int4 *)(op == 0 ? f.splitK : f.splitT);
+        if (o.nrows) HIPCHK(hipMemcpyAsync(rows, ord.data(), ord.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        if (!tasks.empty()) HIPCHK(hipMemcpyAsync(tk, tasks.data(), tasks.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+        if (!splits.empty()) HIPCHK(hipMemcpyAsync(sp, splits.data(), splits.size() * sizeof(int4), hipMemcpyHostToDevice, s));
         HIPCHK(hipStreamSynchronize(s));
+        if (op == 0) {
+            f.ntaskK = (int64_t)tasks.size();
+            f.nsplitK = (int64_t)splits.size();
+        } else {
+            f.ntaskT = (int64_t)tasks.size();
+            f.nsplitT = (int64_t)splits.size();
+        }
     }
     h->fish_rows = true;
     return PDHG_OK;
@@ -1310,6 +1347,10 @@ static int fishnet_impl(pdhg_handle *h, int P, int32_t k, const double *G, const
                         double *gaps, int32_t *keep, hipStream_t s)
 {
     Dev &d = h->d;
+    if (!h->fish_rows) {
+        int rc = fish_build_tables(h, s);
+        if (rc) return rc;
+    }
     FishDev f = h->fish;
     int rounds;
     int64_t need;
@@ -1325,10 +1366,6 @@ static int fishnet_impl(pdhg_handle *h, int P, int32_t k, const double *G, const
     const hipMemcpyKind kind = mem == PDHG_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     if (ng) HIPCHK(hipMemcpyAsync(f.gstage, G, ng * sizeof(double), kind, s));
     if (need) HIPCHK(hipMemcpyAsync(f.wstage, wraw, need * sizeof(double), kind, s));
-    if (!h->fish_rows) {
-        int rc = fish_build_rows(h, s);
-        if (rc) return rc;
-    }
     const InstState &st = h->st0[0];
     const InstInfo &in = h->info[0];
     const double sc = d.N > 0 ? st.knorm / std::sqrt((double)d.N) : 0.0;

@@ -7,7 +7,9 @@
 // group loads the same matrix entry (one transaction for the group) and
 // gathers point q's entry of the column, so a gather moves j contiguous
 // values: the multi-point sweep reads the matrix once for all points.  Rows
-// are taken in order of decreasing length (longest chains start first).
+// longer than FISH_CHUNK entries are cut into chunks (their partial sums are
+// added by a combine pass in chunk order), and the tasks run longest first,
+// so no lane group walks a long dependent chain.
 //
 // One round: k primal/dual steps on the live points, the duality gap of each
 // point (grid-stride partials, reduced in a fixed order), a one-workgroup
@@ -24,13 +26,12 @@
 
 namespace pdhg {
 
-// sum over a row of the lane's point: acc = sum_p v_p * G[c_p * PS + q],
-// entries in row order (4 loads in flight per lane)
+// sum over entries [b, e) of a row for the lane's point:
+// acc = sum_p v_p * G[c_p * PS + q], in entry order (4 loads in flight)
 template <typename MV, typename GV>
-__device__ __forceinline__ double fish_row_dot(const OpDev &op, const MV *__restrict__ va, int64_t row,
-                                               const GV *__restrict__ G, int PS, int q)
+__device__ __forceinline__ double fish_dot(const OpDev &op, const MV *__restrict__ va, int64_t b, int64_t e,
+                                           const GV *__restrict__ G, int PS, int q)
 {
-    const int64_t b = op.rp[row], e = op.rp[row + 1];
     const int32_t *__restrict__ ci = op.ci;
     double acc = 0.0;
     int64_t p = b;
@@ -48,44 +49,97 @@ __device__ __forceinline__ double fish_row_dot(const OpDev &op, const MV *__rest
     return acc;
 }
 
-// x+ = clip(x - tau (c~ - K~^T y), l~, u~), xbar = 2 x+ - x, for every live point
-template <typename T>
-__global__ __launch_bounds__(WG) void k_fish_primal(Dev d, FishDev f, int lj, double tau)
+template <typename MV, typename GV>
+__device__ __forceinline__ double fish_row_dot(const OpDev &op, const MV *__restrict__ va, int64_t row,
+                                               const GV *__restrict__ G, int PS, int q)
 {
-    const int tid = threadIdx.x, q = tid & ((1 << lj) - 1);
-    const int64_t g = (int64_t)blockIdx.x * (WG >> lj) + (tid >> lj);
-    if (g >= d.Kt.nrows) return;
-    const int64_t row = f.rowT[g];
-    const int PS = f.PS;
-    const double acc = fish_row_dot(d.Kt, op_vals<T>(d.Kt), row, (const T *)f.Y, PS, q);
+    return fish_dot(op, va, op.rp[row], op.rp[row + 1], G, PS, q);
+}
+
+// x+ = clip(x - tau (c~ - g), l~, u~), xbar = 2 x+ - x
+template <typename T>
+__device__ __forceinline__ void fish_primal_epi(const Dev &d, const FishDev &f, int64_t row, int q, double g,
+                                                double tau)
+{
     T *X = (T *)f.X;
-    const int64_t at = row * PS + q;
+    const int64_t at = row * f.PS + q;
     const double xo = (double)X[at];
-    const double v = xo - tau * ((double)((const T *)d.c)[row] - acc);
+    const double v = xo - tau * ((double)((const T *)d.c)[row] - g);
     const double lo = (double)((const T *)d.l)[row], hi = (double)((const T *)d.u)[row];
     const T xn = (T)(v < lo ? lo : (v > hi ? hi : v));
     X[at] = xn;
     ((T *)f.XB)[at] = (T)(2.0 * (double)xn - xo);
 }
 
-// INIT = 0: y+ = proj_Y(y + sigma (q~ - K~ xbar)); INIT = 1: y = K~ x
+// INIT = 0: y+ = proj_Y(y + sigma (q~ - r)); INIT = 1: y = r
+template <typename T, int INIT>
+__device__ __forceinline__ void fish_dual_epi(const Dev &d, const FishDev &f, int64_t row, int q, double r,
+                                              double sigma, int64_t m1)
+{
+    T *Y = (T *)f.Y;
+    const int64_t at = row * f.PS + q;
+    if (INIT) {
+        Y[at] = (T)r;
+        return;
+    }
+    const double w = (double)Y[at] + sigma * ((double)((const T *)d.q)[row] - r);
+    Y[at] = (T)((row < m1 && w < 0.0) ? 0.0 : w);
+}
+
+// One lane group (j lanes, one per live point) per task, tasks longest first.
+// A task that covers its whole row applies the update; a chunk of a split
+// row stores its partial sum for the combine pass.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_fish_primal(Dev d, FishDev f, int lj, double tau)
+{
+    const int tid = threadIdx.x, q = tid & ((1 << lj) - 1);
+    const int64_t g = (int64_t)blockIdx.x * (WG >> lj) + (tid >> lj);
+    if (g >= f.ntaskT) return;
+    const int4 t = f.taskT[g];
+    const double acc = fish_dot(d.Kt, op_vals<T>(d.Kt), t.y, t.z, (const T *)f.Y, f.PS, q);
+    if (t.w < 0)
+        fish_primal_epi<T>(d, f, t.x, q, acc, tau);
+    else
+        f.cpart[(int64_t)t.w * f.PS + q] = acc;
+}
+
 template <typename T, int INIT>
 __global__ __launch_bounds__(WG) void k_fish_dual(Dev d, FishDev f, int lj, double sigma, int64_t m1)
 {
     const int tid = threadIdx.x, q = tid & ((1 << lj) - 1);
     const int64_t g = (int64_t)blockIdx.x * (WG >> lj) + (tid >> lj);
-    if (g >= d.K.nrows) return;
-    const int64_t row = f.rowK[g];
-    const int PS = f.PS;
-    const double acc = fish_row_dot(d.K, op_vals<T>(d.K), row, (const T *)(INIT ? f.X : f.XB), PS, q);
-    T *Y = (T *)f.Y;
-    const int64_t at = row * PS + q;
-    if (INIT) {
-        Y[at] = (T)acc;
-        return;
-    }
-    const double w = (double)Y[at] + sigma * ((double)((const T *)d.q)[row] - acc);
-    Y[at] = (T)((row < m1 && w < 0.0) ? 0.0 : w);
+    if (g >= f.ntaskK) return;
+    const int4 t = f.taskK[g];
+    const double acc = fish_dot(d.K, op_vals<T>(d.K), t.y, t.z, (const T *)(INIT ? f.X : f.XB), f.PS, q);
+    if (t.w < 0)
+        fish_dual_epi<T, INIT>(d, f, t.x, q, acc, sigma, m1);
+    else
+        f.cpart[(int64_t)t.w * f.PS + q] = acc;
+}
+
+// Combine passes: the chunk partials of each split row, in chunk order.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_fish_combine_primal(Dev d, FishDev f, int lj, double tau)
+{
+    const int tid = threadIdx.x, q = tid & ((1 << lj) - 1);
+    const int64_t g = (int64_t)blockIdx.x * (WG >> lj) + (tid >> lj);
+    if (g >= f.nsplitT) return;
+    const int4 sp = f.splitT[g];
+    double acc = 0.0;
+    for (int c = 0; c < sp.z; ++c) acc += f.cpart[(int64_t)(sp.y + c) * f.PS + q];
+    fish_primal_epi<T>(d, f, sp.x, q, acc, tau);
+}
+
+template <typename T, int INIT>
+__global__ __launch_bounds__(WG) void k_fish_combine_dual(Dev d, FishDev f, int lj, double sigma, int64_t m1)
+{
+    const int tid = threadIdx.x, q = tid & ((1 << lj) - 1);
+    const int64_t g = (int64_t)blockIdx.x * (WG >> lj) + (tid >> lj);
+    if (g >= f.nsplitK) return;
+    const int4 sp = f.splitK[g];
+    double acc = 0.0;
+    for (int c = 0; c < sp.z; ++c) acc += f.cpart[(int64_t)(sp.y + c) * f.PS + q];
+    fish_dual_epi<T, INIT>(d, f, sp.x, q, acc, sigma, m1);
 }
 
 // Per-workgroup partials of dobj - pobj for every live point (scaled data,
@@ -239,9 +293,12 @@ static inline unsigned fish_groups(int64_t rows, int lj)
 template <typename T>
 void launch_fish_step(const Dev &d, const FishDev &f, int lj, double tau, double sigma, int64_t m1, hipStream_t s)
 {
-    const unsigned gT = fish_groups(d.Kt.nrows, lj), gK = fish_groups(d.K.nrows, lj);
-    if (gT) hipLaunchKernelGGL(k_fish_primal<T>, dim3(gT), dim3(WG), 0, s, d, f, lj, tau);
-    if (gK) hipLaunchKernelGGL((k_fish_dual<T, 0>), dim3(gK), dim3(WG), 0, s, d, f, lj, sigma, m1);
+    const unsigned tT = fish_groups(f.ntaskT, lj), cT = fish_groups(f.nsplitT, lj);
+    const unsigned tK = fish_groups(f.ntaskK, lj), cK = fish_groups(f.nsplitK, lj);
+    if (tT) hipLaunchKernelGGL(k_fish_primal<T>, dim3(tT), dim3(WG), 0, s, d, f, lj, tau);
+    if (cT) hipLaunchKernelGGL(k_fish_combine_primal<T>, dim3(cT), dim3(WG), 0, s, d, f, lj, tau);
+    if (tK) hipLaunchKernelGGL((k_fish_dual<T, 0>), dim3(tK), dim3(WG), 0, s, d, f, lj, sigma, m1);
+    if (cK) hipLaunchKernelGGL((k_fish_combine_dual<T, 0>), dim3(cK), dim3(WG), 0, s, d, f, lj, sigma, m1);
 }
 
 template <typename T>
@@ -249,8 +306,9 @@ void launch_fish_init(const Dev &d, const FishDev &f, int lp, double sc, hipStre
 {
     const int64_t tot = d.N << lp;
     if (tot > 0) hipLaunchKernelGGL(k_fish_init<T>, dim3((unsigned)((tot + WG - 1) / WG)), dim3(WG), 0, s, d, f, lp, sc);
-    const unsigned gK = fish_groups(d.K.nrows, lp);
-    if (gK) hipLaunchKernelGGL((k_fish_dual<T, 1>), dim3(gK), dim3(WG), 0, s, d, f, lp, 0.0, (int64_t)0);
+    const unsigned tK = fish_groups(f.ntaskK, lp), cK = fish_groups(f.nsplitK, lp);
+    if (tK) hipLaunchKernelGGL((k_fish_dual<T, 1>), dim3(tK), dim3(WG), 0, s, d, f, lp, 0.0, (int64_t)0);
+    if (cK) hipLaunchKernelGGL((k_fish_combine_dual<T, 1>), dim3(cK), dim3(WG), 0, s, d, f, lp, 0.0, (int64_t)0);
 }
 
 template <typename T>

@@ -162,6 +162,13 @@ struct FishDev {
     void *X, *XB, *Y;           // current points (type T): N x PS, N x PS, M x PS
     void *X2, *Y2;              // next round's points
     const int32_t *rowK, *rowT; // rows of K / K^T by decreasing length
+    // sweep tasks: {row, first entry, end entry, partial slot or -1}; rows
+    // longer than FISH_CHUNK entries are split into chunks whose partial sums
+    // a combine pass adds ({row, first slot, chunks, 0} per split row)
+    const int4 *taskK, *taskT;
+    const int4 *splitK, *splitT;
+    int64_t ntaskK, ntaskT, nsplitK, nsplitT;
+    double *cpart;              // chunk partials, slots x PS
     double *part;               // per-workgroup gap partials, FISH_GRID x PS
     double *wmat;               // repopulation weights, (PS/2) x (PS/2)
     int32_t *keep;              // kept point indices of the current round (PS)
@@ -171,6 +178,7 @@ struct FishDev {
     int32_t *rec_keep;          // nrec x PS
 };
 constexpr int FISH_GRID = 512;  // workgroups of the gap pass
+constexpr int FISH_CHUNK = 256; // longest row a lane group sums in one pass
 
 // FP64 adjoint vectors of the unrolled-step backward pass.
 struct AdjBufs {
