@@ -120,6 +120,29 @@ def cpu_baseline(lp, budget_s=15.0):
                       f"at 20 passes in both; setup cancels)"}
 
 
+def _gen_one(a):
+    import lpgen
+
+    i, m_max = a
+    return lpgen.config3_instance(i, m_range=(1000, m_max))
+
+
+def _gen_batched(B, m_max):
+    """The batch's instances, generated by a pool of worker processes (each
+    instance has its own seed, so the result does not depend on the pool)."""
+    import multiprocessing as mp
+
+    workers = max(1, min(16, (os.cpu_count() or 1), B))
+    out = []
+    # spawned workers: they share no state with this process (no GPU context)
+    with mp.get_context("spawn").Pool(workers) as pool:
+        for i, lp in enumerate(pool.imap(_gen_one, [(i, m_max) for i in range(B)], chunksize=1)):
+            out.append(lp)
+            if (i + 1) % 32 == 0:
+                print(f"[bench] generated {i + 1}/{B}", file=sys.stderr, flush=True)
+    return out
+
+
 def bench_batched(args):
     """256 planted LPs (C3 recipe, m ~ U{1000..m_max}): one batched solve vs the
     same LPs solved one at a time with the same library on the same GPU."""
@@ -131,17 +154,21 @@ def bench_batched(args):
 
     B = args.batch
     t = time.perf_counter()
-    lps = [lpgen.config3_instance(i, m_range=(1000, args.m_max)) for i in range(B)]
+    lps = _gen_batched(B, args.m_max)
     gen_s = time.perf_counter() - t
     nnz = sum(lp.nnz for lp in lps)
     print(f"[bench] generated {B} LPs (m <= {args.m_max}), nnz {nnz} in {gen_s:.1f}s", file=sys.stderr, flush=True)
-    kw = dict(precision="f32", eps=1e-4, max_iters=200000, time_limit=300.0)
+    kw = dict(precision="f32", eps=1e-4, max_iters=200000, time_limit=170.0)
+    t0 = time.perf_counter()
     sb = pd.Solver(lps, **kw)
+    print(f"[bench] batched setup {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rb = sb.solve()
     tb = time.perf_counter() - t0
     print(f"[bench] batched: {tb:.2f}s, iters max {max(r['iters'] for r in rb)}", file=sys.stderr, flush=True)
+    sb.close()
+    del sb
     solo = []
     for i, lp in enumerate(lps):
         s = pd.Solver(lp, **kw)
@@ -150,6 +177,9 @@ def bench_batched(args):
         r = s.solve()[0]
         solo.append((time.perf_counter() - t0, r, lp.m, lp.nnz))
         s.close()
+        if (i + 1) % 16 == 0:
+            print(f"[bench] one by one: {i + 1}/{B} solved, {sum(x[0] for x in solo):.1f}s so far", file=sys.stderr,
+                  flush=True)
     ts = sum(x[0] for x in solo)
     same = all(rb[i]["iters"] == solo[i][1]["iters"] for i in range(B))
     gaps = [abs(r["kkt"]["pobj"] - lp.f_star) / (1 + abs(lp.f_star)) for r, lp in zip(rb, lps)]
@@ -237,7 +267,7 @@ def main():
     ap.add_argument("--workload", default="c1", choices=["c1", "c3", "c4"],
                     help="c1: SCED-shaped LP (default); c3: batched vs one-by-one; c4: unrolled adjoint")
     ap.add_argument("--batch", type=int, default=0)
-    ap.add_argument("--m-max", type=int, default=10000)
+    ap.add_argument("--m-max", type=int, default=50000)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run plain 256 MiB device copies (counter calibration under rocprofv3 --pmc)")
     args = ap.parse_args()

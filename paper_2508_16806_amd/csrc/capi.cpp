@@ -290,6 +290,7 @@ struct Buffers {
     double *ax, *ay, *aw, *av, *axb, *ac, *al, *au, *aq;
     double *vecN64c;
     int32_t *l2inst;
+    int64_t *bcumK, *bcumT;  // block cost prefix sums
 };
 
 struct pdhg_handle {
@@ -384,6 +385,10 @@ static void carve(Carve &cv, const Sizes &sz, int prec, const pdhg_opts &o, Dev 
     d.actT = cv.take<int32_t>(sz.nblkT + 1);
     d.act_cnt = cv.take<int32_t>(2);
     d.act_off = cv.take<int32_t>(2 * (size_t)sz.batch);
+    d.act_coff = cv.take<int64_t>(2 * (size_t)sz.batch + 2);
+    d.act_split = cv.take<int32_t>(18);
+    b.bcumK = cv.take<int64_t>(sz.nblkK + 1);
+    b.bcumT = cv.take<int64_t>(sz.nblkT + 1);
     b.l2inst = cv.take<int32_t>(sz.nl2 + 1);
     d.vecN64 = cv.take<double>(N);
     d.vecN64b = cv.take<double>(N);
@@ -662,7 +667,15 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
         yoff += p.m;
         nzoff = pos;
     }
+    // block costs for the XCD split of the sweeps: entries + 4 per row
+    std::vector<int64_t> cumK(sz.nblkK + 1, 0), cumT(sz.nblkT + 1, 0);
+    for (int64_t t = 0; t < sz.nblkK; ++t)
+        cumK[t + 1] = cumK[t] + (Krp[Kbd[t].x + Kbd[t].y] - Krp[Kbd[t].x]) + 4 * (int64_t)Kbd[t].y;
+    for (int64_t t = 0; t < sz.nblkT; ++t)
+        cumT[t + 1] = cumT[t] + (Ktrp[Ktbd[t].x + Ktbd[t].y] - Ktrp[Ktbd[t].x]) + 4 * (int64_t)Ktbd[t].y;
     int rc;
+    if ((rc = h2d(b.bcumK, cumK.data(), cumK.size(), s)) || (rc = h2d(b.bcumT, cumT.data(), cumT.size(), s)))
+        return rc;
     if ((rc = h2d(b.Krp, Krp.data(), Krp.size(), s)) || (rc = h2d(b.Kci, Kci.data(), Kci.size(), s)) ||
         (rc = h2d(b.Kv64, Kv.data(), Kv.size(), s)) || (rc = h2d(b.Kseg, Kseg.data(), Kseg.size(), s)) ||
         (rc = h2d(b.Kbs, Kbs.data(), Kbs.size(), s)) || (rc = h2d(b.Ktrp, Ktrp.data(), Ktrp.size(), s)) ||
@@ -840,6 +853,8 @@ extern "C" int pdhg_setup(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, 
     d.info = info;
     d.st = st;
     d.l2_inst = h->buf.l2inst;
+    d.bcumK = h->buf.bcumK;
+    d.bcumT = h->buf.bcumT;
     d.nl2 = (int32_t)h->sz.nl2;
     d.grid_cap = o->max_grid > 0 ? o->max_grid : 8192;
     Buffers &b = h->buf;

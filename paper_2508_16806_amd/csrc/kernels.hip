@@ -46,7 +46,7 @@ __global__ __launch_bounds__(WG) void k_primal(Dev d, int j_in_chunk, uint8_t *_
     const T *__restrict__ y = (const T *)d.y;
     const int cnt = d.act_cnt[1];
     const bool full = cnt == op.nblk;  // every block active: the list is the identity
-    for_each_item(cnt, d.remap, [&](int it) {
+    for_each_item_split(cnt, d.remap, d.act_split + 9, [&](int it) {
         const int lb = full ? it : d.actT[it];
         const Seg s = block_seg(op, lb);
         const InstState *st = d.st + s.inst;
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(WG) void k_dual(Dev d, int j_in_chunk, uint8_t *__r
     const T *__restrict__ xb = (const T *)d.xbar;
     const int cnt = d.act_cnt[0];
     const bool full = cnt == op.nblk;
-    for_each_item(cnt, d.remap, [&](int it) {
+    for_each_item_split(cnt, d.remap, d.act_split, [&](int it) {
         const int lb = full ? it : d.actK[it];
         const Seg s = block_seg(op, lb);
         const InstState *st = d.st + s.inst;
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(WG) void k_primal_ad(Dev d)
     const T *__restrict__ u = (const T *)d.u;
     const int cnt = d.act_cnt[1];
     const bool full = cnt == op.nblk;
-    for_each_item(cnt, d.remap, [&](int it) {
+    for_each_item_split(cnt, d.remap, d.act_split + 9, [&](int it) {
         const int lb = full ? it : d.actT[it];
         const Seg s = block_seg(op, lb);
         const InstState *st = d.st + s.inst;
@@ -238,7 +238,7 @@ __global__ __launch_bounds__(WG) void k_dual_ad(Dev d)
     const T *__restrict__ q = (const T *)d.q;
     const int cnt = d.act_cnt[0];
     const bool full = cnt == op.nblk;
-    for_each_item(cnt, d.remap, [&](int it) {
+    for_each_item_split(cnt, d.remap, d.act_split, [&](int it) {
         const int lb = full ? it : d.actK[it];
         const Seg s = block_seg(op, lb);
         const InstState *st = d.st + s.inst;
@@ -885,17 +885,62 @@ __global__ void k_act_scan(Dev d)
 {
     if (threadIdx.x != 0) return;
     int oK = 0, oT = 0;
+    int64_t cK = 0, cT = 0;
     for (int b = 0; b < d.batch; ++b) {
         const InstInfo &in = d.info[b];
         d.act_off[2 * b] = oK;
         d.act_off[2 * b + 1] = oT;
+        d.act_coff[2 * b] = cK;
+        d.act_coff[2 * b + 1] = cT;
         if (!d.st[b].done) {
             oK += in.blkK1 - in.blkK0;
             oT += in.blkT1 - in.blkT0;
+            cK += d.bcumK[in.blkK1] - d.bcumK[in.blkK0];
+            cT += d.bcumT[in.blkT1] - d.bcumT[in.blkT0];
         }
     }
     d.act_cnt[0] = oK;
     d.act_cnt[1] = oT;
+    d.act_coff[2 * d.batch] = cK;
+    d.act_coff[2 * d.batch + 1] = cT;
+}
+
+// XCD boundaries of the sweeps' active lists: thread (op, x) finds the list
+// position where the running cost reaches x/8 of the total (instance by a
+// scan, block by bisection of the cost prefix sums).
+__global__ void k_act_split(Dev d)
+{
+    const int t = threadIdx.x;
+    if (t >= 16) return;
+    const int op = t >> 3, x = t & 7;
+    int32_t *sp = d.act_split + op * 9;
+    const int cnt = d.act_cnt[op];
+    if (x == 0) {
+        sp[0] = 0;
+        sp[8] = cnt;
+        return;
+    }
+    const int64_t *cum = op == 0 ? d.bcumK : d.bcumT;
+    const int64_t total = d.act_coff[2 * d.batch + op];
+    const int64_t target = total * x / 8;
+    int pos = cnt;
+    for (int b = 0; b < d.batch; ++b) {
+        if (d.st[b].done) continue;
+        const InstInfo &in = d.info[b];
+        const int b0 = op == 0 ? in.blkK0 : in.blkT0, b1 = op == 0 ? in.blkK1 : in.blkT1;
+        const int64_t c0 = d.act_coff[2 * b + op];
+        if (target >= c0 + (cum[b1] - cum[b0])) continue;
+        // largest k in [b0, b1) with cum[k] - cum[b0] <= target - c0
+        int lo = b0, hi = b1 - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (cum[mid] - cum[b0] <= target - c0) lo = mid;
+            else hi = mid - 1;
+        }
+        pos = d.act_off[2 * b + op] + (lo - b0);
+        break;
+    }
+    sp[x] = pos;
 }
 
 // ... then every logical block of a running instance writes itself into place
@@ -1455,6 +1500,7 @@ void launch_active(const Dev &d, hipStream_t s)
     hipLaunchKernelGGL(k_act_scan, dim3(1), dim3(64), 0, s, d);
     const int64_t n = d.K.nblk > d.Kt.nblk ? d.K.nblk : d.Kt.nblk;
     LAUNCH(k_act_fill, nblk_elem(n), d);
+    hipLaunchKernelGGL(k_act_split, dim3(1), dim3(64), 0, s, d);
 }
 
 void launch_control(const Dev &d, const CtlParams &P, int iters_done, hipStream_t s)

@@ -147,6 +147,12 @@ struct Dev {
     int32_t *actK, *actT;         // logical blocks of running instances (K, K^T sweeps)
     int32_t *act_cnt;             // [2]: lengths of actK, actT
     int32_t *act_off;             // [2 * batch]: list offsets per instance
+    // XCD split of the sweeps' active lists by cost: bcum = prefix sums of the
+    // blocks' cost (entries + 4 per row) in block order, act_coff the list
+    // cost before each instance, act_split 2 x 9 list positions (K, then K^T)
+    const int64_t *bcumK, *bcumT;
+    int64_t *act_coff;            // [2 * batch + 2]: per instance, then the totals
+    int32_t *act_split;
     int32_t grid_cap;             // workgroups of a solve-time sweep launch
     double *vecN64, *vecN64b;     // FP64 scratch vectors (N)
     double *vecM64, *vecM64b;     // FP64 scratch vectors (M)

@@ -59,6 +59,22 @@ __device__ __forceinline__ void for_each_item(int cnt, int remap, F &&f)
     for (int it = i0 + loc; it < i1; it += nloc) f(it);
 }
 
+// As for_each_item, but with `remap` XCD x takes the item range
+// [split[x], split[x + 1]) (ranges of equal cost, computed by k_act_split).
+template <typename F>
+__device__ __forceinline__ void for_each_item_split(int cnt, int remap, const int32_t *split, F &&f)
+{
+    const int G = gridDim.x, b = blockIdx.x;
+    if (!remap || G < 8) {
+        for (int it = b; it < cnt; it += G) f(it);
+        return;
+    }
+    const int xcd = b & 7, loc = b >> 3;
+    const int nloc = (G - xcd + 7) >> 3;
+    const int i0 = split[xcd], i1 = min(cnt, split[xcd + 1]);
+    for (int it = i0 + loc; it < i1; it += nloc) f(it);
+}
+
 // The rows of logical block lb as a one-block segment (one 16-byte load):
 // rows [row0, row0 + nrows) of one instance and one length bin.
 __device__ __forceinline__ Seg block_seg(const OpDev &op, int lb)
