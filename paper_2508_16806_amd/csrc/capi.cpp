@@ -873,7 +873,7 @@ extern "C" int pdhg_setup(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, 
     }
     std::memset(h->hdone_host, 0, sizeof(int32_t) * batch);
     if (hipHostGetDevicePointer((void **)&d.hdone, h->hdone_host, 0) != hipSuccess) {
-        hipHostFree(h->hdone_host);
+        (void)hipHostFree(h->hdone_host);
         delete h;
         return fail(PDHG_ERR_HIP, "hipHostGetDevicePointer failed");
     }
@@ -894,9 +894,9 @@ extern "C" int pdhg_setup(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, 
 extern "C" void pdhg_destroy(pdhg_handle *h)
 {
     if (!h) return;
-    if (h->graph) hipGraphExecDestroy(h->graph);
-    if (h->cap_stream) hipStreamDestroy(h->cap_stream);
-    if (h->hdone_host) hipHostFree(h->hdone_host);
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    if (h->hdone_host) (void)hipHostFree(h->hdone_host);
     delete h;
 }
 
@@ -968,7 +968,7 @@ static int build_graph(pdhg_handle *h)
     enqueue_chunk<T>(h, h->cap_stream);
     HIPCHK(hipStreamEndCapture(h->cap_stream, &g));
     hipError_t e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
         h->graph = nullptr;
         return fail(PDHG_ERR_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
@@ -1038,9 +1038,15 @@ static int solve_impl(pdhg_handle *h, pdhg_result *res, hipStream_t s)
             } else {
                 enqueue_chunk<T>(h, s);
             }
-            hipEventRecord(ev[chunk % DEPTH], s);
+            if (hipEventRecord(ev[chunk % DEPTH], s) != hipSuccess) {
+                rc = fail(PDHG_ERR_HIP, "hipEventRecord failed");
+                break;
+            }
             if (chunk >= DEPTH - 1) {
-                hipEventSynchronize(ev[(chunk - (DEPTH - 1)) % DEPTH]);
+                if (hipEventSynchronize(ev[(chunk - (DEPTH - 1)) % DEPTH]) != hipSuccess) {
+                    rc = fail(PDHG_ERR_HIP, "solve: %s", hipGetErrorString(hipGetLastError()));
+                    break;
+                }
                 if (all_done()) break;
                 if (tl > 0.0 &&
                     std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > tl) {
@@ -1051,7 +1057,7 @@ static int solve_impl(pdhg_handle *h, pdhg_result *res, hipStream_t s)
         }
     }
     hipError_t se = hipStreamSynchronize(s);
-    for (int k = 0; k < DEPTH; ++k) hipEventDestroy(ev[k]);
+    for (int k = 0; k < DEPTH; ++k) (void)hipEventDestroy(ev[k]);
     if (rc) return rc;
     if (se != hipSuccess) return fail(PDHG_ERR_HIP, "solve: %s", hipGetErrorString(se));
     HIPCHK(hipMemcpy(st.data(), d.st, B * sizeof(InstState), hipMemcpyDeviceToHost));
@@ -1571,7 +1577,7 @@ static int time_impl(pdhg_handle *h, int32_t reps, pdhg_kernel_times *out, hipSt
     for (int phase = 0; phase < 8; ++phase) {
         if (phase == 4 && !avg) continue;
         if (phase == 5) launch_kx_ad<T>(d, 1, s);
-        hipEventRecord(e0, s);
+        HIPCHK(hipEventRecord(e0, s));
         for (int r = 0; r < reps; ++r) {
             switch (phase) {
                 case 0: launch_primal<T>(d, r, avg, nullptr, s); break;
@@ -1584,10 +1590,10 @@ static int time_impl(pdhg_handle *h, int32_t reps, pdhg_kernel_times *out, hipSt
                 default: launch_step_ad(d, s); break;
             }
         }
-        hipEventRecord(e1, s);
-        hipEventSynchronize(e1);
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
         float t = 0.f;
-        hipEventElapsedTime(&t, e0, e1);
+        HIPCHK(hipEventElapsedTime(&t, e0, e1));
         ms[phase] = (double)t / reps;
         if (phase == 3 || phase == 7) {
             // the control kernel may have stopped an instance and the step
@@ -1596,8 +1602,8 @@ static int time_impl(pdhg_handle *h, int32_t reps, pdhg_kernel_times *out, hipSt
             launch_active(d, s);
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
     out->ms_primal = ms[0];
@@ -1645,7 +1651,7 @@ extern "C" int pdhg_set_opts(pdhg_handle *h, const pdhg_opts *o)
                          t.eps_zero != h->opts.eps_zero || t.adaptive_step != h->opts.adaptive_step ||
                          t.detect_infeas != h->opts.detect_infeas || t.infeas_tol != h->opts.infeas_tol;
     if (regraph && h->graph) {
-        hipGraphExecDestroy(h->graph);
+        (void)hipGraphExecDestroy(h->graph);
         h->graph = nullptr;
     }
     h->opts = t;
