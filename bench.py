@@ -299,9 +299,9 @@ def main():
     CE = 64
     tune = {}
     if not args.small and not args.no_tuning:
-        from paper_2508_16806_amd import autotune
+        from paper_2508_16806_amd import tuner
 
-        tune = autotune.load(os.path.join(ROOT, "paper_2508_16806_amd", "tuning", "sced_c1_f32.json"))
+        tune = tuner.load(os.path.join(ROOT, "paper_2508_16806_amd", "tuning", "sced_c1_f32.json"))
     s = pd.Solver(lp, precision="f32", eps=1e-12, max_iters=CE * max(args.warmup, 1), **tune)
     info = s.info()
     print(f"[bench] setup {info['setup_seconds']:.2f}s knorm={info['knorm']:.6g} "

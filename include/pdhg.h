@@ -319,6 +319,22 @@ int pdhg_backward(pdhg_handle *h, const double *gx, const double *gy, double *gc
  * Synchronous. */
 int pdhg_time_kernels(pdhg_handle *h, int32_t reps, pdhg_kernel_times *out, hipStream_t stream);
 
+/* Autotuner of the launch layout for `batch` LPs (lp as for pdhg_setup): times
+ * the primal and dual sweeps (pdhg_time_kernels, `reps` launches each) over
+ *   bins:  bin_len = f * 2^k (k = 0..5), w, inf for f in {2, 4, 8, 16},
+ *          w in {512, 2048} (w >= 64 f), best limits per operator;
+ *   rows per lane group in bins 0..4: 1, 2 or 4, best per operator;
+ *   launch shape: xcd_remap in {0, 1} x max_grid in {4096, 8192, 16384,
+ *          65536}, best by primal + dual + check / check_every;
+ * every other option is taken from *base.  *best receives the chosen
+ * options; out_json (may be NULL) a JSON record of every trial and the
+ * choice.  Each trial sets the LP up in the caller's workspace `ws`, which
+ * must hold the largest candidate: *ws_needed (may be NULL) receives that
+ * size, and a NULL or smaller workspace fails with PDHG_ERR_NOMEM after
+ * setting it.  Synchronous. */
+int pdhg_autotune(const pdhg_lp *lp, int32_t batch, const pdhg_opts *base, void *ws, size_t ws_bytes,
+                  size_t *ws_needed, int32_t reps, hipStream_t stream, pdhg_opts *best, const char *out_json);
+
 /* Ruiz factors of instance `inst` (Algorithm 3): the scaled problem is
  * K~ = diag(rho) K diag(kappa), x = kappa x~, y = rho y~.  rho has m entries
  * (caller row order), kappa n entries; either pointer may be NULL. */

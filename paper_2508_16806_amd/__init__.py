@@ -16,7 +16,7 @@ from typing import Optional, Sequence
 
 import numpy as np
 
-__all__ = ["Solver", "Opts", "lib", "LIB_PATH", "PDHGError", "STATUS", "SOL_RESULT", "SOL_CURRENT",
+__all__ = ["Solver", "autotune", "autotune_workspace_bytes", "Opts", "lib", "LIB_PATH", "PDHGError", "STATUS", "SOL_RESULT", "SOL_CURRENT",
            "SOL_AVERAGE"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpdhg.so")
@@ -26,6 +26,7 @@ PREC_F64, PREC_F32 = 0, 1
 SOL_RESULT, SOL_CURRENT, SOL_AVERAGE = 0, 1, 2
 STATUS = {0: "OPTIMAL", 1: "ITERATION_LIMIT", 2: "TIME_LIMIT", 3: "NUMERICAL_ERROR", 4: "PRIMAL_INFEASIBLE",
           5: "DUAL_INFEASIBLE"}
+ERR_NOMEM = -5
 ERRORS = {-1: "INVALID_ARG", -2: "SHAPE", -3: "BOUNDS", -4: "NONFINITE", -5: "NOMEM", -6: "HIP",
           -7: "STATE"}
 
@@ -101,7 +102,7 @@ class Info(C.Structure):
 EXPORTS = ["pdhg_default_opts", "pdhg_workspace_bytes", "pdhg_setup", "pdhg_iterate", "pdhg_solve",
            "pdhg_get_solution", "pdhg_set_state", "pdhg_kkt", "pdhg_backward", "pdhg_get_scaling",
            "pdhg_get_info", "pdhg_time_kernels", "pdhg_set_opts", "pdhg_set_data",
-           "pdhg_destroy", "pdhg_last_error", "pdhg_fishnet", "pdhg_fishnet_rounds"]
+           "pdhg_destroy", "pdhg_last_error", "pdhg_fishnet", "pdhg_fishnet_rounds", "pdhg_autotune"]
 
 _lib = None
 
@@ -131,6 +132,8 @@ def lib():
         L.pdhg_time_kernels.argtypes = [P, I32, C.POINTER(KernelTimes), S]
         L.pdhg_fishnet.argtypes = [P, I32, I32, P, P, I64, I32, P, P, S]
         L.pdhg_fishnet_rounds.argtypes = [I32, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
+        L.pdhg_autotune.argtypes = [P, I32, C.POINTER(Opts), P, C.c_size_t, C.POINTER(C.c_size_t), I32, S,
+                                    C.POINTER(Opts), C.c_char_p]
         L.pdhg_destroy.argtypes = [P]
         L.pdhg_last_error.restype = C.c_char_p
         _lib = L
@@ -198,6 +201,60 @@ class _Desc:
         self.desc = LPDesc(int(lp.n), int(lp.m), int(a["rowptr"][-1]), _ptr(a["rowptr"]), _ptr(a["col"]),
                            _ptr(a["val"]), _ptr(a["c"]), _ptr(a["rhs"]), _ptr(a["l"]), _ptr(a["u"]),
                            _ptr(a.get("row_type")), MEM_DEVICE if dev else MEM_HOST)
+
+
+def autotune_workspace_bytes(lps, opts: Optional[Opts] = None, **kw) -> int:
+    """Workspace pdhg_autotune needs for these LPs (host-side planning only)."""
+    L = lib()
+    if not isinstance(lps, (list, tuple)):
+        lps = [lps]
+    o = opts if opts is not None else default_opts(**kw)
+    descs = [_Desc(lp) for lp in lps]
+    arr = (LPDesc * len(lps))(*[d.desc for d in descs])
+    need = C.c_size_t(0)
+    best = Opts()
+    rc = L.pdhg_autotune(C.cast(arr, C.c_void_p), len(lps), C.byref(o), None, 0, C.byref(need), 1, None,
+                         C.byref(best), None)
+    if rc != ERR_NOMEM:
+        raise PDHGError(rc, L.pdhg_last_error().decode())
+    return int(need.value)
+
+
+def autotune(lps, reps: int = 20, out_json: Optional[str] = None, device: str = "cuda", stream=None,
+             opts: Optional[Opts] = None, **kw):
+    """Runs the library's launch-layout autotuner (pdhg_autotune) on ``lps``.
+
+    Returns (best options, the tuner's JSON record as a dict).  Options other
+    than the bins, rows per lane group, XCD remap and grid cap come from
+    ``opts`` / ``kw``.
+    """
+    import json
+    import tempfile
+
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("libpdhg needs an AMD GPU; torch.cuda.is_available() is False")
+    L = lib()
+    if not isinstance(lps, (list, tuple)):
+        lps = [lps]
+    o = opts if opts is not None else default_opts(**kw)
+    need = autotune_workspace_bytes(lps, o)
+    descs = [_Desc(lp) for lp in lps]
+    arr = (LPDesc * len(lps))(*[d.desc for d in descs])
+    dev = torch.device(device)
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    best = Opts()
+    got = C.c_size_t(0)
+    with tempfile.TemporaryDirectory() as td:
+        path = out_json or os.path.join(td, "tune.json")
+        with torch.cuda.device(dev):
+            _check(L.pdhg_autotune(C.cast(arr, C.c_void_p), len(lps), C.byref(o), ws.data_ptr(), need,
+                                   C.byref(got), int(reps), _stream(stream), C.byref(best), path.encode()))
+        with open(path) as f:
+            rec = json.load(f)
+    del ws, descs
+    return best, rec
 
 
 class Solver:

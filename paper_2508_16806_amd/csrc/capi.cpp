@@ -1624,6 +1624,210 @@ extern "C" int pdhg_time_kernels(pdhg_handle *h, int32_t reps, pdhg_kernel_times
     return h->prec == PDHG_PREC_F32 ? time_impl<float>(h, reps, out, s) : time_impl<double>(h, reps, out, s);
 }
 
+// ---------------------------------------------------------------------------
+// autotuner of the launch layout
+// ---------------------------------------------------------------------------
+
+namespace {
+
+void tune_limits(int f, int w, int32_t *lim)
+{
+    for (int k = 0; k < 6; ++k) lim[k] = f << k;
+    lim[6] = std::max(w, 64 * f);
+    lim[7] = 0;
+}
+
+// the candidate grid, in the order it is timed (stage 0: bins, 1: rows per
+// group, 2: launch shape); later stages start from the best of earlier ones
+std::vector<pdhg_opts> tune_stage(const pdhg_opts &base, int stage, const pdhg_opts &bp, const pdhg_opts &bd,
+                                  std::vector<int> *tag)
+{
+    std::vector<pdhg_opts> out;
+    if (stage == 0) {
+        for (int f : {2, 4, 8, 16})
+            for (int w : {512, 2048}) {
+                if (w < 64 * f) continue;
+                pdhg_opts o = base;
+                tune_limits(f, w, o.bin_len_primal);
+                tune_limits(f, w, o.bin_len_dual);
+                out.push_back(o);
+                if (tag) tag->push_back(f * 100000 + w);
+            }
+    } else if (stage == 1) {
+        for (int r : {1, 2, 4}) {
+            pdhg_opts o = base;
+            std::memcpy(o.bin_len_primal, bp.bin_len_primal, sizeof o.bin_len_primal);
+            std::memcpy(o.bin_len_dual, bd.bin_len_dual, sizeof o.bin_len_dual);
+            for (int k = 0; k < 8; ++k) o.bin_rows_primal[k] = o.bin_rows_dual[k] = k < 5 ? r : 1;
+            out.push_back(o);
+            if (tag) tag->push_back(r);
+        }
+    } else {
+        for (int remap : {0, 1})
+            for (int grid : {4096, 8192, 16384, 65536}) {
+                pdhg_opts o = base;
+                std::memcpy(o.bin_len_primal, bp.bin_len_primal, sizeof o.bin_len_primal);
+                std::memcpy(o.bin_len_dual, bd.bin_len_dual, sizeof o.bin_len_dual);
+                std::memcpy(o.bin_rows_primal, bp.bin_rows_primal, sizeof o.bin_rows_primal);
+                std::memcpy(o.bin_rows_dual, bd.bin_rows_dual, sizeof o.bin_rows_dual);
+                o.xcd_remap = remap;
+                o.max_grid = grid;
+                out.push_back(o);
+                if (tag) tag->push_back(remap * 100000 + grid);
+            }
+    }
+    return out;
+}
+
+int tune_time(const pdhg_lp *lp, int32_t batch, const pdhg_opts &o, void *ws, size_t ws_bytes, int32_t reps,
+              hipStream_t s, pdhg_kernel_times *kt)
+{
+    pdhg_handle *h = nullptr;
+    int rc = pdhg_setup(lp, batch, &o, ws, ws_bytes, s, &h);
+    if (rc) return rc;
+    pdhg_kernel_times warm;
+    rc = pdhg_time_kernels(h, 3, &warm, s);
+    if (!rc) rc = pdhg_time_kernels(h, reps, kt, s);
+    pdhg_destroy(h);
+    return rc;
+}
+
+std::string jnum(double v)
+{
+    char buf[32];
+    std::snprintf(buf, sizeof buf, "%.9g", v);
+    return buf;
+}
+
+void json_ints(std::string &js, const char *key, const int32_t *v)
+{
+    js += "\"";
+    js += key;
+    js += "\": [";
+    for (int k = 0; k < 8; ++k) js += (k ? ", " : "") + std::to_string(v[k]);
+    js += "]";
+}
+
+}  // namespace
+
+extern "C" int pdhg_autotune(const pdhg_lp *lp, int32_t batch, const pdhg_opts *base, void *ws, size_t ws_bytes,
+                             size_t *ws_needed, int32_t reps, hipStream_t s, pdhg_opts *best, const char *out_json)
+{
+    if (!lp || !base || !best || batch < 1 || reps < 1)
+        return fail(PDHG_ERR_INVALID_ARG, "need lp, base, best != NULL, batch >= 1 and reps >= 1");
+    // workspace: every candidate pairs one of the stage-0 limit sets per
+    // operator with rows per group >= 1, so the largest workspace has at most
+    // the most blocks and segments any limit set gives with one row per group
+    Sizes bound{};
+    {
+        std::vector<int> t0;
+        for (pdhg_opts o : tune_stage(*base, 0, *base, *base, &t0)) {
+            for (int k = 0; k < 8; ++k) o.bin_rows_primal[k] = o.bin_rows_dual[k] = 1;
+            std::vector<HostLP> hosts;
+            std::vector<InstPlan> plans;
+            Sizes sz;
+            const int rc = plan_all(lp, batch, &o, hosts, plans, sz, true);
+            if (rc) {
+                if (ws_needed) *ws_needed = 0;
+                return rc;
+            }
+            bound.N = sz.N, bound.M = sz.M, bound.NNZ = sz.NNZ, bound.batch = sz.batch;
+            bound.nsegK = std::max(bound.nsegK, sz.nsegK);
+            bound.nsegT = std::max(bound.nsegT, sz.nsegT);
+            bound.nblkK = std::max(bound.nblkK, sz.nblkK);
+            bound.nblkT = std::max(bound.nblkT, sz.nblkT);
+        }
+        // second-level rows: sum over instances of ceil((K + K^T blocks) / L2CH)
+        bound.nl2 = (bound.nblkK + bound.nblkT + L2CH - 1) / L2CH + batch;
+    }
+    size_t need;
+    {
+        Carve cv;
+        Dev d{};
+        Buffers b{};
+        InstInfo *info;
+        InstState *st;
+        FishDev fish{};
+        carve(cv, bound, base->precision, *base, d, b, &info, &st, &fish);
+        need = (cv.off + 255) & ~(size_t)255;
+    }
+    if (ws_needed) *ws_needed = need;
+    if (!ws || ws_bytes < need)
+        return fail(PDHG_ERR_NOMEM, "autotune needs a workspace of %zu bytes", need);
+    pdhg_opts bp = *base, bd = *base;
+    double best_p = INFINITY, best_d = INFINITY;
+    std::vector<int> tag;
+    std::string js = "{\"trials\": [";
+    int nt = 0;
+    for (const pdhg_opts &o : tune_stage(*base, 0, bp, bd, &tag)) {
+        pdhg_kernel_times kt;
+        const int rc = tune_time(lp, batch, o, ws, ws_bytes, reps, s, &kt);
+        if (rc) return rc;
+        if (kt.ms_primal < best_p) best_p = kt.ms_primal, bp = o;
+        if (kt.ms_dual < best_d) best_d = kt.ms_dual, bd = o;
+        const int t = tag[nt];
+        js += std::string(nt++ ? ", " : "") + "{\"f\": " + std::to_string(t / 100000) + ", \"w\": " +
+              std::to_string(t % 100000) + ", \"ms_primal\": " + jnum(kt.ms_primal) +
+              ", \"ms_dual\": " + jnum(kt.ms_dual) + "}";
+    }
+    js += "], \"rows_trials\": [";
+    tag.clear();
+    best_p = best_d = INFINITY;
+    int32_t rows_p[8], rows_d[8];
+    std::memcpy(rows_p, base->bin_rows_primal, sizeof rows_p);
+    std::memcpy(rows_d, base->bin_rows_dual, sizeof rows_d);
+    nt = 0;
+    for (const pdhg_opts &o : tune_stage(*base, 1, bp, bd, &tag)) {
+        pdhg_kernel_times kt;
+        const int rc = tune_time(lp, batch, o, ws, ws_bytes, reps, s, &kt);
+        if (rc) return rc;
+        if (kt.ms_primal < best_p) best_p = kt.ms_primal, std::memcpy(rows_p, o.bin_rows_primal, sizeof rows_p);
+        if (kt.ms_dual < best_d) best_d = kt.ms_dual, std::memcpy(rows_d, o.bin_rows_dual, sizeof rows_d);
+        const int t = tag[nt];
+        js += std::string(nt++ ? ", " : "") + "{\"rows\": " + std::to_string(t) + ", \"ms_primal\": " +
+              jnum(kt.ms_primal) + ", \"ms_dual\": " + jnum(kt.ms_dual) + "}";
+    }
+    std::memcpy(bp.bin_rows_primal, rows_p, sizeof rows_p);
+    std::memcpy(bd.bin_rows_dual, rows_d, sizeof rows_d);
+    js += "], \"shapes\": [";
+    tag.clear();
+    double best_it = INFINITY;
+    pdhg_opts shape = *base;
+    pdhg_kernel_times best_kt{};
+    nt = 0;
+    for (const pdhg_opts &o : tune_stage(*base, 2, bp, bd, &tag)) {
+        pdhg_kernel_times kt;
+        const int rc = tune_time(lp, batch, o, ws, ws_bytes, reps, s, &kt);
+        if (rc) return rc;
+        const double it = kt.ms_primal + kt.ms_dual + kt.ms_check / std::max(1, base->check_every);
+        if (it < best_it) best_it = it, shape = o, best_kt = kt;
+        const int t = tag[nt];
+        js += std::string(nt++ ? ", " : "") + "{\"xcd_remap\": " + std::to_string(t / 100000) +
+              ", \"max_grid\": " + std::to_string(t % 100000) + ", \"ms_primal\": " +
+              jnum(kt.ms_primal) + ", \"ms_dual\": " + jnum(kt.ms_dual) +
+              ", \"ms_check\": " + jnum(kt.ms_check) + ", \"ms_iter\": " + jnum(it) + "}";
+    }
+    *best = shape;
+    js += "], ";
+    json_ints(js, "bin_len_primal", shape.bin_len_primal);
+    js += ", ";
+    json_ints(js, "bin_len_dual", shape.bin_len_dual);
+    js += ", ";
+    json_ints(js, "bin_rows_primal", shape.bin_rows_primal);
+    js += ", ";
+    json_ints(js, "bin_rows_dual", shape.bin_rows_dual);
+    js += ", \"xcd_remap\": " + std::to_string(shape.xcd_remap) + ", \"max_grid\": " + std::to_string(shape.max_grid) +
+          ", \"ms_primal\": " + jnum(best_kt.ms_primal) + ", \"ms_dual\": " + jnum(best_kt.ms_dual) +
+          ", \"precision\": \"" + (base->precision == PDHG_PREC_F64 ? "f64" : "f32") + "\"}\n";
+    if (out_json) {
+        FILE *fp = std::fopen(out_json, "w");
+        if (!fp) return fail(PDHG_ERR_INVALID_ARG, "cannot write %s", out_json);
+        std::fputs(js.c_str(), fp);
+        std::fclose(fp);
+    }
+    return PDHG_OK;
+}
+
 extern "C" int pdhg_set_opts(pdhg_handle *h, const pdhg_opts *o)
 {
     if (!h || !o) return fail(PDHG_ERR_INVALID_ARG, "NULL argument");

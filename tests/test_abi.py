@@ -141,3 +141,44 @@ def test_infinite_bounds_accepted(pd):
     lp = lpgen.tiny(3, n=8, m=4, free_frac=0.5)
     assert np.isinf(lp.l).any()
     assert _nbytes(pd, lp) > 0
+
+
+def test_autotune_workspace_covers_every_candidate(pd):
+    """pdhg_autotune without a workspace fails with NOMEM and reports a size
+    that holds every combination of limits, rows per group and launch shape
+    its search can set up."""
+    from paper_2508_16806_amd.tuner import limits
+
+    for lp in (lpgen.config0(0), lpgen.config2(m=3000, n=6000)):
+        need = pd.autotune_workspace_bytes(lp)
+        assert need > 0 and need % 256 == 0
+        cands = [limits(f, w) for f in (2, 4, 8, 16) for w in (512, 2048) if w >= 64 * f]
+        worst = 0
+        for lp_lim in cands:
+            for ld_lim in cands:
+                for rows in (1, 2, 4):
+                    rr = [rows] * 5 + [1, 1, 1]
+                    b = _nbytes(pd, lp, bin_len_primal=lp_lim, bin_len_dual=ld_lim, bin_rows_primal=rr,
+                                bin_rows_dual=rr)
+                    assert b > 0
+                    worst = max(worst, b)
+        assert need >= worst
+        # and it is a bound, not a gross overestimate
+        assert need <= worst * 1.05
+
+
+def test_autotune_rejects_bad_arguments(pd):
+    L = pd.lib()
+    d = pd._Desc(lpgen.config0(0))
+    arr = (pd.LPDesc * 1)(d.desc)
+    o, best, need = pd.default_opts(), pd.Opts(), C.c_size_t(7)
+    assert L.pdhg_autotune(C.cast(arr, C.c_void_p), 1, C.byref(o), None, 0, C.byref(need), 0, None,
+                           C.byref(best), None) == -1  # reps < 1
+    assert L.pdhg_autotune(C.cast(arr, C.c_void_p), 0, C.byref(o), None, 0, C.byref(need), 1, None,
+                           C.byref(best), None) == -1  # batch < 1
+    bad = pd.default_opts(check_every=0)
+    assert L.pdhg_autotune(C.cast(arr, C.c_void_p), 1, C.byref(bad), None, 0, C.byref(need), 1, None,
+                           C.byref(best), None) == -1
+    assert L.pdhg_autotune(C.cast(arr, C.c_void_p), 1, C.byref(o), None, 0, C.byref(need), 1, None,
+                           C.byref(best), None) == -5
+    assert need.value > 0 and "workspace" in _err(pd)

@@ -37,9 +37,9 @@ def c1():
 
 @pytest.fixture(scope="module")
 def tune():
-    from paper_2508_16806_amd import autotune
+    from paper_2508_16806_amd import tuner
 
-    return autotune.load(os.path.join(ROOT, "paper_2508_16806_amd", "tuning", "sced_c1_f32.json"))
+    return tuner.load(os.path.join(ROOT, "paper_2508_16806_amd", "tuning", "sced_c1_f32.json"))
 
 
 def test_c1_ruiz_bitwise(orc, pd, c1, tune):
