@@ -255,6 +255,100 @@ def bench_adjoint(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_c2(args):
+    """C2: the large random LP (m = 1M, n = 2M, Zipf(1.5) row lengths, ~54M
+    nonzeros) with its tuned layout: chunked iterations/s, per-kernel times
+    and roofline, the time to 1e-4, and the sweeps of one GPU's share under
+    an 8-way row / column partition (rows m/8 of K with the full gathered
+    xbar; rows n/8 of K^T with the full gathered y), each block timed."""
+    import numpy as np
+    import torch
+
+    import lpgen
+    import paper_2508_16806_amd as pd
+    from paper_2508_16806_amd import tuner
+
+    t = time.perf_counter()
+    lp = lpgen.config2()
+    print(f"[bench] generated {lp.name}: n={lp.n} m={lp.m} nnz={lp.nnz} in {time.perf_counter() - t:.1f}s",
+          file=sys.stderr, flush=True)
+    tune = tuner.load(os.path.join(ROOT, "paper_2508_16806_amd", "tuning", "zipf_c2_f32.json"))
+    CE = 64
+    s = pd.Solver(lp, precision="f32", eps=1e-12, max_iters=CE * max(args.warmup, 1), **tune)
+    info = s.info()
+    print(f"[bench] setup {info['setup_seconds']:.2f}s knorm={info['knorm']:.6g}", file=sys.stderr, flush=True)
+    if args.warmup > 0:
+        s.solve()
+    s.set_opts(max_iters=CE * args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = s.solve()[0]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert r["iters"] == CE * args.steps, r
+    ips = r["iters"] / dt
+    kt = s.time_kernels(reps=20)
+    pb, db = sweep_bytes(info, 4)
+    pg, dg = pb / (kt["ms_primal"] * 1e-3) / 1e9, db / (kt["ms_dual"] * 1e-3) / 1e9
+    dom = "dual" if kt["ms_dual"] >= kt["ms_primal"] else "primal"
+    ach = dg if dom == "dual" else pg
+    print(f"[bench] {ips:.1f} iter/s; primal {kt['ms_primal']*1e3:.1f} us ({pg:.0f} GB/s), dual "
+          f"{kt['ms_dual']*1e3:.1f} us ({dg:.0f} GB/s), check {kt['ms_check']*1e3:.1f} us", file=sys.stderr,
+          flush=True)
+    ttt = None
+    if not args.no_ttt:
+        s.set_opts(eps=1e-4, max_iters=2_000_000, time_limit=120.0)
+        s.set_state(np.zeros(lp.n), np.zeros(lp.m))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rt = s.solve()[0]
+        tsec = time.perf_counter() - t0
+        x, y = s.solution()
+        ttt = {"seconds": tsec, "status": rt["status_name"], "iters": rt["iters"], "restarts": rt["restarts"],
+               "rel_kkt_fp64_recheck": s.kkt(x, y)["rel_kkt"], "pobj": rt["kkt"]["pobj"],
+               "rel_obj_gap_vs_planted": abs(rt["kkt"]["pobj"] - lp.f_star) / (1 + abs(lp.f_star)),
+               "setup_seconds": info["setup_seconds"]}
+        print(f"[bench] time to 1e-4: {tsec:.2f}s {rt['status_name']} iters={rt['iters']}", file=sys.stderr,
+              flush=True)
+    s.close()
+    del s
+    # one GPU's share of an 8-way partition, every block
+    P = 8
+    shard = {"parts": P, "dual_ms": [], "primal_ms": [], "dual_gbs": [], "primal_gbs": []}
+    for p in range(P):
+        r0, r1 = p * lp.m // P, (p + 1) * lp.m // P
+        c0, c1 = p * lp.n // P, (p + 1) * lp.n // P
+        for kind, sub in (("dual", lpgen.row_block(lp, r0, r1)), ("primal", lpgen.col_block(lp, c0, c1))):
+            ss = pd.Solver(sub, precision="f32", **tune)
+            si = ss.info()
+            ss.time_kernels(reps=3)
+            k = ss.time_kernels(reps=20)
+            ms = k["ms_" + kind]
+            b = sweep_bytes(si, 4)[0 if kind == "primal" else 1]
+            shard[kind + "_ms"].append(ms)
+            shard[kind + "_gbs"].append(b / (ms * 1e-3) / 1e9)
+            ss.close()
+            del ss, sub
+        print(f"[bench] shard {p}/{P}: dual {shard['dual_ms'][-1]*1e3:.1f} us, primal "
+              f"{shard['primal_ms'][-1]*1e3:.1f} us", file=sys.stderr, flush=True)
+    shard["iter_sweeps_ms_slowest"] = max(shard["dual_ms"]) + max(shard["primal_ms"])
+    shard["full_sweeps_ms_over_parts"] = (kt["ms_dual"] + kt["ms_primal"]) / P
+    out = {"metric": METRIC, "value": ips, "unit": "PDHG iter/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"large random LP {lp.name}: n={lp.n}, m={lp.m}, nnz={lp.nnz}, Zipf(1.5) row "
+                                  f"lengths; FP32 iterates, FP64 accumulation and check; step = {CE} iterations "
+                                  f"+ check", "n": lp.n, "m": lp.m, "nnz": lp.nnz, "iters_per_step": CE,
+                      "bins": tune},
+           "roofline": {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": ach / PEAK_HBM_GBS, "traffic": None, "kernel": f"k_{dom}",
+                        "algorithmic_bytes": db if dom == "dual" else pb,
+                        "ms_per_launch": kt["ms_dual" if dom == "dual" else "ms_primal"]},
+           "kernels_ms": {k: v for k, v in kt.items() if k != "reps"}, "sweep_gbs": {"primal": pg, "dual": dg},
+           "time_to_tol": ttt, "shard": shard, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -264,8 +358,9 @@ def main():
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance solve")
     ap.add_argument("--small", action="store_true", help="reduced SCED size (for profiling tests)")
     ap.add_argument("--no-tuning", action="store_true", help="default bins instead of the tuned ones")
-    ap.add_argument("--workload", default="c1", choices=["c1", "c3", "c4"],
-                    help="c1: SCED-shaped LP (default); c3: batched vs one-by-one; c4: unrolled adjoint")
+    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4"],
+                    help="c1: SCED-shaped LP (default); c2: large Zipf LP and one GPU's 1/8 share; "
+                         "c3: batched vs one-by-one; c4: unrolled adjoint")
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--m-max", type=int, default=50000)
     ap.add_argument("--calib-copy", action="store_true",
@@ -291,6 +386,8 @@ def main():
     if args.workload == "c4":
         args.batch = args.batch or 64
         return bench_adjoint(args)
+    if args.workload == "c2":
+        return bench_c2(args)
     t = time.perf_counter()
     lp = lpgen.sced(500, 200, 24, 125, seed=1) if args.small else lpgen.config1()
     gen_s = time.perf_counter() - t

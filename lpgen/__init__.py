@@ -518,3 +518,26 @@ def fishnet_draws(n: int, P: int, seed: int):
     rounds of 2^p points consume)."""
     rng = np.random.default_rng(seed)
     return rng.standard_normal((P, n)), rng.standard_normal(P * P)
+
+
+def row_block(lp: LP, r0: int, r1: int) -> LP:
+    """Rows r0..r1-1 of ``lp`` with every column: the rows of K one GPU would
+    own under a row partition (its dual sweep gathers the full primal vector)."""
+    a, b = int(lp.rowptr[r0]), int(lp.rowptr[r1])
+    return LP(lp.n, r1 - r0, (lp.rowptr[r0:r1 + 1] - a).astype(np.int64), lp.col[a:b].copy(), lp.val[a:b].copy(),
+              lp.row_type[r0:r1].copy(), lp.rhs[r0:r1].copy(), lp.c.copy(), lp.l.copy(), lp.u.copy(),
+              name=f"{lp.name}[rows {r0}:{r1}]")
+
+
+def col_block(lp: LP, c0: int, c1: int) -> LP:
+    """Columns c0..c1-1 of ``lp`` with every row: the rows of K^T one GPU would
+    own under a column partition (its primal sweep gathers the full dual
+    vector).  Rows without an entry in the block stay, empty."""
+    keep = (lp.col >= c0) & (lp.col < c1)
+    rows = np.repeat(np.arange(lp.m, dtype=np.int64), np.diff(lp.rowptr))
+    cnt = np.bincount(rows[keep], minlength=lp.m)
+    rowptr = np.zeros(lp.m + 1, dtype=np.int64)
+    np.cumsum(cnt, out=rowptr[1:])
+    return LP(c1 - c0, lp.m, rowptr, (lp.col[keep] - c0).astype(np.int32), lp.val[keep].copy(),
+              lp.row_type.copy(), lp.rhs.copy(), lp.c[c0:c1].copy(), lp.l[c0:c1].copy(), lp.u[c0:c1].copy(),
+              name=f"{lp.name}[cols {c0}:{c1}]")
