@@ -160,7 +160,7 @@ def bench_batched(args):
     print(f"[bench] generated {B} LPs (m <= {args.m_max}), nnz {nnz} in {gen_s:.1f}s", file=sys.stderr, flush=True)
     kw = dict(precision="f32", eps=1e-4, max_iters=200000, time_limit=170.0)
     t0 = time.perf_counter()
-    sb = pd.Solver(lps, **kw)
+    sb = pd.Solver(lps, batch_resident_bytes=args.resident_bytes, **kw)
     print(f"[bench] batched setup {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -195,7 +195,7 @@ def bench_batched(args):
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"{B} planted LPs, m ~ U{{1000..{args.m_max}}}, n = 2.5m, density "
                                   f"U(0.001, 0.01); total nnz {nnz}; eps 1e-4",
-                      "batch": B, "nnz_total": nnz},
+                      "batch": B, "nnz_total": nnz, "resident_bytes": args.resident_bytes},
            "batched": {"seconds": tb, "lps_per_s": B / tb,
                        "status": {k: sum(1 for r in rb if r["status_name"] == k) for k in set(r["status_name"] for r in rb)}},
            "one_by_one": {"seconds": ts, "lps_per_s": B / ts, "buckets": buckets},
@@ -363,6 +363,8 @@ def main():
                          "c3: batched vs one-by-one; c4: unrolled adjoint")
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--m-max", type=int, default=50000)
+    ap.add_argument("--resident-bytes", type=int, default=192_000_000,
+                    help="batched solve: admission budget of running instances' sweep bytes (0: all at once)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run plain 256 MiB device copies (counter calibration under rocprofv3 --pmc)")
     args = ap.parse_args()

@@ -158,6 +158,21 @@ typedef struct {
     /* Largest point count of pdhg_fishnet (0, or a power of two in 2..64): the
      * workspace then holds that many interleaved candidate points. */
     int32_t fishnet_points;
+    /* Admission of a batch's instances into pdhg_solve's running set (batch
+     * > 1; 0: all run from the start).  Instances enter in order of
+     * decreasing per-iteration sweep bytes 2 (e + 4) nnz + 8 (n + m + 2) +
+     * e (9 n + 6 m), e = 4 (FP32) or 8 (FP64) (values, columns and row
+     * pointers of K~ and K~^T, the swept and gathered vectors; ties by
+     * index) while the running ones' bytes stay within this budget, and
+     * always at least one runs; a finished instance frees its share at the
+     * next check.  A waiting instance has had its starting-point check and
+     * takes no step, so its iterates, iteration count and status are the
+     * ones it reaches alone.  Sizing the budget below the 256 MB Infinity
+     * Cache keeps the running matrices resident between iterations; the
+     * default, 192e6, also keeps enough instances running to fill the GPU.
+     * Waiting instances at a time limit end with PDHG_TIME_LIMIT and their
+     * starting point. */
+    int64_t batch_resident_bytes;
 } pdhg_opts;
 
 /* Relative KKT error terms (Section 2.3.2, conditions term1-term3) on the

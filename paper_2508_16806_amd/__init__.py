@@ -54,7 +54,8 @@ class Opts(C.Structure):
                 ("use_graph", C.c_int32), ("xcd_remap", C.c_int32), ("bin_len_dual", C.c_int32 * 8),
                 ("bin_len_primal", C.c_int32 * 8), ("bin_rows_dual", C.c_int32 * 8),
                 ("bin_rows_primal", C.c_int32 * 8), ("max_grid", C.c_int32), ("adaptive_step", C.c_int32),
-                ("detect_infeas", C.c_int32), ("infeas_tol", C.c_double), ("fishnet_points", C.c_int32)]
+                ("detect_infeas", C.c_int32), ("infeas_tol", C.c_double), ("fishnet_points", C.c_int32),
+                ("batch_resident_bytes", C.c_int64)]
 
 
 class KKTOut(C.Structure):

@@ -77,6 +77,7 @@ extern "C" void pdhg_default_opts(pdhg_opts *o)
     o->detect_infeas = 0;
     o->infeas_tol = 1e-4;
     o->fishnet_points = 0;
+    o->batch_resident_bytes = 192000000;
 }
 
 // ---------------------------------------------------------------------------
@@ -387,6 +388,7 @@ static void carve(Carve &cv, const Sizes &sz, int prec, const pdhg_opts &o, Dev 
     d.act_off = cv.take<int32_t>(2 * (size_t)sz.batch);
     d.act_coff = cv.take<int64_t>(2 * (size_t)sz.batch + 2);
     d.act_split = cv.take<int32_t>(18);
+    d.adm_order = cv.take<int32_t>(sz.batch);
     b.bcumK = cv.take<int64_t>(sz.nblkK + 1);
     b.bcumT = cv.take<int64_t>(sz.nblkT + 1);
     b.l2inst = cv.take<int32_t>(sz.nl2 + 1);
@@ -459,6 +461,7 @@ static int check_opts(const pdhg_opts *o)
     if (o->fishnet_points != 0 &&
         (o->fishnet_points < 2 || o->fishnet_points > 64 || (o->fishnet_points & (o->fishnet_points - 1))))
         return fail(PDHG_ERR_INVALID_ARG, "fishnet_points must be 0 or a power of two in 2..64");
+    if (o->batch_resident_bytes < 0) return fail(PDHG_ERR_INVALID_ARG, "batch_resident_bytes must be >= 0");
     return PDHG_OK;
 }
 
@@ -663,6 +666,12 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
         for (int64_t i = 0; i < p.m; ++i) qn += lp.rhs[i] * lp.rhs[i];
         in.cnorm = std::sqrt(cn);
         in.qnorm = std::sqrt(qn);
+        {
+            // one iteration's two sweeps: values + columns of K~ and K~^T, row
+            // pointers, and the swept and gathered vectors
+            const int64_t es = (int64_t)elem_size(h->prec), nz = pos - nzoff;
+            in.sweep_bytes = 2 * (es + 4) * nz + 8 * (p.n + p.m + 2) + es * (9 * p.n + 6 * p.m);
+        }
         xoff += p.n;
         yoff += p.m;
         nzoff = pos;
@@ -673,8 +682,14 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
         cumK[t + 1] = cumK[t] + (Krp[Kbd[t].x + Kbd[t].y] - Krp[Kbd[t].x]) + 4 * (int64_t)Kbd[t].y;
     for (int64_t t = 0; t < sz.nblkT; ++t)
         cumT[t + 1] = cumT[t] + (Ktrp[Ktbd[t].x + Ktbd[t].y] - Ktrp[Ktbd[t].x]) + 4 * (int64_t)Ktbd[t].y;
+    // admission order of a batch: decreasing sweep bytes, ties by index
+    std::vector<int32_t> adm(h->batch);
+    for (int bi = 0; bi < h->batch; ++bi) adm[bi] = bi;
+    std::stable_sort(adm.begin(), adm.end(),
+                     [&](int32_t a, int32_t c) { return h->info[a].sweep_bytes > h->info[c].sweep_bytes; });
     int rc;
-    if ((rc = h2d(b.bcumK, cumK.data(), cumK.size(), s)) || (rc = h2d(b.bcumT, cumT.data(), cumT.size(), s)))
+    if ((rc = h2d(b.bcumK, cumK.data(), cumK.size(), s)) || (rc = h2d(b.bcumT, cumT.data(), cumT.size(), s)) ||
+        (rc = h2d(d.adm_order, adm.data(), adm.size(), s)))
         return rc;
     if ((rc = h2d(b.Krp, Krp.data(), Krp.size(), s)) || (rc = h2d(b.Kci, Kci.data(), Kci.size(), s)) ||
         (rc = h2d(b.Kv64, Kv.data(), Kv.size(), s)) || (rc = h2d(b.Kseg, Kseg.data(), Kseg.size(), s)) ||
@@ -904,6 +919,12 @@ extern "C" void pdhg_destroy(pdhg_handle *h)
 // solve
 // ---------------------------------------------------------------------------
 
+// admission budget of pdhg_solve (batches only)
+static int64_t admission_budget(const pdhg_handle *h)
+{
+    return h->batch > 1 ? h->opts.batch_resident_bytes : 0;
+}
+
 static CtlParams ctl_params(const pdhg_handle *h)
 {
     const pdhg_opts &o = h->opts;
@@ -955,7 +976,7 @@ static void enqueue_chunk(const pdhg_handle *h, hipStream_t s)
         launch_restart<T>(d, s);
         if (h->opts.adaptive_step) launch_kx_ad<T>(d, 0, s);  // K~x of the restarted iterates
     }
-    launch_active(d, s);
+    launch_active(d, s, admission_budget(h), 0);
 }
 
 template <typename T>
@@ -1011,6 +1032,10 @@ static int solve_impl(pdhg_handle *h, pdhg_result *res, hipStream_t s)
     launch_control(d, ctl_params(h), 0, s);
     launch_active(d, s);
     if (h->opts.adaptive_step) launch_kx_ad<T>(d, 1, s);
+    // every instance has had its starting-point check: those beyond the
+    // admission budget wait from here on
+    const int64_t budget = admission_budget(h);
+    if (budget > 0) launch_active(d, s, budget, 1);
     HIPCHK(hipGetLastError());
 
     const int DEPTH = 4;
@@ -1026,8 +1051,10 @@ static int solve_impl(pdhg_handle *h, pdhg_result *res, hipStream_t s)
     const double tl = h->opts.time_limit;
     bool timed_out = false;
     int rc = PDHG_OK;
-    // no instance can run past max_iters, so never enqueue more chunks than that
-    const int64_t max_chunks = (h->opts.max_iters + h->opts.check_every - 1) / h->opts.check_every;
+    // no instance can run past max_iters, so never enqueue more chunks than
+    // that (times the batch when instances are admitted one after another)
+    const int64_t max_chunks = (h->opts.max_iters + h->opts.check_every - 1) / h->opts.check_every *
+                               (budget > 0 ? B : 1);
     if (!all_done()) {
         for (int64_t chunk = 0; chunk < max_chunks; ++chunk) {
             if (h->opts.use_graph) {
@@ -1066,7 +1093,7 @@ static int solve_impl(pdhg_handle *h, pdhg_result *res, hipStream_t s)
         const InstState &x = st[b];
         pdhg_result &r = res[b];
         std::memset(&r, 0, sizeof r);
-        r.status = x.done ? x.status : (timed_out ? PDHG_TIME_LIMIT : PDHG_ITERATION_LIMIT);
+        r.status = x.done == 1 ? x.status : (timed_out ? PDHG_TIME_LIMIT : PDHG_ITERATION_LIMIT);
         r.from_avg = x.sol_avg;
         r.iters = x.k_total;
         r.restarts = x.nrestarts;
@@ -1846,6 +1873,7 @@ extern "C" int pdhg_set_opts(pdhg_handle *h, const pdhg_opts *o)
     t.adaptive_step = o->adaptive_step;
     t.detect_infeas = o->detect_infeas;
     t.infeas_tol = o->infeas_tol;
+    t.batch_resident_bytes = o->batch_resident_bytes;
     int rc = check_opts(&t);
     if (rc) return rc;
     const bool regraph = t.use_restarts != h->opts.use_restarts || t.check_every != h->opts.check_every ||
@@ -1853,7 +1881,8 @@ extern "C" int pdhg_set_opts(pdhg_handle *h, const pdhg_opts *o)
                          t.max_iters != h->opts.max_iters || t.beta_suff != h->opts.beta_suff ||
                          t.beta_nec != h->opts.beta_nec || t.beta_art != h->opts.beta_art ||
                          t.eps_zero != h->opts.eps_zero || t.adaptive_step != h->opts.adaptive_step ||
-                         t.detect_infeas != h->opts.detect_infeas || t.infeas_tol != h->opts.infeas_tol;
+                         t.detect_infeas != h->opts.detect_infeas || t.infeas_tol != h->opts.infeas_tol ||
+                         t.batch_resident_bytes != h->opts.batch_resident_bytes;
     if (regraph && h->graph) {
         (void)hipGraphExecDestroy(h->graph);
         h->graph = nullptr;

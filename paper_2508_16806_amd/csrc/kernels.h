@@ -27,7 +27,9 @@ template <typename T>
 void launch_check(const Dev &d, int avg, hipStream_t s);
 void launch_check64(const Dev &d, const double *xs, const double *ys, hipStream_t s);
 void launch_control(const Dev &d, const CtlParams &P, int iters_done, hipStream_t s);
-void launch_active(const Dev &d, hipStream_t s);
+// active lists of the running instances; budget > 0 admits waiting instances
+// (first = 1: instances beyond the budget start waiting)
+void launch_active(const Dev &d, hipStream_t s, int64_t budget = 0, int first = 0);
 template <typename T>
 void launch_restart(const Dev &d, hipStream_t s);
 

@@ -879,11 +879,34 @@ __global__ __launch_bounds__(WG) void k_restart(Dev d)
     });
 }
 
-// Active lists: exclusive scan of the running instances' block counts (one
-// workgroup, sequential over the batch: O(batch) per check) ...
-__global__ void k_act_scan(Dev d)
+// Active lists: admission of waiting instances under the byte budget (first
+// = 1 at the start of a solve: instances beyond the budget start waiting),
+// then an exclusive scan of the running instances' block counts (one lane,
+// sequential over the batch: O(batch) per check) ...
+__global__ void k_act_scan(Dev d, int64_t budget, int first)
 {
     if (threadIdx.x != 0) return;
+    if (budget > 0) {
+        int64_t live = 0;
+        if (!first)
+            for (int b = 0; b < d.batch; ++b)
+                if (d.st[b].done == 0) live += d.info[b].sweep_bytes;
+        bool open = true;
+        for (int k = 0; k < d.batch; ++k) {
+            const int b = d.adm_order[k];
+            InstState &st = d.st[b];
+            const bool cand = first ? st.done == 0 : st.done == 2;
+            if (!cand) continue;
+            const int64_t need = d.info[b].sweep_bytes;
+            if (open && (live == 0 || live + need <= budget)) {
+                st.done = 0;
+                live += need;
+            } else {
+                open = false;  // strict order: later instances wait behind this one
+                st.done = 2;
+            }
+        }
+    }
     int oK = 0, oT = 0;
     int64_t cK = 0, cT = 0;
     for (int b = 0; b < d.batch; ++b) {
@@ -1495,9 +1518,9 @@ void launch_check64(const Dev &d, const double *xs, const double *ys, hipStream_
     RM_SWITCH(rm, { LAUNCH((k_check<double, 1, RMV>), g, d, xs, xs, ys, ys, xs, ys, 0); });
 }
 
-void launch_active(const Dev &d, hipStream_t s)
+void launch_active(const Dev &d, hipStream_t s, int64_t budget, int first)
 {
-    hipLaunchKernelGGL(k_act_scan, dim3(1), dim3(64), 0, s, d);
+    hipLaunchKernelGGL(k_act_scan, dim3(1), dim3(64), 0, s, d, budget, first);
     const int64_t n = d.K.nblk > d.Kt.nblk ? d.K.nblk : d.Kt.nblk;
     LAUNCH(k_act_fill, nblk_elem(n), d);
     hipLaunchKernelGGL(k_act_split, dim3(1), dim3(64), 0, s, d);

@@ -72,6 +72,7 @@ struct InstInfo {
     int32_t l2off, l2cnt;  // second-level partial rows of this instance
     double cnorm, qnorm;   // ||c||_2 and ||q||_2 of the ORIGINAL LP
     double cnorm_s, qnorm_s;  // of the scaled LP
+    int64_t sweep_bytes;   // bytes one iteration's two sweeps read and write
 };
 
 // Solver state per instance, read by every sweep, written by the control kernel.
@@ -81,7 +82,7 @@ struct InstState {
     double kkt_prev;   // restart metric of the previous candidate (inf at epoch start)
     long long k_total; // iterations of this solve
     long long t_inner; // iterations of the current restart epoch
-    int32_t done;      // 1: stopped; sweeps skip the instance
+    int32_t done;      // 1: stopped, 2: waiting for admission; sweeps skip both
     int32_t status;    // PDHG_OPTIMAL / ..._ITERATION_LIMIT / ..._NUMERICAL_ERROR
     int32_t restart;   // the last check decided a restart
     int32_t cand_avg;  // the last check's candidate is the average
@@ -153,6 +154,7 @@ struct Dev {
     const int64_t *bcumK, *bcumT;
     int64_t *act_coff;            // [2 * batch + 2]: per instance, then the totals
     int32_t *act_split;
+    int32_t *adm_order;           // [batch]: admission order (decreasing sweep bytes)
     int32_t grid_cap;             // workgroups of a solve-time sweep launch
     double *vecN64, *vecN64b;     // FP64 scratch vectors (N)
     double *vecM64, *vecM64b;     // FP64 scratch vectors (M)

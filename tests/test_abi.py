@@ -48,6 +48,8 @@ def test_struct_layouts_match_header(pd):
     # end with the adaptive-step fields
     assert pd.Opts.fishnet_points.offset == pd.Opts.infeas_tol.offset + 8
     assert o.fishnet_points == 0
+    assert pd.Opts.batch_resident_bytes.offset == pd.Opts.fishnet_points.offset + 8
+    assert C.sizeof(pd.Opts) == pd.Opts.batch_resident_bytes.offset + 8 and o.batch_resident_bytes == 192_000_000
     assert o.detect_infeas == 0 and o.infeas_tol == 1e-4
     assert pd.Result.eta_next.offset + 8 == C.sizeof(pd.Result)
     assert pd.KernelTimes.ms_step_ad.offset + 8 == C.sizeof(pd.KernelTimes)

@@ -252,11 +252,13 @@ def test_set_state_roundtrip(pd):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_batched_equals_solo_bitwise(pd, prec):
+@pytest.mark.parametrize("budget", [0, None])
+def test_batched_equals_solo_bitwise(pd, prec, budget):
+    """All instances running at once (budget 0) and the default admission."""
     lps = [lpgen.planted(m, int(2.5 * m), 0.02, 30 + i, ge_frac=0.3) for i, m in enumerate([60, 150, 90, 240])]
     lps.append(lpgen.sced(20, 8, 4, 6, seed=9))
     kw = dict(precision=prec, eps=1e-5)
-    b = pd.Solver(lps, **kw)
+    b = pd.Solver(lps, **kw) if budget is None else pd.Solver(lps, batch_resident_bytes=budget, **kw)
     rb = b.solve()
     for i, lp in enumerate(lps):
         s = pd.Solver(lp, **kw)
@@ -267,6 +269,57 @@ def test_batched_equals_solo_bitwise(pd, prec):
         xs, ys = s.solution()
         np.testing.assert_array_equal(xb, xs)
         np.testing.assert_array_equal(yb, ys)
+
+
+def _sweep_bytes(lp, e=4):
+    """Per-iteration sweep bytes of an instance as the admission budget counts them."""
+    return 2 * (e + 4) * lp.nnz + 8 * (lp.n + lp.m + 2) + e * (9 * lp.n + 6 * lp.m)
+
+
+@pytest.mark.parametrize("budget", ["one", "two", "half"])
+@pytest.mark.parametrize("graph", [1, 0])
+def test_admission_equals_solo_bitwise(pd, budget, graph):
+    """A byte budget that admits the batch's instances a few at a time leaves
+    every instance's trajectory as it is alone: same iterations, restarts,
+    status and bits."""
+    lps = [lpgen.planted(m, int(2.5 * m), 0.02, 40 + i, ge_frac=0.3) for i, m in enumerate([60, 150, 90, 240, 120])]
+    lps.append(lpgen.sced(20, 8, 4, 6, seed=9))
+    kw = dict(precision="f32", eps=1e-5, use_graph=graph)
+    sizes = sorted((_sweep_bytes(lp) for lp in lps), reverse=True)
+    cap = {"one": 1, "two": sizes[0] + sizes[1], "half": sum(sizes) // 2}[budget]
+    b = pd.Solver(lps, batch_resident_bytes=cap, **kw)
+    rb = b.solve()
+    for i, lp in enumerate(lps):
+        s = pd.Solver(lp, **kw)
+        rs = s.solve()[0]
+        assert rb[i]["status_name"] == rs["status_name"] == "OPTIMAL", (i, rb[i]["status_name"])
+        assert rb[i]["iters"] == rs["iters"] and rb[i]["restarts"] == rs["restarts"], i
+        xb, yb = b.solution(inst=i)
+        xs, ys = s.solution()
+        np.testing.assert_array_equal(xb, xs)
+        np.testing.assert_array_equal(yb, ys)
+    # a second solve from the solution: the budget state starts afresh
+    rb2 = b.solve()
+    assert all(r["status_name"] == "OPTIMAL" for r in rb2)
+
+
+def test_admission_time_limit_leaves_waiting_at_start(pd):
+    """Instances still waiting at a time limit report TIME_LIMIT with no
+    iterations and their starting point."""
+    lps = [lpgen.planted(m, int(2.5 * m), 0.02, 50 + i, ge_frac=0.3) for i, m in enumerate([300, 200, 100])]
+    b = pd.Solver(lps, precision="f64", eps=1e-300, max_iters=10_000_000, time_limit=0.5,
+                  batch_resident_bytes=1)
+    rb = b.solve()
+    order = np.argsort([-_sweep_bytes(lp) for lp in lps], kind="stable")
+    first = int(order[0])
+    assert rb[first]["status_name"] == "TIME_LIMIT" and rb[first]["iters"] > 0
+    for i in order[1:]:
+        r = rb[int(i)]
+        assert r["status_name"] == "TIME_LIMIT" and r["iters"] == 0, r
+        x, y = b.solution(inst=int(i), which=pd.SOL_CURRENT)
+        lp = lps[int(i)]
+        np.testing.assert_array_equal(x, np.clip(np.zeros(lp.n), lp.l, lp.u))
+        np.testing.assert_array_equal(y, np.zeros(lp.m))
 
 
 def test_graph_and_eager_agree(pd):
