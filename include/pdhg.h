@@ -173,6 +173,10 @@ typedef struct {
      * Waiting instances at a time limit end with PDHG_TIME_LIMIT and their
      * starting point. */
     int64_t batch_resident_bytes;
+    /* Per-instance ring of check records kept by pdhg_solve (0: none): the
+     * last trace_capacity records of the solve, read with pdhg_get_trace.
+     * The solve loop never waits for them. */
+    int32_t trace_capacity;
 } pdhg_opts;
 
 /* Relative KKT error terms (Section 2.3.2, conditions term1-term3) on the
@@ -202,6 +206,20 @@ typedef struct {
     int64_t accepted;    /* accepted steps (= iters without adaptive steps)         */
     double eta_next;     /* trial step of the next attempt (= eta without them)     */
 } pdhg_result;
+
+/* One check of pdhg_solve (Sections 2.3.2 and 2.4.2): written after the
+ * restart / primal-weight / termination decision of that check. */
+typedef struct {
+    int64_t iter;         /* iterations (attempts) of the solve at the check      */
+    int32_t restarted;    /* a restart happened at this check                     */
+    int32_t cand_avg;     /* the restart candidate is the epoch average           */
+    double kkt_cand;      /* KKT_omega of the candidate (scaled LP, omega before) */
+    double omega;         /* primal weight after the check                        */
+    double rel_kkt_cur;   /* relative KKT error of the iterate (original LP)      */
+    double rel_kkt_avg;   /* of the average (+inf without restarts)               */
+    double eta_next;      /* step of the next attempt                             */
+    int64_t accepted;     /* accepted steps so far                                */
+} pdhg_trace_rec;
 
 typedef struct {
     int64_t n, m, m_ineq, nnz;
@@ -355,6 +373,14 @@ int pdhg_autotune(const pdhg_lp *lp, int32_t batch, const pdhg_opts *base, void 
  * (caller row order), kappa n entries; either pointer may be NULL. */
 int pdhg_get_scaling(pdhg_handle *h, int32_t inst, double *rho, double *kappa, int32_t mem,
                      hipStream_t stream);
+
+/* Check records of instance `inst` from the last pdhg_solve (needs
+ * opts.trace_capacity > 0 at setup): *total receives the number of checks
+ * the solve made (the first check after the starting point counts as 1),
+ * out the last min(*total, trace_capacity, cap) of them, oldest first (host
+ * memory).  Synchronous on `stream`. */
+int pdhg_get_trace(pdhg_handle *h, int32_t inst, pdhg_trace_rec *out, int32_t cap, int64_t *total,
+                   hipStream_t stream);
 
 /* Sizes, step parameters and launch layout of the handle (instance 0's
  * parameters for a batch). */

@@ -55,7 +55,13 @@ class Opts(C.Structure):
                 ("bin_len_primal", C.c_int32 * 8), ("bin_rows_dual", C.c_int32 * 8),
                 ("bin_rows_primal", C.c_int32 * 8), ("max_grid", C.c_int32), ("adaptive_step", C.c_int32),
                 ("detect_infeas", C.c_int32), ("infeas_tol", C.c_double), ("fishnet_points", C.c_int32),
-                ("batch_resident_bytes", C.c_int64)]
+                ("batch_resident_bytes", C.c_int64), ("trace_capacity", C.c_int32)]
+
+
+class TraceRec(C.Structure):
+    _fields_ = [("iter", C.c_int64), ("restarted", C.c_int32), ("cand_avg", C.c_int32), ("kkt_cand", C.c_double),
+                ("omega", C.c_double), ("rel_kkt_cur", C.c_double), ("rel_kkt_avg", C.c_double),
+                ("eta_next", C.c_double), ("accepted", C.c_int64)]
 
 
 class KKTOut(C.Structure):
@@ -103,7 +109,8 @@ class Info(C.Structure):
 EXPORTS = ["pdhg_default_opts", "pdhg_workspace_bytes", "pdhg_setup", "pdhg_iterate", "pdhg_solve",
            "pdhg_get_solution", "pdhg_set_state", "pdhg_kkt", "pdhg_backward", "pdhg_get_scaling",
            "pdhg_get_info", "pdhg_time_kernels", "pdhg_set_opts", "pdhg_set_data",
-           "pdhg_destroy", "pdhg_last_error", "pdhg_fishnet", "pdhg_fishnet_rounds", "pdhg_autotune"]
+           "pdhg_destroy", "pdhg_last_error", "pdhg_fishnet", "pdhg_fishnet_rounds", "pdhg_autotune",
+           "pdhg_get_trace"]
 
 _lib = None
 
@@ -135,6 +142,7 @@ def lib():
         L.pdhg_fishnet_rounds.argtypes = [I32, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
         L.pdhg_autotune.argtypes = [P, I32, C.POINTER(Opts), P, C.c_size_t, C.POINTER(C.c_size_t), I32, S,
                                     C.POINTER(Opts), C.c_char_p]
+        L.pdhg_get_trace.argtypes = [P, I32, P, I32, C.POINTER(C.c_int64), S]
         L.pdhg_destroy.argtypes = [P]
         L.pdhg_last_error.restype = C.c_char_p
         _lib = L
@@ -400,6 +408,15 @@ class Solver:
         t = KernelTimes()
         _check(lib().pdhg_time_kernels(self.h, int(reps), C.byref(t), _stream(stream)))
         return t.as_dict()
+
+    def trace(self, inst: int = 0, stream=None):
+        """(check records of the last solve, oldest first, as dicts; total checks)."""
+        cap = int(self.opts.trace_capacity)
+        recs = (TraceRec * max(cap, 1))()
+        total = C.c_int64(0)
+        _check(lib().pdhg_get_trace(self.h, inst, C.cast(recs, C.c_void_p), cap, C.byref(total), _stream(stream)))
+        n = min(cap, total.value)
+        return [{k: getattr(r, k) for k, _ in TraceRec._fields_} for r in recs[:n]], int(total.value)
 
     def info(self) -> dict:
         i = Info()

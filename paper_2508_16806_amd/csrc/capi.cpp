@@ -78,6 +78,7 @@ extern "C" void pdhg_default_opts(pdhg_opts *o)
     o->infeas_tol = 1e-4;
     o->fishnet_points = 0;
     o->batch_resident_bytes = 192000000;
+    o->trace_capacity = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -389,6 +390,8 @@ static void carve(Carve &cv, const Sizes &sz, int prec, const pdhg_opts &o, Dev 
     d.act_coff = cv.take<int64_t>(2 * (size_t)sz.batch + 2);
     d.act_split = cv.take<int32_t>(18);
     d.adm_order = cv.take<int32_t>(sz.batch);
+    d.trace_cap = o.trace_capacity;
+    d.trace = o.trace_capacity > 0 ? cv.take<pdhg_trace_rec>((size_t)sz.batch * o.trace_capacity) : nullptr;
     b.bcumK = cv.take<int64_t>(sz.nblkK + 1);
     b.bcumT = cv.take<int64_t>(sz.nblkT + 1);
     b.l2inst = cv.take<int32_t>(sz.nl2 + 1);
@@ -462,6 +465,8 @@ static int check_opts(const pdhg_opts *o)
         (o->fishnet_points < 2 || o->fishnet_points > 64 || (o->fishnet_points & (o->fishnet_points - 1))))
         return fail(PDHG_ERR_INVALID_ARG, "fishnet_points must be 0 or a power of two in 2..64");
     if (o->batch_resident_bytes < 0) return fail(PDHG_ERR_INVALID_ARG, "batch_resident_bytes must be >= 0");
+    if (o->trace_capacity < 0 || o->trace_capacity > (1 << 20))
+        return fail(PDHG_ERR_INVALID_ARG, "trace_capacity must be in 0..2^20");
     return PDHG_OK;
 }
 
@@ -1023,6 +1028,7 @@ static int solve_impl(pdhg_handle *h, pdhg_result *res, hipStream_t s)
         x.k_att = 0;
         x.n_acc = 0;
         x.prev_ok = 0;
+        x.ntrace = 0;
     }
     std::memset(h->hdone_host, 0, sizeof(int32_t) * B);
     HIPCHK(hipMemcpyAsync(d.st, st.data(), B * sizeof(InstState), hipMemcpyHostToDevice, s));
@@ -1888,6 +1894,27 @@ extern "C" int pdhg_set_opts(pdhg_handle *h, const pdhg_opts *o)
         h->graph = nullptr;
     }
     h->opts = t;
+    return PDHG_OK;
+}
+
+extern "C" int pdhg_get_trace(pdhg_handle *h, int32_t inst, pdhg_trace_rec *out, int32_t cap, int64_t *total,
+                              hipStream_t s)
+{
+    if (!h || inst < 0 || inst >= h->batch) return fail(PDHG_ERR_INVALID_ARG, "bad handle or instance");
+    if (h->d.trace_cap <= 0) return fail(PDHG_ERR_STATE, "the handle keeps no trace (opts.trace_capacity = 0)");
+    if (cap < 0 || (cap > 0 && !out)) return fail(PDHG_ERR_INVALID_ARG, "need cap >= 0 and out != NULL");
+    InstState st;
+    HIPCHK(hipMemcpyAsync(&st, h->d.st + inst, sizeof st, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (total) *total = st.ntrace;
+    const int64_t R = h->d.trace_cap;
+    const int64_t keep = std::min<int64_t>(std::min<int64_t>(st.ntrace, R), cap);
+    if (keep <= 0) return PDHG_OK;
+    std::vector<pdhg_trace_rec> ring((size_t)R);
+    HIPCHK(hipMemcpyAsync(ring.data(), h->d.trace + (size_t)inst * R, R * sizeof(pdhg_trace_rec),
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int64_t k = 0; k < keep; ++k) out[k] = ring[(size_t)((st.ntrace - keep + k) % R)];
     return PDHG_OK;
 }
 

@@ -748,6 +748,25 @@ __device__ __forceinline__ double kkt_omega(const Metrics &m, double w)
     return sqrt(w * w * m.kw_parts[0] + m.kw_parts[1] / (w * w) + m.kw_parts[2]);
 }
 
+// Record of one check in the instance's ring (when the handle keeps one).
+__device__ void trace_put(const Dev &d, int b, InstState &st, int cand, double kwc, const Metrics *mt, int nc,
+                          const CtlParams &P)
+{
+    if (d.trace_cap <= 0) return;
+    pdhg_trace_rec r;
+    r.iter = st.k_total;
+    r.restarted = st.restart;
+    r.cand_avg = cand;
+    r.kkt_cand = kwc;
+    r.omega = st.omega;
+    r.rel_kkt_cur = mt[0].kkt[8];
+    r.rel_kkt_avg = nc > 1 ? mt[1].kkt[8] : INFINITY;
+    r.eta_next = P.adaptive ? st.eta_try : st.eta;
+    r.accepted = P.adaptive ? st.n_acc : st.k_total;
+    d.trace[(size_t)b * d.trace_cap + (size_t)(st.ntrace % d.trace_cap)] = r;
+    st.ntrace += 1;
+}
+
 // One workgroup per instance.  iters_done: iterations since the last check
 // (0 for the check of the starting point).
 __global__ __launch_bounds__(WG) void k_control(Dev d, CtlParams P, int iters_done)
@@ -778,6 +797,7 @@ __global__ __launch_bounds__(WG) void k_control(Dev d, CtlParams P, int iters_do
         st.status = PDHG_NUMERICAL_ERROR;
         st.sol_avg = 0;
         for (int k = 0; k < 9; ++k) st.kkt[k] = mt[0].kkt[k];
+        if (iters_done > 0) trace_put(d, b, st, 0, kw0, mt, nc, P);
         d.hdone[b] = 1;
         return;
     }
@@ -825,12 +845,16 @@ __global__ __launch_bounds__(WG) void k_control(Dev d, CtlParams P, int iters_do
         st.status = stop - 1;
         st.sol_avg = sol;
         for (int k = 0; k < 9; ++k) st.kkt[k] = mt[sol].kkt[k];
+        trace_put(d, b, st, cand, kwc, mt, nc, P);
         d.hdone[b] = 1;
         return;
     }
     for (int k = 0; k < 9; ++k) st.kkt[k] = mt[cand].kkt[k];
     st.sol_avg = cand;
-    if (!P.use_restarts) return;
+    if (!P.use_restarts) {
+        trace_put(d, b, st, cand, kwc, mt, nc, P);
+        return;
+    }
     const bool suff = kwc <= P.beta_suff * st.kkt0;
     const bool nec = kwc <= P.beta_nec * st.kkt0 && kwc > st.kkt_prev;
     const bool art = (double)st.t_inner > P.beta_art * (double)st.k_total;
@@ -850,6 +874,7 @@ __global__ __launch_bounds__(WG) void k_control(Dev d, CtlParams P, int iters_do
     } else {
         st.kkt_prev = kwc;
     }
+    trace_put(d, b, st, cand, kwc, mt, nc, P);
 }
 
 // On restart: z <- candidate, epoch start <- z.  Walks K^T blocks then K blocks

@@ -23,6 +23,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/pdhg.h"
+
 namespace pdhg {
 
 constexpr int WG = 256;   // workgroup size of every sweep (4 wave64)
@@ -98,6 +100,7 @@ struct InstState {
     long long n_acc;   // accepted steps of this solve
     int32_t prev_ok;   // the last attempt was accepted: buffer 1 holds the iterate before it
     int32_t pad2;
+    long long ntrace;  // check records written by this solve
 };
 
 struct CtlParams {
@@ -156,6 +159,8 @@ struct Dev {
     int32_t *act_split;
     int32_t *adm_order;           // [batch]: admission order (decreasing sweep bytes)
     int32_t grid_cap;             // workgroups of a solve-time sweep launch
+    pdhg_trace_rec *trace;        // batch x trace_cap check records (ring per instance)
+    int32_t trace_cap;
     double *vecN64, *vecN64b;     // FP64 scratch vectors (N)
     double *vecM64, *vecM64b;     // FP64 scratch vectors (M)
     double *inst_scratch;         // batch * 16

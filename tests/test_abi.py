@@ -49,7 +49,10 @@ def test_struct_layouts_match_header(pd):
     assert pd.Opts.fishnet_points.offset == pd.Opts.infeas_tol.offset + 8
     assert o.fishnet_points == 0
     assert pd.Opts.batch_resident_bytes.offset == pd.Opts.fishnet_points.offset + 8
-    assert C.sizeof(pd.Opts) == pd.Opts.batch_resident_bytes.offset + 8 and o.batch_resident_bytes == 192_000_000
+    assert o.batch_resident_bytes == 192_000_000
+    assert pd.Opts.trace_capacity.offset == pd.Opts.batch_resident_bytes.offset + 8 and o.trace_capacity == 0
+    assert C.sizeof(pd.Opts) == pd.Opts.trace_capacity.offset + 8
+    assert C.sizeof(pd.TraceRec) == 64
     assert o.detect_infeas == 0 and o.infeas_tol == 1e-4
     assert pd.Result.eta_next.offset + 8 == C.sizeof(pd.Result)
     assert pd.KernelTimes.ms_step_ad.offset + 8 == C.sizeof(pd.KernelTimes)
@@ -126,6 +129,12 @@ def test_rejects_bad_options(pd):
     assert _nbytes(pd, lp, fishnet_points=3) == 0 and "fishnet_points" in _err(pd)
     assert _nbytes(pd, lp, fishnet_points=128) == 0
     assert _nbytes(pd, lp, fishnet_points=32) > _nbytes(pd, lp)
+    assert _nbytes(pd, lp, batch_resident_bytes=-1) == 0 and "batch_resident_bytes" in _err(pd)
+    assert _nbytes(pd, lp, trace_capacity=-1) == 0 and "trace_capacity" in _err(pd)
+    assert _nbytes(pd, lp, trace_capacity=(1 << 20) + 1) == 0
+    # the ring: 64 bytes per record and instance (within the carve's 256-byte alignment)
+    grow = _nbytes(pd, lp, trace_capacity=1000) - _nbytes(pd, lp)
+    assert 64 * 1000 <= grow <= 64 * 1000 + 512
 
 
 def test_fishnet_rounds_and_draws(pd):
