@@ -125,7 +125,8 @@ typedef struct {
     int32_t bin_len_dual[8];   /* rows of K   (dual sweep)                        */
     int32_t bin_len_primal[8]; /* rows of K^T (primal sweep)                      */
     /* Rows handled by one lane group in bins 0..4 (1, 2 or 4; 0 means 1): the
-     * group interleaves the loads of its rows. */
+     * group interleaves the loads of its rows.  Bins 5..7 take one row per
+     * group (0 or 1); other values, and negative bin_len, are rejected. */
     int32_t bin_rows_dual[8];
     int32_t bin_rows_primal[8];
     int32_t max_grid;          /* workgroups per solve-time sweep launch (0: 8192);  */

@@ -465,6 +465,15 @@ static int check_opts(const pdhg_opts *o)
         (o->fishnet_points < 2 || o->fishnet_points > 64 || (o->fishnet_points & (o->fishnet_points - 1))))
         return fail(PDHG_ERR_INVALID_ARG, "fishnet_points must be 0 or a power of two in 2..64");
     if (o->batch_resident_bytes < 0) return fail(PDHG_ERR_INVALID_ARG, "batch_resident_bytes must be >= 0");
+    for (int k = 0; k < NBIN; ++k) {
+        const int32_t rd = o->bin_rows_dual[k], rp = o->bin_rows_primal[k];
+        const bool ok = k <= 4 ? (rd == 0 || rd == 1 || rd == 2 || rd == 4) && (rp == 0 || rp == 1 || rp == 2 || rp == 4)
+                               : (rd == 0 || rd == 1) && (rp == 0 || rp == 1);
+        if (!ok)
+            return fail(PDHG_ERR_INVALID_ARG, "bin_rows[%d] must be %s", k, k <= 4 ? "0, 1, 2 or 4" : "0 or 1");
+        if (o->bin_len_dual[k] < 0 || o->bin_len_primal[k] < 0)
+            return fail(PDHG_ERR_INVALID_ARG, "bin_len[%d] must be >= 0", k);
+    }
     if (o->trace_capacity < 0 || o->trace_capacity > (1 << 20))
         return fail(PDHG_ERR_INVALID_ARG, "trace_capacity must be in 0..2^20");
     return PDHG_OK;

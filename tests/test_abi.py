@@ -130,6 +130,10 @@ def test_rejects_bad_options(pd):
     assert _nbytes(pd, lp, fishnet_points=128) == 0
     assert _nbytes(pd, lp, fishnet_points=32) > _nbytes(pd, lp)
     assert _nbytes(pd, lp, batch_resident_bytes=-1) == 0 and "batch_resident_bytes" in _err(pd)
+    assert _nbytes(pd, lp, bin_rows_dual=[3, 1, 1, 1, 1, 1, 1, 1]) == 0 and "bin_rows" in _err(pd)
+    assert _nbytes(pd, lp, bin_rows_primal=[1, 1, 1, 1, 1, 2, 1, 1]) == 0
+    assert _nbytes(pd, lp, bin_rows_primal=[4, 4, 2, 2, 1, 0, 0, 0]) > 0
+    assert _nbytes(pd, lp, bin_len_dual=[-1, 8, 16, 32, 64, 128, 512, 0]) == 0 and "bin_len" in _err(pd)
     assert _nbytes(pd, lp, trace_capacity=-1) == 0 and "trace_capacity" in _err(pd)
     assert _nbytes(pd, lp, trace_capacity=(1 << 20) + 1) == 0
     # the ring: 64 bytes per record and instance (within the carve's 256-byte alignment)
