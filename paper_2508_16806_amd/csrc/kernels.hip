@@ -481,14 +481,17 @@ __global__ __launch_bounds__(WG) void k_check(Dev d, const V *__restrict__ xa0, 
         const int lbc = onK ? lb : d.K.nblk + lb;
         const OpDev &op = onK ? d.K : d.Kt;
         const Seg s = block_seg(op, lb);
-        double sum[NC * NSUM];
-#pragma unroll
-        for (int k = 0; k < NC * NSUM; ++k) sum[k] = 0.0;
         const int bi = lb - s.blk0;
         const bool ineq = s.ineq != 0;
-        dispatch_lanes<RM>(s.lanes_log2, [&](auto tag, auto rtag) {
-            constexpr int L = decltype(tag)::value, R = decltype(rtag)::value;
-            if (onK) {
+        double *out = d.partials + (size_t)lbc * NPART;
+        // each operator keeps only its own sums live (4 per candidate on K,
+        // 5 on K^T): half the registers of one 18-sum set, twice the waves
+        if (onK) {
+            double sum[NC * 4];
+#pragma unroll
+            for (int k = 0; k < NC * 4; ++k) sum[k] = 0.0;
+            dispatch_lanes<RM>(s.lanes_log2, [&](auto tag, auto rtag) {
+                constexpr int L = decltype(tag)::value, R = decltype(rtag)::value;
                 sweep_rows<L, NC, double, V, R>(op, s, bi, xa0, xa1, nullptr, red, [&](int64_t r, const double *acc) {
                     const double qi = d.q64[r], rh = d.rho[r];
 #pragma unroll
@@ -498,13 +501,27 @@ __global__ __launch_bounds__(WG) void k_check(Dev d, const V *__restrict__ xa0, 
                         const double eu = e / rh;
                         const double ya = (double)(a == 0 ? ya0 : ya1)[r];
                         const double dy = ya - (double)ys[r];
-                        sum[a * NSUM + 0] += e * e;
-                        sum[a * NSUM + 1] += eu * eu;
-                        sum[a * NSUM + 2] += qi * ya;
-                        sum[a * NSUM + 3] += dy * dy;
+                        sum[a * 4 + 0] += e * e;
+                        sum[a * 4 + 1] += eu * eu;
+                        sum[a * 4 + 2] += qi * ya;
+                        sum[a * 4 + 3] += dy * dy;
                     }
                 });
-            } else {
+            });
+            block_sum<NC * 4>(sum, red);
+            if (threadIdx.x == 0) {
+#pragma unroll
+                for (int k = 0; k < NCAND * NSUM; ++k) {
+                    const int a = k / NSUM, j = k % NSUM;
+                    out[k] = (a < NC && j < 4) ? sum[a * 4 + j] : 0.0;
+                }
+            }
+        } else {
+            double sum[NC * 5];
+#pragma unroll
+            for (int k = 0; k < NC * 5; ++k) sum[k] = 0.0;
+            dispatch_lanes<RM>(s.lanes_log2, [&](auto tag, auto rtag) {
+                constexpr int L = decltype(tag)::value, R = decltype(rtag)::value;
                 sweep_rows<L, NC, double, V, R>(op, s, bi, ya0, ya1, nullptr, red, [&](int64_t r, const double *acc) {
                     const double cj = d.c64[r], lj = d.l64[r], uj = d.u64[r], kj = d.kap[r];
 #pragma unroll
@@ -515,20 +532,22 @@ __global__ __launch_bounds__(WG) void k_check(Dev d, const V *__restrict__ xa0, 
                         const double rdu = rd / kj;
                         const double xv = (double)(a == 0 ? xa0 : xa1)[r];
                         const double dx = xv - (double)xs[r];
-                        sum[a * NSUM + 4] += rd * rd;
-                        sum[a * NSUM + 5] += rdu * rdu;
-                        sum[a * NSUM + 6] += cj * xv;
-                        sum[a * NSUM + 7] += lam > 0.0 ? lj * lam : (lam < 0.0 ? uj * lam : 0.0);
-                        sum[a * NSUM + 8] += dx * dx;
+                        sum[a * 5 + 0] += rd * rd;
+                        sum[a * 5 + 1] += rdu * rdu;
+                        sum[a * 5 + 2] += cj * xv;
+                        sum[a * 5 + 3] += lam > 0.0 ? lj * lam : (lam < 0.0 ? uj * lam : 0.0);
+                        sum[a * 5 + 4] += dx * dx;
                     }
                 });
-            }
-        });
-        block_sum<NC * NSUM>(sum, red);
-        if (threadIdx.x == 0) {
-            double *out = d.partials + (size_t)lbc * NPART;
+            });
+            block_sum<NC * 5>(sum, red);
+            if (threadIdx.x == 0) {
 #pragma unroll
-            for (int k = 0; k < NCAND * NSUM; ++k) out[k] = k < NC * NSUM ? sum[k] : 0.0;
+                for (int k = 0; k < NCAND * NSUM; ++k) {
+                    const int a = k / NSUM, j = k % NSUM;
+                    out[k] = (a < NC && j >= 4) ? sum[a * 5 + (j - 4)] : 0.0;
+                }
+            }
         }
         __syncthreads();
     });
