@@ -16,7 +16,7 @@ from typing import Optional, Sequence
 
 import numpy as np
 
-__all__ = ["Solver", "autotune", "autotune_workspace_bytes", "Opts", "lib", "LIB_PATH", "PDHGError", "STATUS", "SOL_RESULT", "SOL_CURRENT",
+__all__ = ["Solver", "autotune", "autotune_workspace_bytes", "read_mps", "write_mps", "MPSModel", "Opts", "lib", "LIB_PATH", "PDHGError", "STATUS", "SOL_RESULT", "SOL_CURRENT",
            "SOL_AVERAGE"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpdhg.so")
@@ -422,3 +422,6 @@ class Solver:
         i = Info()
         _check(lib().pdhg_get_info(self.h, C.byref(i)))
         return i.as_dict()
+
+
+from .mps import MPSModel, parse_mps, read_mps, write_mps  # noqa: E402
