@@ -230,6 +230,10 @@ typedef struct {
     int64_t workspace_bytes;
     int32_t nseg_primal, nseg_dual; /* row-length bins in use                     */
     int64_t nblk_primal, nblk_dual; /* workgroups per primal / dual sweep         */
+    /* phases of setup_seconds: validation and row binning, building the
+     * device images of K~ and K~^T on the host, copying them to the device,
+     * and the device work (Ruiz scaling, FP32 copies, power iteration) */
+    double setup_plan_seconds, setup_host_seconds, setup_copy_seconds, setup_device_seconds;
 } pdhg_info;
 
 /* Average device time per launch of each phase kernel (milliseconds). */

@@ -100,7 +100,9 @@ class Info(C.Structure):
                 ("knorm", C.c_double), ("eta", C.c_double), ("omega", C.c_double), ("tau", C.c_double),
                 ("sigma", C.c_double), ("setup_seconds", C.c_double), ("precision", C.c_int32),
                 ("batch", C.c_int32), ("workspace_bytes", C.c_int64), ("nseg_primal", C.c_int32),
-                ("nseg_dual", C.c_int32), ("nblk_primal", C.c_int64), ("nblk_dual", C.c_int64)]
+                ("nseg_dual", C.c_int32), ("nblk_primal", C.c_int64), ("nblk_dual", C.c_int64),
+                ("setup_plan_seconds", C.c_double), ("setup_host_seconds", C.c_double),
+                ("setup_copy_seconds", C.c_double), ("setup_device_seconds", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

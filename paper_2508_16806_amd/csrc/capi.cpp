@@ -15,6 +15,9 @@
 #include <thread>
 #include <vector>
 
+#include <stdlib.h>
+#include <sys/mman.h>
+
 #include "../../include/pdhg.h"
 #include "kernels.h"
 #include "pdhg_internal.h"
@@ -310,6 +313,7 @@ struct pdhg_handle {
     int32_t *hdone_host = nullptr;
     size_t ws_bytes = 0;
     double setup_seconds = 0;
+    double setup_phase[4] = {0, 0, 0, 0};  // plan, host images, copies, device
     hipGraphExec_t graph = nullptr;
     hipStream_t cap_stream = nullptr;
     FishDev fish{};          // fishnet buffers (opts.fishnet_points > 0)
@@ -520,7 +524,7 @@ static int plan_all(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, std::v
     return PDHG_OK;
 }
 
-extern "C" size_t pdhg_workspace_bytes(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o)
+static size_t workspace_bytes_impl(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o)
 {
     pdhg_opts def;
     if (!o) {
@@ -541,6 +545,16 @@ extern "C" size_t pdhg_workspace_bytes(const pdhg_lp *lp, int32_t batch, const p
     return (cv.off + 255) & ~(size_t)255;
 }
 
+extern "C" size_t pdhg_workspace_bytes(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o)
+{
+    try {
+        return workspace_bytes_impl(lp, batch, o);
+    } catch (...) {
+        fail(PDHG_ERR_NOMEM, "sizing: host memory exhausted");
+        return 0;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // setup
 // ---------------------------------------------------------------------------
@@ -552,16 +566,96 @@ static int h2d(X *dst, const X *src, size_t cnt, hipStream_t s)
     return PDHG_OK;
 }
 
+// Host vectors whose elements are all written before use: no zero fill (the
+// matrix images run to hundreds of MB, and the fill would be a full pass).
+// Large ones sit on 2 MB-aligned memory marked for transparent huge pages, so
+// the first touch faults in 2 MB steps rather than 4 KB ones.
+template <typename T>
+struct NoInitAlloc : std::allocator<T> {
+    template <typename U>
+    struct rebind {
+        using other = NoInitAlloc<U>;
+    };
+    NoInitAlloc() = default;
+    template <typename U>
+    NoInitAlloc(const NoInitAlloc<U> &) noexcept
+    {
+    }
+    static constexpr size_t HUGE_MIN = (size_t)8 << 20, HUGE_ALIGN = (size_t)2 << 20;
+    T *allocate(size_t n)
+    {
+        const size_t bytes = n * sizeof(T);
+        if (bytes < HUGE_MIN) return std::allocator<T>::allocate(n);
+        void *p = nullptr;
+        if (posix_memalign(&p, HUGE_ALIGN, (bytes + HUGE_ALIGN - 1) & ~(HUGE_ALIGN - 1)) != 0 || !p)
+            throw std::bad_alloc();
+        (void)madvise(p, (bytes + HUGE_ALIGN - 1) & ~(HUGE_ALIGN - 1), MADV_HUGEPAGE);
+        return (T *)p;
+    }
+    void deallocate(T *p, size_t n)
+    {
+        if (n * sizeof(T) < HUGE_MIN) {
+            std::allocator<T>::deallocate(p, n);
+            return;
+        }
+        free(p);
+    }
+    template <typename U>
+    void construct(U *) noexcept
+    {
+    }
+    template <typename U, typename... A>
+    void construct(U *p, A &&...a)
+    {
+        ::new ((void *)p) U(std::forward<A>(a)...);
+    }
+};
+template <typename T>
+using hvec = std::vector<T, NoInitAlloc<T>>;
+
+// Host threads for setup work: the machine's, at most 16.
+static int host_threads()
+{
+    const unsigned hc = std::thread::hardware_concurrency();
+    return (int)std::max(1u, std::min(16u, hc ? hc : 1u));
+}
+
+// f(t, begin, end) on T contiguous ranges of [0, n) (T = 1 below `grain`
+// items per thread), each on its own thread; returns when all are done.  f
+// must not throw (it runs on threads of its own).
+template <typename F>
+static void parallel_ranges(int64_t n, int64_t grain, int T, F &&f)
+{
+    T = (int)std::max<int64_t>(1, std::min<int64_t>(T, n / std::max<int64_t>(1, grain)));
+    if (T <= 1) {
+        f(0, (int64_t)0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve(T);
+    for (int t = 0; t < T; ++t) {
+        try {
+            th.emplace_back(f, t, n * t / T, n * (t + 1) / T);
+        } catch (...) {
+            f(t, n * t / T, n * (t + 1) / T);  // no thread to spare: run the range here
+        }
+    }
+    for (auto &x : th) x.join();
+}
+
 // builds the host images of both operators and all vectors, then uploads
 static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
 {
+    const auto t_up = std::chrono::steady_clock::now();
     const Sizes &sz = h->sz;
     Buffers &b = h->buf;
     Dev &d = h->d;
-    std::vector<int64_t> Krp(sz.M + 1), Ktrp(sz.N + 1);
-    std::vector<int32_t> Kci(sz.NNZ), Ktci(sz.NNZ), Kbs(sz.nblkK), Ktbs(sz.nblkT);
+    hvec<int64_t> Krp(sz.M + 1), Ktrp(sz.N + 1);
+    hvec<int32_t> Kci(sz.NNZ), Ktci(sz.NNZ);
+    std::vector<int32_t> Kbs(sz.nblkK), Ktbs(sz.nblkT);
     std::vector<int4> Kbd(sz.nblkK), Ktbd(sz.nblkT);
-    std::vector<double> Kv(sz.NNZ), Ktv(sz.NNZ);
+    hvec<double> Kv(sz.NNZ), Ktv(sz.NNZ);
+    const int HT = host_threads();
     std::vector<Seg> Kseg, Ktseg;
     std::vector<int32_t> l2inst;
     std::vector<double> craw(sz.N), lraw(sz.N), uraw(sz.N), qraw(sz.M);
@@ -582,33 +676,75 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
         in.m1 = (int32_t)p.m1;
         std::vector<int32_t> col_new(p.n);
         for (int64_t j = 0; j < p.n; ++j) col_new[p.col_order[j]] = (int32_t)j;
-        // K rows in internal order, global column index
-        int64_t pos = nzoff;
+        // K rows in internal order, global column index: row pointers by a
+        // scan, then the entries on HT threads over ranges of rows
+        Krp[yoff] = nzoff;
         for (int64_t i = 0; i < p.m; ++i) {
             const int32_t r = p.row_order[i];
-            for (int64_t k = lp.rp[r]; k < lp.rp[r + 1]; ++k) {
-                Kci[pos] = (int32_t)(xoff + col_new[lp.ci[k]]);
-                Kv[pos] = lp.v[k];
-                ++pos;
-            }
-            Krp[yoff + i + 1] = pos;
-            row_orig[yoff + i] = r;
-            inst_row[yoff + i] = bi;
-            qraw[yoff + i] = lp.rhs[r];
+            Krp[yoff + i + 1] = Krp[yoff + i] + (lp.rp[r + 1] - lp.rp[r]);
         }
-        // K^T by a stable counting sort over the internal rows of K
-        std::vector<int64_t> cnt(p.n + 1, 0);
-        for (int64_t k = nzoff; k < pos; ++k) cnt[Kci[k] - xoff + 1]++;
-        for (int64_t j = 0; j < p.n; ++j) cnt[j + 1] += cnt[j];
-        for (int64_t j = 0; j < p.n; ++j) Ktrp[xoff + j + 1] = nzoff + cnt[j + 1];
-        std::vector<int64_t> next(cnt.begin(), cnt.end() - 1);
-        for (int64_t i = 0; i < p.m; ++i)
-            for (int64_t k = Krp[yoff + i]; k < Krp[yoff + i + 1]; ++k) {
-                const int64_t j = Kci[k] - xoff;
-                const int64_t dst = nzoff + next[j]++;
-                Ktci[dst] = (int32_t)(yoff + i);
-                Ktv[dst] = Kv[k];
+        const int64_t pos = Krp[yoff + p.m];
+        parallel_ranges(p.m, 4096, HT, [&](int, int64_t i0, int64_t i1) {
+            for (int64_t i = i0; i < i1; ++i) {
+                const int32_t r = p.row_order[i];
+                int64_t q = Krp[yoff + i];
+                for (int64_t k = lp.rp[r]; k < lp.rp[r + 1]; ++k, ++q) {
+                    Kci[q] = (int32_t)(xoff + col_new[lp.ci[k]]);
+                    Kv[q] = lp.v[k];
+                }
+                row_orig[yoff + i] = r;
+                inst_row[yoff + i] = bi;
+                qraw[yoff + i] = lp.rhs[r];
             }
+        });
+        // K^T by a stable counting sort over the internal rows of K.  Column
+        // counts: per-thread histograms over ranges of rows, summed.  Entries:
+        // thread t owns a range of columns holding about 1/T of the entries,
+        // scans K in row order and places only its own columns' entries, so
+        // every column lists its rows in increasing order and no two threads
+        // write the same cache lines.
+        {
+            const int64_t nzi = pos - nzoff;
+            int TT = (int)std::max<int64_t>(1, std::min<int64_t>(HT, nzi / (1 << 18)));
+            while (TT > 1 && (int64_t)TT * (p.n + 1) > ((int64_t)1 << 26)) --TT;  // <= 512 MB of counters
+            std::vector<int64_t> hist((size_t)TT * p.n, 0);
+            parallel_ranges(TT, 1, TT, [&](int, int64_t t0, int64_t t1) {
+                for (int64_t t = t0; t < t1; ++t) {
+                    int64_t *hc = hist.data() + (size_t)t * p.n;
+                    const int64_t r0 = p.m * t / TT, r1 = p.m * (t + 1) / TT;
+                    for (int64_t k = Krp[yoff + r0]; k < Krp[yoff + r1]; ++k) hc[Kci[k] - xoff]++;
+                }
+            });
+            Ktrp[xoff] = nzoff;
+            for (int64_t j = 0; j < p.n; ++j) {
+                int64_t c = 0;
+                for (int t = 0; t < TT; ++t) c += hist[(size_t)t * p.n + j];
+                Ktrp[xoff + j + 1] = Ktrp[xoff + j] + c;
+            }
+            std::vector<int64_t>().swap(hist);
+            std::vector<int64_t> ccut(TT + 1, p.n);
+            ccut[0] = 0;
+            for (int t = 1, j = 0; t < TT; ++t) {
+                const int64_t target = nzoff + nzi * t / TT;
+                while (j < p.n && Ktrp[xoff + j] < target) ++j;
+                ccut[t] = j;
+            }
+            std::vector<int64_t> nx(Ktrp.begin() + xoff, Ktrp.begin() + xoff + p.n);  // next slot per column
+            parallel_ranges(TT, 1, TT, [&](int, int64_t t0, int64_t t1) {
+                for (int64_t t = t0; t < t1; ++t) {
+                    const int64_t c0 = ccut[t], c1 = ccut[t + 1];
+                    if (c1 <= c0) continue;
+                    for (int64_t i = 0; i < p.m; ++i)
+                        for (int64_t k = Krp[yoff + i]; k < Krp[yoff + i + 1]; ++k) {
+                            const int64_t j = Kci[k] - xoff;
+                            if (j < c0 || j >= c1) continue;
+                            const int64_t dst = nx[j]++;
+                            Ktci[dst] = (int32_t)(yoff + i);
+                            Ktv[dst] = Kv[k];
+                        }
+                }
+            });
+        }
         for (int64_t j = 0; j < p.n; ++j) {
             const int32_t cj = p.col_order[j];
             col_orig[xoff + j] = cj;
@@ -701,6 +837,8 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
     for (int bi = 0; bi < h->batch; ++bi) adm[bi] = bi;
     std::stable_sort(adm.begin(), adm.end(),
                      [&](int32_t a, int32_t c) { return h->info[a].sweep_bytes > h->info[c].sweep_bytes; });
+    const auto t_copy = std::chrono::steady_clock::now();
+    h->setup_phase[1] = std::chrono::duration<double>(t_copy - t_up).count();
     int rc;
     if ((rc = h2d(b.bcumK, cumK.data(), cumK.size(), s)) || (rc = h2d(b.bcumT, cumT.data(), cumT.size(), s)) ||
         (rc = h2d(d.adm_order, adm.data(), adm.size(), s)))
@@ -722,6 +860,7 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
         return rc;
     // the host images die with this scope: wait for the copies
     HIPCHK(hipStreamSynchronize(s));
+    h->setup_phase[2] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_copy).count();
     return PDHG_OK;
 }
 
@@ -841,8 +980,8 @@ static int device_setup(pdhg_handle *h, hipStream_t s)
     return PDHG_OK;
 }
 
-extern "C" int pdhg_setup(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, void *ws, size_t ws_bytes,
-                          hipStream_t stream, pdhg_handle **out)
+static int setup_impl(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, void *ws, size_t ws_bytes,
+                      hipStream_t stream, pdhg_handle **out)
 {
     auto t0 = std::chrono::steady_clock::now();
     if (!out) return fail(PDHG_ERR_INVALID_ARG, "out is NULL");
@@ -861,6 +1000,7 @@ extern "C" int pdhg_setup(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, 
         delete h;
         return rc;
     }
+    h->setup_phase[0] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     h->batch = batch;
     h->prec = o->precision;
     h->opts = *o;
@@ -908,7 +1048,9 @@ extern "C" int pdhg_setup(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, 
     }
     rc = upload(h, hosts, stream);
     hosts.clear();
+    auto t_dev = std::chrono::steady_clock::now();
     if (!rc) rc = h->prec == PDHG_PREC_F32 ? device_setup<float>(h, stream) : device_setup<double>(h, stream);
+    h->setup_phase[3] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_dev).count();
     if (rc) {
         std::string m = g_err;
         pdhg_destroy(h);
@@ -918,6 +1060,20 @@ extern "C" int pdhg_setup(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, 
     h->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     *out = h;
     return PDHG_OK;
+}
+
+// host allocations of setup may fail: report that instead of letting the
+// exception cross the C ABI
+extern "C" int pdhg_setup(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, void *ws, size_t ws_bytes,
+                          hipStream_t stream, pdhg_handle **out)
+{
+    try {
+        return setup_impl(lp, batch, o, ws, ws_bytes, stream, out);
+    } catch (const std::bad_alloc &) {
+        return fail(PDHG_ERR_NOMEM, "setup: host memory exhausted");
+    } catch (...) {
+        return fail(PDHG_ERR_INVALID_ARG, "setup: unexpected host error");
+    }
 }
 
 extern "C" void pdhg_destroy(pdhg_handle *h)
@@ -1752,8 +1908,8 @@ void json_ints(std::string &js, const char *key, const int32_t *v)
 
 }  // namespace
 
-extern "C" int pdhg_autotune(const pdhg_lp *lp, int32_t batch, const pdhg_opts *base, void *ws, size_t ws_bytes,
-                             size_t *ws_needed, int32_t reps, hipStream_t s, pdhg_opts *best, const char *out_json)
+static int autotune_impl(const pdhg_lp *lp, int32_t batch, const pdhg_opts *base, void *ws, size_t ws_bytes,
+                         size_t *ws_needed, int32_t reps, hipStream_t s, pdhg_opts *best, const char *out_json)
 {
     if (!lp || !base || !best || batch < 1 || reps < 1)
         return fail(PDHG_ERR_INVALID_ARG, "need lp, base, best != NULL, batch >= 1 and reps >= 1");
@@ -1870,6 +2026,16 @@ extern "C" int pdhg_autotune(const pdhg_lp *lp, int32_t batch, const pdhg_opts *
     return PDHG_OK;
 }
 
+extern "C" int pdhg_autotune(const pdhg_lp *lp, int32_t batch, const pdhg_opts *base, void *ws, size_t ws_bytes,
+                             size_t *ws_needed, int32_t reps, hipStream_t s, pdhg_opts *best, const char *out_json)
+{
+    try {
+        return autotune_impl(lp, batch, base, ws, ws_bytes, ws_needed, reps, s, best, out_json);
+    } catch (...) {
+        return fail(PDHG_ERR_NOMEM, "autotune: host memory exhausted");
+    }
+}
+
 extern "C" int pdhg_set_opts(pdhg_handle *h, const pdhg_opts *o)
 {
     if (!h || !o) return fail(PDHG_ERR_INVALID_ARG, "NULL argument");
@@ -1971,5 +2137,9 @@ extern "C" int pdhg_get_info(const pdhg_handle *h, pdhg_info *info)
     info->nseg_dual = (int32_t)h->sz.nsegK;
     info->nblk_primal = h->sz.nblkT;
     info->nblk_dual = h->sz.nblkK;
+    info->setup_plan_seconds = h->setup_phase[0];
+    info->setup_host_seconds = h->setup_phase[1];
+    info->setup_copy_seconds = h->setup_phase[2];
+    info->setup_device_seconds = h->setup_phase[3];
     return PDHG_OK;
 }
