@@ -161,7 +161,11 @@ def bench_batched(args):
     kw = dict(precision="f32", eps=1e-4, max_iters=200000, time_limit=170.0)
     t0 = time.perf_counter()
     sb = pd.Solver(lps, batch_resident_bytes=args.resident_bytes, **kw)
-    print(f"[bench] batched setup {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    setup_s = time.perf_counter() - t0
+    si = sb.info()
+    setup = {"seconds": setup_s, **{k: si["setup_" + k + "_seconds"] for k in ("plan", "host", "copy", "device")}}
+    print(f"[bench] batched setup {setup_s:.1f}s ({json.dumps({k: round(v, 2) for k, v in setup.items()})})",
+          file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rb = sb.solve()
@@ -196,7 +200,7 @@ def bench_batched(args):
            "config": {"workload": f"{B} planted LPs, m ~ U{{1000..{args.m_max}}}, n = 2.5m, density "
                                   f"U(0.001, 0.01); total nnz {nnz}; eps 1e-4",
                       "batch": B, "nnz_total": nnz, "resident_bytes": args.resident_bytes},
-           "batched": {"seconds": tb, "lps_per_s": B / tb,
+           "batched": {"seconds": tb, "lps_per_s": B / tb, "setup": setup,
                        "status": {k: sum(1 for r in rb if r["status_name"] == k) for k in set(r["status_name"] for r in rb)}},
            "one_by_one": {"seconds": ts, "lps_per_s": B / ts, "buckets": buckets},
            "speedup": ts / tb, "iterations_identical": same, "max_rel_obj_gap_vs_planted": max(gaps)}

@@ -898,13 +898,25 @@ static int device_setup(pdhg_handle *h, hipStream_t s)
     double *bv = d.vecN64, *wv = d.vecM64, *bt = d.vecN64b;
     double *pk = d.partials, *pt = d.partials + h->sz.nblkK + 1;
     launch_fill(bv, d.N, 1.0, s);
+    // the sweeps walk the active lists: an instance whose estimate has
+    // converged is marked done and drops out of them (its numbers are final)
+    std::vector<InstState> pst(B, InstState{});
+    auto mark_converged = [&](const std::vector<int> &flag) -> int {
+        for (int b = 0; b < B; ++b) pst[b].done = flag[b];
+        HIPCHK(hipMemcpyAsync(d.st, pst.data(), B * sizeof(InstState), hipMemcpyHostToDevice, s));
+        launch_active(d, s);
+        return PDHG_OK;
+    };
+    if (mark_converged(conv)) return PDHG_ERR_HIP;
+    const int32_t *lK = d.actK, *lT = d.actT, *cK = d.act_cnt, *cT = d.act_cnt + 1;
     int remaining = B;
     for (int it = 0; it < o.power_max_iters && remaining > 0; ++it) {
-        launch_spmv64(d.K, d.remap, bv, wv, pk, s);
+        launch_spmv64(d.K, d.remap, bv, wv, pk, lK, cK, s);
         if (it > 0) {
             launch_inst_sum(d, 1, pk, sc, s);
             HIPCHK(hipMemcpyAsync(w2.data(), sc, B * sizeof(double), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
+            const int before = remaining;
             for (int b = 0; b < B; ++b) {
                 if (conv[b]) continue;
                 est[b] = std::sqrt(w2[b]);
@@ -916,14 +928,17 @@ static int device_setup(pdhg_handle *h, hipStream_t s)
                 prev[b] = est[b];
             }
             if (remaining == 0) break;
+            if (remaining != before && mark_converged(conv)) return PDHG_ERR_HIP;
         }
-        launch_spmv64(d.Kt, d.remap, wv, bt, pt, s);
+        launch_spmv64(d.Kt, d.remap, wv, bt, pt, lT, cT, s);
         launch_inst_sum(d, 0, pt, sc + B, s);
         launch_normalize(bt, d.inst_of_col, d.N, sc + B, s);
         std::swap(bv, bt);
     }
+    // the handle's lists hold every instance again
+    if (mark_converged(std::vector<int>(B, 0))) return PDHG_ERR_HIP;
     if (remaining > 0) {
-        launch_spmv64(d.K, d.remap, bv, wv, pk, s);
+        launch_spmv64(d.K, d.remap, bv, wv, pk, nullptr, nullptr, s);
         launch_inst_sum(d, 1, pk, sc, s);
         HIPCHK(hipMemcpyAsync(w2.data(), sc, B * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));

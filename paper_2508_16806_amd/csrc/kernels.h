@@ -42,7 +42,7 @@ void launch_scale_vals(const OpDev &op, double *v64, float *v32, bool row_first,
 template <typename T>
 void launch_scale_data(const Dev &d, hipStream_t s);
 void launch_spmv64(const OpDev &op, int remap, const double *v, double *out, double *partials,
-                   hipStream_t s);
+                   const int32_t *list, const int32_t *cnt, hipStream_t s);
 void launch_inst_sum(const Dev &d, int onK, const double *partials, double *out, hipStream_t s);
 void launch_normalize(double *v, const int32_t *inst_of, int64_t n, const double *nrm2, hipStream_t s);
 void launch_inst_nrm2(const Dev &d, int primal, const double *v, double *out, hipStream_t s);

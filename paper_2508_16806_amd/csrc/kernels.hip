@@ -1102,23 +1102,29 @@ __global__ void k_scale_dual(Dev d)
 }
 
 // out = K v (FP64), per-workgroup partial of sum(out^2) in partials[lb]
+// out = op v (FP64) over the blocks of `list` (list[0 .. *cnt); every block
+// when list is NULL), with each block's sum of squares in partials[block]
 __global__ __launch_bounds__(WG) void k_spmv64(OpDev op, int remap, const double *v, double *out,
-                                               double *partials)
+                                               double *partials, const int32_t *list, const int32_t *cntp)
 {
     __shared__ double red[8];
-    const int lb = logical_block(remap);
-    const Seg s = block_seg(op, lb);
-    const int bi = lb - s.blk0;
-    double sq[1] = {0.0};
-    dispatch_lanes<4>(s.lanes_log2, [&](auto tag, auto rtag) {
-        constexpr int L = decltype(tag)::value, R = decltype(rtag)::value;
-        sweep_rows<L, 1, double, double, R>(op, s, bi, v, nullptr, nullptr, red, [&](int64_t r, const double *acc) {
-            out[r] = acc[0];
-            sq[0] += acc[0] * acc[0];
+    const int cnt = list ? *cntp : op.nblk;
+    for_each_item(cnt, remap, [&](int it) {
+        const int lb = list ? list[it] : it;
+        const Seg s = block_seg(op, lb);
+        const int bi = lb - s.blk0;
+        double sq[1] = {0.0};
+        dispatch_lanes<4>(s.lanes_log2, [&](auto tag, auto rtag) {
+            constexpr int L = decltype(tag)::value, R = decltype(rtag)::value;
+            sweep_rows<L, 1, double, double, R>(op, s, bi, v, nullptr, nullptr, red, [&](int64_t r, const double *acc) {
+                out[r] = acc[0];
+                sq[0] += acc[0] * acc[0];
+            });
         });
+        block_sum<1>(sq, red);
+        if (threadIdx.x == 0 && partials) partials[lb] = sq[0];
+        __syncthreads();
     });
-    block_sum<1>(sq, red);
-    if (threadIdx.x == 0 && partials) partials[lb] = sq[0];
 }
 
 // per-instance sum of partials[blk0 .. blk1) (ranges from InstInfo), fixed order
@@ -1617,9 +1623,11 @@ void launch_scale_data(const Dev &d, hipStream_t s)
 }
 
 void launch_spmv64(const OpDev &op, int remap, const double *v, double *out, double *partials,
-                   hipStream_t s)
+                   const int32_t *list, const int32_t *cnt, hipStream_t s)
 {
-    LAUNCH(k_spmv64, (unsigned)op.nblk, op, remap, v, out, partials);
+    const unsigned g = (unsigned)(op.nblk < 65536 ? op.nblk : 65536);
+    if (g == 0) return;
+    LAUNCH(k_spmv64, g, op, remap, v, out, partials, list, cnt);
 }
 
 void launch_inst_sum(const Dev &d, int onK, const double *partials, double *out, hipStream_t s)
