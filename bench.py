@@ -163,7 +163,8 @@ def bench_batched(args):
     sb = pd.Solver(lps, batch_resident_bytes=args.resident_bytes, **kw)
     setup_s = time.perf_counter() - t0
     si = sb.info()
-    setup = {"seconds": setup_s, **{k: si["setup_" + k + "_seconds"] for k in ("plan", "host", "copy", "device")}}
+    setup = {"seconds": setup_s, **{k: si["setup_" + k + "_seconds"] for k in ("plan", "host", "copy", "device", "power")},
+             "power_iters_max": si["power_iters_max"]}
     print(f"[bench] batched setup {setup_s:.1f}s ({json.dumps({k: round(v, 2) for k, v in setup.items()})})",
           file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -199,7 +200,10 @@ def bench_batched(args):
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"{B} planted LPs, m ~ U{{1000..{args.m_max}}}, n = 2.5m, density "
                                   f"U(0.001, 0.01); total nnz {nnz}; eps 1e-4",
-                      "batch": B, "nnz_total": nnz, "resident_bytes": args.resident_bytes},
+                      "batch": B, "nnz_total": nnz, "resident_bytes": args.resident_bytes,
+                      "bins": {k: kw[k] for k in ("bin_len_primal", "bin_len_dual", "bin_rows_primal",
+                                                  "bin_rows_dual", "xcd_remap", "max_grid") if k in kw}
+                      or "default"},
            "batched": {"seconds": tb, "lps_per_s": B / tb, "setup": setup,
                        "status": {k: sum(1 for r in rb if r["status_name"] == k) for k in set(r["status_name"] for r in rb)}},
            "one_by_one": {"seconds": ts, "lps_per_s": B / ts, "buckets": buckets},

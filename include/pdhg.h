@@ -234,6 +234,8 @@ typedef struct {
      * device images of K~ and K~^T on the host, copying them to the device,
      * and the device work (Ruiz scaling, FP32 copies, power iteration) */
     double setup_plan_seconds, setup_host_seconds, setup_copy_seconds, setup_device_seconds;
+    double setup_power_seconds;     /* the power iteration's part of the device work */
+    int32_t power_iters_max;        /* most power iterations of any instance        */
 } pdhg_info;
 
 /* Average device time per launch of each phase kernel (milliseconds). */

@@ -102,7 +102,8 @@ class Info(C.Structure):
                 ("batch", C.c_int32), ("workspace_bytes", C.c_int64), ("nseg_primal", C.c_int32),
                 ("nseg_dual", C.c_int32), ("nblk_primal", C.c_int64), ("nblk_dual", C.c_int64),
                 ("setup_plan_seconds", C.c_double), ("setup_host_seconds", C.c_double),
-                ("setup_copy_seconds", C.c_double), ("setup_device_seconds", C.c_double)]
+                ("setup_copy_seconds", C.c_double), ("setup_device_seconds", C.c_double),
+                ("setup_power_seconds", C.c_double), ("power_iters_max", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -313,7 +313,7 @@ struct pdhg_handle {
     int32_t *hdone_host = nullptr;
     size_t ws_bytes = 0;
     double setup_seconds = 0;
-    double setup_phase[4] = {0, 0, 0, 0};  // plan, host images, copies, device
+    double setup_phase[5] = {0, 0, 0, 0, 0};  // plan, host images, copies, device, power iteration
     hipGraphExec_t graph = nullptr;
     hipStream_t cap_stream = nullptr;
     FishDev fish{};          // fishnet buffers (opts.fishnet_points > 0)
@@ -893,6 +893,7 @@ static int device_setup(pdhg_handle *h, hipStream_t s)
     HIPCHK(hipMemcpyAsync(qn2.data(), sc + B, B * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     // power iteration (Algorithm 2) on every instance at once
+    const auto t_pow = std::chrono::steady_clock::now();
     std::vector<double> est(B, 0.0), prev(B, -1.0), w2(B);
     std::vector<int> conv(B, 0), its(B, 0);
     double *bv = d.vecN64, *wv = d.vecM64, *bt = d.vecN64b;
@@ -949,6 +950,8 @@ static int device_setup(pdhg_handle *h, hipStream_t s)
             }
     }
     HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    h->setup_phase[4] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_pow).count();
     // step size and primal weight (Sections 2.3.1, 2.4.3)
     h->st0.assign(B, InstState{});
     h->knorm = est;
@@ -2156,5 +2159,7 @@ extern "C" int pdhg_get_info(const pdhg_handle *h, pdhg_info *info)
     info->setup_host_seconds = h->setup_phase[1];
     info->setup_copy_seconds = h->setup_phase[2];
     info->setup_device_seconds = h->setup_phase[3];
+    info->setup_power_seconds = h->setup_phase[4];
+    for (int b = 0; b < h->batch; ++b) info->power_iters_max = std::max(info->power_iters_max, h->st0[b].power_iters);
     return PDHG_OK;
 }

@@ -63,7 +63,7 @@ def load(path: str) -> dict:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="sced", choices=["sced", "sced_small", "zipf", "zipf_small"])
+    ap.add_argument("--workload", default="sced", choices=["sced", "sced_small", "zipf", "zipf_small", "planted16"])
     ap.add_argument("--precision", default="f32")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--out", required=True)
@@ -73,9 +73,11 @@ def main():
         sys.path.insert(0, root)
     import lpgen
 
+    # planted16: the first 16 planted LPs of the batched workload (m ~ U{1000..50000}, n = 2.5m,
+    # density U(0.1%, 1%)), tuned as one batch
     lp = {"sced": lambda: lpgen.config1(), "sced_small": lambda: lpgen.sced(500, 200, 24, 125, seed=1),
-          "zipf": lambda: lpgen.config2(), "zipf_small": lambda: lpgen.config2(m=100000, n=200000)}[
-        args.workload]()
+          "zipf": lambda: lpgen.config2(), "zipf_small": lambda: lpgen.config2(m=100000, n=200000),
+          "planted16": lambda: [lpgen.config3_instance(i) for i in range(16)]}[args.workload]()
     res = autotune(lp, precision=args.precision, reps=args.reps)
     res["workload"] = args.workload
     with open(args.out, "w") as f:
