@@ -541,3 +541,47 @@ def col_block(lp: LP, c0: int, c1: int) -> LP:
     return LP(c1 - c0, lp.m, rowptr, (lp.col[keep] - c0).astype(np.int32), lp.val[keep].copy(),
               lp.row_type.copy(), lp.rhs.copy(), lp.c[c0:c1].copy(), lp.l[c0:c1].copy(), lp.u[c0:c1].copy(),
               name=f"{lp.name}[cols {c0}:{c1}]")
+
+
+def random_case(seed: int) -> LP:
+    """A planted LP of a shape drawn from `seed` (for sweeps over many
+    structures): either a dense tiny LP with free and half-bounded variables
+    or a sparse planted LP with m in [5, 400], n in [m, 3m], density in
+    [0.5%, 20%] (at least 1.5 entries per row on average), ">=" rows 0-100%,
+    and in a quarter of the sparse cases one row and one column emptied."""
+    rng = np.random.default_rng(90_000 + seed)
+    if rng.random() < 0.3:
+        n = int(rng.integers(2, 12))
+        m = int(rng.integers(1, n + 1))
+        return tiny(int(rng.integers(1 << 31)), n=n, m=m, ge_frac=float(rng.random()),
+                    free_frac=float(rng.uniform(0.0, 0.6)))
+    m = int(rng.integers(5, 401))
+    n = int(rng.integers(m, 3 * m + 1))
+    d = float(min(0.2, max(rng.uniform(0.005, 0.2), 1.5 / n)))
+    lp = planted(m, n, d, int(rng.integers(1 << 31)), ge_frac=float(rng.random()),
+                 u_range=(float(rng.uniform(0.5, 2.0)), float(rng.uniform(3.0, 20.0))))
+    if rng.random() >= 0.25:
+        return lp
+    # empty row i and column j.  The planted reduced costs z = c - K'y* stay,
+    # so c' = K2'y2 + z keeps (x*, y2) optimal; row i becomes an "=" row with
+    # right-hand side 0 and multiplier 0
+    i, j = int(rng.integers(m)), int(rng.integers(n))
+    rows = np.repeat(np.arange(m), np.diff(lp.rowptr))
+    A = np.zeros((m, n))
+    np.add.at(A, (rows, lp.col), lp.val)
+    z = lp.c - A.T @ lp.y_star
+    A[i, :] = 0.0
+    A[:, j] = 0.0
+    y = lp.y_star.copy()
+    y[i] = 0.0
+    rt = lp.row_type.copy()
+    rt[i] = EQ
+    ax = A @ lp.x_star
+    inactive = (rt == GE) & (y == 0.0)
+    rhs = ax.copy()
+    rhs[inactive] -= rng.uniform(0.1, 1.0, size=int(inactive.sum()))
+    c = A.T @ y + z
+    r, cc = np.nonzero(A)
+    rowptr, col, val = _csr_from_coo(m, r.astype(np.int64), cc.astype(np.int64), A[r, cc])
+    return LP(n, m, rowptr, col, val, rt, rhs, c, lp.l.copy(), lp.u.copy(), name=lp.name + "-emptied",
+              x_star=lp.x_star, y_star=y, f_star=float(c @ lp.x_star))

@@ -1,5 +1,6 @@
 """Row and column blocks of an LP (the share of K and K^T one GPU would own
-under a partition) reassemble the LP exactly."""
+under a partition) reassemble the LP exactly; the random-structure cases
+carry optimal planted pairs."""
 import numpy as np
 import scipy.sparse as sp
 
@@ -44,3 +45,16 @@ def test_col_blocks_concatenate_to_k():
             sel = (c >= cuts[p]) & (c < cuts[p + 1])
             np.testing.assert_array_equal(b.col[b.rowptr[i]:b.rowptr[i + 1]], c[sel] - cuts[p])
             np.testing.assert_array_equal(b.val[b.rowptr[i]:b.rowptr[i + 1]], v[sel])
+
+
+def test_random_cases_plant_optimal_pairs(orc):
+    """The planted (x*, y*) of every random-structure case has KKT error 0 to
+    rounding under the oracle's KKT function (Section 2.3.2) and is feasible."""
+    names = set()
+    for seed in range(32):
+        lp = lpgen.random_case(seed)
+        k = orc.Oracle(lp).kkt(lp.x_star, lp.y_star)
+        assert k["rel_kkt"] <= 1e-9, (seed, lp.name, k)
+        assert np.all(lp.x_star >= lp.l - 1e-12) and np.all(lp.x_star <= lp.u + 1e-12)
+        names.add(lp.name.split("-")[-1] if "-" in lp.name else lp.name[:4])
+    assert "emptied" in names and "tiny" in names  # every family occurs
