@@ -70,3 +70,24 @@ def test_random_case_solve_f64(orc, pd, seed):
     # the same method in FP64: the same work up to a rounding-level flip of a
     # restart decision
     assert abs(r["iters"] - ro.iters) <= max(128, ro.iters // 10), (r["iters"], ro.iters)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("adaptive", [0, 1])
+@pytest.mark.parametrize("budget", [0, None])
+def test_random_batch_equals_solo_bitwise(pd, prec, adaptive, budget):
+    """A batch of 12 different structures (tiny dense with free variables next
+    to sparse planted LPs) gives every instance bitwise its solo result, with
+    all instances running at once and under the default admission."""
+    lps = [lpgen.random_case(s) for s in range(100, 112)]
+    kw = dict(precision=prec, eps=1e-6, max_iters=100000, adaptive_step=adaptive)
+    b = pd.Solver(lps, **kw) if budget is None else pd.Solver(lps, batch_resident_bytes=budget, **kw)
+    rb = b.solve()
+    for i, lp in enumerate(lps):
+        s = pd.Solver(lp, **kw)
+        rs = s.solve()[0]
+        assert rb[i]["status"] == rs["status"] and rb[i]["iters"] == rs["iters"], (i, lp.name)
+        xb, yb = b.solution(inst=i)
+        xs, ys = s.solution()
+        np.testing.assert_array_equal(xb, xs)
+        np.testing.assert_array_equal(yb, ys)
