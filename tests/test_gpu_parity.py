@@ -409,3 +409,27 @@ def test_layouts_batched_bitwise(pd):
         rs = s.solve()[0]
         assert rb[i]["iters"] == rs["iters"]
         np.testing.assert_array_equal(b.solution(inst=i)[0], s.solution()[0])
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_run_to_run_bitwise(pd, prec):
+    """No atomics on the floating-point path: the same solve on two handles,
+    and twice on one handle from the same start, gives the same bits (iterate,
+    average, KKT terms, restart trace), and so do the check and the KKT of a
+    caller point."""
+    lp = lpgen.sced(40, 16, 8, 12, seed=5)
+    kw = dict(precision=prec, eps=1e-6, trace_capacity=1024)
+    a, b = pd.Solver(lp, **kw), pd.Solver(lp, **kw)
+    ra, rb = a.solve()[0], b.solve()[0]
+    assert ra["iters"] == rb["iters"] and ra["kkt"] == rb["kkt"]
+    assert a.trace() == b.trace()
+    for which in (pd.SOL_CURRENT, pd.SOL_AVERAGE):
+        for u, v in zip(a.solution(which=which), b.solution(which=which)):
+            np.testing.assert_array_equal(u, v)
+    x, y = a.solution()
+    a.set_state(np.zeros(lp.n), np.zeros(lp.m))
+    ra2 = a.solve()[0]
+    b.set_state(np.zeros(lp.n), np.zeros(lp.m))
+    rb2 = b.solve()[0]
+    assert ra2["kkt"] == rb2["kkt"] and ra2["iters"] == rb2["iters"]
+    assert a.kkt(x, y) == a.kkt(x, y) == b.kkt(x, y)
