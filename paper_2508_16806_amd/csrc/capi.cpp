@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <climits>
 #include <cmath>
@@ -483,89 +484,6 @@ static int check_opts(const pdhg_opts *o)
     return PDHG_OK;
 }
 
-static int plan_all(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, std::vector<HostLP> &hosts,
-                    std::vector<InstPlan> &plans, Sizes &sz, bool pattern_only)
-{
-    if (!lp || batch < 1) return fail(PDHG_ERR_INVALID_ARG, "need lp != NULL and batch >= 1");
-    int rc = check_opts(o);
-    if (rc) return rc;
-    hosts.resize(batch);
-    plans.resize(batch);
-    const Bins bins = make_bins(o->bin_len_dual, o->bin_rows_dual);
-    const Bins tbins = make_bins(o->bin_len_primal, o->bin_rows_primal);
-    sz = Sizes{};
-    sz.batch = batch;
-    for (int b = 0; b < batch; ++b) {
-        if ((rc = load_lp(lp[b], hosts[b], pattern_only))) {
-            if (batch > 1) {
-                std::string m = g_err;
-                return fail(rc, "instance %d: %s", b, m.c_str());
-            }
-            return rc;
-        }
-        plan_instance(hosts[b], bins, tbins, plans[b]);
-        sz.N += hosts[b].n;
-        sz.M += hosts[b].m;
-        sz.NNZ += hosts[b].nnz;
-        int64_t pb = 0;
-        for (auto &s : plans[b].segK) pb += (s.nrows + seg_group(s.lanes_log2) - 1) / seg_group(s.lanes_log2);
-        sz.nblkK += pb;
-        int64_t pt = 0;
-        for (auto &s : plans[b].segT) pt += (s.nrows + seg_group(s.lanes_log2) - 1) / seg_group(s.lanes_log2);
-        sz.nblkT += pt;
-        sz.nl2 += (pb + pt + L2CH - 1) / L2CH;
-        sz.nsegK += plans[b].segK.size();
-        sz.nsegT += plans[b].segT.size();
-    }
-    // sweeps address the gathered vectors with 32-bit byte offsets
-    if (sz.N >= (int64_t(1) << 29) || sz.M >= (int64_t(1) << 29))
-        return fail(PDHG_ERR_SHAPE, "total n and m over the batch must be < 2^29");
-    if (sz.nblkK + sz.nblkT >= INT32_MAX) return fail(PDHG_ERR_SHAPE, "too many workgroups");
-    return PDHG_OK;
-}
-
-static size_t workspace_bytes_impl(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o)
-{
-    pdhg_opts def;
-    if (!o) {
-        pdhg_default_opts(&def);
-        o = &def;
-    }
-    std::vector<HostLP> hosts;
-    std::vector<InstPlan> plans;
-    Sizes sz;
-    if (plan_all(lp, batch, o, hosts, plans, sz, false)) return 0;
-    Carve cv;
-    Dev d{};
-    Buffers b{};
-    InstInfo *info;
-    InstState *st;
-    FishDev fish{};
-    carve(cv, sz, o->precision, *o, d, b, &info, &st, &fish);
-    return (cv.off + 255) & ~(size_t)255;
-}
-
-extern "C" size_t pdhg_workspace_bytes(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o)
-{
-    try {
-        return workspace_bytes_impl(lp, batch, o);
-    } catch (...) {
-        fail(PDHG_ERR_NOMEM, "sizing: host memory exhausted");
-        return 0;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// setup
-// ---------------------------------------------------------------------------
-
-template <typename X>
-static int h2d(X *dst, const X *src, size_t cnt, hipStream_t s)
-{
-    if (cnt) HIPCHK(hipMemcpyAsync(dst, src, cnt * sizeof(X), hipMemcpyHostToDevice, s));
-    return PDHG_OK;
-}
-
 // Host vectors whose elements are all written before use: no zero fill (the
 // matrix images run to hundreds of MB, and the fill would be a full pass).
 // Large ones sit on 2 MB-aligned memory marked for transparent huge pages, so
@@ -643,6 +561,122 @@ static void parallel_ranges(int64_t n, int64_t grain, int T, F &&f)
     for (auto &x : th) x.join();
 }
 
+// f(i) for every i in [0, n) on up to T threads, items handed out in order
+// as threads become free.  f must not throw.
+template <typename F>
+static void parallel_items(int64_t n, int T, F &&f)
+{
+    std::atomic<int64_t> next{0};
+    parallel_ranges(std::min<int64_t>(T, n), 1, T, [&](int, int64_t, int64_t) {
+        for (;;) {
+            const int64_t i = next.fetch_add(1);
+            if (i >= n) break;
+            f(i);
+        }
+    });
+}
+
+static int plan_all(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, std::vector<HostLP> &hosts,
+                    std::vector<InstPlan> &plans, Sizes &sz, bool pattern_only)
+{
+    if (!lp || batch < 1) return fail(PDHG_ERR_INVALID_ARG, "need lp != NULL and batch >= 1");
+    int rc = check_opts(o);
+    if (rc) return rc;
+    hosts.resize(batch);
+    plans.resize(batch);
+    const Bins bins = make_bins(o->bin_len_dual, o->bin_rows_dual);
+    const Bins tbins = make_bins(o->bin_len_primal, o->bin_rows_primal);
+    sz = Sizes{};
+    sz.batch = batch;
+    // validation and binning of each instance: on host threads, one
+    // instance at a time each, when every instance is in host memory
+    // (device inputs are copied with the caller's current device)
+    bool all_host = true;
+    for (int b = 0; b < batch; ++b) all_host = all_host && lp[b].mem == PDHG_MEM_HOST;
+    std::vector<int> rcs(batch, PDHG_OK);
+    std::vector<std::string> msgs(batch);
+    auto plan_one = [&](int64_t b) {
+        try {
+            rcs[b] = load_lp(lp[b], hosts[b], pattern_only);
+            if (rcs[b]) {
+                msgs[b] = g_err;  // the message is per thread
+                return;
+            }
+            plan_instance(hosts[b], bins, tbins, plans[b]);
+        } catch (...) {
+            rcs[b] = PDHG_ERR_NOMEM;
+            msgs[b] = "host memory exhausted";
+        }
+    };
+    if (all_host && batch > 1)
+        parallel_items(batch, host_threads(), plan_one);
+    else
+        for (int b = 0; b < batch; ++b) plan_one(b);
+    for (int b = 0; b < batch; ++b)
+        if (rcs[b]) return batch > 1 ? fail(rcs[b], "instance %d: %s", b, msgs[b].c_str()) : fail(rcs[b], "%s", msgs[b].c_str());
+    for (int b = 0; b < batch; ++b) {
+        sz.N += hosts[b].n;
+        sz.M += hosts[b].m;
+        sz.NNZ += hosts[b].nnz;
+        int64_t pb = 0;
+        for (auto &s : plans[b].segK) pb += (s.nrows + seg_group(s.lanes_log2) - 1) / seg_group(s.lanes_log2);
+        sz.nblkK += pb;
+        int64_t pt = 0;
+        for (auto &s : plans[b].segT) pt += (s.nrows + seg_group(s.lanes_log2) - 1) / seg_group(s.lanes_log2);
+        sz.nblkT += pt;
+        sz.nl2 += (pb + pt + L2CH - 1) / L2CH;
+        sz.nsegK += plans[b].segK.size();
+        sz.nsegT += plans[b].segT.size();
+    }
+    // sweeps address the gathered vectors with 32-bit byte offsets
+    if (sz.N >= (int64_t(1) << 29) || sz.M >= (int64_t(1) << 29))
+        return fail(PDHG_ERR_SHAPE, "total n and m over the batch must be < 2^29");
+    if (sz.nblkK + sz.nblkT >= INT32_MAX) return fail(PDHG_ERR_SHAPE, "too many workgroups");
+    return PDHG_OK;
+}
+
+static size_t workspace_bytes_impl(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o)
+{
+    pdhg_opts def;
+    if (!o) {
+        pdhg_default_opts(&def);
+        o = &def;
+    }
+    std::vector<HostLP> hosts;
+    std::vector<InstPlan> plans;
+    Sizes sz;
+    if (plan_all(lp, batch, o, hosts, plans, sz, false)) return 0;
+    Carve cv;
+    Dev d{};
+    Buffers b{};
+    InstInfo *info;
+    InstState *st;
+    FishDev fish{};
+    carve(cv, sz, o->precision, *o, d, b, &info, &st, &fish);
+    return (cv.off + 255) & ~(size_t)255;
+}
+
+extern "C" size_t pdhg_workspace_bytes(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o)
+{
+    try {
+        return workspace_bytes_impl(lp, batch, o);
+    } catch (...) {
+        fail(PDHG_ERR_NOMEM, "sizing: host memory exhausted");
+        return 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// setup
+// ---------------------------------------------------------------------------
+
+template <typename X>
+static int h2d(X *dst, const X *src, size_t cnt, hipStream_t s)
+{
+    if (cnt) HIPCHK(hipMemcpyAsync(dst, src, cnt * sizeof(X), hipMemcpyHostToDevice, s));
+    return PDHG_OK;
+}
+
 // builds the host images of both operators and all vectors, then uploads
 static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
 {
@@ -661,14 +695,27 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
     std::vector<double> craw(sz.N), lraw(sz.N), uraw(sz.N), qraw(sz.M);
     std::vector<int32_t> col_orig(sz.N), row_orig(sz.M), inst_col(sz.N), inst_row(sz.M);
     h->info.assign(h->batch, InstInfo{});
-    int64_t xoff = 0, yoff = 0, nzoff = 0;
-    int32_t blkK = 0, blkT = 0;
-    Krp[0] = 0;
-    Ktrp[0] = 0;
+    // offsets of every instance in the concatenated vectors and operators
+    std::vector<int64_t> xo(h->batch + 1, 0), yo(h->batch + 1, 0), zo(h->batch + 1, 0);
     for (int bi = 0; bi < h->batch; ++bi) {
+        xo[bi + 1] = xo[bi] + h->plan[bi].n;
+        yo[bi + 1] = yo[bi] + h->plan[bi].m;
+        zo[bi + 1] = zo[bi] + h->plan[bi].nnz;
+    }
+    // the row pointers at instance boundaries, written here: an instance's
+    // build writes only the pointers strictly inside its range
+    for (int bi = 0; bi <= h->batch; ++bi) {
+        Krp[yo[bi]] = zo[bi];
+        Ktrp[xo[bi]] = zo[bi];
+    }
+    // each instance's part of the images depends on no other instance: one
+    // instance uses every thread; a batch gives each thread whole instances,
+    // largest first
+    auto build_inst = [&](int bi, int HT) {
         const HostLP &lp = hosts[bi];
         const InstPlan &p = h->plan[bi];
         InstInfo &in = h->info[bi];
+        const int64_t xoff = xo[bi], yoff = yo[bi], nzoff = zo[bi];
         in.xoff = xoff;
         in.yoff = yoff;
         in.n = (int32_t)p.n;
@@ -678,12 +725,15 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
         for (int64_t j = 0; j < p.n; ++j) col_new[p.col_order[j]] = (int32_t)j;
         // K rows in internal order, global column index: row pointers by a
         // scan, then the entries on HT threads over ranges of rows
-        Krp[yoff] = nzoff;
-        for (int64_t i = 0; i < p.m; ++i) {
-            const int32_t r = p.row_order[i];
-            Krp[yoff + i + 1] = Krp[yoff + i] + (lp.rp[r + 1] - lp.rp[r]);
+        {
+            int64_t acc = nzoff;
+            for (int64_t i = 0; i + 1 < p.m; ++i) {
+                const int32_t r = p.row_order[i];
+                acc += lp.rp[r + 1] - lp.rp[r];
+                Krp[yoff + i + 1] = acc;
+            }
         }
-        const int64_t pos = Krp[yoff + p.m];
+        const int64_t pos = zo[bi + 1];
         parallel_ranges(p.m, 4096, HT, [&](int, int64_t i0, int64_t i1) {
             for (int64_t i = i0; i < i1; ++i) {
                 const int32_t r = p.row_order[i];
@@ -715,11 +765,10 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
                     for (int64_t k = Krp[yoff + r0]; k < Krp[yoff + r1]; ++k) hc[Kci[k] - xoff]++;
                 }
             });
-            Ktrp[xoff] = nzoff;
-            for (int64_t j = 0; j < p.n; ++j) {
-                int64_t c = 0;
-                for (int t = 0; t < TT; ++t) c += hist[(size_t)t * p.n + j];
-                Ktrp[xoff + j + 1] = Ktrp[xoff + j] + c;
+            int64_t acc = nzoff;
+            for (int64_t j = 0; j + 1 < p.n; ++j) {
+                for (int t = 0; t < TT; ++t) acc += hist[(size_t)t * p.n + j];
+                Ktrp[xoff + j + 1] = acc;
             }
             std::vector<int64_t>().swap(hist);
             std::vector<int64_t> ccut(TT + 1, p.n);
@@ -753,6 +802,41 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
             lraw[xoff + j] = lp.l[cj];
             uraw[xoff + j] = lp.u[cj];
         }
+        double cn = 0, qn = 0;
+        for (int64_t j = 0; j < p.n; ++j) cn += lp.c[j] * lp.c[j];
+        for (int64_t i = 0; i < p.m; ++i) qn += lp.rhs[i] * lp.rhs[i];
+        in.cnorm = std::sqrt(cn);
+        in.qnorm = std::sqrt(qn);
+        {
+            // one iteration's two sweeps: values + columns of K~ and K~^T, row
+            // pointers, and the swept and gathered vectors
+            const int64_t es = (int64_t)elem_size(h->prec), nz = pos - nzoff;
+            in.sweep_bytes = 2 * (es + 4) * nz + 8 * (p.n + p.m + 2) + es * (9 * p.n + 6 * p.m);
+        }
+    };
+    if (h->batch == 1) {
+        build_inst(0, HT);
+    } else {
+        std::vector<int32_t> order(h->batch);
+        for (int bi = 0; bi < h->batch; ++bi) order[bi] = bi;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t u, int32_t v) { return h->plan[u].nnz > h->plan[v].nnz; });
+        std::atomic<bool> oom{false};
+        parallel_items(h->batch, HT, [&](int64_t k) {
+            try {
+                build_inst(order[k], 1);
+            } catch (...) {
+                oom = true;
+            }
+        });
+        if (oom) throw std::bad_alloc();
+    }
+    // segments and block maps, in instance order
+    int32_t blkK = 0, blkT = 0;
+    for (int bi = 0; bi < h->batch; ++bi) {
+        const InstPlan &p = h->plan[bi];
+        InstInfo &in = h->info[bi];
+        const int64_t xoff = xo[bi], yoff = yo[bi];
         // segments and block maps (instance-major, so an instance's blocks are contiguous)
         // block numbering: segments of long rows first (the dispatcher starts
         // the expensive workgroups early and short-row workgroups fill the
@@ -811,20 +895,6 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
         in.l2off = (int32_t)l2inst.size();
         in.l2cnt = (int32_t)((in.blkK1 - in.blkK0 + in.blkT1 - in.blkT0 + L2CH - 1) / L2CH);
         for (int t = 0; t < in.l2cnt; ++t) l2inst.push_back(bi);
-        double cn = 0, qn = 0;
-        for (int64_t j = 0; j < p.n; ++j) cn += lp.c[j] * lp.c[j];
-        for (int64_t i = 0; i < p.m; ++i) qn += lp.rhs[i] * lp.rhs[i];
-        in.cnorm = std::sqrt(cn);
-        in.qnorm = std::sqrt(qn);
-        {
-            // one iteration's two sweeps: values + columns of K~ and K~^T, row
-            // pointers, and the swept and gathered vectors
-            const int64_t es = (int64_t)elem_size(h->prec), nz = pos - nzoff;
-            in.sweep_bytes = 2 * (es + 4) * nz + 8 * (p.n + p.m + 2) + es * (9 * p.n + 6 * p.m);
-        }
-        xoff += p.n;
-        yoff += p.m;
-        nzoff = pos;
     }
     // block costs for the XCD split of the sweeps: entries + 4 per row
     std::vector<int64_t> cumK(sz.nblkK + 1, 0), cumT(sz.nblkT + 1, 0);
