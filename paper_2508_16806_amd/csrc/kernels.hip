@@ -923,58 +923,112 @@ __global__ __launch_bounds__(WG) void k_restart(Dev d)
     });
 }
 
-// Active lists: admission of waiting instances under the byte budget (first
-// = 1 at the start of a solve: instances beyond the budget start waiting),
-// then an exclusive scan of the running instances' block counts (one lane,
-// sequential over the batch: O(batch) per check) ...
-__global__ void k_act_scan(Dev d, int64_t budget, int first)
+// Active lists, rebuilt after every check by one workgroup of ACT_T threads
+// walking the batch in chunks of ACT_T instances (block-wide scans in LDS).
+constexpr int ACT_T = 1024;
+
+// inclusive sum over the ACT_T entries of each of the NQ rows of s
+template <int NQ>
+__device__ void act_scan_lds(int64_t (*s)[ACT_T])
 {
-    if (threadIdx.x != 0) return;
-    if (budget > 0) {
-        int64_t live = 0;
-        if (!first)
-            for (int b = 0; b < d.batch; ++b)
-                if (d.st[b].done == 0) live += d.info[b].sweep_bytes;
-        bool open = true;
-        for (int k = 0; k < d.batch; ++k) {
-            const int b = d.adm_order[k];
-            InstState &st = d.st[b];
-            const bool cand = first ? st.done == 0 : st.done == 2;
-            if (!cand) continue;
-            const int64_t need = d.info[b].sweep_bytes;
-            if (open && (live == 0 || live + need <= budget)) {
-                st.done = 0;
-                live += need;
-            } else {
-                open = false;  // strict order: later instances wait behind this one
-                st.done = 2;
-            }
-        }
+    const int t = threadIdx.x;
+    for (int off = 1; off < ACT_T; off <<= 1) {
+        int64_t a[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) a[q] = t >= off ? s[q][t - off] : 0;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) s[q][t] += a[q];
+        __syncthreads();
     }
-    int oK = 0, oT = 0;
-    int64_t cK = 0, cT = 0;
-    for (int b = 0; b < d.batch; ++b) {
-        const InstInfo &in = d.info[b];
-        d.act_off[2 * b] = oK;
-        d.act_off[2 * b + 1] = oT;
-        d.act_coff[2 * b] = cK;
-        d.act_coff[2 * b + 1] = cT;
-        if (!d.st[b].done) {
-            oK += in.blkK1 - in.blkK0;
-            oT += in.blkT1 - in.blkT0;
-            cK += d.bcumK[in.blkK1] - d.bcumK[in.blkK0];
-            cT += d.bcumT[in.blkT1] - d.bcumT[in.blkT0];
+}
+
+// Admission of waiting instances under the byte budget (first = 1 at the
+// start of a solve: instances beyond the budget start waiting).  Walking the
+// admission order, a candidate (running at the first call, waiting later)
+// is admitted while the running bytes plus the candidates' bytes before it
+// plus its own stay within the budget, and always when nothing runs and no
+// candidate precedes it: every instance needs some bytes, so the candidates
+// admitted are a prefix of the order, as a one-by-one walk that stops at
+// the first candidate that does not fit gives.
+__global__ __launch_bounds__(ACT_T) void k_act_admit(Dev d, int64_t budget, int first)
+{
+    __shared__ int64_t s[1][ACT_T];
+    const int t = threadIdx.x, B = d.batch;
+    int64_t lv = 0;
+    if (!first)
+        for (int b = t; b < B; b += ACT_T)
+            if (d.st[b].done == 0) lv += d.info[b].sweep_bytes;
+    s[0][t] = lv;
+    __syncthreads();
+    act_scan_lds<1>(s);
+    const int64_t live = s[0][ACT_T - 1];
+    __syncthreads();
+    int64_t carry = 0;
+    for (int k0 = 0; k0 < B; k0 += ACT_T) {
+        const int k = k0 + t;
+        int b = -1;
+        bool cand = false;
+        int64_t need = 0;
+        if (k < B) {
+            b = d.adm_order[k];
+            const int dn = d.st[b].done;
+            cand = first ? dn == 0 : dn == 2;
+            need = cand ? d.info[b].sweep_bytes : 0;
         }
+        s[0][t] = need;
+        __syncthreads();
+        act_scan_lds<1>(s);
+        const int64_t before = carry + s[0][t] - need;  // candidates' bytes ahead of this one
+        if (cand) d.st[b].done = ((live == 0 && before == 0) || live + before + need <= budget) ? 0 : 2;
+        carry += s[0][ACT_T - 1];
+        __syncthreads();
     }
-    d.act_cnt[0] = oK;
-    d.act_cnt[1] = oT;
-    d.act_coff[2 * d.batch] = cK;
-    d.act_coff[2 * d.batch + 1] = cT;
+}
+
+// ... then exclusive scans over the running instances' block counts and
+// costs in instance order ...
+__global__ __launch_bounds__(ACT_T) void k_act_scan(Dev d)
+{
+    __shared__ int64_t s[4][ACT_T];
+    const int t = threadIdx.x, B = d.batch;
+    int64_t carry[4] = {0, 0, 0, 0};
+    for (int b0 = 0; b0 < B; b0 += ACT_T) {
+        const int b = b0 + t;
+        int64_t v[4] = {0, 0, 0, 0};
+        if (b < B && d.st[b].done == 0) {
+            const InstInfo &in = d.info[b];
+            v[0] = in.blkK1 - in.blkK0;
+            v[1] = in.blkT1 - in.blkT0;
+            v[2] = d.bcumK[in.blkK1] - d.bcumK[in.blkK0];
+            v[3] = d.bcumT[in.blkT1] - d.bcumT[in.blkT0];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s[q][t] = v[q];
+        __syncthreads();
+        act_scan_lds<4>(s);
+        if (b < B) {
+            d.act_off[2 * b] = (int32_t)(carry[0] + s[0][t] - v[0]);
+            d.act_off[2 * b + 1] = (int32_t)(carry[1] + s[1][t] - v[1]);
+            d.act_coff[2 * b] = carry[2] + s[2][t] - v[2];
+            d.act_coff[2 * b + 1] = carry[3] + s[3][t] - v[3];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) carry[q] += s[q][ACT_T - 1];
+        __syncthreads();
+    }
+    if (t == 0) {
+        d.act_cnt[0] = (int32_t)carry[0];
+        d.act_cnt[1] = (int32_t)carry[1];
+        d.act_coff[2 * B] = carry[2];
+        d.act_coff[2 * B + 1] = carry[3];
+    }
 }
 
 // XCD boundaries of the sweeps' active lists: thread (op, x) finds the list
-// position where the running cost reaches x/8 of the total (instance by a
-// scan, block by bisection of the cost prefix sums).
+// position where the running cost reaches x/8 of the total: the instance by
+// bisection of the running-cost prefix (it rises only at running instances),
+// then the block by bisection of the blocks' cost prefix sums.
 __global__ void k_act_split(Dev d)
 {
     const int t = threadIdx.x;
@@ -988,24 +1042,30 @@ __global__ void k_act_split(Dev d)
         return;
     }
     const int64_t *cum = op == 0 ? d.bcumK : d.bcumT;
-    const int64_t total = d.act_coff[2 * d.batch + op];
+    const int B = d.batch;
+    const int64_t total = d.act_coff[2 * B + op];
     const int64_t target = total * x / 8;
+    // first instance whose running cost through itself exceeds the target
+    int lo = 0, hi = B;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (d.act_coff[2 * (mid + 1) + op] > target) hi = mid;
+        else lo = mid + 1;
+    }
     int pos = cnt;
-    for (int b = 0; b < d.batch; ++b) {
-        if (d.st[b].done) continue;
+    if (lo < B) {
+        const int b = lo;
         const InstInfo &in = d.info[b];
         const int b0 = op == 0 ? in.blkK0 : in.blkT0, b1 = op == 0 ? in.blkK1 : in.blkT1;
         const int64_t c0 = d.act_coff[2 * b + op];
-        if (target >= c0 + (cum[b1] - cum[b0])) continue;
         // largest k in [b0, b1) with cum[k] - cum[b0] <= target - c0
-        int lo = b0, hi = b1 - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (cum[mid] - cum[b0] <= target - c0) lo = mid;
-            else hi = mid - 1;
+        int l2 = b0, h2 = b1 - 1;
+        while (l2 < h2) {
+            const int mid = (l2 + h2 + 1) >> 1;
+            if (cum[mid] - cum[b0] <= target - c0) l2 = mid;
+            else h2 = mid - 1;
         }
-        pos = d.act_off[2 * b + op] + (lo - b0);
-        break;
+        pos = d.act_off[2 * b + op] + (l2 - b0);
     }
     sp[x] = pos;
 }
@@ -1570,7 +1630,8 @@ void launch_check64(const Dev &d, const double *xs, const double *ys, hipStream_
 
 void launch_active(const Dev &d, hipStream_t s, int64_t budget, int first)
 {
-    hipLaunchKernelGGL(k_act_scan, dim3(1), dim3(64), 0, s, d, budget, first);
+    if (budget > 0) hipLaunchKernelGGL(k_act_admit, dim3(1), dim3(ACT_T), 0, s, d, budget, first);
+    hipLaunchKernelGGL(k_act_scan, dim3(1), dim3(ACT_T), 0, s, d);
     const int64_t n = d.K.nblk > d.Kt.nblk ? d.K.nblk : d.Kt.nblk;
     LAUNCH(k_act_fill, nblk_elem(n), d);
     hipLaunchKernelGGL(k_act_split, dim3(1), dim3(64), 0, s, d);
