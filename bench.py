@@ -143,9 +143,10 @@ def _gen_batched(B, m_max):
     return out
 
 
-def bench_batched(args):
+def bench_batched(args, emit=True):
     """256 planted LPs (C3 recipe, m ~ U{1000..m_max}): one batched solve vs the
-    same LPs solved one at a time with the same library on the same GPU."""
+    same LPs solved one at a time with the same library on the same GPU.
+    Prints the JSON line (emit) and returns it."""
     import numpy as np
     import torch
 
@@ -208,7 +209,9 @@ def bench_batched(args):
                        "status": {k: sum(1 for r in rb if r["status_name"] == k) for k in set(r["status_name"] for r in rb)}},
            "one_by_one": {"seconds": ts, "lps_per_s": B / ts, "buckets": buckets},
            "speedup": ts / tb, "iterations_identical": same, "max_rel_obj_gap_vs_planted": max(gaps)}
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_adjoint(args):
@@ -364,6 +367,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance solve")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-vs-one-by-one leg of the default run (256 LPs, m <= 10,000)")
     ap.add_argument("--small", action="store_true", help="reduced SCED size (for profiling tests)")
     ap.add_argument("--no-tuning", action="store_true", help="default bins instead of the tuned ones")
     ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4"],
@@ -512,6 +517,21 @@ def main():
         print(f"[bench] fishnet 32 x 64: {tfn:.3f}s ({pts / tfn:.0f} point-iter/s), then solve to 1e-4 in "
               f"{tfs:.3f}s {rf['status_name']} iters={rf['iters']}", file=sys.stderr, flush=True)
 
+    # batched vs one-by-one LPs/s on 256 planted LPs with m <= 10,000 (the
+    # batched workload's small-m range; --workload c3 runs the full range)
+    batched = None
+    if not args.no_batched and not args.small:
+        s.close()
+        del s
+        ba = argparse.Namespace(batch=256, m_max=10000, resident_bytes=args.resident_bytes)
+        bo = bench_batched(ba, emit=False)
+        batched = {"workload": bo["config"]["workload"], "lps": 256,
+                   "batched_lps_per_s": bo["batched"]["lps_per_s"], "one_by_one_lps_per_s": bo["one_by_one"]["lps_per_s"],
+                   "speedup": bo["speedup"], "iterations_identical": bo["iterations_identical"],
+                   "max_rel_obj_gap_vs_planted": bo["max_rel_obj_gap_vs_planted"]}
+        print(f"[bench] batched vs one-by-one (256 LPs, m <= 10k): {batched['speedup']:.2f}x", file=sys.stderr,
+              flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(lp)
@@ -545,6 +565,7 @@ def main():
         "time_to_tol": ttt,
         "adaptive_step": adaptive,
         "fishnet": fish,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
