@@ -32,18 +32,24 @@ ERRORS = {-1: "INVALID_ARG", -2: "SHAPE", -3: "BOUNDS", -4: "NONFINITE", -5: "NO
 
 
 class PDHGError(RuntimeError):
+    """A negative status of the C-ABI (code) with the library's message."""
+
     def __init__(self, code: int, msg: str):
         super().__init__(f"PDHG_ERR_{ERRORS.get(code, code)}: {msg}")
         self.code = code
 
 
 class LPDesc(C.Structure):
+    """pdhg_lp: one LP in CSR form (pointers in memory space `mem`)."""
+
     _fields_ = [("n", C.c_int64), ("m", C.c_int64), ("nnz", C.c_int64), ("row_ptr", C.c_void_p),
                 ("col", C.c_void_p), ("val", C.c_void_p), ("c", C.c_void_p), ("rhs", C.c_void_p),
                 ("l", C.c_void_p), ("u", C.c_void_p), ("row_type", C.c_void_p), ("mem", C.c_int32)]
 
 
 class Opts(C.Structure):
+    """pdhg_opts (field meanings in include/pdhg.h)."""
+
     _fields_ = [("precision", C.c_int32), ("ruiz_iters", C.c_int32), ("use_restarts", C.c_int32),
                 ("use_pw_update", C.c_int32), ("check_every", C.c_int32),
                 ("power_max_iters", C.c_int32), ("max_iters", C.c_int64), ("eps", C.c_double),
@@ -59,12 +65,16 @@ class Opts(C.Structure):
 
 
 class TraceRec(C.Structure):
+    """pdhg_trace_rec: one check of pdhg_solve."""
+
     _fields_ = [("iter", C.c_int64), ("restarted", C.c_int32), ("cand_avg", C.c_int32), ("kkt_cand", C.c_double),
                 ("omega", C.c_double), ("rel_kkt_cur", C.c_double), ("rel_kkt_avg", C.c_double),
                 ("eta_next", C.c_double), ("accepted", C.c_int64)]
 
 
 class KKTOut(C.Structure):
+    """pdhg_kkt_out: relative KKT terms on the original LP."""
+
     _fields_ = [(k, C.c_double) for k in
                 ("pres", "dres", "pobj", "dobj", "gap", "rel_pres", "rel_dres", "rel_gap", "rel_kkt")]
 
@@ -73,6 +83,8 @@ class KKTOut(C.Structure):
 
 
 class Result(C.Structure):
+    """pdhg_result: status and counters of one instance's solve."""
+
     _fields_ = [("status", C.c_int32), ("from_avg", C.c_int32), ("iters", C.c_int64),
                 ("restarts", C.c_int32), ("power_iters", C.c_int32), ("knorm", C.c_double),
                 ("eta", C.c_double), ("omega0", C.c_double), ("omega", C.c_double),
@@ -87,6 +99,8 @@ class Result(C.Structure):
 
 
 class KernelTimes(C.Structure):
+    """pdhg_kernel_times: average device ms per launch of each phase."""
+
     _fields_ = [("ms_primal", C.c_double), ("ms_dual", C.c_double), ("ms_check", C.c_double),
                 ("ms_control", C.c_double), ("ms_restart", C.c_double), ("reps", C.c_int32),
                 ("ms_primal_ad", C.c_double), ("ms_dual_ad", C.c_double), ("ms_step_ad", C.c_double)]
@@ -96,6 +110,8 @@ class KernelTimes(C.Structure):
 
 
 class Info(C.Structure):
+    """pdhg_info: sizes, step parameters, layout and setup phases."""
+
     _fields_ = [("n", C.c_int64), ("m", C.c_int64), ("m_ineq", C.c_int64), ("nnz", C.c_int64),
                 ("knorm", C.c_double), ("eta", C.c_double), ("omega", C.c_double), ("tau", C.c_double),
                 ("sigma", C.c_double), ("setup_seconds", C.c_double), ("precision", C.c_int32),
@@ -158,6 +174,7 @@ def _check(rc: int):
 
 
 def default_opts(**kw) -> Opts:
+    """pdhg_default_opts with the given fields replaced (precision may be "f32" / "f64")."""
     o = Opts()
     lib().pdhg_default_opts(C.byref(o))
     for k, v in kw.items():
@@ -303,6 +320,7 @@ class Solver:
         del descs
 
     def close(self):
+        """pdhg_destroy (the workspace tensor is freed with the object)."""
         if getattr(self, "h", None) and self.h.value:
             lib().pdhg_destroy(self.h)
             self.h = None
@@ -323,11 +341,13 @@ class Solver:
         _check(lib().pdhg_set_opts(self.h, C.byref(self.opts)))
 
     def solve(self, stream=None) -> list:
+        """pdhg_solve: one result dict per instance."""
         res = (Result * self.batch)()
         _check(lib().pdhg_solve(self.h, C.cast(res, C.c_void_p), _stream(stream)))
         return [r.as_dict() for r in res]
 
     def iterate(self, k: int, record: bool = False, stream=None):
+        """pdhg_iterate: k fixed steps (recorded for backward when record)."""
         _check(lib().pdhg_iterate(self.h, int(k), int(bool(record)), _stream(stream)))
 
     def solution(self, inst: int = 0, which: int = SOL_RESULT, lam: bool = False, stream=None):
@@ -341,6 +361,7 @@ class Solver:
         return (x, y, la) if lam else (x, y)
 
     def set_state(self, x, y, inst: int = 0, stream=None):
+        """pdhg_set_state: the iterate of instance inst, original variables."""
         x = np.ascontiguousarray(x, dtype=np.float64)
         y = np.ascontiguousarray(y, dtype=np.float64)
         _check(lib().pdhg_set_state(self.h, inst, x.ctypes.data, y.ctypes.data, MEM_HOST, _stream(stream)))
@@ -352,6 +373,7 @@ class Solver:
         _check(lib().pdhg_set_data(self.h, *ptrs, MEM_HOST, _stream(stream)))
 
     def kkt(self, x, y, inst: int = 0, stream=None) -> dict:
+        """pdhg_kkt: FP64 relative KKT terms of a caller point (host arrays or CUDA tensors)."""
         if _is_torch_cuda(x):
             xp, yp, mem = x.data_ptr(), y.data_ptr(), MEM_DEVICE
         else:
@@ -422,6 +444,7 @@ class Solver:
         return [{k: getattr(r, k) for k, _ in TraceRec._fields_} for r in recs[:n]], int(total.value)
 
     def info(self) -> dict:
+        """pdhg_get_info as a dict."""
         i = Info()
         _check(lib().pdhg_get_info(self.h, C.byref(i)))
         return i.as_dict()
