@@ -132,3 +132,34 @@ def test_single_long_row(orc, pd, prec):
     assert orc.Oracle(lp).kkt(x, y)["rel_kkt"] <= 1.01 * eps
     assert r["kkt"]["pobj"] == pytest.approx(c[jmin], rel=10 * eps)
     assert y[0] == pytest.approx(c[jmin], rel=1e-3)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_batch_of_degenerate_shapes_equals_solo(pd, prec):
+    """A batch mixing an LP with no rows, a 1 x 1 LP, an LP whose rows are all
+    empty, one with an empty column and ordinary ones: the threaded setup
+    writes each instance's part of the shared images, and every instance
+    still gets bitwise its solo result."""
+    c = np.array([1.0, -2.0, 0.0, 3.0, -1.0])
+    lps = [
+        lpgen.from_dense(np.zeros((0, 5)), [], [], c, np.zeros(5), np.full(5, 2.0)),
+        lpgen.from_dense(np.array([[2.0]]), [0], [3.0], [1.0], [0.0], [10.0]),
+        lpgen.from_dense(np.zeros((3, 4)), [1, 0, 1], [0.0, -1.0, 0.0], [1.0, -1.0, 0.5, 0.0], np.zeros(4),
+                         np.full(4, 3.0)),
+        lpgen.from_dense(np.array([[1.0, 1.0, 0.0], [0.0, 1.0, 0.0]]), [1, 0], [1.0, 0.5], [1.0, 2.0, -1.0],
+                         np.zeros(3), np.full(3, 4.0)),
+        lpgen.planted(50, 120, 0.05, 3, ge_frac=0.5),
+        lpgen.tiny(7, n=6, m=3, free_frac=0.3),
+    ]
+    kw = dict(precision=prec, eps=1e-6, max_iters=200000)
+    for budget in (0, None):
+        b = pd.Solver(lps, **kw) if budget is None else pd.Solver(lps, batch_resident_bytes=budget, **kw)
+        rb = b.solve()
+        for i, lp in enumerate(lps):
+            s = pd.Solver(lp, **kw)
+            rs = s.solve()[0]
+            assert rb[i]["status"] == rs["status"] and rb[i]["iters"] == rs["iters"], (i, rb[i], rs)
+            xb, yb = b.solution(inst=i)
+            xs, ys = s.solution()
+            np.testing.assert_array_equal(xb, xs)
+            np.testing.assert_array_equal(yb, ys)
