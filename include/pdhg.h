@@ -399,6 +399,10 @@ void pdhg_destroy(pdhg_handle *h);
 /* Thread-local message for the last error ("" if none). */
 const char *pdhg_last_error(void);
 
+/* Thread-local status code (PDHG_ERR_*) of the last failure in the thread,
+ * PDHG_OK if none: the code behind a pdhg_workspace_bytes that returned 0. */
+int pdhg_last_error_code(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -129,7 +129,7 @@ EXPORTS = ["pdhg_default_opts", "pdhg_workspace_bytes", "pdhg_setup", "pdhg_iter
            "pdhg_get_solution", "pdhg_set_state", "pdhg_kkt", "pdhg_backward", "pdhg_get_scaling",
            "pdhg_get_info", "pdhg_time_kernels", "pdhg_set_opts", "pdhg_set_data",
            "pdhg_destroy", "pdhg_last_error", "pdhg_fishnet", "pdhg_fishnet_rounds", "pdhg_autotune",
-           "pdhg_get_trace"]
+           "pdhg_get_trace", "pdhg_last_error_code"]
 
 _lib = None
 
@@ -164,6 +164,7 @@ def lib():
         L.pdhg_get_trace.argtypes = [P, I32, P, I32, C.POINTER(C.c_int64), S]
         L.pdhg_destroy.argtypes = [P]
         L.pdhg_last_error.restype = C.c_char_p
+        L.pdhg_last_error_code.restype = C.c_int32
         _lib = L
     return _lib
 
@@ -309,7 +310,7 @@ class Solver:
         self.sizes = [(int(lp.n), int(lp.m)) for lp in lps]
         nbytes = L.pdhg_workspace_bytes(C.cast(arr, C.c_void_p), self.batch, C.byref(self.opts))
         if nbytes == 0:
-            raise PDHGError(-1, L.pdhg_last_error().decode())
+            raise PDHGError(L.pdhg_last_error_code(), L.pdhg_last_error().decode())
         self.device = torch.device(device)
         self.ws = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
         h = C.c_void_p()

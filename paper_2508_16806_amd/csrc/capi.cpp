@@ -30,6 +30,7 @@ using namespace pdhg;
 // ---------------------------------------------------------------------------
 
 static thread_local std::string g_err;
+static thread_local int g_err_code = PDHG_OK;
 
 static int fail(int code, const char *fmt, ...)
 {
@@ -39,6 +40,7 @@ static int fail(int code, const char *fmt, ...)
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
     g_err = buf;
+    g_err_code = code;
     return code;
 }
 
@@ -51,6 +53,8 @@ static int fail(int code, const char *fmt, ...)
     } while (0)
 
 extern "C" const char *pdhg_last_error(void) { return g_err.c_str(); }
+
+extern "C" int pdhg_last_error_code(void) { return g_err_code; }
 
 extern "C" void pdhg_default_opts(pdhg_opts *o)
 {

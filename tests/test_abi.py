@@ -116,6 +116,20 @@ def test_rejects_bounds_and_nonfinite(pd):
     assert _nbytes(pd, bad) == 0 and "bounds" in _err(pd)
 
 
+def test_last_error_code(pd):
+    """A sizing call that fails leaves its status code beside the message."""
+    lp = lpgen.config0(0)
+    bad = lpgen.config0(0)
+    bad.val = bad.val.copy()
+    bad.val[0] = np.nan
+    assert _nbytes(pd, bad) == 0 and pd.lib().pdhg_last_error_code() == -4
+    bad = lpgen.config0(0)
+    bad.l = bad.l.copy()
+    bad.l[0] = bad.u[0] + 1
+    assert _nbytes(pd, bad) == 0 and pd.lib().pdhg_last_error_code() == -3
+    assert _nbytes(pd, lp, check_every=0) == 0 and pd.lib().pdhg_last_error_code() == -1
+
+
 def test_rejects_bad_options(pd):
     lp = lpgen.config0(0)
     assert _nbytes(pd, lp, check_every=0) == 0 and "check_every" in _err(pd)
