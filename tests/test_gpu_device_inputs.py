@@ -92,3 +92,26 @@ def test_device_points_and_outputs(pd):
     s2.set_state(xh, yh)
     s2.iterate(1)
     np.testing.assert_array_equal(s.solution(which=pd.SOL_CURRENT)[0], s2.solution(which=pd.SOL_CURRENT)[0])
+
+
+def test_calls_on_a_side_stream(pd):
+    """Every call is ordered on the stream it is given: setup, solve, fixed
+    steps, solution and KKT on a created stream (default priority) give the
+    null stream's bits."""
+    import torch
+
+    lp = lpgen.planted(90, 230, 0.04, 6, ge_frac=0.5)
+    st = torch.cuda.Stream()
+    a = pd.Solver(lp, precision="f32", eps=1e-6, stream=st)
+    ra = a.solve(stream=st)[0]
+    a.iterate(7, stream=st)
+    xa, ya = a.solution(which=pd.SOL_CURRENT, stream=st)
+    ka = a.kkt(xa, ya, stream=st)
+    b = pd.Solver(lp, precision="f32", eps=1e-6)
+    rb = b.solve()[0]
+    b.iterate(7)
+    xb, yb = b.solution(which=pd.SOL_CURRENT)
+    assert ra["iters"] == rb["iters"] and ra["kkt"] == rb["kkt"]
+    np.testing.assert_array_equal(xa, xb)
+    np.testing.assert_array_equal(ya, yb)
+    assert ka == b.kkt(xb, yb)
