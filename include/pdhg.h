@@ -353,10 +353,16 @@ int pdhg_backward(pdhg_handle *h, const double *gx, const double *gy, double *gc
                   double *gl, double *gu, double *gx0, double *gy0, int32_t mem,
                   hipStream_t stream);
 
-/* Phase timers: launches each phase kernel `reps` times back to back on
- * `stream`, bracketed by HIP events, and reports the average time per launch.
- * The sweeps advance the iterate (fixed steps); solver counters are restored.
- * Synchronous. */
+/* Phase timers: average device time per launch of each phase kernel over
+ * `reps` launches on `stream`, from HIP events.  The two sweeps run
+ * alternately, primal then dual, with an event after each launch, as in the
+ * iteration (each finds the caches as the other leaves them); likewise the
+ * adaptive attempt's primal sweep, dual sweep and step decision.  The packet
+ * that each separating event adds is measured (the same sequence timed with
+ * events at its ends only) and taken out evenly.  The check,
+ * control and restart kernels, which run once per check interval, are timed
+ * back to back.  The sweeps advance the iterate (fixed steps); solver counters
+ * are restored.  Synchronous. */
 int pdhg_time_kernels(pdhg_handle *h, int32_t reps, pdhg_kernel_times *out, hipStream_t stream);
 
 /* Autotuner of the launch layout for `batch` LPs (lp as for pdhg_setup): times

@@ -1859,41 +1859,96 @@ static int time_impl(pdhg_handle *h, int32_t reps, pdhg_kernel_times *out, hipSt
     for (auto &x : st) x.done = 0;
     HIPCHK(hipMemcpyAsync(d.st, st.data(), h->batch * sizeof(InstState), hipMemcpyHostToDevice, s));
     launch_active(d, s);
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
+    // an event between every two launches, created up front
+    const int NE = 3 * reps + 1;
+    std::vector<hipEvent_t> ev(NE, nullptr);
+    int rc = PDHG_OK;
+    for (int k = 0; k < NE && !rc; ++k)
+        if (hipEventCreate(&ev[k]) != hipSuccess) rc = fail(PDHG_ERR_HIP, "hipEventCreate failed");
+    auto gap = [&](int k0, int k1) -> double {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, ev[k0], ev[k1]) != hipSuccess && !rc)
+            rc = fail(PDHG_ERR_HIP, "hipEventElapsedTime failed");
+        return (double)t;
+    };
     double ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     const CtlParams P = ctl_params(h);
-    for (int phase = 0; phase < 8; ++phase) {
+    // Times a sequence of `nk` kernels launched in turn, `reps` times, into
+    // out[0..nk).  An event after every launch separates the kernels but adds
+    // its own packet to each interval, so the same sequence also runs with
+    // events at its two ends only, and the excess of the separated total over
+    // that total is taken out evenly from the intervals.
+    auto time_seq = [&](int nk, auto &&launch, double *out) {
+        if (rc) return;
+        for (int k = 0; k < nk; ++k) launch(k, 0); // untimed, warms the caches
+        (void)hipEventRecord(ev[0], s);
+        for (int r = 0; r < reps; ++r)
+            for (int k = 0; k < nk; ++k) launch(k, r);
+        (void)hipEventRecord(ev[1], s);
+        (void)hipEventSynchronize(ev[1]);
+        const double whole = gap(0, 1);
+        (void)hipEventRecord(ev[0], s);
+        for (int r = 0; r < reps; ++r)
+            for (int k = 0; k < nk; ++k) {
+                launch(k, r);
+                (void)hipEventRecord(ev[nk * r + k + 1], s);
+            }
+        (void)hipEventSynchronize(ev[nk * reps]);
+        double sep = 0;
+        for (int k = 0; k < nk; ++k) out[k] = 0;
+        for (int r = 0; r < reps; ++r)
+            for (int k = 0; k < nk; ++k) {
+                const double t = gap(nk * r + k, nk * r + k + 1);
+                out[k] += t;
+                sep += t;
+            }
+        const double excess = sep > whole ? (sep - whole) / ((double)nk * reps) : 0.0;
+        for (int k = 0; k < nk; ++k) out[k] = std::max(0.0, out[k] / reps - excess);
+    };
+    // the two sweeps alternate as in the iteration (each one finds the caches
+    // as the other leaves them)
+    time_seq(2, [&](int k, int r) {
+        if (k == 0) launch_primal<T>(d, r, avg, nullptr, s);
+        else launch_dual<T>(d, r, avg, nullptr, s);
+    }, ms);
+    // once-per-chunk kernels, back to back
+    for (int phase = 2; phase < 5 && !rc; ++phase) {
         if (phase == 4 && !avg) continue;
-        if (phase == 5) launch_kx_ad<T>(d, 1, s);
-        HIPCHK(hipEventRecord(e0, s));
+        (void)hipEventRecord(ev[0], s);
         for (int r = 0; r < reps; ++r) {
             switch (phase) {
-                case 0: launch_primal<T>(d, r, avg, nullptr, s); break;
-                case 1: launch_dual<T>(d, r, avg, nullptr, s); break;
                 case 2: launch_check<T>(d, avg, s); break;
                 case 3: launch_control(d, P, 0, s); break;
-                case 4: launch_restart<T>(d, s); break;
-                case 5: launch_primal_ad<T>(d, s); break;
-                case 6: launch_dual_ad<T>(d, s); break;
-                default: launch_step_ad(d, s); break;
+                default: launch_restart<T>(d, s); break;
             }
         }
-        HIPCHK(hipEventRecord(e1, s));
-        HIPCHK(hipEventSynchronize(e1));
-        float t = 0.f;
-        HIPCHK(hipEventElapsedTime(&t, e0, e1));
-        ms[phase] = (double)t / reps;
-        if (phase == 3 || phase == 7) {
-            // the control kernel may have stopped an instance and the step
-            // kernel flips buffers: restore the state
-            HIPCHK(hipMemcpyAsync(d.st, st.data(), h->batch * sizeof(InstState), hipMemcpyHostToDevice, s));
+        (void)hipEventRecord(ev[1], s);
+        (void)hipEventSynchronize(ev[1]);
+        ms[phase] = gap(0, 1) / reps;
+        if (phase == 3) {
+            // the control kernel may have stopped an instance: restore the state
+            if (hipMemcpyAsync(d.st, st.data(), h->batch * sizeof(InstState), hipMemcpyHostToDevice, s) != hipSuccess)
+                rc = fail(PDHG_ERR_HIP, "state restore failed");
             launch_active(d, s);
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    // adaptive attempts: the primal sweep, the dual sweep and the step
+    // decision in turn, as the solve runs them
+    if (!rc) launch_kx_ad<T>(d, 1, s);
+    time_seq(3, [&](int k, int) {
+        if (k == 0) launch_primal_ad<T>(d, s);
+        else if (k == 1) launch_dual_ad<T>(d, s);
+        else launch_step_ad(d, s);
+    }, ms + 5);
+    if (!rc) {
+        // the step kernel flips buffers: restore the state
+        if (hipMemcpyAsync(d.st, st.data(), h->batch * sizeof(InstState), hipMemcpyHostToDevice, s) != hipSuccess)
+            rc = fail(PDHG_ERR_HIP, "state restore failed");
+        launch_active(d, s);
+    }
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (rc) return rc;
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
     out->ms_primal = ms[0];
