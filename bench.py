@@ -382,8 +382,8 @@ def main():
                     help="run plain 256 MiB device copies (counter calibration under rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of the "
-              f"PDHG path is a design note, not part of this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the PDHG path is not sharded over "
+              f"several GPUs; `--workload c2` times one GPU's 1/8 share of the large LP instead.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
