@@ -362,7 +362,8 @@ int pdhg_backward(pdhg_handle *h, const double *gx, const double *gy, double *gc
  * events at its ends only) and taken out evenly.  The check,
  * control and restart kernels, which run once per check interval, are timed
  * back to back.  The sweeps advance the iterate (fixed steps); solver counters
- * are restored.  Synchronous. */
+ * are restored.  1 <= reps <= 10000 (one event per launch is created),
+ * else PDHG_ERR_INVALID_ARG.  Synchronous. */
 int pdhg_time_kernels(pdhg_handle *h, int32_t reps, pdhg_kernel_times *out, hipStream_t stream);
 
 /* Autotuner of the launch layout for `batch` LPs (lp as for pdhg_setup): times

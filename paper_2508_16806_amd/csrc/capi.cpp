@@ -1965,7 +1965,7 @@ static int time_impl(pdhg_handle *h, int32_t reps, pdhg_kernel_times *out, hipSt
 
 extern "C" int pdhg_time_kernels(pdhg_handle *h, int32_t reps, pdhg_kernel_times *out, hipStream_t s)
 {
-    if (!h || !out || reps < 1) return fail(PDHG_ERR_INVALID_ARG, "bad arguments");
+    if (!h || !out || reps < 1 || reps > 10000) return fail(PDHG_ERR_INVALID_ARG, "bad arguments (1 <= reps <= 10000)");
     return h->prec == PDHG_PREC_F32 ? time_impl<float>(h, reps, out, s) : time_impl<double>(h, reps, out, s);
 }
 

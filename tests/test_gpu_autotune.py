@@ -97,3 +97,23 @@ def test_autotune_rejects_small_workspace(pd):
     rc = pd.lib().pdhg_autotune(C.cast(arr, C.c_void_p), 1, C.byref(o), ws.data_ptr(), need - 256, C.byref(got),
                                 1, None, C.byref(best), None)
     assert rc == pd.ERR_NOMEM and got.value == need
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_time_kernels_figures_and_bounds(pd, prec):
+    """The phase timers the search ranks layouts by: every figure is a finite,
+    positive time (the restart kernel runs, restarts being on), the call
+    reports its repetitions, and repetitions outside 1..10000 are refused."""
+    lp = lpgen.planted(300, 700, 0.02, 4, ge_frac=0.5)
+    s = pd.Solver(lp, precision=prec)
+    t = s.time_kernels(reps=3)
+    assert t["reps"] == 3
+    for k, v in t.items():
+        if k.startswith("ms_"):
+            assert np.isfinite(v) and v > 0, (k, v)
+    for bad in (0, -1, 10001):
+        with pytest.raises(pd.PDHGError):
+            s.time_kernels(reps=bad)
+    # the handle still solves after the timers (solver counters restored)
+    r = s.solve()[0]
+    assert r["status_name"] == "OPTIMAL"
