@@ -46,7 +46,7 @@ __global__ __launch_bounds__(WG) void k_primal(Dev d, int j_in_chunk, uint8_t *_
     const T *__restrict__ y = (const T *)d.y;
     const int cnt = d.act_cnt[1];
     const bool full = cnt == op.nblk;  // every block active: the list is the identity
-    for_each_item_split(cnt, d.remap, d.act_split + 9, [&](int it) {
+    for_each_item_split(cnt, d.remap, d.act_split + 9, j_in_chunk & 1, [&](int it) {
         const int lb = full ? it : d.actT[it];
         const Seg s = block_seg(op, lb);
         const InstState *st = d.st + s.inst;
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(WG) void k_dual(Dev d, int j_in_chunk, uint8_t *__r
     const T *__restrict__ xb = (const T *)d.xbar;
     const int cnt = d.act_cnt[0];
     const bool full = cnt == op.nblk;
-    for_each_item_split(cnt, d.remap, d.act_split, [&](int it) {
+    for_each_item_split(cnt, d.remap, d.act_split, j_in_chunk & 1, [&](int it) {
         const int lb = full ? it : d.actK[it];
         const Seg s = block_seg(op, lb);
         const InstState *st = d.st + s.inst;
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(WG) void k_primal_ad(Dev d)
     const T *__restrict__ u = (const T *)d.u;
     const int cnt = d.act_cnt[1];
     const bool full = cnt == op.nblk;
-    for_each_item_split(cnt, d.remap, d.act_split + 9, [&](int it) {
+    for_each_item_split(cnt, d.remap, d.act_split + 9, 0, [&](int it) {
         const int lb = full ? it : d.actT[it];
         const Seg s = block_seg(op, lb);
         const InstState *st = d.st + s.inst;
@@ -238,7 +238,7 @@ __global__ __launch_bounds__(WG) void k_dual_ad(Dev d)
     const T *__restrict__ q = (const T *)d.q;
     const int cnt = d.act_cnt[0];
     const bool full = cnt == op.nblk;
-    for_each_item_split(cnt, d.remap, d.act_split, [&](int it) {
+    for_each_item_split(cnt, d.remap, d.act_split, 0, [&](int it) {
         const int lb = full ? it : d.actK[it];
         const Seg s = block_seg(op, lb);
         const InstState *st = d.st + s.inst;
