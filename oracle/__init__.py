@@ -27,14 +27,17 @@ _SRC = os.path.join(_HERE, "pdhg_oracle.c")
 _LIB = os.path.join(_HERE, "liborc.so")
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain IEEE double; x86-64 without FMA)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
+def build(force: bool = True, src: str = _SRC, out: str = _LIB) -> str:
+    """Compile the oracle with gcc (plain IEEE double; x86-64 without FMA).
+
+    ``src`` / ``out`` default to this package's source and library; the tests
+    that plant a mistake in a copy of the source build that copy elsewhere."""
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(src):
+        tmp = out + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-                               "-fno-fast-math", "-ffp-contract=off", _SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+                               "-fno-fast-math", "-ffp-contract=off", src, "-o", tmp, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 class KKT(C.Structure):
@@ -74,18 +77,24 @@ class Result(C.Structure):
 class TraceRec(C.Structure):
     _fields_ = [("iter", C.c_longlong), ("restarted", C.c_int), ("cand_avg", C.c_int),
                 ("kkt_cand", C.c_double), ("omega", C.c_double), ("rel_kkt_cur", C.c_double),
-                ("rel_kkt_avg", C.c_double), ("eta_next", C.c_double), ("accepted", C.c_longlong)]
+                ("rel_kkt_avg", C.c_double), ("eta_next", C.c_double), ("accepted", C.c_longlong),
+                ("t_inner", C.c_longlong), ("kkt0", C.c_double), ("kkt_prev", C.c_double),
+                ("omega_before", C.c_double), ("delta_x", C.c_double), ("delta_y", C.c_double),
+                ("kkt0_next", C.c_double), ("cand_pres", C.c_double), ("cand_dres", C.c_double),
+                ("cand_gap", C.c_double)]
 
 
 _lib = None
 
 
-def _load():
+def _load(path: Optional[str] = None):
+    """The oracle library with its signatures declared (``path``: a library
+    built from a copy of the source, loaded beside this package's own)."""
     global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
+    if path is not None or _lib is None:
+        if path is None and not os.path.exists(_LIB):
             build()
-        L = C.CDLL(_LIB)
+        L = C.CDLL(path or _LIB)
         P = C.c_void_p
         D = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
         I64 = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
@@ -119,6 +128,8 @@ def _load():
                                    C.c_longlong, D, D]
         L.orc_unrolled_vjp.argtypes = [P, D, D, C.c_double, C.c_double, D, D, D, D, D, D,
                                        C.c_longlong, D, D, D, D, D, D, D, D]
+        if path is not None:
+            return L
         _lib = L
     return _lib
 
@@ -198,8 +209,8 @@ class SolveResult:
 class Oracle:
     """An LP loaded into the oracle (rows reordered to [G; A] internally)."""
 
-    def __init__(self, lp):
-        self.lib = _load()
+    def __init__(self, lp, lib=None):
+        self.lib = lib if lib is not None else _load()
         self.lp = lp
         rt = np.asarray(lp.row_type)
         ge = np.nonzero(rt == 0)[0]
@@ -290,10 +301,7 @@ class Oracle:
         self.lib.orc_solve_from(self.h, C.byref(opts.c()), None if xs is None else xs.ctypes.data,
                                 None if ys is None else ys.ctypes.data, x, y, C.byref(r),
                                 C.cast(tr, C.c_void_p), trace_cap)
-        trace = [dict(iter=t.iter, restarted=t.restarted, cand_avg=t.cand_avg,
-                      kkt_cand=t.kkt_cand, omega=t.omega, rel_kkt_cur=t.rel_kkt_cur,
-                      rel_kkt_avg=t.rel_kkt_avg, eta_next=t.eta_next, accepted=t.accepted)
-                 for t in tr[:r.trace_len]]
+        trace = [{k: getattr(t, k) for k, _ in TraceRec._fields_} for t in tr[:r.trace_len]]
         return SolveResult(r.status, x, self.to_user_rows(y), r.iters, r.restarts, bool(r.from_avg),
                            r.knorm, r.eta, r.omega0, r.omega, r.kkt.as_dict(), r.power_iters, trace,
                            r.accepted, r.eta_next)

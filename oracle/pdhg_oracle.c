@@ -691,7 +691,8 @@ typedef struct {
     double eta_next;       /* step the next attempt would try                  */
 } orc_result;
 
-/* one restart (or check) record */
+/* one restart (or check) record: the inputs of the Section 2.4.2 decision
+ * and what it changed */
 typedef struct {
     long long iter;        /* total iterations at the check                    */
     int restarted;         /* 1 when a restart happened at this check          */
@@ -701,6 +702,13 @@ typedef struct {
     double rel_kkt_cur, rel_kkt_avg;
     double eta_next;       /* step the next attempt would try                  */
     long long accepted;    /* accepted steps so far                            */
+    long long t_inner;     /* iterations of the epoch at the check             */
+    double kkt0;           /* epoch reference KKT_omega(z_n^0) at the check    */
+    double kkt_prev;       /* previous candidate's KKT_omega (inf at epoch start) */
+    double omega_before;   /* primal weight the check's metrics use            */
+    double delta_x, delta_y; /* ||x^ - x_n^0||, ||y^ - y_n^0|| (scaled; restarts) */
+    double kkt0_next;      /* reference value after the check                  */
+    double cand_pres, cand_dres, cand_gap; /* candidate's scaled-LP KKT terms  */
 } orc_trace_rec;
 
 /* Solves the LP (rows already ordered [G; A]).  x_out / y_out receive the
@@ -846,9 +854,12 @@ int orc_solve_from(const orc_prob *p, const orc_opts *o, const double *x_start, 
         double kw_cand = cand_avg ? kw_a : kw_c;
         const orc_kkt_t *k_cand = cand_avg ? &ka : &kc;
         const orc_kkt_t *k_other = cand_avg ? &kc : &ka;
+        const orc_kkt_t *ks_cand = cand_avg ? &ksa : &ksc;
         orc_trace_rec rec = {k_total, 0, cand_avg, kw_cand, omega, kc.rel_kkt,
                              o->use_restarts ? ka.rel_kkt : INFINITY,
-                             o->adaptive_step ? eta_try : eta, n_acc};
+                             o->adaptive_step ? eta_try : eta, n_acc,
+                             t_inner, kkt0, kkt_prev, omega, 0.0, 0.0, kkt0,
+                             ks_cand->pres, ks_cand->dres, ks_cand->gap};
 
         /* termination (Section 2.3.2): candidate first, then the other point */
         if (k_cand->rel_kkt <= o->eps) {
@@ -912,7 +923,9 @@ int orc_solve_from(const orc_prob *p, const orc_opts *o, const double *x_start, 
                 if (o->use_pw_update && dx > o->eps_zero && dy > o->eps_zero)
                     omega = exp(0.5 * log(dy / dx) + 0.5 * log(omega));
                 /* the new epoch's reference value is the candidate's metric at the new omega */
-                kkt0 = kkt_omega(cand_avg ? &ksa : &ksc, omega);
+                kkt0 = kkt_omega(ks_cand, omega);
+                rec.delta_x = dx;
+                rec.delta_y = dy;
                 kkt_prev = INFINITY;
                 t_inner = 0;
                 wsum = 0.0;
@@ -924,6 +937,7 @@ int orc_solve_from(const orc_prob *p, const orc_opts *o, const double *x_start, 
             } else {
                 kkt_prev = kw_cand;
             }
+            rec.kkt0_next = kkt0;
         }
         if (trace && tl < trace_cap) trace[tl++] = rec;
     }

@@ -6,6 +6,7 @@ brute-force vertex enumeration, a planted optimal pair (Section 2.2 duality),
 hand-derived fixtures under tests/golden/, or inequalities proved in
 Appendix D (boundedness and the ergodic gap bound).
 """
+import ctypes
 import json
 import os
 
@@ -335,33 +336,134 @@ def test_solve_small_sced_matches_highs(orc):
     assert _rel(r.kkt["pobj"], h.fun) < 1e-5
 
 
-def test_solve_restart_trace_properties(orc):
-    """Restarts fire only when a Section 2.4.2 criterion holds; omega moves only at restarts."""
-    lp = lpgen.planted(200, 500, 0.02, 8, ge_frac=0.3)
-    o = orc.Oracle(lp)
-    opts = orc.SolveOpts(eps=1e-7)
+def _kkt_w(pres, dres, gap, w):
+    """KKT_omega of Section 2.4.2 from a point's scaled-LP terms."""
+    return np.sqrt(w * w * pres * pres + dres * dres / (w * w) + gap * gap)
+
+
+def _assert_restart_rule(tr, omega0, kkt0_start, bs=0.2, bn=0.8, ba=0.36, eps_zero=1e-6):
+    """Every check of a trace follows Section 2.4.2 and Algorithm 4.
+
+    The epoch reference, the previous candidate, the epoch length and the
+    primal weight are tracked here from the trace itself (not read from the
+    solver's state), so a solver that keeps any of them wrongly disagrees with
+    its own records.  Returns how often each criterion decided a restart.
+    """
+    omega, kkt0, prev, last_restart = omega0, kkt0_start, np.inf, 0
+    fired = {"sufficient": 0, "necessary": 0, "artificial": 0, "none": 0}
+    for i, t in enumerate(tr):
+        assert t["omega_before"] == omega
+        assert t["kkt0"] == pytest.approx(kkt0, rel=1e-14)
+        assert t["kkt_prev"] == prev
+        assert t["t_inner"] == t["iter"] - last_restart
+        kc = t["kkt_cand"]
+        assert kc == pytest.approx(_kkt_w(t["cand_pres"], t["cand_dres"], t["cand_gap"], omega), rel=1e-13)
+        if i == len(tr) - 1:
+            break  # the terminating check makes no restart decision
+        suff = kc <= bs * kkt0
+        nec = kc <= bn * kkt0 and kc > prev
+        art = t["t_inner"] > ba * t["iter"]
+        assert t["restarted"] == int(suff or nec or art), (i, t, suff, nec, art)
+        if not t["restarted"]:
+            fired["none"] += 1
+            assert t["omega"] == omega and t["kkt0_next"] == kkt0
+            prev = kc
+            continue
+        for name, f in (("sufficient", suff), ("necessary", nec), ("artificial", art)):
+            fired[name] += f
+        dx, dy = t["delta_x"], t["delta_y"]
+        if dx > eps_zero and dy > eps_zero:
+            want = np.exp(0.5 * np.log(dy / dx) + 0.5 * np.log(omega))
+            assert t["omega"] == pytest.approx(want, rel=1e-14)
+        else:
+            assert t["omega"] == omega
+        omega = t["omega"]
+        # the new epoch's reference: the candidate's KKT_omega at the NEW omega (reading R10)
+        kkt0 = _kkt_w(t["cand_pres"], t["cand_dres"], t["cand_gap"], omega)
+        assert t["kkt0_next"] == pytest.approx(kkt0, rel=1e-13)
+        prev, last_restart = np.inf, t["iter"]
+    return fired
+
+
+def _start_kkt_w(o, opts, omega0):
+    from oracle import KKT as _KKTStruct
+
+    """KKT_omega of the starting point (proj_X(0), 0) on the scaled LP."""
+    s = o.scaled(opts.ruiz_iters)
+    x = np.clip(np.zeros(o.n), o.l / s.kap, o.u / s.kap)
+    k = _KKTStruct()
+    o.lib.orc_kkt(s.h, x, np.zeros(o.m), ctypes.byref(k))
+    return _kkt_w(k.pres, k.dres, k.gap, omega0)
+
+
+RESTART_CASES = {"mixed": lambda: lpgen.planted(200, 500, 0.02, 8, ge_frac=0.3),
+                 "c0u": lambda: lpgen.config0(3, unique=True),
+                 "sced": lambda: lpgen.sced(20, 8, 6, 6, seed=2)}
+
+
+def check_restart_properties(orc, case, lib=None):
+    """Solves RESTART_CASES[case] to 1e-7 and checks every check of its trace
+    with _assert_restart_rule (``lib``: an oracle library built elsewhere)."""
+    lp = RESTART_CASES[case]()
+    o = orc.Oracle(lp, lib=lib)
+    opts = orc.SolveOpts(eps=1e-7, max_iters=200000)
     r = o.solve(opts)
     assert r.status == 0 and r.restarts > 0
-    tr = r.trace
-    omega = r.omega0
-    kkt0 = None
-    prev = np.inf
-    for i, t in enumerate(tr):
-        if not t["restarted"]:
-            assert t["omega"] == omega
-            prev = t["kkt_cand"]
-            continue
-        art = True  # the long-inner-loop rule needs the epoch length; checked below
-        if kkt0 is not None:
-            suff = t["kkt_cand"] <= 0.2 * kkt0
-            nec = t["kkt_cand"] <= 0.8 * kkt0 and t["kkt_cand"] > prev
-            last = max([0] + [u["iter"] for u in tr[:i] if u["restarted"]])
-            art = (t["iter"] - last) > 0.36 * t["iter"]
-            assert suff or nec or art
-        omega = t["omega"]
-        kkt0 = None  # recomputed at the new omega inside the solver; not observable here
-        prev = np.inf
-    assert tr[0]["restarted"] == 1  # first check: t_inner = k_total > 0.36 k_total
+    fired = _assert_restart_rule(r.trace, r.omega0, _start_kkt_w(o, opts, r.omega0))
+    assert r.trace[0]["restarted"] == 1  # first check: t_inner = k_total > 0.36 k_total
+    assert sum(t["restarted"] for t in r.trace) == r.restarts
+    return fired
+
+
+def check_golden_1x1(orc, lib=None):
+    """The oracle's trace on the 1 x 1 LP of tests/golden/restart_1x1.py
+    against the stored hand derivation; returns the restart kinds seen."""
+    g = json.load(open(os.path.join(GOLD, "restart_trace_1x1.json")))
+    lp = lpgen.from_dense(np.array(g["lp"]["K"]), g["lp"]["row_type"], g["lp"]["q"], g["lp"]["c"],
+                          np.array(g["lp"]["l"]), np.array([np.inf]))
+    o = orc.Oracle(lp, lib=lib)
+    opts = orc.SolveOpts(eps=g["opts"]["eps"], check_every=g["opts"]["check_every"],
+                         ruiz_iters=g["opts"]["ruiz_iters"])
+    r = o.solve(opts)
+    assert r.eta == g["opts"]["eta"] and r.omega0 == g["opts"]["omega0"]
+    assert r.status == 0
+    want = g["checks"]
+    assert len(r.trace) == len(want)
+    kinds = set()
+    for t, w in zip(r.trace, want):
+        assert t["iter"] == w["iter"] and t["t_inner"] == w["t_inner"]
+        assert t["restarted"] == w["restarted"] and t["cand_avg"] == w["cand_avg"], (t, w)
+        for k in ("kkt_cand", "kkt0", "omega_before", "omega", "kkt0_next", "rel_kkt_cur", "rel_kkt_avg",
+                  "delta_x", "delta_y"):
+            assert t[k] == pytest.approx(w[k], rel=1e-9, abs=1e-300), (k, t, w)
+        wp = np.inf if w["kkt_prev"] == "inf" else w["kkt_prev"]
+        assert t["kkt_prev"] == pytest.approx(wp, rel=1e-9)
+        if w["restarted"] and len(w["criteria"]) == 1:
+            kinds.add(w["criteria"][0])
+    assert r.iters == want[-1]["iter"] and r.restarts == sum(w["restarted"] for w in want)
+    # the start (0, 0) has pres = 4, dres = 0, gap = 0: KKT_omega0 = 0.75 * 4 = 3
+    _assert_restart_rule(r.trace, r.omega0, 3.0)
+    return kinds
+
+
+@pytest.mark.parametrize("case", sorted(RESTART_CASES))
+def test_solve_restart_trace_properties(orc, case):
+    """At every check the restart decision is exactly (sufficient decay) or
+    (necessary decay and no progress) or (long inner loop) with 0.2 / 0.8 /
+    0.36 (Section 2.4.2); omega moves only at restarts, by Algorithm 4; the
+    new epoch's reference is the candidate's metric at the new omega."""
+    fired = check_restart_properties(orc, case)
+    # the trace exercises more than the artificial rule and has checks without a restart
+    assert fired["sufficient"] + fired["necessary"] > 0 and fired["none"] > 0, fired
+
+
+def test_restart_trace_1x1_golden(orc):
+    """The oracle's check-by-check trace on a 1 x 1 LP equals the trace derived
+    by hand from Section 2.4.2 and Algorithm 4 (tests/golden/restart_1x1.py,
+    60-digit arithmetic): the same restart decisions and candidates at every
+    check, every kind of restart present, and the KKT_omega values, the
+    reference values and omega to 1e-9."""
+    assert check_golden_1x1(orc) == {"sufficient", "necessary", "artificial"}
 
 
 def test_solve_zero_rows_closed_form(orc):
