@@ -209,7 +209,8 @@ typedef struct {
 } pdhg_result;
 
 /* One check of pdhg_solve (Sections 2.3.2 and 2.4.2): written after the
- * restart / primal-weight / termination decision of that check. */
+ * restart / primal-weight / termination decision of that check, with the
+ * inputs of that decision (KKT_omega values are on the scaled LP). */
 typedef struct {
     int64_t iter;         /* iterations (attempts) of the solve at the check      */
     int32_t restarted;    /* a restart happened at this check                     */
@@ -220,6 +221,16 @@ typedef struct {
     double rel_kkt_avg;   /* of the average (+inf without restarts)               */
     double eta_next;      /* step of the next attempt                             */
     int64_t accepted;     /* accepted steps so far                                */
+    int64_t t_inner;      /* iterations of the restart epoch at the check         */
+    double kkt0;          /* the epoch's reference KKT_omega(z_n^0) at the check  */
+    double kkt_prev;      /* previous candidate's KKT_omega (+inf at epoch start) */
+    double omega_before;  /* primal weight of the check's metrics                 */
+    double delta_x;       /* on restart: ||x^ - x_n^0||, scaled (0 otherwise)     */
+    double delta_y;       /* on restart: ||y^ - y_n^0||, scaled (0 otherwise)     */
+    double kkt0_next;     /* the reference after the check (new on restart)       */
+    double cand_pres;     /* candidate's primal residual, scaled LP               */
+    double cand_dres;     /* candidate's dual residual, scaled LP                 */
+    double cand_gap;      /* candidate's |dobj - pobj|, scaled LP                 */
 } pdhg_trace_rec;
 
 typedef struct {
@@ -236,6 +247,11 @@ typedef struct {
     double setup_plan_seconds, setup_host_seconds, setup_copy_seconds, setup_device_seconds;
     double setup_power_seconds;     /* the power iteration's part of the device work */
     int32_t power_iters_max;        /* most power iterations of any instance        */
+    int32_t record_valid;           /* pdhg_backward has a tape for the current data */
+    int64_t record_generation;      /* bumped by each recording pdhg_iterate and each
+                                     * pdhg_set_data: a caller that keeps the value
+                                     * from its recording call can tell whether the
+                                     * tape is still the one it recorded           */
 } pdhg_info;
 
 /* Average device time per launch of each phase kernel (milliseconds). */
@@ -243,8 +259,10 @@ typedef struct {
     double ms_primal;   /* fused K~^T y sweep + primal update + averaging      */
     double ms_dual;     /* fused K~ xbar sweep + dual update + averaging       */
     double ms_check;    /* FP64 KKT partial sums of iterate and average        */
-    double ms_control;  /* per-instance reduction + restart / stop decisions  */
-    double ms_restart;  /* restart copy (0 when restarts are off)              */
+    double ms_control;  /* per-instance reduction + restart / stop decisions,
+                         * timed on a check that restarts (omega update)      */
+    double ms_restart;  /* restart copy of every running instance's candidate
+                         * (0 when restarts are off)                          */
     int32_t reps;
     double ms_primal_ad; /* adaptive step: K~^T y sweep + candidate x' + sums   */
     double ms_dual_ad;   /* adaptive step: K~ x' sweep + candidate y' + sums    */
@@ -308,7 +326,9 @@ int pdhg_set_state(pdhg_handle *h, int32_t inst, const double *x, const double *
 /* Replaces the cost, right-hand side and bounds of every instance (arrays
  * concatenated over the batch in the caller's layout; NULL keeps a vector).
  * The matrix, the Ruiz factors and the step parameters stay those of setup.
- * Host arrays are validated like pdhg_setup's; device arrays are trusted. */
+ * Host arrays are validated like pdhg_setup's; device arrays are trusted.
+ * Once the arrays pass validation the recorded tape of pdhg_iterate is
+ * dropped (pdhg_backward then fails with PDHG_ERR_STATE). */
 int pdhg_set_data(pdhg_handle *h, const double *c, const double *rhs, const double *l, const double *u,
                   int32_t mem, hipStream_t stream);
 
@@ -348,7 +368,10 @@ int pdhg_kkt(pdhg_handle *h, int32_t inst, const double *x, const double *y, int
  * batch, y parts in caller row order), writes dL/dc, dL/drhs, dL/dl, dL/du,
  * dL/dx_0 and dL/dy_0 in the original variables (tau, sigma and the Ruiz
  * factors are constants).  Output pointers may be NULL.  The replay uses the
- * checkpoints stored every unroll_checkpoint steps. */
+ * checkpoints stored every unroll_checkpoint steps.  PDHG_ERR_STATE when no
+ * recording pdhg_iterate ran since setup or since the last pdhg_set_data
+ * (the tape would replay against other data); pdhg_info.record_generation
+ * tells a caller whether a later recording call replaced its tape. */
 int pdhg_backward(pdhg_handle *h, const double *gx, const double *gy, double *gc, double *grhs,
                   double *gl, double *gu, double *gx0, double *gy0, int32_t mem,
                   hipStream_t stream);

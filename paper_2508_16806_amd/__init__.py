@@ -27,6 +27,7 @@ SOL_RESULT, SOL_CURRENT, SOL_AVERAGE = 0, 1, 2
 STATUS = {0: "OPTIMAL", 1: "ITERATION_LIMIT", 2: "TIME_LIMIT", 3: "NUMERICAL_ERROR", 4: "PRIMAL_INFEASIBLE",
           5: "DUAL_INFEASIBLE"}
 ERR_NOMEM = -5
+PDHG_ERR_STATE = -7
 ERRORS = {-1: "INVALID_ARG", -2: "SHAPE", -3: "BOUNDS", -4: "NONFINITE", -5: "NOMEM", -6: "HIP",
           -7: "STATE"}
 
@@ -69,7 +70,10 @@ class TraceRec(C.Structure):
 
     _fields_ = [("iter", C.c_int64), ("restarted", C.c_int32), ("cand_avg", C.c_int32), ("kkt_cand", C.c_double),
                 ("omega", C.c_double), ("rel_kkt_cur", C.c_double), ("rel_kkt_avg", C.c_double),
-                ("eta_next", C.c_double), ("accepted", C.c_int64)]
+                ("eta_next", C.c_double), ("accepted", C.c_int64), ("t_inner", C.c_int64),
+                ("kkt0", C.c_double), ("kkt_prev", C.c_double), ("omega_before", C.c_double),
+                ("delta_x", C.c_double), ("delta_y", C.c_double), ("kkt0_next", C.c_double),
+                ("cand_pres", C.c_double), ("cand_dres", C.c_double), ("cand_gap", C.c_double)]
 
 
 class KKTOut(C.Structure):
@@ -119,7 +123,8 @@ class Info(C.Structure):
                 ("nseg_dual", C.c_int32), ("nblk_primal", C.c_int64), ("nblk_dual", C.c_int64),
                 ("setup_plan_seconds", C.c_double), ("setup_host_seconds", C.c_double),
                 ("setup_copy_seconds", C.c_double), ("setup_device_seconds", C.c_double),
-                ("setup_power_seconds", C.c_double), ("power_iters_max", C.c_int32)]
+                ("setup_power_seconds", C.c_double), ("power_iters_max", C.c_int32),
+                ("record_valid", C.c_int32), ("record_generation", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -308,12 +313,12 @@ class Solver:
         descs = [_Desc(lp) for lp in lps]
         arr = (LPDesc * self.batch)(*[d.desc for d in descs])
         self.sizes = [(int(lp.n), int(lp.m)) for lp in lps]
+        self.device = torch.device(device)
+        h = C.c_void_p()
         nbytes = L.pdhg_workspace_bytes(C.cast(arr, C.c_void_p), self.batch, C.byref(self.opts))
         if nbytes == 0:
             raise PDHGError(L.pdhg_last_error_code(), L.pdhg_last_error().decode())
-        self.device = torch.device(device)
         self.ws = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
-        h = C.c_void_p()
         with torch.cuda.device(self.device):
             _check(L.pdhg_setup(C.cast(arr, C.c_void_p), self.batch, C.byref(self.opts), self.ws.data_ptr(),
                                 int(nbytes), _stream(stream), C.byref(h)))

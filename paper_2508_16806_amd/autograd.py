@@ -7,6 +7,8 @@ instance at (x0, y0) (pdhg_set_state), and runs K recorded fixed-step
 iterations (pdhg_iterate with record = 1: checkpoints every
 opts.unroll_checkpoint steps).  Backward: pdhg_backward replays each
 checkpoint segment with the clip masks and runs the reverse steps on the GPU.
+A handle keeps one tape: backward raises PDHGError (PDHG_ERR_STATE) when a
+later forward call or set_data on the same handle has replaced it.
 
 All tensors are FP64 and concatenated over the solver's batch (the y parts in
 the caller's row order).  tau, sigma and the Ruiz factors are constants of
@@ -18,7 +20,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import SOL_CURRENT
+from . import PDHG_ERR_STATE, SOL_CURRENT, PDHGError
 
 
 def _np(t):
@@ -36,6 +38,7 @@ class PDHGUnroll(torch.autograd.Function):
             xo += n
             yo += m
         solver.iterate(int(K), record=True)
+        ctx.generation = solver.info()["record_generation"]
         xk, yk = [], []
         for i in range(solver.batch):
             x, y = solver.solution(inst=i, which=SOL_CURRENT)
@@ -48,6 +51,10 @@ class PDHGUnroll(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gx, gy):
         s = ctx.solver
+        if s.info()["record_generation"] != ctx.generation:
+            # another forward (or new data) replaced this call's tape in the handle
+            raise PDHGError(PDHG_ERR_STATE, "the handle's recorded steps are no longer those of this "
+                            "forward call (a later forward or set_data replaced them)")
         nt = sum(n for n, _ in s.sizes)
         mt = sum(m for _, m in s.sizes)
         gxn = np.zeros(nt) if gx is None else _np(gx)

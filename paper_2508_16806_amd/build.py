@@ -1,4 +1,7 @@
-"""Build step for libpdhg.so (gfx950) -- run by __graft_entry__.build()."""
+"""Build step for libpdhg.so (gfx950) -- run by __graft_entry__.build().
+
+Each source is compiled to an object by its own hipcc process (in parallel),
+then the objects are linked into the shared library."""
 import os
 import subprocess
 import sys
@@ -10,10 +13,11 @@ LIB = os.path.join(HERE, "libpdhg.so")
 SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "fishnet.hip", "capi.cpp")]
 HEADERS = [os.path.join(CSRC, f) for f in ("pdhg_internal.h", "sweep.h", "kernels.h")] + \
     [os.path.join(ROOT, "include", "pdhg.h")]
+OBJDIR = os.path.join(HERE, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no packed-FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
@@ -21,14 +25,33 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
+    os.makedirs(OBJDIR, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include")]
+    objs, procs = [], []
+    for src in SOURCES:
+        obj = os.path.join(OBJDIR, os.path.splitext(os.path.basename(src))[0] + ".o")
+        lang = [] if src.endswith(".hip") else ["-x", "hip"]
+        cmd = [HIPCC] + FLAGS + inc + ["-c"] + lang + [src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+        objs.append(obj)
+    failed = False
+    for src, p in procs:
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            sys.stderr.write(out)
+            failed = True
+    if failed:
+        raise RuntimeError("hipcc failed compiling libpdhg sources")
     tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-I", os.path.join(ROOT, "include")] + SOURCES + ["-o", tmp]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libpdhg.so")
+        raise RuntimeError("hipcc failed linking libpdhg.so")
     os.replace(tmp, LIB)
     return LIB
 

@@ -324,7 +324,8 @@ struct pdhg_handle {
     FishDev fish{};          // fishnet buffers (opts.fishnet_points > 0)
     bool fish_rows = false;  // fish.rowK / rowT hold the rows by decreasing length
     int64_t rec_steps = 0;  // steps recorded by the last recording pdhg_iterate
-    int rec_valid = 0;
+    int rec_valid = 0;      // the tape matches the handle's data (cleared by pdhg_set_data)
+    int64_t rec_gen = 0;    // bumped by every recording pdhg_iterate and by pdhg_set_data
     std::vector<InstState> rec_st;  // step parameters of the recorded steps
 };
 
@@ -392,6 +393,8 @@ static void carve(Carve &cv, const Sizes &sz, int prec, const pdhg_opts &o, Dev 
     d.yavg1 = cv.take<char>(M * es);
     d.kx0 = cv.take<double>(M);
     d.kx1 = cv.take<double>(M);
+    d.xam = cv.take<char>(N * es);
+    d.yam = cv.take<char>(M * es);
     d.actK = cv.take<int32_t>(sz.nblkK + 1);
     d.actT = cv.take<int32_t>(sz.nblkT + 1);
     d.act_cnt = cv.take<int32_t>(2);
@@ -966,63 +969,62 @@ static int device_setup(pdhg_handle *h, hipStream_t s)
     HIPCHK(hipMemcpyAsync(cn2.data(), sc, B * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(qn2.data(), sc + B, B * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    // power iteration (Algorithm 2) on every instance at once
+    // power iteration (Algorithm 2) on every instance at once.  Each pass's
+    // stopping test runs on the device (k_power_test), so the host does not
+    // wait on the passes; it reads the states back every POLL passes to stop
+    // enqueuing once every instance has stopped (later passes sweep nothing).
     const auto t_pow = std::chrono::steady_clock::now();
-    std::vector<double> est(B, 0.0), prev(B, -1.0), w2(B);
-    std::vector<int> conv(B, 0), its(B, 0);
+    std::vector<double> est(B, 0.0);
+    std::vector<int> its(B, 0);
     double *bv = d.vecN64, *wv = d.vecM64, *bt = d.vecN64b;
     double *pk = d.partials, *pt = d.partials + h->sz.nblkK + 1;
     launch_fill(bv, d.N, 1.0, s);
-    // the sweeps walk the active lists: an instance whose estimate has
-    // converged is marked done and drops out of them (its numbers are final)
     std::vector<InstState> pst(B, InstState{});
-    auto mark_converged = [&](const std::vector<int> &flag) -> int {
-        for (int b = 0; b < B; ++b) pst[b].done = flag[b];
-        HIPCHK(hipMemcpyAsync(d.st, pst.data(), B * sizeof(InstState), hipMemcpyHostToDevice, s));
-        launch_active(d, s);
+    for (auto &x : pst) x.kkt_prev = -1.0;  // no previous estimate
+    HIPCHK(hipMemcpyAsync(d.st, pst.data(), B * sizeof(InstState), hipMemcpyHostToDevice, s));
+    launch_active(d, s);
+    const int32_t *lK = d.actK, *lT = d.actT, *cK = d.act_cnt, *cT = d.act_cnt + 1;
+    const int POLL = 16;
+    auto remaining = [&](int *left) -> int {
+        HIPCHK(hipMemcpyAsync(pst.data(), d.st, B * sizeof(InstState), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        *left = 0;
+        for (int b = 0; b < B; ++b) *left += pst[b].done ? 0 : 1;
         return PDHG_OK;
     };
-    if (mark_converged(conv)) return PDHG_ERR_HIP;
-    const int32_t *lK = d.actK, *lT = d.actT, *cK = d.act_cnt, *cT = d.act_cnt + 1;
-    int remaining = B;
-    for (int it = 0; it < o.power_max_iters && remaining > 0; ++it) {
+    int left = B;
+    for (int it = 0; it < o.power_max_iters; ++it) {
         launch_spmv64(d.K, d.remap, bv, wv, pk, lK, cK, s);
         if (it > 0) {
             launch_inst_sum(d, 1, pk, sc, s);
-            HIPCHK(hipMemcpyAsync(w2.data(), sc, B * sizeof(double), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            const int before = remaining;
-            for (int b = 0; b < B; ++b) {
-                if (conv[b]) continue;
-                est[b] = std::sqrt(w2[b]);
-                its[b] = it;
-                if (prev[b] >= 0.0 && std::fabs(est[b] - prev[b]) <= o.power_tol * est[b]) {
-                    conv[b] = 1;
-                    --remaining;
-                }
-                prev[b] = est[b];
+            launch_power_test(d, sc, it, o.power_tol, 0, s);
+            launch_active(d, s);
+            if (it % POLL == 0) {
+                if (remaining(&left)) return PDHG_ERR_HIP;
+                if (left == 0) break;
             }
-            if (remaining == 0) break;
-            if (remaining != before && mark_converged(conv)) return PDHG_ERR_HIP;
         }
         launch_spmv64(d.Kt, d.remap, wv, bt, pt, lT, cT, s);
         launch_inst_sum(d, 0, pt, sc + B, s);
         launch_normalize(bt, d.inst_of_col, d.N, sc + B, s);
         std::swap(bv, bt);
     }
-    // the handle's lists hold every instance again
-    if (mark_converged(std::vector<int>(B, 0))) return PDHG_ERR_HIP;
-    if (remaining > 0) {
-        launch_spmv64(d.K, d.remap, bv, wv, pk, nullptr, nullptr, s);
+    if (remaining(&left)) return PDHG_ERR_HIP;
+    if (left > 0) {
+        // the pass limit: every instance still iterating takes ||K b|| of its last b
+        launch_spmv64(d.K, d.remap, bv, wv, pk, lK, cK, s);
         launch_inst_sum(d, 1, pk, sc, s);
-        HIPCHK(hipMemcpyAsync(w2.data(), sc, B * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        for (int b = 0; b < B; ++b)
-            if (!conv[b]) {
-                est[b] = std::sqrt(w2[b]);
-                its[b] = o.power_max_iters;
-            }
+        launch_power_test(d, sc, o.power_max_iters, o.power_tol, 1, s);
+        if (remaining(&left)) return PDHG_ERR_HIP;
     }
+    for (int b = 0; b < B; ++b) {
+        est[b] = pst[b].knorm;
+        its[b] = pst[b].power_iters;
+    }
+    // the handle's lists hold every instance again
+    pst.assign(B, InstState{});
+    HIPCHK(hipMemcpyAsync(d.st, pst.data(), B * sizeof(InstState), hipMemcpyHostToDevice, s));
+    launch_active(d, s);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
     h->setup_phase[4] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_pow).count();
@@ -1423,6 +1425,7 @@ static int iterate_impl(pdhg_handle *h, int64_t k, int32_t record, hipStream_t s
     if (record) {
         h->rec_steps = k;
         h->rec_valid = 1;
+        h->rec_gen += 1;
         h->rec_st = st;
     }
     return PDHG_OK;
@@ -1432,7 +1435,9 @@ template <typename T>
 static int backward_impl(pdhg_handle *h, const double *gx, const double *gy, double *gc, double *grhs,
                          double *gl, double *gu, double *gx0, double *gy0, int32_t mem, hipStream_t s)
 {
-    if (!h->rec_valid) return fail(PDHG_ERR_STATE, "no recorded pdhg_iterate to differentiate");
+    if (!h->rec_valid)
+        return fail(PDHG_ERR_STATE, "no recorded pdhg_iterate to differentiate (none since setup or the last "
+                                    "pdhg_set_data)");
     Dev d = h->d;
     Buffers &b = h->buf;
     AdjBufs a{b.ax, b.av, b.ac, b.al, b.au, b.ay, b.aw, b.aq};
@@ -1817,6 +1822,9 @@ extern "C" int pdhg_set_data(pdhg_handle *h, const double *c, const double *rhs,
         }
     }
     const double *cd = c, *qd = rhs, *ld = l, *ud = u;
+    // the recorded tape belongs to the old data: pdhg_backward refuses it from here on
+    h->rec_valid = 0;
+    h->rec_gen += 1;
     if (mem == PDHG_MEM_HOST) {
         double *st[4] = {d.vecN64, d.vecM64, d.vecN64b, h->buf.vecN64c};
         const double *src[4] = {c, rhs, l, u};
@@ -1911,22 +1919,40 @@ static int time_impl(pdhg_handle *h, int32_t reps, pdhg_kernel_times *out, hipSt
         if (k == 0) launch_primal<T>(d, r, avg, nullptr, s);
         else launch_dual<T>(d, r, avg, nullptr, s);
     }, ms);
-    // once-per-chunk kernels, back to back
+    // once-per-chunk kernels, back to back, each on the path a check takes
+    // when it restarts: the control kernel runs a whole check decision (a
+    // check interval done, no stop: eps 0, no iteration limit, and the long
+    // inner loop rule always met, so every launch restarts and updates omega),
+    // the restart kernel copies every running instance's candidate
+    CtlParams Pr = P;
+    Pr.eps = 0.0;
+    Pr.max_iters = LLONG_MAX;
+    Pr.beta_art = 0.0;
+    Pr.detect = 0;
+    std::vector<InstState> sr = st;
+    for (auto &x : sr) {
+        x.kkt0 = x.kkt0 < INFINITY ? x.kkt0 : 1.0;
+        x.restart = 1;
+        x.cand_avg = 1;
+    }
     for (int phase = 2; phase < 5 && !rc; ++phase) {
         if (phase == 4 && !avg) continue;
+        if (phase >= 3 &&
+            hipMemcpyAsync(d.st, sr.data(), h->batch * sizeof(InstState), hipMemcpyHostToDevice, s) != hipSuccess)
+            rc = fail(PDHG_ERR_HIP, "state upload failed");
         (void)hipEventRecord(ev[0], s);
         for (int r = 0; r < reps; ++r) {
             switch (phase) {
                 case 2: launch_check<T>(d, avg, s); break;
-                case 3: launch_control(d, P, 0, s); break;
+                case 3: launch_control(d, Pr, h->opts.check_every, s); break;
                 default: launch_restart<T>(d, s); break;
             }
         }
         (void)hipEventRecord(ev[1], s);
         (void)hipEventSynchronize(ev[1]);
         ms[phase] = gap(0, 1) / reps;
-        if (phase == 3) {
-            // the control kernel may have stopped an instance: restore the state
+        if (phase >= 3) {
+            // restore the state the timed launches changed
             if (hipMemcpyAsync(d.st, st.data(), h->batch * sizeof(InstState), hipMemcpyHostToDevice, s) != hipSuccess)
                 rc = fail(PDHG_ERR_HIP, "state restore failed");
             launch_active(d, s);
@@ -2290,5 +2316,7 @@ extern "C" int pdhg_get_info(const pdhg_handle *h, pdhg_info *info)
     info->setup_device_seconds = h->setup_phase[3];
     info->setup_power_seconds = h->setup_phase[4];
     for (int b = 0; b < h->batch; ++b) info->power_iters_max = std::max(info->power_iters_max, h->st0[b].power_iters);
+    info->record_generation = h->rec_gen;
+    info->record_valid = h->rec_valid;
     return PDHG_OK;
 }

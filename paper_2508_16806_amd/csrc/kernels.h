@@ -45,6 +45,7 @@ void launch_spmv64(const OpDev &op, int remap, const double *v, double *out, dou
                    const int32_t *list, const int32_t *cnt, hipStream_t s);
 void launch_inst_sum(const Dev &d, int onK, const double *partials, double *out, hipStream_t s);
 void launch_normalize(double *v, const int32_t *inst_of, int64_t n, const double *nrm2, hipStream_t s);
+void launch_power_test(const Dev &d, const double *w2, int it, double tol, int final_pass, hipStream_t s);
 void launch_inst_nrm2(const Dev &d, int primal, const double *v, double *out, hipStream_t s);
 template <typename T>
 void launch_init_point(const Dev &d, hipStream_t s);

@@ -4,7 +4,8 @@
 // theta = 1), all in the scaled variables of Section 2.4.1:
 //   primal sweep over rows j of K~^T:  g = (K~^T y)_j,
 //       x+_j = clip(x_j - tau (c~_j - g), l~_j, u~_j),  xbar_j = 2 x+_j - x_j,
-//       running epoch average xavg_j += (x+_j - xavg_j) / (t + 1)
+//       running epoch average kept as the mean offset from the epoch start x0:
+//       xavg_j += ((x+_j - x0_j) - xavg_j) / (t + 1), average = x0 + xavg
 //   dual sweep over rows i of K~:      r = (K~ xbar)_i,
 //       y+_i = proj_Y(y_i + sigma (q~_i - r)) (clip at 0 for ">=" rows), yavg
 // Check every N iterations: FP64 residual sums of the current iterate and of
@@ -40,6 +41,7 @@ __global__ __launch_bounds__(WG) void k_primal(Dev d, int j_in_chunk, uint8_t *_
     T *__restrict__ x = (T *)d.x;
     T *__restrict__ xb = (T *)d.xbar;
     T *__restrict__ xa = (T *)d.xavg;
+    const T *__restrict__ x0 = (const T *)d.x0;
     const T *__restrict__ c = (const T *)d.c;
     const T *__restrict__ l = (const T *)d.l;
     const T *__restrict__ u = (const T *)d.u;
@@ -60,7 +62,7 @@ __global__ __launch_bounds__(WG) void k_primal(Dev d, int j_in_chunk, uint8_t *_
             // the update's operands are loaded before the dot products so their
             // latency overlaps the streaming of the rows (unconditional loads
             // from clamped rows: no branch forces a wait)
-            T r_x[R], r_c[R], r_l[R], r_u[R], r_a[R];
+            T r_x[R], r_c[R], r_l[R], r_u[R], r_a[R], r_0[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int64_t jj = r < ps.nvalid ? ps.row0 + r : ps.blk_row0;
@@ -69,6 +71,7 @@ __global__ __launch_bounds__(WG) void k_primal(Dev d, int j_in_chunk, uint8_t *_
                 r_l[r] = l[jj];
                 r_u[r] = u[jj];
                 r_a[r] = AVG ? xa[jj] : T(0);
+                r_0[r] = AVG ? x0[jj] : T(0);
             }
             double acc[R][1];
             RS::dot(op, ps, y, nullptr, nullptr, red, acc);
@@ -84,7 +87,7 @@ __global__ __launch_bounds__(WG) void k_primal(Dev d, int j_in_chunk, uint8_t *_
                     const T xnT = (T)xn;
                     x[j] = xnT;
                     xb[j] = (T)(2.0 * (double)xnT - xo);
-                    if (AVG) xa[j] = (T)(xav + ((double)xnT - xav) * w);
+                    if (AVG) xa[j] = (T)(xav + (((double)xnT - (double)r_0[r]) - xav) * w);
                     if (MASK) mask[j] = (uint8_t)(v <= lo ? 1 : (v >= hi ? 2 : 0));
                 }
             }
@@ -99,6 +102,7 @@ __global__ __launch_bounds__(WG) void k_dual(Dev d, int j_in_chunk, uint8_t *__r
     const OpDev &op = d.K;
     T *__restrict__ y = (T *)d.y;
     T *__restrict__ ya = (T *)d.yavg;
+    const T *__restrict__ y0 = (const T *)d.y0;
     const T *__restrict__ q = (const T *)d.q;
     const T *__restrict__ xb = (const T *)d.xbar;
     const int cnt = d.act_cnt[0];
@@ -115,13 +119,14 @@ __global__ __launch_bounds__(WG) void k_dual(Dev d, int j_in_chunk, uint8_t *__r
             constexpr int L = decltype(tag)::value, R = decltype(rtag)::value;
             using RS = RowSweep<L, 1, T, T, R>;
             const typename RS::Pos ps = RS::locate(s, bi);
-            T r_y[R], r_q[R], r_a[R];
+            T r_y[R], r_q[R], r_a[R], r_0[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int64_t ii = r < ps.nvalid ? ps.row0 + r : ps.blk_row0;
                 r_y[r] = y[ii];
                 r_q[r] = q[ii];
                 r_a[r] = AVG ? ya[ii] : T(0);
+                r_0[r] = AVG ? y0[ii] : T(0);
             }
             double acc[R][1];
             RS::dot(op, ps, xb, nullptr, nullptr, red, acc);
@@ -135,7 +140,7 @@ __global__ __launch_bounds__(WG) void k_dual(Dev d, int j_in_chunk, uint8_t *__r
                     const double yn = (ineq && wv < 0.0) ? 0.0 : wv;
                     const T ynT = (T)yn;
                     y[i] = ynT;
-                    if (AVG) ya[i] = (T)(yav + ((double)ynT - yav) * w);
+                    if (AVG) ya[i] = (T)(yav + (((double)ynT - (double)r_0[r]) - yav) * w);
                     if (MASK) mask[i] = (uint8_t)((!ineq || wv > 0.0) ? 1 : 0);
                 }
             }
@@ -187,6 +192,7 @@ __global__ __launch_bounds__(WG) void k_primal_ad(Dev d)
         T *__restrict__ xn = (T *)(par ? d.x : d.xbar);
         const T *__restrict__ xa = (const T *)(par ? d.xavg1 : d.xavg);
         T *__restrict__ xan = (T *)(par ? d.xavg : d.xavg1);
+        const T *__restrict__ x0 = (const T *)d.x0;
         const T *__restrict__ y = (const T *)(par ? d.y1 : d.y);
         const int bi = lb - s.blk0;
         double part[1] = {0.0};
@@ -195,7 +201,7 @@ __global__ __launch_bounds__(WG) void k_primal_ad(Dev d)
             using RS = RowSweep<L, 1, T, T, R>;
             const typename RS::Pos ps = RS::locate(s, bi);
             // rows are < 2^29: 32-bit offsets from the scalar bases
-            T r_x[R], r_c[R], r_l[R], r_u[R], r_a[R];
+            T r_x[R], r_c[R], r_l[R], r_u[R], r_a[R], r_0[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const uint32_t jj = (uint32_t)(r < ps.nvalid ? ps.row0 + r : ps.blk_row0);
@@ -204,6 +210,7 @@ __global__ __launch_bounds__(WG) void k_primal_ad(Dev d)
                 r_l[r] = ldo(l, jj);
                 r_u[r] = ldo(u, jj);
                 r_a[r] = ldo(xa, jj);
+                r_0[r] = ldo(x0, jj);
             }
             double acc[R][1];
             RS::dot(op, ps, y, nullptr, nullptr, red, acc);
@@ -218,7 +225,8 @@ __global__ __launch_bounds__(WG) void k_primal_ad(Dev d)
                     const double xv = v < lo ? lo : (v > hi ? hi : v);
                     const T xnT = (T)xv;
                     sto(xn, j, xnT);
-                    sto(xan, j, first ? xnT : (T)(xav + ((double)xnT - xav) * wa));
+                    const double off = (double)xnT - (double)r_0[r];
+                    sto(xan, j, (T)(first ? off : xav + (off - xav) * wa));
                     const double dx = (double)xnT - xo;
                     part[0] += dx * dx;
                 }
@@ -252,6 +260,7 @@ __global__ __launch_bounds__(WG) void k_dual_ad(Dev d)
         T *__restrict__ yn = (T *)(par ? d.y : d.y1);
         const T *__restrict__ ya = (const T *)(par ? d.yavg1 : d.yavg);
         T *__restrict__ yan = (T *)(par ? d.yavg : d.yavg1);
+        const T *__restrict__ y0 = (const T *)d.y0;
         const double *__restrict__ kx = par ? d.kx1 : d.kx0;
         double *__restrict__ kxn = par ? d.kx0 : d.kx1;
         const bool ineq = s.ineq != 0;
@@ -261,7 +270,7 @@ __global__ __launch_bounds__(WG) void k_dual_ad(Dev d)
             constexpr int L = decltype(tag)::value, R = decltype(rtag)::value;
             using RS = RowSweep<L, 1, T, T, R>;
             const typename RS::Pos ps = RS::locate(s, bi);
-            T r_y[R], r_q[R], r_a[R];
+            T r_y[R], r_q[R], r_a[R], r_0[R];
             double r_k[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -269,6 +278,7 @@ __global__ __launch_bounds__(WG) void k_dual_ad(Dev d)
                 r_y[r] = ldo(y, ii);
                 r_q[r] = ldo(q, ii);
                 r_a[r] = ldo(ya, ii);
+                r_0[r] = ldo(y0, ii);
                 r_k[r] = ldo(kx, ii);
             }
             double acc[R][1];
@@ -285,7 +295,8 @@ __global__ __launch_bounds__(WG) void k_dual_ad(Dev d)
                     const T ynT = (T)yv;
                     sto(yn, i, ynT);
                     sto(kxn, i, a);
-                    sto(yan, i, first ? ynT : (T)(yav + ((double)ynT - yav) * wa));
+                    const double off = (double)ynT - (double)r_0[r];
+                    sto(yan, i, (T)(first ? off : yav + (off - yav) * wa));
                     const double dy = (double)ynT - yo;
                     part[0] += dy * dy;
                     part[1] += dy * (a - kxo);
@@ -397,6 +408,7 @@ __global__ __launch_bounds__(WG) void k_commit_ad(Dev d)
         const T *z1 = (const T *)(onT ? d.xbar : d.y1);
         T *za0 = (T *)(onT ? d.xavg : d.yavg);
         const T *za1 = (const T *)(onT ? d.xavg1 : d.yavg1);
+        const T *ze = (const T *)(onT ? d.x0 : d.y0);  // epoch start
         const int64_t r1 = s.row0 + s.nrows;
         T *z1w = (T *)z1;
         for (int64_t r = s.row0 + threadIdx.x; r < r1; r += WG) {
@@ -406,7 +418,8 @@ __global__ __launch_bounds__(WG) void k_commit_ad(Dev d)
                 z1w[r] = z0[r];
                 z0[r] = v;
             }
-            za0[r] = noavg ? v : za1[r];
+            // averages are offsets from the epoch start
+            za0[r] = noavg ? (T)((double)v - (double)ze[r]) : za1[r];
             if (!onT && flip) d.kx0[r] = d.kx1[r];
         }
     });
@@ -767,9 +780,15 @@ __device__ __forceinline__ double kkt_omega(const Metrics &m, double w)
     return sqrt(w * w * m.kw_parts[0] + m.kw_parts[1] / (w * w) + m.kw_parts[2]);
 }
 
+// The inputs of one check's restart decision, as they were before it.
+struct CheckIn {
+    long long t_inner;
+    double kkt0, kkt_prev, omega;
+};
+
 // Record of one check in the instance's ring (when the handle keeps one).
 __device__ void trace_put(const Dev &d, int b, InstState &st, int cand, double kwc, const Metrics *mt, int nc,
-                          const CtlParams &P)
+                          const CtlParams &P, const CheckIn &ci, double dx = 0.0, double dy = 0.0)
 {
     if (d.trace_cap <= 0) return;
     pdhg_trace_rec r;
@@ -782,6 +801,16 @@ __device__ void trace_put(const Dev &d, int b, InstState &st, int cand, double k
     r.rel_kkt_avg = nc > 1 ? mt[1].kkt[8] : INFINITY;
     r.eta_next = P.adaptive ? st.eta_try : st.eta;
     r.accepted = P.adaptive ? st.n_acc : st.k_total;
+    r.t_inner = ci.t_inner;
+    r.kkt0 = ci.kkt0;
+    r.kkt_prev = ci.kkt_prev;
+    r.omega_before = ci.omega;
+    r.delta_x = dx;
+    r.delta_y = dy;
+    r.kkt0_next = st.kkt0;
+    r.cand_pres = sqrt(mt[cand].kw_parts[0]);
+    r.cand_dres = sqrt(mt[cand].kw_parts[1]);
+    r.cand_gap = sqrt(mt[cand].kw_parts[2]);
     d.trace[(size_t)b * d.trace_cap + (size_t)(st.ntrace % d.trace_cap)] = r;
     st.ntrace += 1;
 }
@@ -810,13 +839,14 @@ __global__ __launch_bounds__(WG) void k_control(Dev d, CtlParams P, int iters_do
     }
     const double omega = st.omega;
     const double kw0 = kkt_omega(mt[0], omega);
+    const CheckIn ci = {st.t_inner, st.kkt0, st.kkt_prev, omega};
     st.restart = 0;
     if (!finite) {
         st.done = 1;
         st.status = PDHG_NUMERICAL_ERROR;
         st.sol_avg = 0;
         for (int k = 0; k < 9; ++k) st.kkt[k] = mt[0].kkt[k];
-        if (iters_done > 0) trace_put(d, b, st, 0, kw0, mt, nc, P);
+        if (iters_done > 0) trace_put(d, b, st, 0, kw0, mt, nc, P, ci);
         d.hdone[b] = 1;
         return;
     }
@@ -864,14 +894,14 @@ __global__ __launch_bounds__(WG) void k_control(Dev d, CtlParams P, int iters_do
         st.status = stop - 1;
         st.sol_avg = sol;
         for (int k = 0; k < 9; ++k) st.kkt[k] = mt[sol].kkt[k];
-        trace_put(d, b, st, cand, kwc, mt, nc, P);
+        trace_put(d, b, st, cand, kwc, mt, nc, P, ci);
         d.hdone[b] = 1;
         return;
     }
     for (int k = 0; k < 9; ++k) st.kkt[k] = mt[cand].kkt[k];
     st.sol_avg = cand;
     if (!P.use_restarts) {
-        trace_put(d, b, st, cand, kwc, mt, nc, P);
+        trace_put(d, b, st, cand, kwc, mt, nc, P, ci);
         return;
     }
     const bool suff = kwc <= P.beta_suff * st.kkt0;
@@ -890,10 +920,31 @@ __global__ __launch_bounds__(WG) void k_control(Dev d, CtlParams P, int iters_do
         st.eta_sum = 0.0;
         st.restart = 1;
         st.nrestarts += 1;
-    } else {
-        st.kkt_prev = kwc;
+        trace_put(d, b, st, cand, kwc, mt, nc, P, ci, dx, dy);
+        return;
     }
-    trace_put(d, b, st, cand, kwc, mt, nc, P);
+    st.kkt_prev = kwc;
+    trace_put(d, b, st, cand, kwc, mt, nc, P, ci);
+}
+
+// The average point of the running instances, x0 + xavg rounded to T, into
+// (xam, yam): what the check evaluates and a restart copies.  Walks K^T blocks
+// then K blocks of the running instances.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_avg_point(Dev d)
+{
+    const int nT = d.act_cnt[1], nK = d.act_cnt[0];
+    const bool fullK = nK == d.K.nblk, fullT = nT == d.Kt.nblk;
+    for_each_item(nT + nK, d.remap, [&](int it) {
+        const bool onT = it < nT;
+        const int lb = onT ? (fullT ? it : d.actT[it]) : (fullK ? it - nT : d.actK[it - nT]);
+        const Seg s = block_seg(onT ? d.Kt : d.K, lb);
+        const int64_t r1 = s.row0 + s.nrows;
+        const T *za = (const T *)(onT ? d.xavg : d.yavg);
+        const T *z0 = (const T *)(onT ? d.x0 : d.y0);
+        T *zm = (T *)(onT ? d.xam : d.yam);
+        for (int64_t r = s.row0 + threadIdx.x; r < r1; r += WG) zm[r] = (T)((double)z0[r] + (double)za[r]);
+    });
 }
 
 // On restart: z <- candidate, epoch start <- z.  Walks K^T blocks then K blocks
@@ -913,7 +964,7 @@ __global__ __launch_bounds__(WG) void k_restart(Dev d)
         const int64_t r0 = s.row0;  // one logical block = rows [row0, row0 + nrows)
         const int64_t r1 = s.row0 + s.nrows;
         T *z = (T *)(onT ? d.x : d.y);
-        T *za = (T *)(onT ? d.xavg : d.yavg);
+        const T *za = (const T *)(onT ? d.xam : d.yam);  // the average the check evaluated
         T *z0 = (T *)(onT ? d.x0 : d.y0);
         for (int64_t r = r0 + threadIdx.x; r < r1; r += WG) {
             const T v = st.cand_avg ? za[r] : z[r];
@@ -1200,6 +1251,27 @@ __global__ __launch_bounds__(WG) void k_inst_sum(const InstInfo *info, int onK, 
     if (threadIdx.x == 0) out[blockIdx.x] = v[0];
 }
 
+// The stopping test of the power iteration (Algorithm 2) for every instance
+// still iterating (one lane each): est = ||K b|| from w2 = ||K b||^2; stop
+// when two successive estimates differ by at most tol * est.  The state keeps
+// est in knorm, the previous estimate in kkt_prev (negative before the first)
+// and the pass in power_iters; a stopped instance is marked done, so the next
+// active-list rebuild drops it from the sweeps.  final_pass: the pass limit
+// was reached, every instance still iterating takes this estimate.
+__global__ void k_power_test(Dev d, const double *w2, int it, double tol, int final_pass)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= d.batch) return;
+    InstState &st = d.st[b];
+    if (st.done) return;
+    const double est = sqrt(w2[b]);
+    st.knorm = est;
+    st.power_iters = it;
+    if (final_pass) return;
+    if (st.kkt_prev >= 0.0 && fabs(est - st.kkt_prev) <= tol * est) st.done = 1;
+    st.kkt_prev = est;
+}
+
 // v_i /= sqrt(nrm2[inst(i)])  (skips zero norms)
 __global__ void k_normalize(double *v, const int32_t *inst_of, int64_t n, const double *nrm2)
 {
@@ -1236,7 +1308,7 @@ __global__ void k_init_point(Dev d)
         const T v = (T)(0.0 < l ? l : (0.0 > u ? u : 0.0));
         ((T *)d.x)[i] = v;
         ((T *)d.x0)[i] = v;
-        ((T *)d.xavg)[i] = v;
+        ((T *)d.xavg)[i] = (T)0;  // offset from the epoch start
         ((T *)d.xbar)[i] = v;
     }
     if (i < d.M) {
@@ -1253,23 +1325,26 @@ __global__ void k_epoch_start(Dev d)
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < d.N) {
         ((T *)d.x0)[i] = ((T *)d.x)[i];
-        ((T *)d.xavg)[i] = ((T *)d.x)[i];
+        ((T *)d.xavg)[i] = (T)0;
     }
     if (i < d.M) {
         ((T *)d.y0)[i] = ((T *)d.y)[i];
-        ((T *)d.yavg)[i] = ((T *)d.y)[i];
+        ((T *)d.yavg)[i] = (T)0;
     }
 }
 
-// FP64 copies of a point (which: 0 current, 1 average) in scaled variables
+// FP64 copies of a point (which: 0 current, 1 average) in scaled variables;
+// the average is x0 + xavg rounded to T, as the check evaluates it
 template <typename T>
 __global__ void k_point_to64(Dev d, int which, double *xo, double *yo)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const T *x = (const T *)(which ? d.xavg : d.x);
-    const T *y = (const T *)(which ? d.yavg : d.y);
-    if (i < d.N) xo[i] = (double)x[i];
-    if (i < d.M) yo[i] = (double)y[i];
+    if (i < d.N)
+        xo[i] = which ? (double)(T)((double)((const T *)d.x0)[i] + (double)((const T *)d.xavg)[i])
+                      : (double)((const T *)d.x)[i];
+    if (i < d.M)
+        yo[i] = which ? (double)(T)((double)((const T *)d.y0)[i] + (double)((const T *)d.yavg)[i])
+                      : (double)((const T *)d.y)[i];
 }
 
 // original-variable outputs of one instance: x (clipped to [l, u]), y
@@ -1346,7 +1421,7 @@ __global__ void k_set_point(Dev d, int64_t xoff, int64_t n, int64_t yoff, int64_
         v = v < l ? l : (v > u ? u : v);
         ((T *)d.x)[j] = (T)v;
         ((T *)d.x0)[j] = (T)v;
-        ((T *)d.xavg)[j] = (T)v;
+        ((T *)d.xavg)[j] = (T)0;
     }
     if (t < m) {
         const int64_t i = yoff + t;
@@ -1354,7 +1429,7 @@ __global__ void k_set_point(Dev d, int64_t xoff, int64_t n, int64_t yoff, int64_
         if (t < m1 && v < 0.0) v = 0.0;
         ((T *)d.y)[i] = (T)v;
         ((T *)d.y0)[i] = (T)v;
-        ((T *)d.yavg)[i] = (T)v;
+        ((T *)d.yavg)[i] = (T)0;
     }
 }
 
@@ -1609,9 +1684,10 @@ template <typename T>
 void launch_check(const Dev &d, int avg, hipStream_t s)
 {
     const unsigned g = sweep_grid(d, d.K.nblk + d.Kt.nblk);
-    const T *x = (const T *)d.x, *xa = (const T *)d.xavg, *x0 = (const T *)d.x0;
-    const T *y = (const T *)d.y, *ya = (const T *)d.yavg, *y0 = (const T *)d.y0;
+    const T *x = (const T *)d.x, *xa = (const T *)d.xam, *x0 = (const T *)d.x0;
+    const T *y = (const T *)d.y, *ya = (const T *)d.yam, *y0 = (const T *)d.y0;
     const int rm = d.K.rmax > d.Kt.rmax ? d.K.rmax : d.Kt.rmax;
+    if (avg) LAUNCH(k_avg_point<T>, sweep_grid(d, d.K.nblk + d.Kt.nblk), d);
     RM_SWITCH(rm, {
         if (avg) {
             LAUNCH((k_check<T, 2, RMV>), g, d, x, xa, y, ya, x0, y0, 1);
@@ -1694,6 +1770,11 @@ void launch_spmv64(const OpDev &op, int remap, const double *v, double *out, dou
 void launch_inst_sum(const Dev &d, int onK, const double *partials, double *out, hipStream_t s)
 {
     LAUNCH(k_inst_sum, (unsigned)d.batch, d.info, onK, partials, out);
+}
+
+void launch_power_test(const Dev &d, const double *w2, int it, double tol, int final_pass, hipStream_t s)
+{
+    LAUNCH(k_power_test, (unsigned)((d.batch + WG - 1) / WG), d, w2, it, tol, final_pass);
 }
 
 void launch_normalize(double *v, const int32_t *inst_of, int64_t n, const double *nrm2, hipStream_t s)

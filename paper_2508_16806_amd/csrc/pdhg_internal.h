@@ -123,8 +123,13 @@ struct Dev {
     // primal vectors (length N).  With adaptive steps the iterate and its
     // average are double-buffered per instance: buffer 0 = (x, xavg), buffer 1
     // = (xbar, xavg1); likewise (y, yavg, kx0) / (y1, yavg1, kx1) for the dual.
+    // The epoch averages are kept as means of offsets from the epoch start:
+    // xavg holds mean_t (x_t - x0), so the average is x0 + xavg (its FP32
+    // rounding error scales with the distance from x0, not with |x|).  xam /
+    // yam receive the average point (x0 + xavg rounded to T) before a check.
     void *x, *xbar, *xavg, *x0;   // iterate type T
     void *xavg1;
+    void *xam, *yam;              // the average point of the last check, type T
     void *c, *l, *u;              // scaled data, type T
     double *c64, *l64, *u64;      // scaled data, FP64
     double *kap;                  // column factors (x = kap * x~)

@@ -61,23 +61,28 @@ __device__ __forceinline__ void for_each_item(int cnt, int remap, F &&f)
 
 // As for_each_item, but with `remap` XCD x takes the item range
 // [split[x], split[x + 1]) (ranges of equal cost, computed by k_act_split).
-// With `rev` every visit of item i becomes one of item cnt - 1 - i, so the
-// grid walks the matrix from its end: the two sweeps of an iteration alternate
+// With `rev` the walk runs backwards: the two sweeps of an iteration alternate
 // direction between iterations, and each then starts on the part of its matrix
 // that the other sweep's pass has not yet pushed out of the last-level cache.
+// Without `remap` item i becomes item cnt - 1 - i; with it, each XCD walks its
+// own range from its end, so it keeps its share of the cost.
 template <typename F>
 __device__ __forceinline__ void for_each_item_split(int cnt, int remap, const int32_t *split, int rev, F &&f)
 {
     const int G = gridDim.x, b = blockIdx.x;
-    const int last = rev ? cnt - 1 : 0, sgn = rev ? -1 : 1;
     if (!remap || G < 8) {
+        const int last = rev ? cnt - 1 : 0, sgn = rev ? -1 : 1;
         for (int it = b; it < cnt; it += G) f(last + sgn * it);
         return;
     }
     const int xcd = b & 7, loc = b >> 3;
     const int nloc = (G - xcd + 7) >> 3;
     const int i0 = split[xcd], i1 = min(cnt, split[xcd + 1]);
-    for (int it = i0 + loc; it < i1; it += nloc) f(last + sgn * it);
+    if (rev) {
+        for (int it = i1 - 1 - loc; it >= i0; it -= nloc) f(it);
+    } else {
+        for (int it = i0 + loc; it < i1; it += nloc) f(it);
+    }
 }
 
 // The rows of logical block lb as a one-block segment (one 16-byte load):

@@ -4,6 +4,8 @@ validation in pdhg_workspace_bytes runs on the host only)."""
 import ctypes as C
 import os
 import re
+import shutil
+import subprocess
 
 import numpy as np
 import pytest
@@ -52,11 +54,51 @@ def test_struct_layouts_match_header(pd):
     assert o.batch_resident_bytes == 192_000_000
     assert pd.Opts.trace_capacity.offset == pd.Opts.batch_resident_bytes.offset + 8 and o.trace_capacity == 0
     assert C.sizeof(pd.Opts) == pd.Opts.trace_capacity.offset + 8
-    assert C.sizeof(pd.TraceRec) == 64
+    assert C.sizeof(pd.TraceRec) == 144
     assert o.detect_infeas == 0 and o.infeas_tol == 1e-4
     assert pd.Result.eta_next.offset + 8 == C.sizeof(pd.Result)
     assert pd.KernelTimes.ms_step_ad.offset + 8 == C.sizeof(pd.KernelTimes)
     assert L.pdhg_last_error() is not None
+
+
+_LAYOUT_C = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "pdhg.h"
+#define S(T) printf(#T " size %zu\n", sizeof(T));
+#define F(T, f) printf(#T " %s %zu\n", #f, offsetof(T, f));
+int main(void) {
+    S(pdhg_opts) S(pdhg_result) S(pdhg_trace_rec) S(pdhg_info) S(pdhg_kernel_times) S(pdhg_kkt_out) S(pdhg_lp)
+    F(pdhg_trace_rec, t_inner) F(pdhg_trace_rec, kkt0) F(pdhg_trace_rec, cand_gap)
+    F(pdhg_info, power_iters_max) F(pdhg_info, record_valid) F(pdhg_info, record_generation)
+    F(pdhg_opts, trace_capacity) F(pdhg_result, eta_next)
+    return 0;
+}
+"""
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+def test_ctypes_mirrors_match_the_c_header(pd, tmp_path):
+    """Sizes and field offsets of the binding's ctypes structs equal what a C
+    compiler makes of include/pdhg.h."""
+    src = tmp_path / "layout.c"
+    src.write_text(_LAYOUT_C)
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+                           "-I" + os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        parts = line.split()
+        got[" ".join(parts[:-1])] = int(parts[-1])
+    mirrors = {"pdhg_opts": pd.Opts, "pdhg_result": pd.Result, "pdhg_trace_rec": pd.TraceRec,
+               "pdhg_info": pd.Info, "pdhg_kernel_times": pd.KernelTimes, "pdhg_kkt_out": pd.KKTOut,
+               "pdhg_lp": pd.LPDesc}
+    for name, cls in mirrors.items():
+        assert got[f"{name} size"] == C.sizeof(cls), name
+    for key, off in got.items():
+        parts = key.split()
+        if len(parts) == 2 and parts[1] != "size" and parts[0] in mirrors:
+            assert getattr(mirrors[parts[0]], parts[1]).offset == off, key
 
 
 def _nbytes(pd, lp, **kw):
@@ -150,9 +192,10 @@ def test_rejects_bad_options(pd):
     assert _nbytes(pd, lp, bin_len_dual=[-1, 8, 16, 32, 64, 128, 512, 0]) == 0 and "bin_len" in _err(pd)
     assert _nbytes(pd, lp, trace_capacity=-1) == 0 and "trace_capacity" in _err(pd)
     assert _nbytes(pd, lp, trace_capacity=(1 << 20) + 1) == 0
-    # the ring: 64 bytes per record and instance (within the carve's 256-byte alignment)
+    # the ring: one pdhg_trace_rec (144 bytes) per record and instance (within the carve's
+    # 256-byte alignment)
     grow = _nbytes(pd, lp, trace_capacity=1000) - _nbytes(pd, lp)
-    assert 64 * 1000 <= grow <= 64 * 1000 + 512
+    assert 144 * 1000 <= grow <= 144 * 1000 + 512
 
 
 def test_fishnet_rounds_and_draws(pd):

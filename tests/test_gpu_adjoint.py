@@ -154,3 +154,45 @@ def test_autograd_function(orc, pd):
     np.testing.assert_allclose(c.grad.numpy(), go["c"], rtol=1e-8, atol=1e-10)
     np.testing.assert_allclose(q.grad.numpy(), go["q"], rtol=1e-8, atol=1e-10)
     np.testing.assert_allclose(xs.grad.numpy(), go["x0"], rtol=1e-8, atol=1e-10)
+
+
+def test_backward_refuses_a_tape_replaced_by_set_data(pd):
+    """pdhg_set_data drops the recorded tape: backward raises PDHG_ERR_STATE
+    instead of replaying old checkpoints against the new data."""
+    lp = lpgen.planted(60, 150, 0.05, 8, ge_frac=0.3)
+    s = pd.Solver(lp, precision="f64", unroll_capacity=12, unroll_checkpoint=4)
+    g0 = s.info()["record_generation"]
+    s.iterate(12, record=True)
+    assert s.info()["record_valid"] == 1 and s.info()["record_generation"] == g0 + 1
+    s.backward(np.ones(lp.n), np.zeros(lp.m))
+    s.set_data(c=lp.c * 1.5)
+    assert s.info()["record_valid"] == 0 and s.info()["record_generation"] == g0 + 2
+    with pytest.raises(pd.PDHGError) as e:
+        s.backward(np.ones(lp.n), np.zeros(lp.m))
+    assert e.value.code == -7
+    # a new recording restores it
+    s.iterate(5, record=True)
+    s.backward(np.ones(lp.n), np.zeros(lp.m))
+
+
+def test_autograd_refuses_a_replaced_tape(orc, pd):
+    """Two forward calls on one handle, then the first one's backward: raises
+    (the handle keeps only the second tape); the second's backward is right."""
+    import torch
+
+    from paper_2508_16806_amd.autograd import PDHGUnroll
+
+    lp = lpgen.planted(80, 200, 0.04, 14, ge_frac=0.5)
+    K = 20
+    o, s, tau, sigma, x0, y0, gx, gy = _setup(pd, orc, lp, "f64", K=K, C=8, seed=4)
+    T = lambda a: torch.tensor(a, dtype=torch.float64, requires_grad=True)
+    c1 = T(lp.c)
+    xk1, _ = PDHGUnroll.apply(s, K, c1, T(lp.rhs), T(lp.l), T(lp.u), T(x0), T(y0))
+    c2 = T(lp.c * 1.1)
+    xk2, _ = PDHGUnroll.apply(s, K, c2, T(lp.rhs), T(lp.l), T(lp.u), T(x0), T(y0))
+    with pytest.raises(pd.PDHGError) as e:
+        (xk1 * torch.from_numpy(gx)).sum().backward()
+    assert e.value.code == -7
+    (xk2 * torch.from_numpy(gx)).sum().backward()
+    go = o.unrolled_vjp(10, tau, sigma, lp.c * 1.1, lp.rhs, lp.l, lp.u, x0, y0, K, gx, np.zeros(lp.m))
+    np.testing.assert_allclose(c2.grad.numpy(), go["c"], rtol=1e-8, atol=1e-10)

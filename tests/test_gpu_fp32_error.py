@@ -49,11 +49,10 @@ CASES = {
 }
 
 
-# the tight tolerance of each case: 1e-6, except the Zipf LP, whose FP32
-# iterates stall between 1e-5 and 1e-4: there the solve runs 300,000
-# iterations at 1e-5 and its returned point must meet 1e-4 and the gap bar
+# the tight tolerance of each case: 1e-6, except the Zipf LP at 1e-5 (the
+# FP64 solve of its 1/100-scale sibling needs ~96k iterations to 1e-5)
 TIGHT = {"C2/10": 1e-5}
-STALLS = {"C2/10"}
+STALLS = set()
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -83,3 +82,18 @@ def test_fp32_error_per_result(orc, pd, name, tol):
         assert rec["oracle_rel_kkt"] <= (1e-4 if stall else eps) * 1.05, rec
         if tol == "tight":
             assert rec["obj_gap"] <= 1e-5, rec
+
+
+@pytest.mark.parametrize("seed", [48, 55])
+def test_fp32_reaches_1e5_on_former_floor_cases(orc, pd, seed):
+    """Two dense random structures whose FP32 solves stalled near 2e-5 while
+    the epoch averages were FP32 incremental means of the iterates (each
+    update rounded at the average's own magnitude): with the averages kept as
+    FP32 means of offsets from the epoch start they reach 1e-5."""
+    lp = lpgen.random_case(seed)
+    s = pd.Solver(lp, precision="f32", eps=1e-5, max_iters=300_000)
+    r = s.solve()[0]
+    x, y = s.solution()
+    k = orc.Oracle(lp).kkt(x, y)
+    print("[fp32-floor]", seed, r["status_name"], r["iters"], r["restarts"], k["rel_kkt"], flush=True)
+    assert r["status_name"] == "OPTIMAL" and k["rel_kkt"] <= 1.05e-5, (r, k)

@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import lpgen
+from test_gpu_parity import fp32_step_bounds
 
 pytestmark = pytest.mark.gpu
 
@@ -69,12 +70,9 @@ def test_c1_one_step_every_element(orc, pd, c1, tune):
     s.iterate(1)
     x, y = s.solution(which=pd.SOL_CURRENT)
     xo, yo = o.steps(xs, ys, eta, eta, 1, ruiz_iters=10)
-    u = 2.0 ** -24
     Ks = abs(lp.scipy().multiply(rho[:, None]).multiply(kap[None, :])).tocsr()
-    cs, qs = kap * lp.c, rho * lp.rhs
-    xb = 2 * xo - xs
-    bx = 6 * u * (np.abs(xo) + np.abs(xs) + eta * (np.abs(cs) + Ks.T @ np.abs(ys))) + 1e-300
-    by = 6 * u * (np.abs(yo) + np.abs(ys) + eta * (np.abs(qs) + Ks @ np.abs(xb))) + 1e-300
+    # the bound derived in test_gpu_parity.fp32_step_bounds
+    bx, by = fp32_step_bounds(Ks, kap * lp.c, rho * lp.rhs, xs, ys, xo, yo, eta, eta)
     ex = np.abs(x / kap - xo) / bx
     ey = np.abs(y / rho - yo) / by
     assert ex.max() <= 1.0, (ex.max(), int(ex.argmax()))

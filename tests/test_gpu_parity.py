@@ -152,19 +152,36 @@ def test_one_step_f32_matches_oracle(orc, pd):
     s.iterate(1)
     x, y = s.solution(which=pd.SOL_CURRENT)
     xo, yo = o.steps(xs, ys, eta, eta, 1, ruiz_iters=10)
-    # error bound of the FP32 path, per element: every FP32 rounding (matrix
-    # entry, data entry, xbar, output) is at most u = 2^-24 relative, and the
-    # FP64 accumulation adds nothing at this scale, so
-    #   |dx_j| <= 4u (|x+_j| + |x_j| + tau (|c~_j| + (|K~^T| |y|)_j))
-    #   |dy_i| <= 4u (|y+_i| + |y_i| + sigma (|q~_i| + (|K~| |xbar|)_i))
+    rho = o.ruiz(10)[0]
+    Ks = abs(lp.scipy().multiply(rho[:, None]).multiply(kap[None, :])).tocsr()
+    bx, by = fp32_step_bounds(Ks, kap * lp.c, rho * lp.rhs, xs, ys, xo, yo, eta, eta)
+    assert np.all(np.abs(x / kap - xo) <= bx)
+    assert np.all(np.abs(y / rho - yo) <= by)
+
+
+def fp32_step_bounds(Ks, cs, qs, xs, ys, xo, yo, tau, sigma):
+    """Per-element bounds on one FP32 step's deviation from the exact FP64
+    step (xo, yo) from the same FP32-representable start (xs, ys), in scaled
+    variables.
+
+    Each FP32 rounding (a matrix entry, c~, q~, the bounds, x+, xbar, y+) is at
+    most u = 2^-24 relative; products of FP32 numbers are exact in FP64 and the
+    FP64 sums add ~2^-53 per term, covered by a 1% margin.  With |K~| the
+    entrywise absolute matrix:
+      primal: v = x - tau (c~ - K~'y): |dv| <= tau u (|c~| + |K~|'|y|); the
+        clip to FP32 bounds and the output rounding add u |x+| each:
+        |dx+| <= Bx = 2u |x+| + tau u (|c~| + |K~|'|y|)
+      xbar = 2 x+ - x, rounded: |dxbar| <= 2 Bx + u |xbar|
+      dual: w = y + sigma (q~ - K~ xbar):
+        |dw| <= sigma (u |q~| + u |K~||xbar| + |K~| |dxbar|)
+      y+ = proj(w), rounded: |dy+| <= |dw| + u |y+|
+    """
     u = 2.0 ** -24
-    Ks = abs(lp.scipy().multiply(o.ruiz(10)[0][:, None]).multiply(kap[None, :])).tocsr()
-    cs, qs = kap * lp.c, o.ruiz(10)[0] * lp.rhs
     xb = 2 * xo - xs
-    bx = 4 * u * (np.abs(xo) + np.abs(xs) + eta * (np.abs(cs) + Ks.T @ np.abs(ys)))
-    by = 4 * u * (np.abs(yo) + np.abs(ys) + eta * (np.abs(qs) + Ks @ np.abs(xb)))
-    assert np.all(np.abs(x / kap - xo) <= bx + 1e-30)
-    assert np.all(np.abs(y / rho - yo) <= by + 1e-30)
+    bx = 2 * u * np.abs(xo) + tau * u * (np.abs(cs) + Ks.T @ np.abs(ys))
+    dxb = 2 * bx + u * np.abs(xb)
+    by = sigma * (u * np.abs(qs) + u * (Ks @ np.abs(xb)) + Ks @ dxb) + u * np.abs(yo)
+    return 1.01 * bx + 1e-300, 1.01 * by + 1e-300
 
 
 # ---------------------------------------------------------------------------
@@ -204,11 +221,17 @@ def test_solve_restarted_f64(orc, pd, name):
     assert r["omega0"] == pytest.approx(ro.omega0, rel=1e-12)
 
 
+# the Zipf LP at 1e-5: even the FP64 method stalls above 1e-6 on it within
+# 200,000 iterations (its best check in a CPU replay: 1.3e-6)
+F32_EPS = {"zipf": 1e-5}
+
+
 @pytest.mark.parametrize("name", ["c0", "mixed", "sced_small", "zipf"])
 def test_solve_f32_parity(orc, pd, name):
     lp = _cases()[name]
     o = orc.Oracle(lp)
-    s = pd.Solver(lp, precision="f32", eps=1e-6, max_iters=200000)
+    eps = F32_EPS.get(name, 1e-6)
+    s = pd.Solver(lp, precision="f32", eps=eps, max_iters=200000)
     r = s.solve()[0]
     x, y = s.solution()
     chk = o.kkt(x, y)
@@ -218,7 +241,7 @@ def test_solve_f32_parity(orc, pd, name):
         fref = o.solve(orc.SolveOpts(eps=1e-7, max_iters=2_000_000)).kkt["pobj"]
     print(name, r["status_name"], r["iters"], r["restarts"], r["kkt"]["rel_kkt"], chk["rel_kkt"],
           _rel(chk["pobj"], fref))
-    assert chk["rel_kkt"] <= 1e-4
+    assert r["status_name"] == "OPTIMAL" and chk["rel_kkt"] <= 1.05 * eps, (r["status_name"], chk)
     assert _rel(chk["pobj"], fref) <= 1e-5
 
 
@@ -395,7 +418,7 @@ def test_layouts_solve_f32(orc, pd, li):
     r = s.solve()[0]
     x, y = s.solution()
     chk = orc.Oracle(lp).kkt(x, y)
-    assert chk["rel_kkt"] <= 1e-4, (r["status_name"], chk)
+    assert r["status_name"] == "OPTIMAL" and chk["rel_kkt"] <= 1.05e-5, (r["status_name"], chk)
     assert _rel(chk["pobj"], lp.f_star) <= 1e-5
 
 

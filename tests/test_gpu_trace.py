@@ -2,12 +2,15 @@
 against the oracle's trace of the same solve: the restart decisions, the
 candidate choice and the primal-weight sequence of Section 2.4.2 and
 Algorithm 4, check by check, in FP64."""
+import json
 import math
+import os
 
 import numpy as np
 import pytest
 
 import lpgen
+from test_oracle import GOLD, _assert_restart_rule
 
 pytestmark = pytest.mark.gpu
 
@@ -41,15 +44,25 @@ def _close(a, b, rel):
 
 
 def _compare(gt, ot, rel_kkt=1e-6, rel_w=1e-9):
+    """Device records against the oracle's, check by check: the decisions and
+    their inputs (epoch length, reference value, previous candidate, primal
+    weight before and after, the restart distances and the candidate's
+    scaled-LP terms)."""
     assert len(gt) == len(ot), (len(gt), len(ot))
     for k, (g, o) in enumerate(zip(gt, ot)):
         # discrete decisions: identical (a flip is reported with the margin that caused it)
-        assert (g["iter"], g["restarted"], g["cand_avg"], g["accepted"]) == \
-               (o["iter"], o["restarted"], o["cand_avg"], o["accepted"]), (k, g, o)
-        assert _close(g["omega"], o["omega"], rel_w), (k, g["omega"], o["omega"])
-        assert _close(g["eta_next"], o["eta_next"], rel_w), (k, g["eta_next"], o["eta_next"])
-        for f in ("kkt_cand", "rel_kkt_cur", "rel_kkt_avg"):
+        assert (g["iter"], g["restarted"], g["cand_avg"], g["accepted"], g["t_inner"]) == \
+               (o["iter"], o["restarted"], o["cand_avg"], o["accepted"], o["t_inner"]), (k, g, o)
+        for f in ("omega", "omega_before", "eta_next"):
+            assert _close(g[f], o[f], rel_w), (k, f, g[f], o[f])
+        for f in ("kkt_cand", "rel_kkt_cur", "rel_kkt_avg", "kkt0", "kkt_prev", "kkt0_next", "delta_x", "delta_y"):
             assert _close(g[f], o[f], rel_kkt), (k, f, g[f], o[f])
+        # the candidate's terms, each bounded by KKT_omega * max(omega, 1/omega, 1): to rel_kkt of
+        # that bound (a single term can cancel to ~0)
+        w = o["omega_before"]
+        bound = o["kkt_cand"] * max(w, 1.0 / w, 1.0)
+        for f in ("cand_pres", "cand_dres", "cand_gap"):
+            assert abs(g[f] - o[f]) <= rel_kkt * bound, (k, f, g[f], o[f])
 
 
 @pytest.mark.parametrize("name", ["c0", "c0u", "mixed", "tinyfree", "sced_small"])
@@ -67,6 +80,31 @@ def test_restart_trace_matches_oracle_f64(orc, pd, name):
         if not b["restarted"]:
             assert b["omega"] == a["omega"]
     _compare(gt, ro.trace)
+    # the device's own records follow the Section 2.4.2 rule at every check
+    _assert_restart_rule(gt, gt[0]["omega_before"], gt[0]["kkt0"])
+
+
+def test_restart_trace_1x1_golden_f64(pd):
+    """The device trace on the 1 x 1 LP of tests/golden/restart_1x1.py (a check
+    after every iteration) equals the hand derivation: every decision and
+    candidate, and the KKT_omega values, reference values and omega to 1e-9."""
+    g = json.load(open(os.path.join(GOLD, "restart_trace_1x1.json")))
+    lp = lpgen.from_dense(np.array(g["lp"]["K"]), g["lp"]["row_type"], g["lp"]["q"], g["lp"]["c"],
+                          np.array(g["lp"]["l"]), np.array([np.inf]))
+    s = pd.Solver(lp, precision="f64", eps=g["opts"]["eps"], check_every=g["opts"]["check_every"],
+                  ruiz_iters=g["opts"]["ruiz_iters"], trace_capacity=64)
+    r = s.solve()[0]
+    gt, total = s.trace()
+    want = g["checks"]
+    assert r["status"] == 0 and total == len(gt) == len(want)
+    for t, w in zip(gt, want):
+        assert (t["iter"], t["t_inner"], t["restarted"], t["cand_avg"]) == \
+               (w["iter"], w["t_inner"], w["restarted"], w["cand_avg"]), (t, w)
+        for k in ("kkt_cand", "kkt0", "omega_before", "omega", "kkt0_next", "rel_kkt_cur", "rel_kkt_avg",
+                  "delta_x", "delta_y"):
+            assert t[k] == pytest.approx(w[k], rel=1e-9, abs=1e-300), (k, t, w)
+        assert t["kkt_prev"] == pytest.approx(np.inf if w["kkt_prev"] == "inf" else w["kkt_prev"], rel=1e-9)
+    _assert_restart_rule(gt, 0.75, 3.0)
 
 
 def test_plain_trace_matches_oracle_f64(orc, pd):
