@@ -87,7 +87,7 @@ def sweep_bytes_ad(info, es=4):
     return primal, dual
 
 
-def cpu_baseline(lp, budget_s=15.0):
+def _oracle_rate(lp, budget_s):
     """FP64 CPU oracle iterations/s on this host: two restarted solves that
     differ only in their iteration limit; the rate is the difference of
     iterations over the difference of wall time, so setup cancels.  The
@@ -96,8 +96,6 @@ def cpu_baseline(lp, budget_s=15.0):
 
     import oracle
 
-    oracle.build(force=False)
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     o = oracle.Oracle(lp)
     sc = o.scaled(10)
     x, y = np.zeros(lp.n), np.zeros(lp.m)
@@ -114,10 +112,99 @@ def cpu_baseline(lp, budget_s=15.0):
     r2 = o.solve(opts)
     t2 = time.perf_counter()
     rate = (r2.iters - r1.iters) / max((t2 - t1) - (t1 - t0), 1e-9)
-    return {"value": rate, "unit": "PDHG iter/s", "cores": cores, "kind": "oracle",
-            "sample": f"restarted FP64 oracle solve of the same LP: rate from the difference of two "
-                      f"solves capped at {r1.iters} and {r2.iters} iterations (power iteration capped "
-                      f"at 20 passes in both; setup cancels)"}
+    return rate, r1.iters, r2.iters
+
+
+def _omp_threads():
+    """Threads an OpenMP parallel region of this process uses."""
+    import ctypes
+
+    try:
+        return int(ctypes.CDLL("libgomp.so.1").omp_get_max_threads())
+    except OSError:
+        return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_ONE_CORE = r"""
+import json, sys
+sys.path.insert(0, {root!r})
+import bench, lpgen
+lp = lpgen.sced(500, 200, 24, 125, seed=1) if {small} else lpgen.config1()
+rate, i1, i2 = bench._oracle_rate(lp, {budget})
+print(json.dumps({{"rate": rate, "i1": i1, "i2": i2}}))
+"""
+
+
+def _oracle_time_to_tol(lp, eps=1e-4):
+    import oracle
+
+    o = oracle.Oracle(lp)
+    t = time.perf_counter()
+    r = o.solve(oracle.SolveOpts(eps=eps, max_iters=400_000))
+    return {"seconds": time.perf_counter() - t, "status": {0: "OPTIMAL", 1: "ITERATION_LIMIT"}.get(r.status, r.status),
+            "iters": r.iters, "restarts": r.restarts, "rel_kkt": r.kkt["rel_kkt"]}
+
+
+def oracle_leg(lp, points=None, small=False, budget_s=15.0, ttt_c1=True):
+    """The benchmark's CPU leg: the FP64 oracle as it stands, on this host.
+
+    cpu_baseline: its iteration rate on the same LP with every OpenMP thread
+    of the process and, in a child process, on one thread; its time to a
+    relative KKT error of 1e-4 from a cold start on C0 (and on C1 unless
+    ttt_c1 is off), with the host's CPU model.  checks: the oracle's relative
+    KKT error of each GPU point in ``points`` (name -> (x, y)) on the original
+    LP, and its objective -- the checker side of the FP32 error report."""
+    import subprocess
+
+    import lpgen
+    import oracle
+
+    oracle.build(force=False)
+    rate, i1, i2 = _oracle_rate(lp, budget_s)
+    cpu = {"value": rate, "unit": "PDHG iter/s", "cores": _omp_threads(), "kind": "oracle",
+           "sample": f"restarted FP64 oracle solve of the same LP: rate from the difference of two solves capped "
+                     f"at {i1} and {i2} iterations (power iteration capped at 20 passes in both; setup cancels)",
+           "cpu_model": _cpu_model()}
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    code = _ONE_CORE.format(root=ROOT, small=bool(small), budget=max(budget_s / 2, 5.0))
+    try:
+        out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+        one = json.loads(out.stdout.strip().splitlines()[-1])
+        cpu["value_1core"] = one["rate"]
+        cpu["sample_1core"] = f"the same two solves capped at {one['i1']} and {one['i2']} iterations, one thread"
+    except Exception as e:  # noqa: BLE001 -- the one-core figure is optional
+        cpu["value_1core"] = None
+        cpu["sample_1core"] = f"not measured: {type(e).__name__}"
+    ttt = {"C0": _oracle_time_to_tol(lpgen.config0(0))}
+    if ttt_c1 and not small:
+        ttt["C1"] = _oracle_time_to_tol(lp)
+    cpu["time_to_1e-4"] = ttt
+    return cpu, oracle_checks(lp, points or {})
+
+
+def oracle_checks(lp, points):
+    """Part of the CPU leg: the oracle's relative KKT error and objective of
+    each GPU point (name -> (x, y)) on the original LP."""
+    import oracle
+
+    out = {}
+    if points:
+        o = oracle.Oracle(lp)
+        for name, (x, y) in points.items():
+            k = o.kkt(x, y)
+            out[name] = {"rel_kkt": k["rel_kkt"], "pobj": k["pobj"]}
+    return out
 
 
 def _gen_one(a):
@@ -127,16 +214,17 @@ def _gen_one(a):
     return lpgen.config3_instance(i, m_range=(1000, m_max))
 
 
-def _gen_batched(B, m_max):
-    """The batch's instances, generated by a pool of worker processes (each
-    instance has its own seed, so the result does not depend on the pool)."""
+def _gen_batched(B, m_max, stride=1):
+    """The batch's instances (ids 0, stride, 2 stride, ...), generated by a
+    pool of worker processes (each instance has its own seed, so the result
+    does not depend on the pool)."""
     import multiprocessing as mp
 
     workers = max(1, min(16, (os.cpu_count() or 1), B))
     out = []
     # spawned workers: they share no state with this process (no GPU context)
     with mp.get_context("spawn").Pool(workers) as pool:
-        for i, lp in enumerate(pool.imap(_gen_one, [(i, m_max) for i in range(B)], chunksize=1)):
+        for i, lp in enumerate(pool.imap(_gen_one, [(i * stride, m_max) for i in range(B)], chunksize=1)):
             out.append(lp)
             if (i + 1) % 32 == 0:
                 print(f"[bench] generated {i + 1}/{B}", file=sys.stderr, flush=True)
@@ -154,11 +242,13 @@ def bench_batched(args, emit=True):
     import paper_2508_16806_amd as pd
 
     B = args.batch
+    stride = getattr(args, "stride", 1)
     t = time.perf_counter()
-    lps = _gen_batched(B, args.m_max)
+    lps = _gen_batched(B, args.m_max, stride)
     gen_s = time.perf_counter() - t
     nnz = sum(lp.nnz for lp in lps)
-    print(f"[bench] generated {B} LPs (m <= {args.m_max}), nnz {nnz} in {gen_s:.1f}s", file=sys.stderr, flush=True)
+    print(f"[bench] generated {B} LPs (m <= {args.m_max}, every {stride}. instance), nnz {nnz} in {gen_s:.1f}s",
+          file=sys.stderr, flush=True)
     kw = dict(precision="f32", eps=1e-4, max_iters=200000, time_limit=170.0)
     t0 = time.perf_counter()
     sb = pd.Solver(lps, batch_resident_bytes=args.resident_bytes, **kw)
@@ -199,8 +289,9 @@ def bench_batched(args, emit=True):
     out = {"metric": METRIC, "value": B / tb, "unit": "LPs/s (batched)", "n_gpus": 1, "steps": 1,
            "warmup": 0, "ms_per_step": tb * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": f"{B} planted LPs, m ~ U{{1000..{args.m_max}}}, n = 2.5m, density "
-                                  f"U(0.001, 0.01); total nnz {nnz}; eps 1e-4",
+           "config": {"workload": f"{B} planted LPs (instances 0, {stride}, .., {(B - 1) * stride} of the batched "
+                                  f"recipe), m ~ U{{1000..{args.m_max}}}, n = 2.5m, density U(0.001, 0.01); "
+                                  f"total nnz {nnz}; eps 1e-4",
                       "batch": B, "nnz_total": nnz, "resident_bytes": args.resident_bytes,
                       "bins": {k: kw[k] for k in ("bin_len_primal", "bin_len_dual", "bin_rows_primal",
                                                   "bin_rows_dual", "xcd_remap", "max_grid") if k in kw}
@@ -266,12 +357,14 @@ def bench_adjoint(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_c2(args):
+def bench_c2(args, emit=True, shard_leg=True):
     """C2: the large random LP (m = 1M, n = 2M, Zipf(1.5) row lengths, ~54M
     nonzeros) with its tuned layout: chunked iterations/s, per-kernel times
-    and roofline, the time to 1e-4, and the sweeps of one GPU's share under
-    an 8-way row / column partition (rows m/8 of K with the full gathered
-    xbar; rows n/8 of K^T with the full gathered y), each block timed."""
+    and roofline, the time to 1e-4 (objective gap to the planted optimum),
+    and (shard_leg) the sweeps of one GPU's share under an 8-way row / column
+    partition (rows m/8 of K with the full gathered xbar; rows n/8 of K^T with
+    the full gathered y), each block timed.  Returns (record, lp, point):
+    point is the time-to-tolerance solve's (x, y) for the oracle leg."""
     import numpy as np
     import torch
 
@@ -287,7 +380,7 @@ def bench_c2(args):
     CE = 64
     s = pd.Solver(lp, precision="f32", eps=1e-12, max_iters=CE * max(args.warmup, 1), **tune)
     info = s.info()
-    print(f"[bench] setup {info['setup_seconds']:.2f}s knorm={info['knorm']:.6g}", file=sys.stderr, flush=True)
+    print(f"[bench] C2 setup {info['setup_seconds']:.2f}s knorm={info['knorm']:.6g}", file=sys.stderr, flush=True)
     if args.warmup > 0:
         s.solve()
     s.set_opts(max_iters=CE * args.steps)
@@ -298,15 +391,17 @@ def bench_c2(args):
     dt = time.perf_counter() - t0
     assert r["iters"] == CE * args.steps, r
     ips = r["iters"] / dt
+    if getattr(args, "calib_copy", False):
+        _calib_copy()
     kt = s.time_kernels(reps=20)
     pb, db = sweep_bytes(info, 4)
     pg, dg = pb / (kt["ms_primal"] * 1e-3) / 1e9, db / (kt["ms_dual"] * 1e-3) / 1e9
     dom = "dual" if kt["ms_dual"] >= kt["ms_primal"] else "primal"
     ach = dg if dom == "dual" else pg
-    print(f"[bench] {ips:.1f} iter/s; primal {kt['ms_primal']*1e3:.1f} us ({pg:.0f} GB/s), dual "
+    print(f"[bench] C2 {ips:.1f} iter/s; primal {kt['ms_primal']*1e3:.1f} us ({pg:.0f} GB/s), dual "
           f"{kt['ms_dual']*1e3:.1f} us ({dg:.0f} GB/s), check {kt['ms_check']*1e3:.1f} us", file=sys.stderr,
           flush=True)
-    ttt = None
+    ttt, point = None, None
     if not args.no_ttt:
         s.set_opts(eps=1e-4, max_iters=2_000_000, time_limit=120.0)
         s.set_state(np.zeros(lp.n), np.zeros(lp.m))
@@ -315,35 +410,39 @@ def bench_c2(args):
         rt = s.solve()[0]
         tsec = time.perf_counter() - t0
         x, y = s.solution()
+        point = (x, y)
         ttt = {"seconds": tsec, "status": rt["status_name"], "iters": rt["iters"], "restarts": rt["restarts"],
-               "rel_kkt_fp64_recheck": s.kkt(x, y)["rel_kkt"], "pobj": rt["kkt"]["pobj"],
+               "rel_kkt_gpu": rt["kkt"]["rel_kkt"], "rel_kkt_fp64_recheck": s.kkt(x, y)["rel_kkt"],
+               "pobj": rt["kkt"]["pobj"],
                "rel_obj_gap_vs_planted": abs(rt["kkt"]["pobj"] - lp.f_star) / (1 + abs(lp.f_star)),
                "setup_seconds": info["setup_seconds"]}
-        print(f"[bench] time to 1e-4: {tsec:.2f}s {rt['status_name']} iters={rt['iters']}", file=sys.stderr,
+        print(f"[bench] C2 time to 1e-4: {tsec:.2f}s {rt['status_name']} iters={rt['iters']}", file=sys.stderr,
               flush=True)
     s.close()
     del s
-    # one GPU's share of an 8-way partition, every block
-    P = 8
-    shard = {"parts": P, "dual_ms": [], "primal_ms": [], "dual_gbs": [], "primal_gbs": []}
-    for p in range(P):
-        r0, r1 = p * lp.m // P, (p + 1) * lp.m // P
-        c0, c1 = p * lp.n // P, (p + 1) * lp.n // P
-        for kind, sub in (("dual", lpgen.row_block(lp, r0, r1)), ("primal", lpgen.col_block(lp, c0, c1))):
-            ss = pd.Solver(sub, precision="f32", **tune)
-            si = ss.info()
-            ss.time_kernels(reps=3)
-            k = ss.time_kernels(reps=20)
-            ms = k["ms_" + kind]
-            b = sweep_bytes(si, 4)[0 if kind == "primal" else 1]
-            shard[kind + "_ms"].append(ms)
-            shard[kind + "_gbs"].append(b / (ms * 1e-3) / 1e9)
-            ss.close()
-            del ss, sub
-        print(f"[bench] shard {p}/{P}: dual {shard['dual_ms'][-1]*1e3:.1f} us, primal "
-              f"{shard['primal_ms'][-1]*1e3:.1f} us", file=sys.stderr, flush=True)
-    shard["iter_sweeps_ms_slowest"] = max(shard["dual_ms"]) + max(shard["primal_ms"])
-    shard["full_sweeps_ms_over_parts"] = (kt["ms_dual"] + kt["ms_primal"]) / P
+    shard = None
+    if shard_leg:
+        # one GPU's share of an 8-way partition, every block
+        P = 8
+        shard = {"parts": P, "dual_ms": [], "primal_ms": [], "dual_gbs": [], "primal_gbs": []}
+        for p in range(P):
+            r0, r1 = p * lp.m // P, (p + 1) * lp.m // P
+            c0, c1 = p * lp.n // P, (p + 1) * lp.n // P
+            for kind, sub in (("dual", lpgen.row_block(lp, r0, r1)), ("primal", lpgen.col_block(lp, c0, c1))):
+                ss = pd.Solver(sub, precision="f32", **tune)
+                si = ss.info()
+                ss.time_kernels(reps=3)
+                k = ss.time_kernels(reps=20)
+                ms = k["ms_" + kind]
+                b = sweep_bytes(si, 4)[0 if kind == "primal" else 1]
+                shard[kind + "_ms"].append(ms)
+                shard[kind + "_gbs"].append(b / (ms * 1e-3) / 1e9)
+                ss.close()
+                del ss, sub
+            print(f"[bench] shard {p}/{P}: dual {shard['dual_ms'][-1]*1e3:.1f} us, primal "
+                  f"{shard['primal_ms'][-1]*1e3:.1f} us", file=sys.stderr, flush=True)
+        shard["iter_sweeps_ms_slowest"] = max(shard["dual_ms"]) + max(shard["primal_ms"])
+        shard["full_sweeps_ms_over_parts"] = (kt["ms_dual"] + kt["ms_primal"]) / P
     out = {"metric": METRIC, "value": ips, "unit": "PDHG iter/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -357,7 +456,22 @@ def bench_c2(args):
                         "ms_per_launch": kt["ms_dual" if dom == "dual" else "ms_primal"]},
            "kernels_ms": {k: v for k, v in kt.items() if k != "reps"}, "sweep_gbs": {"primal": pg, "dual": dg},
            "time_to_tol": ttt, "shard": shard, "cpu_baseline": None}
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out, lp, point
+
+
+def _calib_copy():
+    """Three plain 256 MiB device copies: the reference kernel against which
+    the FETCH_SIZE / WRITE_SIZE counters are scaled under rocprofv3 --pmc."""
+    import torch
+
+    a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
 
 
 def main():
@@ -368,7 +482,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance solve")
     ap.add_argument("--no-batched", action="store_true",
-                    help="skip the batched-vs-one-by-one leg of the default run (256 LPs, m <= 10,000)")
+                    help="skip the batched-vs-one-by-one legs of the default run (256 LPs with m <= 10,000; "
+                         "64 LPs over m <= 50,000)")
+    ap.add_argument("--no-c2", action="store_true", help="skip the large Zipf LP leg of the default run")
+    ap.add_argument("--no-shard", action="store_true", help="--workload c2: skip the 8-way share leg")
     ap.add_argument("--small", action="store_true", help="reduced SCED size (for profiling tests)")
     ap.add_argument("--no-tuning", action="store_true", help="default bins instead of the tuned ones")
     ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c3", "c4"],
@@ -402,7 +519,8 @@ def main():
         args.batch = args.batch or 64
         return bench_adjoint(args)
     if args.workload == "c2":
-        return bench_c2(args)
+        bench_c2(args, shard_leg=not args.no_shard)
+        return
     t = time.perf_counter()
     lp = lpgen.sced(500, 200, 24, 125, seed=1) if args.small else lpgen.config1()
     gen_s = time.perf_counter() - t
@@ -434,12 +552,7 @@ def main():
           file=sys.stderr, flush=True)
 
     if args.calib_copy:
-        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
+        _calib_copy()
     kt = s.time_kernels(reps=20)
     pb, db = sweep_bytes(info, 4)
     pg, dg = pb / (kt["ms_primal"] * 1e-3) / 1e9, db / (kt["ms_dual"] * 1e-3) / 1e9
@@ -449,6 +562,7 @@ def main():
           f"primal {pg:.0f} GB/s dual {dg:.0f} GB/s", file=sys.stderr, flush=True)
 
     ttt = None
+    points = {}  # returned points, checked by the oracle leg
     if not args.no_ttt:
         s.set_opts(eps=1e-4, max_iters=2_000_000, time_limit=120.0)
         s.set_state(np.zeros(lp.n), np.zeros(lp.m))
@@ -457,6 +571,7 @@ def main():
         rt = s.solve()[0]
         tsec = time.perf_counter() - t0
         x, y = s.solution()
+        points["time_to_tol"] = (x, y)
         ttt = {"seconds": tsec, "status": rt["status_name"], "iters": rt["iters"],
                "restarts": rt["restarts"], "rel_kkt_gpu": rt["kkt"]["rel_kkt"], "pobj": rt["kkt"]["pobj"],
                "setup_seconds": info["setup_seconds"]}
@@ -480,6 +595,7 @@ def main():
         ra = s.solve()[0]
         tsa = time.perf_counter() - t0
         x, y = s.solution()
+        points["adaptive_step"] = (x, y)
         adaptive["time_to_tol"] = {"seconds": tsa, "status": ra["status_name"], "iters": ra["iters"],
                                    "accepted": ra["accepted"], "restarts": ra["restarts"],
                                    "rel_kkt_fp64_recheck": s.kkt(x, y)["rel_kkt"],
@@ -503,6 +619,7 @@ def main():
         rf = sf.solve()[0]
         tfs = time.perf_counter() - t0
         x, y = sf.solution()
+        points["fishnet"] = (x, y)
         pts = 0
         j = 32
         for r in range(fo["rounds"]):  # live points per round
@@ -512,31 +629,82 @@ def main():
         fish = {"points": 32, "k": 64, "rounds": fo["rounds"], "seconds_fishnet": tfn, "point_iters": pts,
                 "point_iters_per_s": pts / tfn, "seconds_solve_after": tfs, "status": rf["status_name"],
                 "iters_after": rf["iters"], "restarts_after": rf["restarts"],
-                "rel_kkt_fp64_recheck": sf.kkt(x, y)["rel_kkt"], "seconds_total": tfn + tfs}
+                "rel_kkt_fp64_recheck": sf.kkt(x, y)["rel_kkt"], "pobj": rf["kkt"]["pobj"],
+                "seconds_total": tfn + tfs}
         sf.close()
+        del sf
         print(f"[bench] fishnet 32 x 64: {tfn:.3f}s ({pts / tfn:.0f} point-iter/s), then solve to 1e-4 in "
               f"{tfs:.3f}s {rf['status_name']} iters={rf['iters']}", file=sys.stderr, flush=True)
 
-    # batched vs one-by-one LPs/s on 256 planted LPs with m <= 10,000 (the
-    # batched workload's small-m range; --workload c3 runs the full range)
-    batched = None
+    # FP64 reference for the objective gaps of the FP32 points: an FP64 solve
+    # to 1e-8, certified by the oracle leg below
+    ref64 = None
+    if not args.no_ttt and not args.no_cpu_baseline:
+        s64 = pd.Solver(lp, precision="f64", eps=1e-8, max_iters=2_000_000, time_limit=120.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r64 = s64.solve()[0]
+        t64 = time.perf_counter() - t0
+        points["fp64_ref"] = s64.solution()
+        ref64 = {"seconds": t64, "status": r64["status_name"], "iters": r64["iters"], "eps": 1e-8,
+                 "pobj": r64["kkt"]["pobj"]}
+        s64.close()
+        del s64
+        print(f"[bench] FP64 reference to 1e-8: {t64:.2f}s {r64['status_name']} iters={r64['iters']}",
+              file=sys.stderr, flush=True)
+    s.close()
+    del s
+
+    # the large Zipf LP (C2): its iteration rate, dominant sweep and time to 1e-4
+    c2 = c2_lp = c2_point = None
+    if not args.no_c2 and not args.small:
+        c2a = argparse.Namespace(steps=20, warmup=1, no_ttt=args.no_ttt)
+        c2o, c2_lp, c2_point = bench_c2(c2a, emit=False, shard_leg=False)
+        c2 = {k: c2o[k] for k in ("value", "unit", "ms_per_step", "roofline", "kernels_ms", "sweep_gbs",
+                                  "time_to_tol")}
+        c2["workload"] = c2o["config"]["workload"]
+
+    # batched vs one-by-one LPs/s: 256 planted LPs with m <= 10,000 (the
+    # batched workload's small-m range), and 64 of its instances spread over
+    # the full range m <= 50,000 (--workload c3 runs all 256 of them)
+    batched = batched_full = None
     if not args.no_batched and not args.small:
-        s.close()
-        del s
-        ba = argparse.Namespace(batch=256, m_max=10000, resident_bytes=args.resident_bytes)
-        bo = bench_batched(ba, emit=False)
-        batched = {"workload": bo["config"]["workload"], "lps": 256,
-                   "batched_lps_per_s": bo["batched"]["lps_per_s"], "one_by_one_lps_per_s": bo["one_by_one"]["lps_per_s"],
-                   "speedup": bo["speedup"], "iterations_identical": bo["iterations_identical"],
-                   "max_rel_obj_gap_vs_planted": bo["max_rel_obj_gap_vs_planted"]}
+        def _brief(bo):
+            return {"workload": bo["config"]["workload"], "lps": bo["config"]["batch"],
+                    "batched_lps_per_s": bo["batched"]["lps_per_s"],
+                    "one_by_one_lps_per_s": bo["one_by_one"]["lps_per_s"], "speedup": bo["speedup"],
+                    "iterations_identical": bo["iterations_identical"],
+                    "max_rel_obj_gap_vs_planted": bo["max_rel_obj_gap_vs_planted"],
+                    "batched_setup_seconds": bo["batched"]["setup"]["seconds"],
+                    "buckets_one_by_one": bo["one_by_one"]["buckets"]}
+
+        batched = _brief(bench_batched(argparse.Namespace(batch=256, m_max=10000, stride=1,
+                                                          resident_bytes=args.resident_bytes), emit=False))
         print(f"[bench] batched vs one-by-one (256 LPs, m <= 10k): {batched['speedup']:.2f}x", file=sys.stderr,
               flush=True)
+        batched_full = _brief(bench_batched(argparse.Namespace(batch=64, m_max=50000, stride=4,
+                                                               resident_bytes=args.resident_bytes), emit=False))
+        print(f"[bench] batched vs one-by-one (64 LPs over m <= 50k): {batched_full['speedup']:.2f}x",
+              file=sys.stderr, flush=True)
 
+    # the CPU leg: the oracle's rates and times, and its checks of the GPU points
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(lp)
-        print(f"[bench] cpu baseline {cpu['value']:.2f} iter/s on {cpu['cores']} threads", file=sys.stderr,
-              flush=True)
+        cpu, checks = oracle_leg(lp, points, small=args.small)
+        print(f"[bench] cpu baseline {cpu['value']:.2f} iter/s on {cpu['cores']} threads, "
+              f"{cpu.get('value_1core') or 0:.2f} on one", file=sys.stderr, flush=True)
+        if "fp64_ref" in checks:
+            ref64["rel_kkt_oracle"] = checks["fp64_ref"]["rel_kkt"]
+            ref64["certified"] = checks["fp64_ref"]["rel_kkt"] <= 1e-8 * 1.01
+            fref = checks["fp64_ref"]["pobj"]
+            for name, rec in (("time_to_tol", ttt), ("adaptive_step", adaptive.get("time_to_tol")),
+                              ("fishnet", fish)):
+                if rec is not None and name in checks:
+                    rec["rel_kkt_oracle"] = checks[name]["rel_kkt"]
+                    rec["rel_obj_gap_fp64_ref"] = abs(checks[name]["pobj"] - fref) / (1 + abs(fref))
+        if c2_point is not None:
+            c2chk = oracle_checks(c2_lp, {"time_to_tol": c2_point})
+            c2["time_to_tol"]["rel_kkt_oracle"] = c2chk["time_to_tol"]["rel_kkt"]
 
     out = {
         "metric": METRIC,
@@ -565,7 +733,10 @@ def main():
         "time_to_tol": ttt,
         "adaptive_step": adaptive,
         "fishnet": fish,
+        "fp64_reference": ref64,
+        "c2": c2,
         "batched": batched,
+        "batched_full": batched_full,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

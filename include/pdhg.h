@@ -382,7 +382,9 @@ int pdhg_backward(pdhg_handle *h, const double *gx, const double *gy, double *gc
  * iteration (each finds the caches as the other leaves them); likewise the
  * adaptive attempt's primal sweep, dual sweep and step decision.  The packet
  * that each separating event adds is measured (the same sequence timed with
- * events at its ends only) and taken out evenly.  The check,
+ * events at its ends only) and taken out evenly; a kernel shorter than that
+ * packet gets its proportional share of the unseparated total instead (so
+ * every figure is positive).  The check,
  * control and restart kernels, which run once per check interval, are timed
  * back to back.  The sweeps advance the iterate (fixed steps); solver counters
  * are restored.  1 <= reps <= 10000 (one event per launch is created),

@@ -24,18 +24,24 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compiles every source (incremental: only those whose object is older
+    than the source or any header) and links libpdhg.so."""
     os.makedirs(OBJDIR, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include")]
     objs, procs = [], []
+    newest_header = max(os.path.getmtime(h) for h in HEADERS)
     for src in SOURCES:
         obj = os.path.join(OBJDIR, os.path.splitext(os.path.basename(src))[0] + ".o")
+        objs.append(obj)
+        if incremental and os.path.exists(obj) and \
+                os.path.getmtime(obj) > max(os.path.getmtime(src), newest_header):
+            continue
         lang = [] if src.endswith(".hip") else ["-x", "hip"]
         cmd = [HIPCC] + FLAGS + inc + ["-c"] + lang + [src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
-        objs.append(obj)
     failed = False
     for src, p in procs:
         out, _ = p.communicate()
@@ -64,4 +70,4 @@ def stale() -> bool:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, incremental="--incremental" in sys.argv))

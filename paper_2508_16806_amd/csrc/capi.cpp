@@ -1911,7 +1911,10 @@ static int time_impl(pdhg_handle *h, int32_t reps, pdhg_kernel_times *out, hipSt
                 sep += t;
             }
         const double excess = sep > whole ? (sep - whole) / ((double)nk * reps) : 0.0;
-        for (int k = 0; k < nk; ++k) out[k] = std::max(0.0, out[k] / reps - excess);
+        // a kernel shorter than the event packet itself would come out at or
+        // below zero: it then gets its share of the unseparated total instead
+        const double share = sep > 0.0 ? whole / sep : 1.0;
+        for (int k = 0; k < nk; ++k) out[k] = std::max(out[k] / reps - excess, out[k] / reps * share);
     };
     // the two sweeps alternate as in the iteration (each one finds the caches
     // as the other leaves them)
