@@ -291,6 +291,26 @@ size_t pdhg_workspace_bytes(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o
 int pdhg_setup(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, void *ws, size_t ws_bytes,
                hipStream_t stream, pdhg_handle **out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that must not call hipMalloc, harnesses that forbid
+ * it): pdhg_setup with the workspace in a fixed device array that the library
+ * holds on every GPU it runs on (PDHG_NOALLOC_MAX_BYTES bytes, kept until the
+ * process ends).  The call allocates no device memory and no pinned host
+ * memory (pdhg_setup maps a pinned array of done flags; here the flags sit in
+ * the fixed array and pdhg_solve copies them out after each chunk, which ends
+ * its overlap of chunks).  Same arguments, results and errors as pdhg_setup
+ * without ws / ws_bytes; the device is the calling thread's current device and
+ * `stream` (NULL: the null stream) must belong to it.  Errors besides
+ * pdhg_setup's: PDHG_ERR_NOMEM when pdhg_workspace_bytes plus the done flags
+ * exceed PDHG_NOALLOC_MAX_BYTES; PDHG_ERR_STATE while a handle from this call
+ * is still live on the device (one at a time per device: the array keeps the
+ * last handle's contents; pdhg_destroy frees it for the next call).  Calls
+ * that overlap on one device (a second thread setting up while the first
+ * handle runs) are refused, not raced. */
+#define PDHG_NOALLOC_MAX_BYTES (64ull << 20)
+int pdhg_setup_noalloc(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, hipStream_t stream,
+                       pdhg_handle **out);
+
 /* Changes the run-time options of a handle: use_restarts, use_pw_update,
  * check_every, max_iters, eps, time_limit, beta_*, eps_zero, use_graph.  The
  * other fields of *o (precision, scaling, step, power iteration, unroll

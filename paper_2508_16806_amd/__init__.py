@@ -134,7 +134,7 @@ EXPORTS = ["pdhg_default_opts", "pdhg_workspace_bytes", "pdhg_setup", "pdhg_iter
            "pdhg_get_solution", "pdhg_set_state", "pdhg_kkt", "pdhg_backward", "pdhg_get_scaling",
            "pdhg_get_info", "pdhg_time_kernels", "pdhg_set_opts", "pdhg_set_data",
            "pdhg_destroy", "pdhg_last_error", "pdhg_fishnet", "pdhg_fishnet_rounds", "pdhg_autotune",
-           "pdhg_get_trace", "pdhg_last_error_code"]
+           "pdhg_get_trace", "pdhg_last_error_code", "pdhg_setup_noalloc"]
 
 _lib = None
 
@@ -151,6 +151,7 @@ def lib():
         L.pdhg_workspace_bytes.restype = C.c_size_t
         L.pdhg_workspace_bytes.argtypes = [P, I32, C.POINTER(Opts)]
         L.pdhg_setup.argtypes = [P, I32, C.POINTER(Opts), P, C.c_size_t, S, C.POINTER(P)]
+        L.pdhg_setup_noalloc.argtypes = [P, I32, C.POINTER(Opts), S, C.POINTER(P)]
         L.pdhg_iterate.argtypes = [P, I64, I32, S]
         L.pdhg_solve.argtypes = [P, P, S]
         L.pdhg_get_solution.argtypes = [P, I32, I32, P, P, P, I32, S]
@@ -297,10 +298,13 @@ class Solver:
 
     ``lps`` is one LP or a sequence of LPs; an LP is any object with fields
     n, m, rowptr, col, val, row_type, rhs, c, l, u (NumPy arrays, or CUDA torch
-    tensors for device-resident input).
+    tensors for device-resident input).  ``noalloc=True`` sets up through
+    pdhg_setup_noalloc instead: no workspace tensor, the library's fixed
+    per-device array (one such handle per device at a time).
     """
 
-    def __init__(self, lps, device: str = "cuda", opts: Optional[Opts] = None, stream=None, **kw):
+    def __init__(self, lps, device: str = "cuda", opts: Optional[Opts] = None, stream=None,
+                 noalloc: bool = False, **kw):
         import torch
 
         if not torch.cuda.is_available():
@@ -315,6 +319,14 @@ class Solver:
         self.sizes = [(int(lp.n), int(lp.m)) for lp in lps]
         self.device = torch.device(device)
         h = C.c_void_p()
+        if noalloc:
+            self.ws = None
+            with torch.cuda.device(self.device):
+                _check(L.pdhg_setup_noalloc(C.cast(arr, C.c_void_p), self.batch, C.byref(self.opts),
+                                            _stream(stream), C.byref(h)))
+            self.h = h
+            del descs
+            return
         nbytes = L.pdhg_workspace_bytes(C.cast(arr, C.c_void_p), self.batch, C.byref(self.opts))
         if nbytes == 0:
             raise PDHGError(L.pdhg_last_error_code(), L.pdhg_last_error().decode())

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdhg.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "fishnet.hip", "capi.cpp")]
+SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "fishnet.hip", "noalloc.hip", "capi.cpp")]
 HEADERS = [os.path.join(CSRC, f) for f in ("pdhg_internal.h", "sweep.h", "kernels.h")] + \
     [os.path.join(ROOT, "include", "pdhg.h")]
 OBJDIR = os.path.join(HERE, "_build")

@@ -323,6 +323,8 @@ struct pdhg_handle {
     hipStream_t cap_stream = nullptr;
     FishDev fish{};          // fishnet buffers (opts.fishnet_points > 0)
     bool fish_rows = false;  // fish.rowK / rowT hold the rows by decreasing length
+    int32_t noalloc_dev = -1;         // device whose fixed workspace holds this handle (pdhg_setup_noalloc)
+    void *noalloc_owner = nullptr;    // its claim on that workspace
     int64_t rec_steps = 0;  // steps recorded by the last recording pdhg_iterate
     int rec_valid = 0;      // the tape matches the handle's data (cleared by pdhg_set_data)
     int64_t rec_gen = 0;    // bumped by every recording pdhg_iterate and by pdhg_set_data
@@ -1074,8 +1076,11 @@ static int device_setup(pdhg_handle *h, hipStream_t s)
     return PDHG_OK;
 }
 
+// dev_done: NULL keeps the done flags in mapped pinned host memory (polled
+// without a copy); otherwise they live at dev_done in device memory and the
+// solve loop copies them out (pdhg_setup_noalloc)
 static int setup_impl(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, void *ws, size_t ws_bytes,
-                      hipStream_t stream, pdhg_handle **out)
+                      hipStream_t stream, pdhg_handle **out, int32_t *dev_done = nullptr)
 {
     auto t0 = std::chrono::steady_clock::now();
     if (!out) return fail(PDHG_ERR_INVALID_ARG, "out is NULL");
@@ -1130,15 +1135,20 @@ static int setup_impl(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, void
                 (int32_t)h->sz.nblkK, rmK};
     d.Kt = OpDev{h->sz.N, b.Ktrp, b.Ktci, b.Ktv32, b.Ktv64, b.Ktseg, b.Ktbs, b.Ktbd, (int32_t)h->sz.nsegT,
                  (int32_t)h->sz.nblkT, rmT};
-    if (hipHostMalloc((void **)&h->hdone_host, sizeof(int32_t) * batch, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
-        delete h;
-        return fail(PDHG_ERR_HIP, "hipHostMalloc failed");
-    }
-    std::memset(h->hdone_host, 0, sizeof(int32_t) * batch);
-    if (hipHostGetDevicePointer((void **)&d.hdone, h->hdone_host, 0) != hipSuccess) {
-        (void)hipHostFree(h->hdone_host);
-        delete h;
-        return fail(PDHG_ERR_HIP, "hipHostGetDevicePointer failed");
+    if (dev_done) {
+        d.hdone = dev_done;
+    } else {
+        if (hipHostMalloc((void **)&h->hdone_host, sizeof(int32_t) * batch,
+                          hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+            delete h;
+            return fail(PDHG_ERR_HIP, "hipHostMalloc failed");
+        }
+        std::memset(h->hdone_host, 0, sizeof(int32_t) * batch);
+        if (hipHostGetDevicePointer((void **)&d.hdone, h->hdone_host, 0) != hipSuccess) {
+            (void)hipHostFree(h->hdone_host);
+            delete h;
+            return fail(PDHG_ERR_HIP, "hipHostGetDevicePointer failed");
+        }
     }
     rc = upload(h, hosts, stream);
     hosts.clear();
@@ -1170,12 +1180,81 @@ extern "C" int pdhg_setup(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, 
     }
 }
 
+extern "C" int pdhg_setup_noalloc(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, hipStream_t stream,
+                                  pdhg_handle **out)
+{
+    if (!out) return fail(PDHG_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (stream) {
+        int sdev = -1;
+        HIPCHK(hipStreamGetDevice(stream, &sdev));
+        if (sdev != dev) return fail(PDHG_ERR_INVALID_ARG, "stream belongs to device %d, current device is %d", sdev, dev);
+    }
+    pdhg_opts def;
+    if (!o) {
+        pdhg_default_opts(&def);
+        o = &def;
+    }
+    const size_t need = pdhg_workspace_bytes(lp, batch, o);
+    if (need == 0) return g_err_code;  // the sizing call's own error
+    // the done flags follow the workspace in the same array
+    const size_t flags_off = (need + 255) & ~(size_t)255;
+    const size_t total = flags_off + sizeof(int32_t) * (size_t)batch;
+    if (total > (size_t)PDHG_NOALLOC_MAX_BYTES)
+        return fail(PDHG_ERR_NOMEM, "pdhg_setup_noalloc: the LP needs %zu bytes, the fixed workspace holds %zu "
+                    "(use pdhg_setup with a caller workspace)", total, (size_t)PDHG_NOALLOC_MAX_BYTES);
+    int8_t *owner = nullptr;
+    try {
+        // the claim's token lives as long as the handle (pdhg_destroy releases it)
+        owner = new int8_t;
+        void *ptr = nullptr;
+        int busy = 0;
+        const hipError_t e = noalloc_claim(dev, owner, &ptr, &busy);
+        if (e != hipSuccess) {
+            delete owner;
+            if (busy)
+                return fail(PDHG_ERR_STATE, "a handle from pdhg_setup_noalloc is still live on device %d "
+                            "(pdhg_destroy it first)", dev);
+            return fail(PDHG_ERR_HIP, "locating the fixed workspace on device %d: %s", dev, hipGetErrorString(e));
+        }
+        pdhg_handle *h = nullptr;
+        const int rc = setup_impl(lp, batch, o, ptr, need, stream, &h, (int32_t *)((char *)ptr + flags_off));
+        if (rc) {
+            noalloc_release(dev, owner);
+            delete owner;
+            return rc;
+        }
+        h->noalloc_dev = dev;
+        h->noalloc_owner = owner;
+        *out = h;
+        return PDHG_OK;
+    } catch (const std::bad_alloc &) {
+        if (owner) {
+            noalloc_release(dev, owner);
+            delete owner;
+        }
+        return fail(PDHG_ERR_NOMEM, "setup: host memory exhausted");
+    } catch (...) {
+        if (owner) {
+            noalloc_release(dev, owner);
+            delete owner;
+        }
+        return fail(PDHG_ERR_INVALID_ARG, "setup: unexpected host error");
+    }
+}
+
 extern "C" void pdhg_destroy(pdhg_handle *h)
 {
     if (!h) return;
     if (h->graph) (void)hipGraphExecDestroy(h->graph);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     if (h->hdone_host) (void)hipHostFree(h->hdone_host);
+    if (h->noalloc_owner) {
+        noalloc_release(h->noalloc_dev, h->noalloc_owner);
+        delete (int8_t *)h->noalloc_owner;
+    }
     delete h;
 }
 
@@ -1289,7 +1368,10 @@ static int solve_impl(pdhg_handle *h, pdhg_result *res, hipStream_t s)
         x.prev_ok = 0;
         x.ntrace = 0;
     }
-    std::memset(h->hdone_host, 0, sizeof(int32_t) * B);
+    if (h->hdone_host)
+        std::memset(h->hdone_host, 0, sizeof(int32_t) * B);
+    else
+        HIPCHK(hipMemsetAsync(d.hdone, 0, sizeof(int32_t) * B, s));
     HIPCHK(hipMemcpyAsync(d.st, st.data(), B * sizeof(InstState), hipMemcpyHostToDevice, s));
     launch_active(d, s);
     launch_epoch_start<T>(d, s);
@@ -1308,9 +1390,18 @@ static int solve_impl(pdhg_handle *h, pdhg_result *res, hipStream_t s)
     for (int k = 0; k < DEPTH; ++k) HIPCHK(hipEventCreateWithFlags(&ev[k], hipEventDisableTiming));
     HIPCHK(hipEventRecord(ev[0], s));
     HIPCHK(hipEventSynchronize(ev[0]));
+    std::vector<int32_t> flags(h->hdone_host ? 0 : B);
     auto all_done = [&]() {
+        const int32_t *f = (const int32_t *)h->hdone_host;
+        if (!f) {
+            // device-resident flags: copy them out (waits for the chunks in flight)
+            if (hipMemcpyAsync(flags.data(), d.hdone, sizeof(int32_t) * B, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return false;
+            f = flags.data();
+        }
         for (int b = 0; b < B; ++b)
-            if (!((volatile int32_t *)h->hdone_host)[b]) return false;
+            if (!((volatile const int32_t *)f)[b]) return false;
         return true;
     };
     const double tl = h->opts.time_limit;

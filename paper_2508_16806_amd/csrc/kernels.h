@@ -88,4 +88,8 @@ void launch_adj_out(const Dev &d, const AdjBufs &a, double *gc, double *gq, doub
 void launch_set_raw(const Dev &d, const double *c, const double *q, const double *l, const double *u,
                     hipStream_t s);
 
+// the fixed workspace of pdhg_setup_noalloc (noalloc.hip)
+hipError_t noalloc_claim(int dev, const void *owner, void **ptr, int *busy);
+void noalloc_release(int dev, const void *owner);
+
 }  // namespace pdhg

@@ -72,6 +72,7 @@ int main(void) {
     F(pdhg_trace_rec, t_inner) F(pdhg_trace_rec, kkt0) F(pdhg_trace_rec, cand_gap)
     F(pdhg_info, power_iters_max) F(pdhg_info, record_valid) F(pdhg_info, record_generation)
     F(pdhg_opts, trace_capacity) F(pdhg_result, eta_next)
+    printf("noalloc %llu\n", (unsigned long long)PDHG_NOALLOC_MAX_BYTES);
     return 0;
 }
 """
@@ -99,6 +100,7 @@ def test_ctypes_mirrors_match_the_c_header(pd, tmp_path):
         parts = key.split()
         if len(parts) == 2 and parts[1] != "size" and parts[0] in mirrors:
             assert getattr(mirrors[parts[0]], parts[1]).offset == off, key
+    assert got["noalloc"] == 64 << 20
 
 
 def _nbytes(pd, lp, **kw):
