@@ -178,6 +178,17 @@ typedef struct {
      * last trace_capacity records of the solve, read with pdhg_get_trace.
      * The solve loop never waits for them. */
     int32_t trace_capacity;
+    /* Column slices of the dual sweep (the product K~ xbar of Algorithm 1),
+     * 0 or 1: none (default).  With S in 2..16, every row of K~ with at least
+     * 16 S entries is swept in S passes over the column ranges
+     * [s n/S, (s+1) n/S) of its instance (FP64 partial sums per row; the last
+     * pass adds them in pass order and updates y), so each pass gathers from
+     * an n/S-entry slice of xbar that stays in one XCD's L2.  Such rows keep
+     * their entries grouped by slice, are binned by their per-slice length,
+     * and every product over them sums in that order.  Applies to pdhg_solve
+     * with fixed steps and to pdhg_iterate without recording; the adaptive
+     * step, the recorded steps of the adjoint and fishnet sweep whole rows. */
+    int32_t col_slices;
 } pdhg_opts;
 
 /* Relative KKT error terms (Section 2.3.2, conditions term1-term3) on the
@@ -418,6 +429,8 @@ int pdhg_time_kernels(pdhg_handle *h, int32_t reps, pdhg_kernel_times *out, hipS
  *   rows per lane group in bins 0..4: 1, 2 or 4, best per operator;
  *   launch shape: xcd_remap in {0, 1} x max_grid in {4096, 8192, 16384,
  *          65536}, best by primal + dual + check / check_every;
+ *   col_slices of the dual sweep in {0, 2, 4, 8} on that layout, by the
+ *          same sum;
  * every other option is taken from *base.  *best receives the chosen
  * options; out_json (may be NULL) a JSON record of every trial and the
  * choice.  Each trial sets the LP up in the caller's workspace `ws`, which

@@ -87,6 +87,7 @@ extern "C" void pdhg_default_opts(pdhg_opts *o)
     o->fishnet_points = 0;
     o->batch_resident_bytes = 192000000;
     o->trace_capacity = 0;
+    o->col_slices = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -180,7 +181,11 @@ static int load_lp(const pdhg_lp &in, HostLP &h, bool pattern_only)
 struct SegH {
     int64_t row0;  // local row within the instance's internal order
     int32_t nrows, lanes_log2, ineq;
+    int32_t sliced = 0;  // rows swept in column slices (dual operator)
 };
+
+// rows of K swept in column slices: at least 16 entries per slice
+static bool row_sliced(int64_t len, int S) { return S > 1 && len >= 16 * (int64_t)S; }
 
 struct InstPlan {
     int64_t n, m, m1, nnz;
@@ -226,26 +231,33 @@ static int seg_group(int code)
     return (lanes_log2 >= 8 ? 1 : (WG >> lanes_log2)) << rows_log2;
 }
 
-static void plan_instance(const HostLP &h, const Bins &bins, const Bins &tbins, InstPlan &p)
+static void plan_instance(const HostLP &h, const Bins &bins, const Bins &tbins, int S, InstPlan &p)
 {
     p.n = h.n;
     p.m = h.m;
     p.m1 = h.m1;
     p.nnz = h.nnz;
-    // rows: ">=" group then "=" group, each ordered by bin, stable
-    std::vector<std::vector<int32_t>> buck(2 * NBIN);
+    // rows: ">=" group then "=" group, each split into whole rows and rows
+    // swept in S column slices (binned by their per-slice length), each
+    // ordered by bin, stable
+    std::vector<std::vector<int32_t>> buck(4 * NBIN);
     for (int64_t i = 0; i < h.m; ++i) {
         const int eq = h.rt ? (h.rt[i] == PDHG_ROW_EQ) : 1;
-        buck[eq * NBIN + bin_of(bins, h.rp[i + 1] - h.rp[i])].push_back((int32_t)i);
+        const int64_t len = h.rp[i + 1] - h.rp[i];
+        const int sl = row_sliced(len, S) ? 1 : 0;
+        const int64_t blen = sl ? (len + S - 1) / S : len;
+        buck[(2 * eq + sl) * NBIN + bin_of(bins, blen)].push_back((int32_t)i);
     }
     p.row_order.clear();
     p.row_order.reserve(h.m);
     p.segK.clear();
-    for (int g = 0; g < 2; ++g)
+    for (int g = 0; g < 4; ++g)
         for (int b = 0; b < NBIN; ++b) {
             auto &v = buck[g * NBIN + b];
             if (v.empty()) continue;
-            p.segK.push_back({(int64_t)p.row_order.size(), (int32_t)v.size(), bins.code[b], g == 0});
+            SegH sh{(int64_t)p.row_order.size(), (int32_t)v.size(), bins.code[b], g < 2};
+            sh.sliced = g & 1;
+            p.segK.push_back(sh);
             p.row_order.insert(p.row_order.end(), v.begin(), v.end());
         }
     // columns: ordered by bin of their entry count, stable
@@ -301,6 +313,7 @@ struct Buffers {
     double *vecN64c;
     int32_t *l2inst;
     int64_t *bcumK, *bcumT;  // block cost prefix sums
+    int32_t *Ksb;            // column-slice starts of every row of K (col_slices > 1)
 };
 
 struct pdhg_handle {
@@ -397,6 +410,11 @@ static void carve(Carve &cv, const Sizes &sz, int prec, const pdhg_opts &o, Dev 
     d.kx1 = cv.take<double>(M);
     d.xam = cv.take<char>(N * es);
     d.yam = cv.take<char>(M * es);
+    const int S = o.col_slices > 1 ? o.col_slices : 1;
+    d.col_slices = S;
+    b.Ksb = S > 1 ? cv.take<int32_t>((size_t)M * (S - 1)) : nullptr;
+    d.ksb = b.Ksb;
+    d.kpart = S > 1 ? cv.take<double>(M) : nullptr;
     d.actK = cv.take<int32_t>(sz.nblkK + 1);
     d.actT = cv.take<int32_t>(sz.nblkT + 1);
     d.act_cnt = cv.take<int32_t>(2);
@@ -488,6 +506,8 @@ static int check_opts(const pdhg_opts *o)
         if (o->bin_len_dual[k] < 0 || o->bin_len_primal[k] < 0)
             return fail(PDHG_ERR_INVALID_ARG, "bin_len[%d] must be >= 0", k);
     }
+    if (o->col_slices < 0 || o->col_slices > 16)
+        return fail(PDHG_ERR_INVALID_ARG, "col_slices must be in 0..16");
     if (o->trace_capacity < 0 || o->trace_capacity > (1 << 20))
         return fail(PDHG_ERR_INVALID_ARG, "trace_capacity must be in 0..2^20");
     return PDHG_OK;
@@ -611,7 +631,7 @@ static int plan_all(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, std::v
                 msgs[b] = g_err;  // the message is per thread
                 return;
             }
-            plan_instance(hosts[b], bins, tbins, plans[b]);
+            plan_instance(hosts[b], bins, tbins, o->col_slices, plans[b]);
         } catch (...) {
             rcs[b] = PDHG_ERR_NOMEM;
             msgs[b] = "host memory exhausted";
@@ -698,6 +718,8 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
     std::vector<int32_t> Kbs(sz.nblkK), Ktbs(sz.nblkT);
     std::vector<int4> Kbd(sz.nblkK), Ktbd(sz.nblkT);
     hvec<double> Kv(sz.NNZ), Ktv(sz.NNZ);
+    const int S = h->opts.col_slices > 1 ? h->opts.col_slices : 1;
+    hvec<int32_t> Ksb(S > 1 ? (size_t)sz.M * (S - 1) : 0);
     const int HT = host_threads();
     std::vector<Seg> Kseg, Ktseg;
     std::vector<int32_t> l2inst;
@@ -743,13 +765,32 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
             }
         }
         const int64_t pos = zo[bi + 1];
+        // a row swept in S column slices lists its entries slice by slice
+        // (internal columns [s W, (s + 1) W), W = ceil(n / S); caller order
+        // within a slice) and records where slices 1 .. S-1 begin
+        const int64_t W = S > 1 ? std::max<int64_t>(1, (p.n + S - 1) / S) : 1;
         parallel_ranges(p.m, 4096, HT, [&](int, int64_t i0, int64_t i1) {
+            std::vector<int64_t> cnt(S + 1);
             for (int64_t i = i0; i < i1; ++i) {
                 const int32_t r = p.row_order[i];
                 int64_t q = Krp[yoff + i];
-                for (int64_t k = lp.rp[r]; k < lp.rp[r + 1]; ++k, ++q) {
-                    Kci[q] = (int32_t)(xoff + col_new[lp.ci[k]]);
-                    Kv[q] = lp.v[k];
+                const int64_t len = lp.rp[r + 1] - lp.rp[r];
+                if (row_sliced(len, S)) {
+                    std::fill(cnt.begin(), cnt.end(), 0);
+                    for (int64_t k = lp.rp[r]; k < lp.rp[r + 1]; ++k) cnt[1 + col_new[lp.ci[k]] / W]++;
+                    for (int t = 1; t <= S; ++t) cnt[t] += cnt[t - 1];
+                    for (int t = 1; t < S; ++t) Ksb[(size_t)(yoff + i) * (S - 1) + (t - 1)] = (int32_t)cnt[t];
+                    for (int64_t k = lp.rp[r]; k < lp.rp[r + 1]; ++k) {
+                        const int64_t dst = q + cnt[col_new[lp.ci[k]] / W]++;
+                        Kci[dst] = (int32_t)(xoff + col_new[lp.ci[k]]);
+                        Kv[dst] = lp.v[k];
+                    }
+                } else {
+                    for (int t = 1; t < S; ++t) Ksb[(size_t)(yoff + i) * (S - 1) + (t - 1)] = 0;
+                    for (int64_t k = lp.rp[r]; k < lp.rp[r + 1]; ++k, ++q) {
+                        Kci[q] = (int32_t)(xoff + col_new[lp.ci[k]]);
+                        Kv[q] = lp.v[k];
+                    }
                 }
                 row_orig[yoff + i] = r;
                 inst_row[yoff + i] = bi;
@@ -868,12 +909,13 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
             sg.lanes_log2 = sh.lanes_log2;
             sg.inst = bi;
             sg.ineq = sh.ineq;
+            sg.sliced = sh.sliced;
             for (int t = 0; t < sg.nblk; ++t) {
                 Kbs[blkK + t] = (int32_t)Kseg.size();
                 const int G = seg_group(sg.lanes_log2);
                 const int64_t r0 = sg.row0 + (int64_t)t * G;
                 const int nr = (int)std::min<int64_t>(G, sg.row0 + sg.nrows - r0);
-                Kbd[blkK + t] = make_int4((int)r0, nr, bi, sg.lanes_log2 | (sg.ineq << 8));
+                Kbd[blkK + t] = make_int4((int)r0, nr, bi, sg.lanes_log2 | (sg.ineq << 8) | (sg.sliced << 9));
             }
             blkK += sg.nblk;
             Kseg.push_back(sg);
@@ -905,6 +947,8 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
         in.l2cnt = (int32_t)((in.blkK1 - in.blkK0 + in.blkT1 - in.blkT0 + L2CH - 1) / L2CH);
         for (int t = 0; t < in.l2cnt; ++t) l2inst.push_back(bi);
     }
+    // no row long enough to slice: one whole-row pass
+    if (std::none_of(Kseg.begin(), Kseg.end(), [](const Seg &g) { return g.sliced != 0; })) d.col_slices = 1;
     // block costs for the XCD split of the sweeps: entries + 4 per row
     std::vector<int64_t> cumK(sz.nblkK + 1, 0), cumT(sz.nblkT + 1, 0);
     for (int64_t t = 0; t < sz.nblkK; ++t)
@@ -935,7 +979,8 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
         (rc = h2d(d.inst_of_col, inst_col.data(), inst_col.size(), s)) ||
         (rc = h2d(d.inst_of_row, inst_row.data(), inst_row.size(), s)) ||
         (rc = h2d((InstInfo *)d.info, h->info.data(), h->info.size(), s)) ||
-        (rc = h2d(b.l2inst, l2inst.data(), l2inst.size(), s)))
+        (rc = h2d(b.l2inst, l2inst.data(), l2inst.size(), s)) ||
+        (S > 1 && (rc = h2d(b.Ksb, Ksb.data(), Ksb.size(), s))))
         return rc;
     // the host images die with this scope: wait for the copies
     HIPCHK(hipStreamSynchronize(s));
@@ -1489,6 +1534,8 @@ template <typename T>
 static int iterate_impl(pdhg_handle *h, int64_t k, int32_t record, hipStream_t s)
 {
     Dev d = h->d;
+    // recorded steps sweep whole rows, as the adjoint's replay of them does
+    if (record) d.col_slices = 1;
     // fixed steps use the handle's tau / sigma and ignore done flags
     std::vector<InstState> st = h->st0;
     for (auto &x : st) x.done = 0;
@@ -2127,6 +2174,14 @@ std::vector<pdhg_opts> tune_stage(const pdhg_opts &base, int stage, const pdhg_o
             out.push_back(o);
             if (tag) tag->push_back(r);
         }
+    } else if (stage == 3) {
+        // column slices of the dual sweep, on the chosen layout (bp)
+        for (int S : {0, 2, 4, 8}) {
+            pdhg_opts o = bp;
+            o.col_slices = S;
+            out.push_back(o);
+            if (tag) tag->push_back(S);
+        }
     } else {
         for (int remap : {0, 1})
             for (int grid : {4096, 8192, 16384, 65536}) {
@@ -2183,38 +2238,45 @@ static int autotune_impl(const pdhg_lp *lp, int32_t batch, const pdhg_opts *base
     // workspace: every candidate pairs one of the stage-0 limit sets per
     // operator with rows per group >= 1, so the largest workspace has at most
     // the most blocks and segments any limit set gives with one row per group
+    // (and with every column-slice count of the last stage, whose sliced rows
+    // form segments and blocks of their own)
+    const int slice_cand[] = {base->col_slices, 0, 2, 4, 8};
     Sizes bound{};
     {
         std::vector<int> t0;
-        for (pdhg_opts o : tune_stage(*base, 0, *base, *base, &t0)) {
-            for (int k = 0; k < 8; ++k) o.bin_rows_primal[k] = o.bin_rows_dual[k] = 1;
-            std::vector<HostLP> hosts;
-            std::vector<InstPlan> plans;
-            Sizes sz;
-            const int rc = plan_all(lp, batch, &o, hosts, plans, sz, true);
-            if (rc) {
-                if (ws_needed) *ws_needed = 0;
-                return rc;
+        for (pdhg_opts o : tune_stage(*base, 0, *base, *base, &t0))
+            for (int S : slice_cand) {
+                for (int k = 0; k < 8; ++k) o.bin_rows_primal[k] = o.bin_rows_dual[k] = 1;
+                o.col_slices = S;
+                std::vector<HostLP> hosts;
+                std::vector<InstPlan> plans;
+                Sizes sz;
+                const int rc = plan_all(lp, batch, &o, hosts, plans, sz, true);
+                if (rc) {
+                    if (ws_needed) *ws_needed = 0;
+                    return rc;
+                }
+                bound.N = sz.N, bound.M = sz.M, bound.NNZ = sz.NNZ, bound.batch = sz.batch;
+                bound.nsegK = std::max(bound.nsegK, sz.nsegK);
+                bound.nsegT = std::max(bound.nsegT, sz.nsegT);
+                bound.nblkK = std::max(bound.nblkK, sz.nblkK);
+                bound.nblkT = std::max(bound.nblkT, sz.nblkT);
             }
-            bound.N = sz.N, bound.M = sz.M, bound.NNZ = sz.NNZ, bound.batch = sz.batch;
-            bound.nsegK = std::max(bound.nsegK, sz.nsegK);
-            bound.nsegT = std::max(bound.nsegT, sz.nsegT);
-            bound.nblkK = std::max(bound.nblkK, sz.nblkK);
-            bound.nblkT = std::max(bound.nblkT, sz.nblkT);
-        }
         // second-level rows: sum over instances of ceil((K + K^T blocks) / L2CH)
         bound.nl2 = (bound.nblkK + bound.nblkT + L2CH - 1) / L2CH + batch;
     }
-    size_t need;
-    {
+    size_t need = 0;
+    for (int S : slice_cand) {
         Carve cv;
         Dev d{};
         Buffers b{};
         InstInfo *info;
         InstState *st;
         FishDev fish{};
-        carve(cv, bound, base->precision, *base, d, b, &info, &st, &fish);
-        need = (cv.off + 255) & ~(size_t)255;
+        pdhg_opts o = *base;
+        o.col_slices = S;
+        carve(cv, bound, base->precision, o, d, b, &info, &st, &fish);
+        need = std::max(need, (cv.off + 255) & ~(size_t)255);
     }
     if (ws_needed) *ws_needed = need;
     if (!ws || ws_bytes < need)
@@ -2272,6 +2334,19 @@ static int autotune_impl(const pdhg_lp *lp, int32_t batch, const pdhg_opts *base
               jnum(kt.ms_primal) + ", \"ms_dual\": " + jnum(kt.ms_dual) +
               ", \"ms_check\": " + jnum(kt.ms_check) + ", \"ms_iter\": " + jnum(it) + "}";
     }
+    js += "], \"slice_trials\": [";
+    tag.clear();
+    nt = 0;
+    for (const pdhg_opts &o : tune_stage(*base, 3, shape, shape, &tag)) {
+        pdhg_kernel_times kt;
+        const int rc = tune_time(lp, batch, o, ws, ws_bytes, reps, s, &kt);
+        if (rc) return rc;
+        const double it = kt.ms_primal + kt.ms_dual + kt.ms_check / std::max(1, base->check_every);
+        if (it < best_it) best_it = it, shape = o, best_kt = kt;
+        js += std::string(nt ? ", " : "") + "{\"col_slices\": " + std::to_string(tag[nt]) + ", \"ms_dual\": " +
+              jnum(kt.ms_dual) + ", \"ms_iter\": " + jnum(it) + "}";
+        ++nt;
+    }
     *best = shape;
     js += "], ";
     json_ints(js, "bin_len_primal", shape.bin_len_primal);
@@ -2282,6 +2357,7 @@ static int autotune_impl(const pdhg_lp *lp, int32_t batch, const pdhg_opts *base
     js += ", ";
     json_ints(js, "bin_rows_dual", shape.bin_rows_dual);
     js += ", \"xcd_remap\": " + std::to_string(shape.xcd_remap) + ", \"max_grid\": " + std::to_string(shape.max_grid) +
+          ", \"col_slices\": " + std::to_string(shape.col_slices) +
           ", \"ms_primal\": " + jnum(best_kt.ms_primal) + ", \"ms_dual\": " + jnum(best_kt.ms_dual) +
           ", \"precision\": \"" + (base->precision == PDHG_PREC_F64 ? "f64" : "f32") + "\"}\n";
     if (out_json) {

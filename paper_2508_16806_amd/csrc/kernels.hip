@@ -148,6 +148,85 @@ __global__ __launch_bounds__(WG) void k_dual(Dev d, int j_in_chunk, uint8_t *__r
     });
 }
 
+// The dual sweep in column slices (opts.col_slices = S > 1), pass `pass` of
+// S.  Rows of sliced segments take the product over their entries in column
+// slice `pass` only, so a pass gathers from one n/S-entry slice of xbar, which
+// stays in the L2 of each XCD.  LAST = 0 (passes 0 .. S-2) touches only the
+// sliced rows and only their FP64 partial products in kpart: pass 0 writes
+// them, later passes add theirs.  LAST = 1 (pass S-1) adds its slice to the
+// partial, sweeps the rows of unsliced segments whole, and updates y and its
+// average exactly as k_dual does.  Keeping the partial store and the y store
+// in different kernels leaves each launch a single store target per row.
+template <typename T, int AVG, int RM, int LAST>
+__global__ __launch_bounds__(WG) void k_dual_slice(Dev d, int j_in_chunk, int pass)
+{
+    __shared__ double red[8];
+    const OpDev &op = d.K;
+    T *__restrict__ y = (T *)d.y;
+    T *__restrict__ ya = (T *)d.yavg;
+    const T *__restrict__ y0 = (const T *)d.y0;
+    const T *__restrict__ q = (const T *)d.q;
+    const T *__restrict__ xb = (const T *)d.xbar;
+    double *__restrict__ part = d.kpart;
+    const int S = d.col_slices;
+    const int cnt = d.act_cnt[0];
+    const bool full = cnt == op.nblk;
+    for_each_item_split(cnt, d.remap, d.act_split, j_in_chunk & 1, [&](int it) {
+        const int lb = full ? it : d.actK[it];
+        const Seg s = block_seg(op, lb);
+        if (!LAST && !s.sliced) return;
+        const int bi = lb - s.blk0;
+        dispatch_lanes<RM>(s.lanes_log2, [&](auto tag, auto rtag) {
+            constexpr int L = decltype(tag)::value, R = decltype(rtag)::value;
+            using RS = RowSweep<L, 1, T, T, R, false, true, true>;
+            const typename RS::Pos ps = RS::locate(s, bi);
+            if constexpr (!LAST) {
+                double acc[R][1];
+                RS::dot(op, ps, xb, nullptr, nullptr, red, acc, d.ksb, S, pass);
+                if (ps.leader) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        if (r >= ps.nvalid) break;
+                        const int64_t i = ps.row0 + r;
+                        part[i] = pass > 0 ? part[i] + acc[r][0] : acc[r][0];
+                    }
+                }
+            } else {
+                const InstState *st = d.st + s.inst;
+                const double sigma = st->sigma;
+                const double w = AVG ? 1.0 / (double)(st->t_inner + j_in_chunk + 1) : 0.0;
+                const bool ineq = s.ineq != 0;
+                T r_y[R], r_q[R], r_a[R], r_0[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int64_t ii = r < ps.nvalid ? ps.row0 + r : ps.blk_row0;
+                    r_y[r] = y[ii];
+                    r_q[r] = q[ii];
+                    r_a[r] = AVG ? ya[ii] : T(0);
+                    r_0[r] = AVG ? y0[ii] : T(0);
+                }
+                double acc[R][1];
+                // one slice, the whole row, for the rows of unsliced segments
+                RS::dot(op, ps, xb, nullptr, nullptr, red, acc, d.ksb, s.sliced ? S : 1, s.sliced ? pass : 0);
+                if (ps.leader) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        if (r >= ps.nvalid) break;
+                        const int64_t i = ps.row0 + r;
+                        const double a = s.sliced ? part[i] + acc[r][0] : acc[r][0];
+                        const double yo = (double)r_y[r], qi = (double)r_q[r], yav = (double)r_a[r];
+                        const double wv = yo + sigma * (qi - a);
+                        const double yn = (ineq && wv < 0.0) ? 0.0 : wv;
+                        const T ynT = (T)yn;
+                        y[i] = ynT;
+                        if (AVG) ya[i] = (T)(yav + (((double)ynT - (double)r_0[r]) - yav) * w);
+                    }
+                }
+            }
+        });
+    });
+}
+
 // ---------------------------------------------------------------------------
 // adaptive step size (Section 2.4.4, Algorithm 5)
 //
@@ -1623,6 +1702,19 @@ template <typename T>
 void launch_dual(const Dev &d, int j, int avg, uint8_t *mask, hipStream_t s)
 {
     const unsigned g = sweep_grid(d, d.K.nblk);
+    if (d.col_slices > 1 && !mask) {
+        // column-sliced sweep: S passes (the recorded steps sweep whole rows)
+        const int last = d.col_slices - 1;
+        RM_SWITCH(d.K.rmax, {
+            for (int pass = 0; pass < last; ++pass) LAUNCH((k_dual_slice<T, 0, RMV, 0>), g, d, j, pass);
+            if (avg) {
+                LAUNCH((k_dual_slice<T, 1, RMV, 1>), g, d, j, last);
+            } else {
+                LAUNCH((k_dual_slice<T, 0, RMV, 1>), g, d, j, last);
+            }
+        });
+        return;
+    }
     RM_SWITCH(d.K.rmax, {
         if (mask) {
             LAUNCH((k_dual<T, 0, 1, RMV>), g, d, j, mask);

@@ -49,6 +49,7 @@ struct Seg {
     int32_t lanes_log2; // log2 of lanes per row: 0..6, or 8 (whole workgroup)
     int32_t inst;
     int32_t ineq;       // rows of this segment are ">=" rows (dual operator only)
+    int32_t sliced;     // rows swept in column slices (dual operator, opts.col_slices)
 };
 
 struct OpDev {
@@ -59,7 +60,7 @@ struct OpDev {
     const double *v64;   // scaled values, FP64 (after setup)
     const Seg *seg;
     const int32_t *blk_seg;
-    const int4 *bdesc;   // per logical block: {first row, rows, instance, lanes_log2 | ineq << 8}
+    const int4 *bdesc;   // per logical block: {first row, rows, instance, lanes_log2 | ineq << 8 | sliced << 9}
     int32_t nseg;
     int32_t nblk;
     int32_t rmax;        // largest rows per lane group in any block (1, 2, 4)
@@ -169,6 +170,12 @@ struct Dev {
     double *vecN64, *vecN64b;     // FP64 scratch vectors (N)
     double *vecM64, *vecM64b;     // FP64 scratch vectors (M)
     double *inst_scratch;         // batch * 16
+    // column slices of the dual sweep (opts.col_slices = S > 1): for every
+    // row of K, the offsets (from the row's first entry) where slices
+    // 1 .. S-1 begin, and the FP64 partial products of the sliced rows
+    int32_t col_slices;
+    const int32_t *ksb;           // M x (S - 1)
+    double *kpart;                // M
 };
 
 // Fishnet casting (Algorithm 7): up to PS candidate points, interleaved

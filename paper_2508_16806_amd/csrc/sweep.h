@@ -97,7 +97,8 @@ __device__ __forceinline__ Seg block_seg(const OpDev &op, int lb)
     s.nblk = 1;
     s.inst = v.z;
     s.lanes_log2 = v.w & 0xff;  // lanes (bits 0-3) and rows per group (bits 4-5)
-    s.ineq = v.w >> 8;
+    s.ineq = (v.w >> 8) & 1;
+    s.sliced = (v.w >> 9) & 1;
     return s;
 }
 
@@ -142,8 +143,11 @@ __device__ __forceinline__ double group_reduce(double v)
 // A group of L lanes handles R consecutive rows (R = 1 for whole-workgroup
 // rows); their loads are interleaved so one chain of memory latencies moves
 // R rows.  MAXABS: instead of a dot product, the max over the row of
-// |(a * v) * b| with the factor vectors (Ruiz pass).
-template <int L, int NR, typename MV, typename GV, int R = 1, bool MAXABS = false, bool FAC_ROW_FIRST = true>
+// |(a * v) * b| with the factor vectors (Ruiz pass).  SLICE: only the entries
+// of column slice `pass` of each row (its entries are grouped by slice; sb
+// holds where slices 1 .. S-1 begin, relative to the row's first entry).
+template <int L, int NR, typename MV, typename GV, int R = 1, bool MAXABS = false, bool FAC_ROW_FIRST = true,
+          bool SLICE = false>
 struct RowSweep {
     static constexpr int G = (L >= WG) ? 1 : WG / L;
     static constexpr int U = (L >= WG) ? 4 : (R >= 4 ? 1 : (R == 2 ? 2 : 4));
@@ -175,7 +179,8 @@ struct RowSweep {
     __device__ __forceinline__ static void dot(const OpDev &op, const Pos &ps,
                                                const GV *__restrict__ g0, const GV *__restrict__ g1,
                                                const double *__restrict__ rowfac, double *red_lds,
-                                               double (&acc)[R][NR])
+                                               double (&acc)[R][NR], const int32_t *__restrict__ sb = nullptr,
+                                               int S = 1, int pass = 0)
     {
         const int tid = threadIdx.x;
         const int lane = ps.lane;
@@ -215,7 +220,13 @@ struct RowSweep {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const int64_t row = ps.row0 + (r < ps.nvalid ? r : ps.nvalid - 1);
-                    const int64_t b = op.rp[row], e = op.rp[row + 1];
+                    int64_t b = op.rp[row], e = op.rp[row + 1];
+                    if constexpr (SLICE) {
+                        const int32_t *rs = sb + (size_t)row * (S - 1);
+                        const int64_t b0 = b;
+                        if (pass > 0) b = b0 + rs[pass - 1];
+                        if (pass < S - 1) e = b0 + rs[pass];
+                    }
                     ob[r] = (uint32_t)(b - base);
                     oe[r] = r < ps.nvalid ? (uint32_t)(e - base) : ob[r];
                     maxlen = max(maxlen, oe[r] - ob[r]);

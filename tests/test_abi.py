@@ -53,7 +53,8 @@ def test_struct_layouts_match_header(pd):
     assert pd.Opts.batch_resident_bytes.offset == pd.Opts.fishnet_points.offset + 8
     assert o.batch_resident_bytes == 192_000_000
     assert pd.Opts.trace_capacity.offset == pd.Opts.batch_resident_bytes.offset + 8 and o.trace_capacity == 0
-    assert C.sizeof(pd.Opts) == pd.Opts.trace_capacity.offset + 8
+    assert pd.Opts.col_slices.offset == pd.Opts.trace_capacity.offset + 4 and o.col_slices == 0
+    assert C.sizeof(pd.Opts) == pd.Opts.col_slices.offset + 4
     assert C.sizeof(pd.TraceRec) == 144
     assert o.detect_infeas == 0 and o.infeas_tol == 1e-4
     assert pd.Result.eta_next.offset + 8 == C.sizeof(pd.Result)
@@ -71,7 +72,7 @@ int main(void) {
     S(pdhg_opts) S(pdhg_result) S(pdhg_trace_rec) S(pdhg_info) S(pdhg_kernel_times) S(pdhg_kkt_out) S(pdhg_lp)
     F(pdhg_trace_rec, t_inner) F(pdhg_trace_rec, kkt0) F(pdhg_trace_rec, cand_gap)
     F(pdhg_info, power_iters_max) F(pdhg_info, record_valid) F(pdhg_info, record_generation)
-    F(pdhg_opts, trace_capacity) F(pdhg_result, eta_next)
+    F(pdhg_opts, trace_capacity) F(pdhg_opts, col_slices) F(pdhg_result, eta_next)
     printf("noalloc %llu\n", (unsigned long long)PDHG_NOALLOC_MAX_BYTES);
     return 0;
 }
@@ -192,6 +193,10 @@ def test_rejects_bad_options(pd):
     assert _nbytes(pd, lp, bin_rows_primal=[1, 1, 1, 1, 1, 2, 1, 1]) == 0
     assert _nbytes(pd, lp, bin_rows_primal=[4, 4, 2, 2, 1, 0, 0, 0]) > 0
     assert _nbytes(pd, lp, bin_len_dual=[-1, 8, 16, 32, 64, 128, 512, 0]) == 0 and "bin_len" in _err(pd)
+    assert _nbytes(pd, lp, col_slices=17) == 0 and "col_slices" in _err(pd)
+    assert _nbytes(pd, lp, col_slices=-1) == 0
+    # slice starts (m x (S - 1) int32) and the partial products (m FP64)
+    assert _nbytes(pd, lp, col_slices=4) >= _nbytes(pd, lp) + lp.m * (3 * 4 + 8)
     assert _nbytes(pd, lp, trace_capacity=-1) == 0 and "trace_capacity" in _err(pd)
     assert _nbytes(pd, lp, trace_capacity=(1 << 20) + 1) == 0
     # the ring: one pdhg_trace_rec (144 bytes) per record and instance (within the carve's
@@ -219,8 +224,8 @@ def test_infinite_bounds_accepted(pd):
 
 def test_autotune_workspace_covers_every_candidate(pd):
     """pdhg_autotune without a workspace fails with NOMEM and reports a size
-    that holds every combination of limits, rows per group and launch shape
-    its search can set up."""
+    that holds every combination of limits, rows per group, launch shape and
+    column slices its search can set up."""
     from paper_2508_16806_amd.tuner import limits
 
     for lp in (lpgen.config0(0), lpgen.config2(m=3000, n=6000)):
@@ -232,10 +237,11 @@ def test_autotune_workspace_covers_every_candidate(pd):
             for ld_lim in cands:
                 for rows in (1, 2, 4):
                     rr = [rows] * 5 + [1, 1, 1]
-                    b = _nbytes(pd, lp, bin_len_primal=lp_lim, bin_len_dual=ld_lim, bin_rows_primal=rr,
-                                bin_rows_dual=rr)
-                    assert b > 0
-                    worst = max(worst, b)
+                    for S in (0, 2, 4, 8):
+                        b = _nbytes(pd, lp, bin_len_primal=lp_lim, bin_len_dual=ld_lim, bin_rows_primal=rr,
+                                    bin_rows_dual=rr, col_slices=S)
+                        assert b > 0
+                        worst = max(worst, b)
         assert need >= worst
         # and it is a bound, not a gross overestimate
         assert need <= worst * 1.05

@@ -38,6 +38,7 @@ def test_autotune_record_and_choice(orc, pd, prec, tmp_path):
     assert json.loads(out.read_text()) == rec
     assert rec["precision"] == prec
     assert len(rec["trials"]) == 7 and len(rec["rows_trials"]) == 3 and len(rec["shapes"]) == 8
+    assert [t["col_slices"] for t in rec["slice_trials"]] == [0, 2, 4, 8]
     assert sorted((t["f"], t["w"]) for t in rec["trials"]) == sorted(
         (f, w) for f in (2, 4, 8, 16) for w in (512, 2048) if w >= 64 * f)
     assert all(t["ms_primal"] > 0 and t["ms_dual"] > 0 for t in rec["trials"])
@@ -55,6 +56,10 @@ def test_autotune_record_and_choice(orc, pd, prec, tmp_path):
     bs = min(rec["shapes"], key=lambda t: t["ms_iter"])
     assert (best.xcd_remap, best.max_grid) == (bs["xcd_remap"], bs["max_grid"])
     assert (rec["xcd_remap"], rec["max_grid"]) == (bs["xcd_remap"], bs["max_grid"])
+    # column slices: kept only when a slice trial beats every shape trial
+    sl = min(rec["slice_trials"], key=lambda t: t["ms_iter"])
+    want = sl["col_slices"] if sl["ms_iter"] < bs["ms_iter"] else 0
+    assert best.col_slices == rec["col_slices"] == want
     for t in rec["shapes"]:
         assert t["ms_iter"] == pytest.approx(t["ms_primal"] + t["ms_dual"] + t["ms_check"] / 64, rel=1e-6)
     # every other option is the base's

@@ -386,6 +386,9 @@ LAYOUTS = [
     dict(bin_rows_dual=[2] * 5 + [1] * 3, bin_rows_primal=[2] * 5 + [1] * 3, xcd_remap=0, max_grid=64),
     dict(bin_len_dual=[16, 32, 64, 128, 256, 512, 2048, 0], bin_len_primal=[1, 2, 4, 8, 16, 32, 64, 0],
          xcd_remap=1, max_grid=100000),
+    # the dual sweep in column slices (rows of >= 16 S entries)
+    dict(col_slices=4),
+    dict(col_slices=3, bin_rows_dual=[2] * 5 + [1] * 3, xcd_remap=1, max_grid=64),
 ]
 
 
