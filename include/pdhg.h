@@ -189,6 +189,13 @@ typedef struct {
      * with fixed steps and to pdhg_iterate without recording; the adaptive
      * step, the recorded steps of the adjoint and fishnet sweep whole rows. */
     int32_t col_slices;
+    /* The same for the primal sweep (the product K~^T y): rows of K~^T
+     * (columns of the LP) with at least 16 S entries are swept in S passes
+     * over the row ranges [s m/S, (s+1) m/S) of K~ of their instance, so each
+     * pass gathers from an m/S-entry slice of y; 0 or 1: none (default).
+     * The entries of every column are in row order, so slicing changes no
+     * entry order, only where the FP64 sums are split. */
+    int32_t col_slices_t;
 } pdhg_opts;
 
 /* Relative KKT error terms (Section 2.3.2, conditions term1-term3) on the
@@ -429,8 +436,8 @@ int pdhg_time_kernels(pdhg_handle *h, int32_t reps, pdhg_kernel_times *out, hipS
  *   rows per lane group in bins 0..4: 1, 2 or 4, best per operator;
  *   launch shape: xcd_remap in {0, 1} x max_grid in {4096, 8192, 16384,
  *          65536}, best by primal + dual + check / check_every;
- *   col_slices of the dual sweep in {0, 2, 4, 8} on that layout, by the
- *          same sum;
+ *   col_slices (dual sweep) and col_slices_t (primal sweep) in
+ *          {0, 2, 4, 8} on that layout, each by its own sweep's time;
  * every other option is taken from *base.  *best receives the chosen
  * options; out_json (may be NULL) a JSON record of every trial and the
  * choice.  Each trial sets the LP up in the caller's workspace `ws`, which

@@ -62,7 +62,8 @@ class Opts(C.Structure):
                 ("bin_len_primal", C.c_int32 * 8), ("bin_rows_dual", C.c_int32 * 8),
                 ("bin_rows_primal", C.c_int32 * 8), ("max_grid", C.c_int32), ("adaptive_step", C.c_int32),
                 ("detect_infeas", C.c_int32), ("infeas_tol", C.c_double), ("fishnet_points", C.c_int32),
-                ("batch_resident_bytes", C.c_int64), ("trace_capacity", C.c_int32), ("col_slices", C.c_int32)]
+                ("batch_resident_bytes", C.c_int64), ("trace_capacity", C.c_int32), ("col_slices", C.c_int32),
+                ("col_slices_t", C.c_int32)]
 
 
 class TraceRec(C.Structure):

@@ -88,6 +88,7 @@ extern "C" void pdhg_default_opts(pdhg_opts *o)
     o->batch_resident_bytes = 192000000;
     o->trace_capacity = 0;
     o->col_slices = 0;
+    o->col_slices_t = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -184,8 +185,11 @@ struct SegH {
     int32_t sliced = 0;  // rows swept in column slices (dual operator)
 };
 
-// rows of K swept in column slices: at least 16 entries per slice
-static bool row_sliced(int64_t len, int S) { return S > 1 && len >= 16 * (int64_t)S; }
+// rows of K (of K^T) swept in column slices: at least SLICE_MIN (SLICE_MIN_T)
+// entries per slice on average
+constexpr int64_t SLICE_MIN = 16, SLICE_MIN_T = 16;
+static bool row_sliced(int64_t len, int S) { return S > 1 && len >= SLICE_MIN * S; }
+static bool row_sliced_t(int64_t len, int S) { return S > 1 && len >= SLICE_MIN_T * S; }
 
 struct InstPlan {
     int64_t n, m, m1, nnz;
@@ -231,7 +235,7 @@ static int seg_group(int code)
     return (lanes_log2 >= 8 ? 1 : (WG >> lanes_log2)) << rows_log2;
 }
 
-static void plan_instance(const HostLP &h, const Bins &bins, const Bins &tbins, int S, InstPlan &p)
+static void plan_instance(const HostLP &h, const Bins &bins, const Bins &tbins, int S, int St, InstPlan &p)
 {
     p.n = h.n;
     p.m = h.m;
@@ -260,19 +264,27 @@ static void plan_instance(const HostLP &h, const Bins &bins, const Bins &tbins, 
             p.segK.push_back(sh);
             p.row_order.insert(p.row_order.end(), v.begin(), v.end());
         }
-    // columns: ordered by bin of their entry count, stable
+    // columns: whole rows of K^T, then rows swept in St slices (binned by
+    // their per-slice count), each ordered by bin of their entry count, stable
     std::vector<int64_t> cnt(h.n, 0);
     for (int64_t k = 0; k < h.nnz; ++k) cnt[h.ci[k]]++;
-    std::vector<std::vector<int32_t>> cb(NBIN);
-    for (int64_t j = 0; j < h.n; ++j) cb[bin_of(tbins, cnt[j])].push_back((int32_t)j);
+    std::vector<std::vector<int32_t>> cb(2 * NBIN);
+    for (int64_t j = 0; j < h.n; ++j) {
+        const int sl = row_sliced_t(cnt[j], St) ? 1 : 0;
+        cb[sl * NBIN + bin_of(tbins, sl ? (cnt[j] + St - 1) / St : cnt[j])].push_back((int32_t)j);
+    }
     p.col_order.clear();
     p.col_order.reserve(h.n);
     p.segT.clear();
-    for (int b = 0; b < NBIN; ++b) {
-        if (cb[b].empty()) continue;
-        p.segT.push_back({(int64_t)p.col_order.size(), (int32_t)cb[b].size(), tbins.code[b], 0});
-        p.col_order.insert(p.col_order.end(), cb[b].begin(), cb[b].end());
-    }
+    for (int g = 0; g < 2; ++g)
+        for (int b = 0; b < NBIN; ++b) {
+            auto &v = cb[g * NBIN + b];
+            if (v.empty()) continue;
+            SegH sh{(int64_t)p.col_order.size(), (int32_t)v.size(), tbins.code[b], 0};
+            sh.sliced = g;
+            p.segT.push_back(sh);
+            p.col_order.insert(p.col_order.end(), v.begin(), v.end());
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -313,7 +325,8 @@ struct Buffers {
     double *vecN64c;
     int32_t *l2inst;
     int64_t *bcumK, *bcumT;  // block cost prefix sums
-    int32_t *Ksb;            // column-slice starts of every row of K (col_slices > 1)
+    int32_t *Ksb, *Ktsb;     // column-slice starts of every row of K / K^T (col_slices(_t) > 1)
+    double *Kpart, *Ktpart;  // FP64 partial products of the sliced rows
 };
 
 struct pdhg_handle {
@@ -410,11 +423,11 @@ static void carve(Carve &cv, const Sizes &sz, int prec, const pdhg_opts &o, Dev 
     d.kx1 = cv.take<double>(M);
     d.xam = cv.take<char>(N * es);
     d.yam = cv.take<char>(M * es);
-    const int S = o.col_slices > 1 ? o.col_slices : 1;
-    d.col_slices = S;
+    const int S = o.col_slices > 1 ? o.col_slices : 1, St = o.col_slices_t > 1 ? o.col_slices_t : 1;
     b.Ksb = S > 1 ? cv.take<int32_t>((size_t)M * (S - 1)) : nullptr;
-    d.ksb = b.Ksb;
-    d.kpart = S > 1 ? cv.take<double>(M) : nullptr;
+    b.Kpart = S > 1 ? cv.take<double>(M) : nullptr;
+    b.Ktsb = St > 1 ? cv.take<int32_t>((size_t)N * (St - 1)) : nullptr;
+    b.Ktpart = St > 1 ? cv.take<double>(N) : nullptr;
     d.actK = cv.take<int32_t>(sz.nblkK + 1);
     d.actT = cv.take<int32_t>(sz.nblkT + 1);
     d.act_cnt = cv.take<int32_t>(2);
@@ -506,8 +519,8 @@ static int check_opts(const pdhg_opts *o)
         if (o->bin_len_dual[k] < 0 || o->bin_len_primal[k] < 0)
             return fail(PDHG_ERR_INVALID_ARG, "bin_len[%d] must be >= 0", k);
     }
-    if (o->col_slices < 0 || o->col_slices > 16)
-        return fail(PDHG_ERR_INVALID_ARG, "col_slices must be in 0..16");
+    if (o->col_slices < 0 || o->col_slices > 16 || o->col_slices_t < 0 || o->col_slices_t > 16)
+        return fail(PDHG_ERR_INVALID_ARG, "col_slices and col_slices_t must be in 0..16");
     if (o->trace_capacity < 0 || o->trace_capacity > (1 << 20))
         return fail(PDHG_ERR_INVALID_ARG, "trace_capacity must be in 0..2^20");
     return PDHG_OK;
@@ -631,7 +644,7 @@ static int plan_all(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, std::v
                 msgs[b] = g_err;  // the message is per thread
                 return;
             }
-            plan_instance(hosts[b], bins, tbins, o->col_slices, plans[b]);
+            plan_instance(hosts[b], bins, tbins, o->col_slices, o->col_slices_t, plans[b]);
         } catch (...) {
             rcs[b] = PDHG_ERR_NOMEM;
             msgs[b] = "host memory exhausted";
@@ -719,7 +732,8 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
     std::vector<int4> Kbd(sz.nblkK), Ktbd(sz.nblkT);
     hvec<double> Kv(sz.NNZ), Ktv(sz.NNZ);
     const int S = h->opts.col_slices > 1 ? h->opts.col_slices : 1;
-    hvec<int32_t> Ksb(S > 1 ? (size_t)sz.M * (S - 1) : 0);
+    const int St = h->opts.col_slices_t > 1 ? h->opts.col_slices_t : 1;
+    hvec<int32_t> Ksb(S > 1 ? (size_t)sz.M * (S - 1) : 0), Ktsb(St > 1 ? (size_t)sz.N * (St - 1) : 0);
     const int HT = host_threads();
     std::vector<Seg> Kseg, Ktseg;
     std::vector<int32_t> l2inst;
@@ -844,6 +858,28 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
                 }
             });
         }
+        // slices of the rows of K^T swept in St passes: every column lists its
+        // rows in increasing order, so slice t (rows [t Wt, (t + 1) Wt) of the
+        // instance) is a contiguous run; record where runs 1 .. St-1 begin
+        if (St > 1) {
+            const int64_t Wt = std::max<int64_t>(1, (p.m + St - 1) / St);
+            parallel_ranges(p.n, 4096, HT, [&](int, int64_t j0, int64_t j1) {
+                for (int64_t j = j0; j < j1; ++j) {
+                    int32_t *sb = Ktsb.data() + (size_t)(xoff + j) * (St - 1);
+                    const int64_t b = Ktrp[xoff + j], e = Ktrp[xoff + j + 1];
+                    if (!row_sliced_t(e - b, St)) {
+                        for (int t = 1; t < St; ++t) sb[t - 1] = 0;
+                        continue;
+                    }
+                    int64_t k = b;
+                    for (int t = 1; t < St; ++t) {
+                        const int64_t lim = yoff + t * Wt;
+                        while (k < e && Ktci[k] < lim) ++k;
+                        sb[t - 1] = (int32_t)(k - b);
+                    }
+                }
+            });
+        }
         for (int64_t j = 0; j < p.n; ++j) {
             const int32_t cj = p.col_order[j];
             col_orig[xoff + j] = cj;
@@ -937,7 +973,7 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
                 const int G = seg_group(sg.lanes_log2);
                 const int64_t r0 = sg.row0 + (int64_t)t * G;
                 const int nr = (int)std::min<int64_t>(G, sg.row0 + sg.nrows - r0);
-                Ktbd[blkT + t] = make_int4((int)r0, nr, bi, sg.lanes_log2);
+                Ktbd[blkT + t] = make_int4((int)r0, nr, bi, sg.lanes_log2 | (sg.sliced << 9));
             }
             blkT += sg.nblk;
             Ktseg.push_back(sg);
@@ -948,7 +984,11 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
         for (int t = 0; t < in.l2cnt; ++t) l2inst.push_back(bi);
     }
     // no row long enough to slice: one whole-row pass
-    if (std::none_of(Kseg.begin(), Kseg.end(), [](const Seg &g) { return g.sliced != 0; })) d.col_slices = 1;
+    auto any_sliced = [](const std::vector<Seg> &v) {
+        return std::any_of(v.begin(), v.end(), [](const Seg &g) { return g.sliced != 0; });
+    };
+    if (!any_sliced(Kseg)) d.K.slices = 1;
+    if (!any_sliced(Ktseg)) d.Kt.slices = 1;
     // block costs for the XCD split of the sweeps: entries + 4 per row
     std::vector<int64_t> cumK(sz.nblkK + 1, 0), cumT(sz.nblkT + 1, 0);
     for (int64_t t = 0; t < sz.nblkK; ++t)
@@ -980,7 +1020,8 @@ static int upload(pdhg_handle *h, std::vector<HostLP> &hosts, hipStream_t s)
         (rc = h2d(d.inst_of_row, inst_row.data(), inst_row.size(), s)) ||
         (rc = h2d((InstInfo *)d.info, h->info.data(), h->info.size(), s)) ||
         (rc = h2d(b.l2inst, l2inst.data(), l2inst.size(), s)) ||
-        (S > 1 && (rc = h2d(b.Ksb, Ksb.data(), Ksb.size(), s))))
+        (S > 1 && (rc = h2d(b.Ksb, Ksb.data(), Ksb.size(), s))) ||
+        (St > 1 && (rc = h2d(b.Ktsb, Ktsb.data(), Ktsb.size(), s))))
         return rc;
     // the host images die with this scope: wait for the copies
     HIPCHK(hipStreamSynchronize(s));
@@ -1180,6 +1221,12 @@ static int setup_impl(const pdhg_lp *lp, int32_t batch, const pdhg_opts *o, void
                 (int32_t)h->sz.nblkK, rmK};
     d.Kt = OpDev{h->sz.N, b.Ktrp, b.Ktci, b.Ktv32, b.Ktv64, b.Ktseg, b.Ktbs, b.Ktbd, (int32_t)h->sz.nsegT,
                  (int32_t)h->sz.nblkT, rmT};
+    d.K.slices = o->col_slices > 1 ? o->col_slices : 1;
+    d.K.sb = b.Ksb;
+    d.K.part = b.Kpart;
+    d.Kt.slices = o->col_slices_t > 1 ? o->col_slices_t : 1;
+    d.Kt.sb = b.Ktsb;
+    d.Kt.part = b.Ktpart;
     if (dev_done) {
         d.hdone = dev_done;
     } else {
@@ -1535,7 +1582,7 @@ static int iterate_impl(pdhg_handle *h, int64_t k, int32_t record, hipStream_t s
 {
     Dev d = h->d;
     // recorded steps sweep whole rows, as the adjoint's replay of them does
-    if (record) d.col_slices = 1;
+    if (record) d.K.slices = d.Kt.slices = 1;
     // fixed steps use the handle's tau / sigma and ignore done flags
     std::vector<InstState> st = h->st0;
     for (auto &x : st) x.done = 0;
@@ -2175,10 +2222,10 @@ std::vector<pdhg_opts> tune_stage(const pdhg_opts &base, int stage, const pdhg_o
             if (tag) tag->push_back(r);
         }
     } else if (stage == 3) {
-        // column slices of the dual sweep, on the chosen layout (bp)
+        // column slices of both sweeps, on the chosen layout (bp)
         for (int S : {0, 2, 4, 8}) {
             pdhg_opts o = bp;
-            o.col_slices = S;
+            o.col_slices = o.col_slices_t = S;
             out.push_back(o);
             if (tag) tag->push_back(S);
         }
@@ -2240,14 +2287,14 @@ static int autotune_impl(const pdhg_lp *lp, int32_t batch, const pdhg_opts *base
     // the most blocks and segments any limit set gives with one row per group
     // (and with every column-slice count of the last stage, whose sliced rows
     // form segments and blocks of their own)
-    const int slice_cand[] = {base->col_slices, 0, 2, 4, 8};
+    const int slice_cand[] = {std::max(base->col_slices, base->col_slices_t), 0, 2, 4, 8};
     Sizes bound{};
     {
         std::vector<int> t0;
         for (pdhg_opts o : tune_stage(*base, 0, *base, *base, &t0))
             for (int S : slice_cand) {
                 for (int k = 0; k < 8; ++k) o.bin_rows_primal[k] = o.bin_rows_dual[k] = 1;
-                o.col_slices = S;
+                o.col_slices = o.col_slices_t = S;
                 std::vector<HostLP> hosts;
                 std::vector<InstPlan> plans;
                 Sizes sz;
@@ -2274,7 +2321,7 @@ static int autotune_impl(const pdhg_lp *lp, int32_t batch, const pdhg_opts *base
         InstState *st;
         FishDev fish{};
         pdhg_opts o = *base;
-        o.col_slices = S;
+        o.col_slices = o.col_slices_t = S;
         carve(cv, bound, base->precision, o, d, b, &info, &st, &fish);
         need = std::max(need, (cv.off + 255) & ~(size_t)255);
     }
@@ -2337,15 +2384,21 @@ static int autotune_impl(const pdhg_lp *lp, int32_t batch, const pdhg_opts *base
     js += "], \"slice_trials\": [";
     tag.clear();
     nt = 0;
-    for (const pdhg_opts &o : tune_stage(*base, 3, shape, shape, &tag)) {
-        pdhg_kernel_times kt;
-        const int rc = tune_time(lp, batch, o, ws, ws_bytes, reps, s, &kt);
-        if (rc) return rc;
-        const double it = kt.ms_primal + kt.ms_dual + kt.ms_check / std::max(1, base->check_every);
-        if (it < best_it) best_it = it, shape = o, best_kt = kt;
-        js += std::string(nt ? ", " : "") + "{\"col_slices\": " + std::to_string(tag[nt]) + ", \"ms_dual\": " +
-              jnum(kt.ms_dual) + ", \"ms_iter\": " + jnum(it) + "}";
-        ++nt;
+    {
+        double bsp = INFINITY, bsd = INFINITY;
+        int sp = shape.col_slices_t, sd = shape.col_slices;
+        for (const pdhg_opts &o : tune_stage(*base, 3, shape, shape, &tag)) {
+            pdhg_kernel_times kt;
+            const int rc = tune_time(lp, batch, o, ws, ws_bytes, reps, s, &kt);
+            if (rc) return rc;
+            if (kt.ms_primal < bsp) bsp = kt.ms_primal, sp = o.col_slices_t, best_kt.ms_primal = kt.ms_primal;
+            if (kt.ms_dual < bsd) bsd = kt.ms_dual, sd = o.col_slices, best_kt.ms_dual = kt.ms_dual;
+            js += std::string(nt ? ", " : "") + "{\"col_slices\": " + std::to_string(tag[nt]) +
+                  ", \"ms_primal\": " + jnum(kt.ms_primal) + ", \"ms_dual\": " + jnum(kt.ms_dual) + "}";
+            ++nt;
+        }
+        shape.col_slices = sd;
+        shape.col_slices_t = sp;
     }
     *best = shape;
     js += "], ";
@@ -2358,6 +2411,7 @@ static int autotune_impl(const pdhg_lp *lp, int32_t batch, const pdhg_opts *base
     json_ints(js, "bin_rows_dual", shape.bin_rows_dual);
     js += ", \"xcd_remap\": " + std::to_string(shape.xcd_remap) + ", \"max_grid\": " + std::to_string(shape.max_grid) +
           ", \"col_slices\": " + std::to_string(shape.col_slices) +
+          ", \"col_slices_t\": " + std::to_string(shape.col_slices_t) +
           ", \"ms_primal\": " + jnum(best_kt.ms_primal) + ", \"ms_dual\": " + jnum(best_kt.ms_dual) +
           ", \"precision\": \"" + (base->precision == PDHG_PREC_F64 ? "f64" : "f32") + "\"}\n";
     if (out_json) {

@@ -30,11 +30,44 @@ namespace pdhg {
 // logical blocks of instances still running (see k_act_fill), so finished
 // instances of a batch cost nothing.  Each logical block computes exactly what
 // it would in a full launch.
+//
+// Column slices (op.slices = S > 1, opts.col_slices / col_slices_t): rows of
+// sliced segments keep their entries grouped by slice of the gathered vector
+// and are swept in S launches, so each launch gathers from one slice of it,
+// which stays in the L2 of each XCD.  SL selects the launch's role:
+//   SL = 0  whole rows, one launch (no slices);
+//   SL = 1  pass `pass` < S-1: the sliced rows only, their FP64 partial
+//           product over slice `pass` into op.part (pass 0 writes it, later
+//           passes add theirs);
+//   SL = 2  pass S-1: the sliced rows add their last slice to the partial,
+//           the rows of unsliced segments are swept whole, and every row is
+//           updated as with SL = 0.
+// The partial store and the update stores are in different launches, so no
+// launch chooses between two store targets for one row.
+
+// One partial pass over the rows of a sliced block (SL = 1).
+template <int L, int R, typename T>
+__device__ __forceinline__ void slice_partial(const OpDev &op, const Seg &s, int bi, const T *__restrict__ g,
+                                              double *red, int pass)
+{
+    using RS = RowSweep<L, 1, T, T, R, false, true, true>;
+    const typename RS::Pos ps = RS::locate(s, bi);
+    double acc[R][1];
+    RS::dot(op, ps, g, nullptr, nullptr, red, acc, op.sb, op.slices, pass);
+    if (ps.leader) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (r >= ps.nvalid) break;
+            const int64_t i = ps.row0 + r;
+            op.part[i] = pass > 0 ? op.part[i] + acc[r][0] : acc[r][0];
+        }
+    }
+}
 
 // MASK: also record the clip region of x (0 interior, 1 at l, 2 at u) for the
-// adjoint replay.
-template <typename T, int AVG, int MASK, int RM>
-__global__ __launch_bounds__(WG) void k_primal(Dev d, int j_in_chunk, uint8_t *__restrict__ mask)
+// adjoint replay (whole rows only).
+template <typename T, int AVG, int MASK, int RM, int SL>
+__global__ __launch_bounds__(WG) void k_primal(Dev d, int j_in_chunk, uint8_t *__restrict__ mask, int pass)
 {
     __shared__ double red[8];
     const OpDev &op = d.Kt;
@@ -51,13 +84,18 @@ __global__ __launch_bounds__(WG) void k_primal(Dev d, int j_in_chunk, uint8_t *_
     for_each_item_split(cnt, d.remap, d.act_split + 9, j_in_chunk & 1, [&](int it) {
         const int lb = full ? it : d.actT[it];
         const Seg s = block_seg(op, lb);
+        if (SL == 1 && !s.sliced) return;
         const InstState *st = d.st + s.inst;
         const double tau = st->tau;
         const double w = AVG ? 1.0 / (double)(st->t_inner + j_in_chunk + 1) : 0.0;
         const int bi = lb - s.blk0;
         dispatch_lanes<RM>(s.lanes_log2, [&](auto tag, auto rtag) {
             constexpr int L = decltype(tag)::value, R = decltype(rtag)::value;
-            using RS = RowSweep<L, 1, T, T, R>;
+            if constexpr (SL == 1) {
+                slice_partial<L, R>(op, s, bi, y, red, pass);
+                return;
+            }
+            using RS = RowSweep<L, 1, T, T, R, false, true, SL == 2>;
             const typename RS::Pos ps = RS::locate(s, bi);
             // the update's operands are loaded before the dot products so their
             // latency overlaps the streaming of the rows (unconditional loads
@@ -74,15 +112,17 @@ __global__ __launch_bounds__(WG) void k_primal(Dev d, int j_in_chunk, uint8_t *_
                 r_0[r] = AVG ? x0[jj] : T(0);
             }
             double acc[R][1];
-            RS::dot(op, ps, y, nullptr, nullptr, red, acc);
+            // SL = 2: rows of unsliced segments as one slice, the whole row
+            RS::dot(op, ps, y, nullptr, nullptr, red, acc, op.sb, s.sliced ? op.slices : 1, s.sliced ? pass : 0);
             if (ps.leader) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     if (r >= ps.nvalid) break;
                     const int64_t j = ps.row0 + r;
+                    const double g = (SL == 2 && s.sliced) ? op.part[j] + acc[r][0] : acc[r][0];
                     const double xo = (double)r_x[r], cj = (double)r_c[r], lo = (double)r_l[r];
                     const double hi = (double)r_u[r], xav = (double)r_a[r];
-                    const double v = xo - tau * (cj - acc[r][0]);
+                    const double v = xo - tau * (cj - g);
                     const double xn = v < lo ? lo : (v > hi ? hi : v);
                     const T xnT = (T)xn;
                     x[j] = xnT;
@@ -95,8 +135,8 @@ __global__ __launch_bounds__(WG) void k_primal(Dev d, int j_in_chunk, uint8_t *_
     });
 }
 
-template <typename T, int AVG, int MASK, int RM>
-__global__ __launch_bounds__(WG) void k_dual(Dev d, int j_in_chunk, uint8_t *__restrict__ mask)
+template <typename T, int AVG, int MASK, int RM, int SL>
+__global__ __launch_bounds__(WG) void k_dual(Dev d, int j_in_chunk, uint8_t *__restrict__ mask, int pass)
 {
     __shared__ double red[8];
     const OpDev &op = d.K;
@@ -110,6 +150,7 @@ __global__ __launch_bounds__(WG) void k_dual(Dev d, int j_in_chunk, uint8_t *__r
     for_each_item_split(cnt, d.remap, d.act_split, j_in_chunk & 1, [&](int it) {
         const int lb = full ? it : d.actK[it];
         const Seg s = block_seg(op, lb);
+        if (SL == 1 && !s.sliced) return;
         const InstState *st = d.st + s.inst;
         const double sigma = st->sigma;
         const double w = AVG ? 1.0 / (double)(st->t_inner + j_in_chunk + 1) : 0.0;
@@ -117,7 +158,11 @@ __global__ __launch_bounds__(WG) void k_dual(Dev d, int j_in_chunk, uint8_t *__r
         const int bi = lb - s.blk0;
         dispatch_lanes<RM>(s.lanes_log2, [&](auto tag, auto rtag) {
             constexpr int L = decltype(tag)::value, R = decltype(rtag)::value;
-            using RS = RowSweep<L, 1, T, T, R>;
+            if constexpr (SL == 1) {
+                slice_partial<L, R>(op, s, bi, xb, red, pass);
+                return;
+            }
+            using RS = RowSweep<L, 1, T, T, R, false, true, SL == 2>;
             const typename RS::Pos ps = RS::locate(s, bi);
             T r_y[R], r_q[R], r_a[R], r_0[R];
 #pragma unroll
@@ -129,98 +174,20 @@ __global__ __launch_bounds__(WG) void k_dual(Dev d, int j_in_chunk, uint8_t *__r
                 r_0[r] = AVG ? y0[ii] : T(0);
             }
             double acc[R][1];
-            RS::dot(op, ps, xb, nullptr, nullptr, red, acc);
+            RS::dot(op, ps, xb, nullptr, nullptr, red, acc, op.sb, s.sliced ? op.slices : 1, s.sliced ? pass : 0);
             if (ps.leader) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     if (r >= ps.nvalid) break;
                     const int64_t i = ps.row0 + r;
+                    const double a = (SL == 2 && s.sliced) ? op.part[i] + acc[r][0] : acc[r][0];
                     const double yo = (double)r_y[r], qi = (double)r_q[r], yav = (double)r_a[r];
-                    const double wv = yo + sigma * (qi - acc[r][0]);
+                    const double wv = yo + sigma * (qi - a);
                     const double yn = (ineq && wv < 0.0) ? 0.0 : wv;
                     const T ynT = (T)yn;
                     y[i] = ynT;
                     if (AVG) ya[i] = (T)(yav + (((double)ynT - (double)r_0[r]) - yav) * w);
                     if (MASK) mask[i] = (uint8_t)((!ineq || wv > 0.0) ? 1 : 0);
-                }
-            }
-        });
-    });
-}
-
-// The dual sweep in column slices (opts.col_slices = S > 1), pass `pass` of
-// S.  Rows of sliced segments take the product over their entries in column
-// slice `pass` only, so a pass gathers from one n/S-entry slice of xbar, which
-// stays in the L2 of each XCD.  LAST = 0 (passes 0 .. S-2) touches only the
-// sliced rows and only their FP64 partial products in kpart: pass 0 writes
-// them, later passes add theirs.  LAST = 1 (pass S-1) adds its slice to the
-// partial, sweeps the rows of unsliced segments whole, and updates y and its
-// average exactly as k_dual does.  Keeping the partial store and the y store
-// in different kernels leaves each launch a single store target per row.
-template <typename T, int AVG, int RM, int LAST>
-__global__ __launch_bounds__(WG) void k_dual_slice(Dev d, int j_in_chunk, int pass)
-{
-    __shared__ double red[8];
-    const OpDev &op = d.K;
-    T *__restrict__ y = (T *)d.y;
-    T *__restrict__ ya = (T *)d.yavg;
-    const T *__restrict__ y0 = (const T *)d.y0;
-    const T *__restrict__ q = (const T *)d.q;
-    const T *__restrict__ xb = (const T *)d.xbar;
-    double *__restrict__ part = d.kpart;
-    const int S = d.col_slices;
-    const int cnt = d.act_cnt[0];
-    const bool full = cnt == op.nblk;
-    for_each_item_split(cnt, d.remap, d.act_split, j_in_chunk & 1, [&](int it) {
-        const int lb = full ? it : d.actK[it];
-        const Seg s = block_seg(op, lb);
-        if (!LAST && !s.sliced) return;
-        const int bi = lb - s.blk0;
-        dispatch_lanes<RM>(s.lanes_log2, [&](auto tag, auto rtag) {
-            constexpr int L = decltype(tag)::value, R = decltype(rtag)::value;
-            using RS = RowSweep<L, 1, T, T, R, false, true, true>;
-            const typename RS::Pos ps = RS::locate(s, bi);
-            if constexpr (!LAST) {
-                double acc[R][1];
-                RS::dot(op, ps, xb, nullptr, nullptr, red, acc, d.ksb, S, pass);
-                if (ps.leader) {
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        if (r >= ps.nvalid) break;
-                        const int64_t i = ps.row0 + r;
-                        part[i] = pass > 0 ? part[i] + acc[r][0] : acc[r][0];
-                    }
-                }
-            } else {
-                const InstState *st = d.st + s.inst;
-                const double sigma = st->sigma;
-                const double w = AVG ? 1.0 / (double)(st->t_inner + j_in_chunk + 1) : 0.0;
-                const bool ineq = s.ineq != 0;
-                T r_y[R], r_q[R], r_a[R], r_0[R];
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int64_t ii = r < ps.nvalid ? ps.row0 + r : ps.blk_row0;
-                    r_y[r] = y[ii];
-                    r_q[r] = q[ii];
-                    r_a[r] = AVG ? ya[ii] : T(0);
-                    r_0[r] = AVG ? y0[ii] : T(0);
-                }
-                double acc[R][1];
-                // one slice, the whole row, for the rows of unsliced segments
-                RS::dot(op, ps, xb, nullptr, nullptr, red, acc, d.ksb, s.sliced ? S : 1, s.sliced ? pass : 0);
-                if (ps.leader) {
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        if (r >= ps.nvalid) break;
-                        const int64_t i = ps.row0 + r;
-                        const double a = s.sliced ? part[i] + acc[r][0] : acc[r][0];
-                        const double yo = (double)r_y[r], qi = (double)r_q[r], yav = (double)r_a[r];
-                        const double wv = yo + sigma * (qi - a);
-                        const double yn = (ineq && wv < 0.0) ? 0.0 : wv;
-                        const T ynT = (T)yn;
-                        y[i] = ynT;
-                        if (AVG) ya[i] = (T)(yav + (((double)ynT - (double)r_0[r]) - yav) * w);
-                    }
                 }
             }
         });
@@ -1687,13 +1654,26 @@ template <typename T>
 void launch_primal(const Dev &d, int j, int avg, uint8_t *mask, hipStream_t s)
 {
     const unsigned g = sweep_grid(d, d.Kt.nblk);
+    if (d.Kt.slices > 1 && !mask) {
+        // column-sliced sweep: S launches (the recorded steps sweep whole rows)
+        const int last = d.Kt.slices - 1;
+        RM_SWITCH(d.Kt.rmax, {
+            for (int pass = 0; pass < last; ++pass) LAUNCH((k_primal<T, 0, 0, RMV, 1>), g, d, j, nullptr, pass);
+            if (avg) {
+                LAUNCH((k_primal<T, 1, 0, RMV, 2>), g, d, j, nullptr, last);
+            } else {
+                LAUNCH((k_primal<T, 0, 0, RMV, 2>), g, d, j, nullptr, last);
+            }
+        });
+        return;
+    }
     RM_SWITCH(d.Kt.rmax, {
         if (mask) {
-            LAUNCH((k_primal<T, 0, 1, RMV>), g, d, j, mask);
+            LAUNCH((k_primal<T, 0, 1, RMV, 0>), g, d, j, mask, 0);
         } else if (avg) {
-            LAUNCH((k_primal<T, 1, 0, RMV>), g, d, j, mask);
+            LAUNCH((k_primal<T, 1, 0, RMV, 0>), g, d, j, mask, 0);
         } else {
-            LAUNCH((k_primal<T, 0, 0, RMV>), g, d, j, mask);
+            LAUNCH((k_primal<T, 0, 0, RMV, 0>), g, d, j, mask, 0);
         }
     });
 }
@@ -1702,26 +1682,25 @@ template <typename T>
 void launch_dual(const Dev &d, int j, int avg, uint8_t *mask, hipStream_t s)
 {
     const unsigned g = sweep_grid(d, d.K.nblk);
-    if (d.col_slices > 1 && !mask) {
-        // column-sliced sweep: S passes (the recorded steps sweep whole rows)
-        const int last = d.col_slices - 1;
+    if (d.K.slices > 1 && !mask) {
+        const int last = d.K.slices - 1;
         RM_SWITCH(d.K.rmax, {
-            for (int pass = 0; pass < last; ++pass) LAUNCH((k_dual_slice<T, 0, RMV, 0>), g, d, j, pass);
+            for (int pass = 0; pass < last; ++pass) LAUNCH((k_dual<T, 0, 0, RMV, 1>), g, d, j, nullptr, pass);
             if (avg) {
-                LAUNCH((k_dual_slice<T, 1, RMV, 1>), g, d, j, last);
+                LAUNCH((k_dual<T, 1, 0, RMV, 2>), g, d, j, nullptr, last);
             } else {
-                LAUNCH((k_dual_slice<T, 0, RMV, 1>), g, d, j, last);
+                LAUNCH((k_dual<T, 0, 0, RMV, 2>), g, d, j, nullptr, last);
             }
         });
         return;
     }
     RM_SWITCH(d.K.rmax, {
         if (mask) {
-            LAUNCH((k_dual<T, 0, 1, RMV>), g, d, j, mask);
+            LAUNCH((k_dual<T, 0, 1, RMV, 0>), g, d, j, mask, 0);
         } else if (avg) {
-            LAUNCH((k_dual<T, 1, 0, RMV>), g, d, j, mask);
+            LAUNCH((k_dual<T, 1, 0, RMV, 0>), g, d, j, mask, 0);
         } else {
-            LAUNCH((k_dual<T, 0, 0, RMV>), g, d, j, mask);
+            LAUNCH((k_dual<T, 0, 0, RMV, 0>), g, d, j, mask, 0);
         }
     });
 }

@@ -49,7 +49,7 @@ struct Seg {
     int32_t lanes_log2; // log2 of lanes per row: 0..6, or 8 (whole workgroup)
     int32_t inst;
     int32_t ineq;       // rows of this segment are ">=" rows (dual operator only)
-    int32_t sliced;     // rows swept in column slices (dual operator, opts.col_slices)
+    int32_t sliced;     // rows swept in column slices (opts.col_slices / col_slices_t)
 };
 
 struct OpDev {
@@ -64,6 +64,12 @@ struct OpDev {
     int32_t nseg;
     int32_t nblk;
     int32_t rmax;        // largest rows per lane group in any block (1, 2, 4)
+    // column slices (S > 1): for every row, the offsets from its first entry
+    // where slices 1 .. S-1 begin (nrows x (S - 1); rows of unsliced segments
+    // hold zeros), and the FP64 partial products of the sliced rows (nrows)
+    int32_t slices;
+    const int32_t *sb;
+    double *part;
 };
 
 // Immutable per-instance facts.
@@ -170,12 +176,6 @@ struct Dev {
     double *vecN64, *vecN64b;     // FP64 scratch vectors (N)
     double *vecM64, *vecM64b;     // FP64 scratch vectors (M)
     double *inst_scratch;         // batch * 16
-    // column slices of the dual sweep (opts.col_slices = S > 1): for every
-    // row of K, the offsets (from the row's first entry) where slices
-    // 1 .. S-1 begin, and the FP64 partial products of the sliced rows
-    int32_t col_slices;
-    const int32_t *ksb;           // M x (S - 1)
-    double *kpart;                // M
 };
 
 // Fishnet casting (Algorithm 7): up to PS candidate points, interleaved

@@ -10,7 +10,7 @@ for f in {2, 4, 8, 16} and w in {512, 2048}, keeps the fastest limits for each
 operator, then the rows handled by one lane group (1, 2 or 4 in the bins of at
 most 16 lanes) and the launch shape (XCD-contiguous workgroup numbering on or
 off, cap on workgroups per sweep launch), and last the column slices of the
-dual sweep (none, 2, 4 or 8).  This module writes the result as a small JSON
+primal and of the dual sweep (none, 2, 4 or 8, each by its own time).  This module writes the result as a small JSON
 tuning file that Solver and bench.py load (``tuning=``).
 
     python -m paper_2508_16806_amd.tuner --workload sced --out tuning.json
@@ -50,8 +50,8 @@ def autotune(lp, precision: str = "f32", reps: int = 20, verbose: bool = True) -
             print(f"[autotune] remap={t['xcd_remap']} grid={t['max_grid']}: primal {t['ms_primal']*1e3:.1f} us, "
                   f"dual {t['ms_dual']*1e3:.1f} us, check {t['ms_check']*1e3:.1f} us", file=sys.stderr, flush=True)
         for t in rec.get("slice_trials", []):
-            print(f"[autotune] col_slices={t['col_slices']}: dual {t['ms_dual']*1e3:.1f} us", file=sys.stderr,
-                  flush=True)
+            print(f"[autotune] col_slices={t['col_slices']}: primal {t['ms_primal']*1e3:.1f} us, dual "
+                  f"{t['ms_dual']*1e3:.1f} us", file=sys.stderr, flush=True)
     return rec
 
 
@@ -59,7 +59,7 @@ def load(path: str) -> dict:
     with open(path) as f:
         t = json.load(f)
     out = {"bin_len_primal": t["bin_len_primal"], "bin_len_dual": t["bin_len_dual"]}
-    for k in ("xcd_remap", "max_grid", "bin_rows_primal", "bin_rows_dual", "col_slices"):
+    for k in ("xcd_remap", "max_grid", "bin_rows_primal", "bin_rows_dual", "col_slices", "col_slices_t"):
         if k in t:
             out[k] = t[k]
     return out
@@ -87,7 +87,8 @@ def main():
     with open(args.out, "w") as f:
         json.dump(res, f, indent=1)
     print(json.dumps({k: res[k] for k in ("bin_len_primal", "bin_len_dual", "bin_rows_primal", "bin_rows_dual",
-                                          "xcd_remap", "max_grid", "col_slices", "ms_primal", "ms_dual")}))
+                                          "xcd_remap", "max_grid", "col_slices", "col_slices_t", "ms_primal",
+                                          "ms_dual")}))
 
 
 if __name__ == "__main__":

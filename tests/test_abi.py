@@ -54,7 +54,8 @@ def test_struct_layouts_match_header(pd):
     assert o.batch_resident_bytes == 192_000_000
     assert pd.Opts.trace_capacity.offset == pd.Opts.batch_resident_bytes.offset + 8 and o.trace_capacity == 0
     assert pd.Opts.col_slices.offset == pd.Opts.trace_capacity.offset + 4 and o.col_slices == 0
-    assert C.sizeof(pd.Opts) == pd.Opts.col_slices.offset + 4
+    assert pd.Opts.col_slices_t.offset == pd.Opts.col_slices.offset + 4 and o.col_slices_t == 0
+    assert C.sizeof(pd.Opts) == (pd.Opts.col_slices_t.offset + 4 + 7) // 8 * 8  # padded to 8-byte alignment
     assert C.sizeof(pd.TraceRec) == 144
     assert o.detect_infeas == 0 and o.infeas_tol == 1e-4
     assert pd.Result.eta_next.offset + 8 == C.sizeof(pd.Result)
@@ -72,7 +73,8 @@ int main(void) {
     S(pdhg_opts) S(pdhg_result) S(pdhg_trace_rec) S(pdhg_info) S(pdhg_kernel_times) S(pdhg_kkt_out) S(pdhg_lp)
     F(pdhg_trace_rec, t_inner) F(pdhg_trace_rec, kkt0) F(pdhg_trace_rec, cand_gap)
     F(pdhg_info, power_iters_max) F(pdhg_info, record_valid) F(pdhg_info, record_generation)
-    F(pdhg_opts, trace_capacity) F(pdhg_opts, col_slices) F(pdhg_result, eta_next)
+    F(pdhg_opts, trace_capacity) F(pdhg_opts, col_slices) F(pdhg_opts, col_slices_t)
+    F(pdhg_result, eta_next)
     printf("noalloc %llu\n", (unsigned long long)PDHG_NOALLOC_MAX_BYTES);
     return 0;
 }
@@ -195,8 +197,12 @@ def test_rejects_bad_options(pd):
     assert _nbytes(pd, lp, bin_len_dual=[-1, 8, 16, 32, 64, 128, 512, 0]) == 0 and "bin_len" in _err(pd)
     assert _nbytes(pd, lp, col_slices=17) == 0 and "col_slices" in _err(pd)
     assert _nbytes(pd, lp, col_slices=-1) == 0
-    # slice starts (m x (S - 1) int32) and the partial products (m FP64)
+    assert _nbytes(pd, lp, col_slices_t=17) == 0 and "col_slices" in _err(pd)
+    assert _nbytes(pd, lp, col_slices_t=-1) == 0
+    # slice starts (m x (S - 1) int32) and the partial products (m FP64); n
+    # of each for the primal sweep
     assert _nbytes(pd, lp, col_slices=4) >= _nbytes(pd, lp) + lp.m * (3 * 4 + 8)
+    assert _nbytes(pd, lp, col_slices_t=4) >= _nbytes(pd, lp) + lp.n * (3 * 4 + 8)
     assert _nbytes(pd, lp, trace_capacity=-1) == 0 and "trace_capacity" in _err(pd)
     assert _nbytes(pd, lp, trace_capacity=(1 << 20) + 1) == 0
     # the ring: one pdhg_trace_rec (144 bytes) per record and instance (within the carve's
@@ -239,7 +245,7 @@ def test_autotune_workspace_covers_every_candidate(pd):
                     rr = [rows] * 5 + [1, 1, 1]
                     for S in (0, 2, 4, 8):
                         b = _nbytes(pd, lp, bin_len_primal=lp_lim, bin_len_dual=ld_lim, bin_rows_primal=rr,
-                                    bin_rows_dual=rr, col_slices=S)
+                                    bin_rows_dual=rr, col_slices=S, col_slices_t=S)
                         assert b > 0
                         worst = max(worst, b)
         assert need >= worst

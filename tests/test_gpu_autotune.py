@@ -56,10 +56,10 @@ def test_autotune_record_and_choice(orc, pd, prec, tmp_path):
     bs = min(rec["shapes"], key=lambda t: t["ms_iter"])
     assert (best.xcd_remap, best.max_grid) == (bs["xcd_remap"], bs["max_grid"])
     assert (rec["xcd_remap"], rec["max_grid"]) == (bs["xcd_remap"], bs["max_grid"])
-    # column slices: kept only when a slice trial beats every shape trial
-    sl = min(rec["slice_trials"], key=lambda t: t["ms_iter"])
-    want = sl["col_slices"] if sl["ms_iter"] < bs["ms_iter"] else 0
-    assert best.col_slices == rec["col_slices"] == want
+    # column slices: each operator's fastest slice trial (ties to the first)
+    sl = rec["slice_trials"]
+    assert best.col_slices == rec["col_slices"] == min(sl, key=lambda t: t["ms_dual"])["col_slices"]
+    assert best.col_slices_t == rec["col_slices_t"] == min(sl, key=lambda t: t["ms_primal"])["col_slices"]
     for t in rec["shapes"]:
         assert t["ms_iter"] == pytest.approx(t["ms_primal"] + t["ms_dual"] + t["ms_check"] / 64, rel=1e-6)
     # every other option is the base's

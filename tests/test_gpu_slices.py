@@ -1,5 +1,6 @@
-"""The dual sweep in column slices (opts.col_slices): the same iteration as
-the whole-row sweep up to FP64 summation order.
+"""The sweeps in column slices (opts.col_slices for the dual sweep,
+opts.col_slices_t for the primal sweep): the same iteration as the whole-row
+sweeps up to FP64 summation order.
 
 Each sliced row sums its slices' FP64 partials in slice order, so results are
 checked against the oracle (FP64 steps to 1e-12 / 1e-9, restart traces check
@@ -27,22 +28,38 @@ def pd():
 
 
 def _zipf():
+    """Long rows (Zipf lengths up to 2000), columns of about 16 entries."""
     return lpgen.config2(7, m=3000, n=6000, kmax=2000)
+
+
+def _tall():
+    """Columns of about 52 entries: St = 2 slices all of them, St = 3 three
+    quarters, St = 4 a few."""
+    return lpgen.config2(7, m=4000, n=2000, kmax=1500)
 
 
 def _sliced_rows(lp, S):
     return int((np.diff(lp.rowptr) >= 16 * S).sum())
 
 
-# (slices, rows per lane group in the short-row bins): groups of 2 and 4 rows
-# give the sliced rows of one group different slice lengths per pass
-@pytest.mark.parametrize("S,rows", [(2, 1), (4, 1), (8, 1), (3, 2), (4, 4)])
-def test_sliced_steps_f64_match_oracle(orc, pd, S, rows):
-    lp = _zipf()
-    assert _sliced_rows(lp, S) > 50
+def _sliced_cols(lp, S):
+    return int((np.bincount(lp.col, minlength=lp.n) >= 16 * S).sum())
+
+
+# (LP, dual slices, primal slices, rows per lane group in the short-row bins):
+# groups of 2 and 4 rows give the sliced rows of one group different slice
+# lengths per pass
+@pytest.mark.parametrize("name,S,St,rows", [
+    ("zipf", 2, 0, 1), ("zipf", 4, 0, 1), ("zipf", 8, 0, 1), ("zipf", 3, 0, 2), ("zipf", 4, 0, 4),
+    ("tall", 0, 2, 1), ("tall", 0, 3, 1), ("tall", 0, 4, 2), ("tall", 3, 3, 2), ("tall", 2, 3, 4)])
+def test_sliced_steps_f64_match_oracle(orc, pd, name, S, St, rows):
+    lp = {"zipf": _zipf, "tall": _tall}[name]()
+    assert S == 0 or _sliced_rows(lp, S) > 50
+    assert St == 0 or _sliced_cols(lp, St) > 50
     o = orc.Oracle(lp)
     rho, kap = o.ruiz(10)
-    lay = dict(col_slices=S, bin_rows_dual=[rows] * 5 + [1] * 3)
+    rr = [rows] * 5 + [1] * 3
+    lay = dict(col_slices=S, col_slices_t=St, bin_rows_dual=rr, bin_rows_primal=rr)
     s = pd.Solver(lp, precision="f64", step_size=0.5, primal_weight=1.0, **lay)
     eta, omega = 0.9 / s.info()["knorm"], 1.3
     s = pd.Solver(lp, precision="f64", step_size=eta, primal_weight=omega, **lay)
@@ -56,9 +73,11 @@ def test_sliced_steps_f64_match_oracle(orc, pd, S, rows):
         np.testing.assert_allclose(y, yo, rtol=tol, atol=tol * (1 + np.abs(yo).max()))
 
 
-def test_sliced_restart_trace_matches_oracle_f64(orc, pd):
-    lp = _zipf()
-    s = pd.Solver(lp, precision="f64", eps=1e-6, col_slices=4, trace_capacity=4096, max_iters=200000)
+@pytest.mark.parametrize("name,S,St", [("zipf", 4, 0), ("tall", 2, 3)])
+def test_sliced_restart_trace_matches_oracle_f64(orc, pd, name, S, St):
+    lp = {"zipf": _zipf, "tall": _tall}[name]()
+    s = pd.Solver(lp, precision="f64", eps=1e-6, col_slices=S, col_slices_t=St, trace_capacity=4096,
+                  max_iters=200000)
     s.solve()
     gt, total = s.trace()
     ro = orc.Oracle(lp).solve(orc.SolveOpts(eps=1e-6, max_iters=200000), trace_cap=4096)
@@ -66,9 +85,10 @@ def test_sliced_restart_trace_matches_oracle_f64(orc, pd):
     _compare(gt, ro.trace)
 
 
-def test_sliced_solve_f32(orc, pd):
-    lp = _zipf()
-    s = pd.Solver(lp, precision="f32", eps=1e-5, col_slices=4, max_iters=200000)
+@pytest.mark.parametrize("name,S,St", [("zipf", 4, 0), ("tall", 2, 3)])
+def test_sliced_solve_f32(orc, pd, name, S, St):
+    lp = {"zipf": _zipf, "tall": _tall}[name]()
+    s = pd.Solver(lp, precision="f32", eps=1e-5, col_slices=S, col_slices_t=St, max_iters=200000)
     r = s.solve()[0]
     x, y = s.solution()
     k = orc.Oracle(lp).kkt(x, y)
@@ -80,8 +100,8 @@ def test_sliced_batched_equals_solo(pd):
     """Instances with sliced rows, with none (all rows short) and with fewer
     columns than slices, in one batch: each one bitwise as alone."""
     lps = [_zipf(), lpgen.planted(90, 200, 0.03, 5, ge_frac=0.4), lpgen.tiny(4, n=3, m=2),
-           lpgen.config2(8, m=2000, n=4000, kmax=1500)]
-    kw = dict(precision="f32", eps=1e-5, col_slices=4, max_iters=200000)
+           lpgen.config2(8, m=2000, n=4000, kmax=1500), _tall()]
+    kw = dict(precision="f32", eps=1e-5, col_slices=4, col_slices_t=2, max_iters=200000)
     b = pd.Solver(lps, batch_resident_bytes=0, **kw)
     rb = b.solve()
     for i, lp in enumerate(lps):
@@ -100,8 +120,8 @@ def test_sliced_handle_adjoint_matches_oracle(orc, pd):
     kn, _ = o.power_norm(10, max_iters=5000, tol=1e-10)
     eta, omega = 0.8 / kn, 1.7
     K = 30
-    s = pd.Solver(lp, precision="f64", col_slices=4, step_size=eta, primal_weight=omega, unroll_capacity=K,
-                  unroll_checkpoint=8)
+    s = pd.Solver(lp, precision="f64", col_slices=4, col_slices_t=2, step_size=eta, primal_weight=omega,
+                  unroll_capacity=K, unroll_checkpoint=8)
     rng = np.random.default_rng(1)
     gx, gy = rng.standard_normal(lp.n), rng.standard_normal(lp.m)
     x0 = np.clip(np.zeros(lp.n), lp.l, lp.u)
@@ -115,7 +135,7 @@ def test_sliced_handle_adjoint_matches_oracle(orc, pd):
 
 
 def test_sliced_phase_timers(pd):
-    lp = _zipf()
-    s = pd.Solver(lp, precision="f32", col_slices=4)
+    lp = _tall()
+    s = pd.Solver(lp, precision="f32", col_slices=4, col_slices_t=3)
     t = s.time_kernels(reps=5)
     assert t["ms_dual"] > 0 and t["ms_primal"] > 0
