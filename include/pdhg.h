@@ -436,8 +436,10 @@ int pdhg_time_kernels(pdhg_handle *h, int32_t reps, pdhg_kernel_times *out, hipS
  *   rows per lane group in bins 0..4: 1, 2 or 4, best per operator;
  *   launch shape: xcd_remap in {0, 1} x max_grid in {4096, 8192, 16384,
  *          65536}, best by primal + dual + check / check_every;
- *   col_slices (dual sweep) and col_slices_t (primal sweep) in
- *          {0, 2, 4, 8} on that layout, each by its own sweep's time;
+ *   column slices on that layout: none, then col_slices = col_slices_t
+ *          = S in {2, 4, 8} with each bin candidate for the dual sweep;
+ *          the fastest dual (S, bins) and the fastest primal S are kept
+ *          where they beat the unsliced sweep by at least 2%;
  * every other option is taken from *base.  *best receives the chosen
  * options; out_json (may be NULL) a JSON record of every trial and the
  * choice.  Each trial sets the LP up in the caller's workspace `ws`, which

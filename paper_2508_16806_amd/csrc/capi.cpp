@@ -2222,13 +2222,24 @@ std::vector<pdhg_opts> tune_stage(const pdhg_opts &base, int stage, const pdhg_o
             if (tag) tag->push_back(r);
         }
     } else if (stage == 3) {
-        // column slices of both sweeps, on the chosen layout (bp)
-        for (int S : {0, 2, 4, 8}) {
-            pdhg_opts o = bp;
-            o.col_slices = o.col_slices_t = S;
-            out.push_back(o);
-            if (tag) tag->push_back(S);
-        }
+        // column slices of both sweeps on the chosen layout (bp): none, then
+        // S in {2, 4, 8} with every stage-0 limit set for the dual sweep
+        // (sliced rows are binned by their per-slice length); the primal
+        // sweep keeps its limits
+        pdhg_opts o = bp;
+        o.col_slices = o.col_slices_t = 0;
+        out.push_back(o);
+        if (tag) tag->push_back(0);
+        for (int S : {2, 4, 8})
+            for (int f : {2, 4, 8, 16})
+                for (int w : {512, 2048}) {
+                    if (w < 64 * f) continue;
+                    o = bp;
+                    o.col_slices = o.col_slices_t = S;
+                    tune_limits(f, w, o.bin_len_dual);
+                    out.push_back(o);
+                    if (tag) tag->push_back(S * 10000000 + f * 100000 + w);
+                }
     } else {
         for (int remap : {0, 1})
             for (int grid : {4096, 8192, 16384, 65536}) {
@@ -2385,20 +2396,34 @@ static int autotune_impl(const pdhg_lp *lp, int32_t batch, const pdhg_opts *base
     tag.clear();
     nt = 0;
     {
-        double bsp = INFINITY, bsd = INFINITY;
-        int sp = shape.col_slices_t, sd = shape.col_slices;
+        // slices are kept only when they beat the unsliced sweep by 2%
+        double t0p = 0, t0d = 0, bsp = INFINITY, bsd = INFINITY;
+        pdhg_opts dual = shape;
+        int sp = 0;
         for (const pdhg_opts &o : tune_stage(*base, 3, shape, shape, &tag)) {
             pdhg_kernel_times kt;
             const int rc = tune_time(lp, batch, o, ws, ws_bytes, reps, s, &kt);
             if (rc) return rc;
-            if (kt.ms_primal < bsp) bsp = kt.ms_primal, sp = o.col_slices_t, best_kt.ms_primal = kt.ms_primal;
-            if (kt.ms_dual < bsd) bsd = kt.ms_dual, sd = o.col_slices, best_kt.ms_dual = kt.ms_dual;
-            js += std::string(nt ? ", " : "") + "{\"col_slices\": " + std::to_string(tag[nt]) +
+            const int t = tag[nt];
+            if (t == 0) {
+                t0p = kt.ms_primal, t0d = kt.ms_dual;
+            } else {
+                if (kt.ms_primal < bsp) bsp = kt.ms_primal, sp = o.col_slices_t;
+                if (kt.ms_dual < bsd) bsd = kt.ms_dual, dual = o;
+            }
+            js += std::string(nt ? ", " : "") + "{\"col_slices\": " + std::to_string(t / 10000000) +
+                  ", \"f\": " + std::to_string(t / 100000 % 100) + ", \"w\": " + std::to_string(t % 100000) +
                   ", \"ms_primal\": " + jnum(kt.ms_primal) + ", \"ms_dual\": " + jnum(kt.ms_dual) + "}";
             ++nt;
         }
-        shape.col_slices = sd;
-        shape.col_slices_t = sp;
+        best_kt.ms_primal = t0p, best_kt.ms_dual = t0d;
+        shape.col_slices = shape.col_slices_t = 0;
+        if (bsd <= 0.98 * t0d) {
+            shape.col_slices = dual.col_slices;
+            std::memcpy(shape.bin_len_dual, dual.bin_len_dual, sizeof shape.bin_len_dual);
+            best_kt.ms_dual = bsd;
+        }
+        if (bsp <= 0.98 * t0p) shape.col_slices_t = sp, best_kt.ms_primal = bsp;
     }
     *best = shape;
     js += "], ";

@@ -10,7 +10,8 @@ for f in {2, 4, 8, 16} and w in {512, 2048}, keeps the fastest limits for each
 operator, then the rows handled by one lane group (1, 2 or 4 in the bins of at
 most 16 lanes) and the launch shape (XCD-contiguous workgroup numbering on or
 off, cap on workgroups per sweep launch), and last the column slices of the
-primal and of the dual sweep (none, 2, 4 or 8, each by its own time).  This module writes the result as a small JSON
+two sweeps (none, or 2, 4 or 8 with every bin candidate for the dual sweep;
+kept where they beat the unsliced sweep by 2%).  This module writes the result as a small JSON
 tuning file that Solver and bench.py load (``tuning=``).
 
     python -m paper_2508_16806_amd.tuner --workload sced --out tuning.json
@@ -50,8 +51,8 @@ def autotune(lp, precision: str = "f32", reps: int = 20, verbose: bool = True) -
             print(f"[autotune] remap={t['xcd_remap']} grid={t['max_grid']}: primal {t['ms_primal']*1e3:.1f} us, "
                   f"dual {t['ms_dual']*1e3:.1f} us, check {t['ms_check']*1e3:.1f} us", file=sys.stderr, flush=True)
         for t in rec.get("slice_trials", []):
-            print(f"[autotune] col_slices={t['col_slices']}: primal {t['ms_primal']*1e3:.1f} us, dual "
-                  f"{t['ms_dual']*1e3:.1f} us", file=sys.stderr, flush=True)
+            print(f"[autotune] col_slices={t['col_slices']} f={t['f']} w={t['w']}: primal "
+                  f"{t['ms_primal']*1e3:.1f} us, dual {t['ms_dual']*1e3:.1f} us", file=sys.stderr, flush=True)
     return rec
 
 

@@ -38,17 +38,29 @@ def test_autotune_record_and_choice(orc, pd, prec, tmp_path):
     assert json.loads(out.read_text()) == rec
     assert rec["precision"] == prec
     assert len(rec["trials"]) == 7 and len(rec["rows_trials"]) == 3 and len(rec["shapes"]) == 8
-    assert [t["col_slices"] for t in rec["slice_trials"]] == [0, 2, 4, 8]
+    sl = rec["slice_trials"]
+    assert [(t["col_slices"], t["f"], t["w"]) for t in sl] == [(0, 0, 0)] + [
+        (S, f, w) for S in (2, 4, 8) for f in (2, 4, 8, 16) for w in (512, 2048) if w >= 64 * f]
     assert sorted((t["f"], t["w"]) for t in rec["trials"]) == sorted(
         (f, w) for f in (2, 4, 8, 16) for w in (512, 2048) if w >= 64 * f)
     assert all(t["ms_primal"] > 0 and t["ms_dual"] > 0 for t in rec["trials"])
     # limits: the fastest stage-0 candidate of each operator
     bp = min(rec["trials"], key=lambda t: t["ms_primal"])
-    bd = min(rec["trials"], key=lambda t: t["ms_dual"])
+    bd0 = min(rec["trials"], key=lambda t: t["ms_dual"])
     from paper_2508_16806_amd.tuner import limits
 
+    # column slices: the fastest sliced trial of each sweep where it beats
+    # the unsliced one by 2% (the dual sweep then takes that trial's bins)
+    t0, sliced = sl[0], sl[1:]
+    bd = min(sliced, key=lambda t: t["ms_dual"])
+    dual_sliced = bd["ms_dual"] <= 0.98 * t0["ms_dual"]
+    bpr = min(sliced, key=lambda t: t["ms_primal"])
+    want_t = bpr["col_slices"] if bpr["ms_primal"] <= 0.98 * t0["ms_primal"] else 0
+    assert best.col_slices == rec["col_slices"] == (bd["col_slices"] if dual_sliced else 0)
+    assert best.col_slices_t == rec["col_slices_t"] == want_t
     assert list(best.bin_len_primal) == limits(bp["f"], bp["w"]) == rec["bin_len_primal"]
-    assert list(best.bin_len_dual) == limits(bd["f"], bd["w"]) == rec["bin_len_dual"]
+    bd_lim = limits(bd["f"], bd["w"]) if dual_sliced else limits(bd0["f"], bd0["w"])
+    assert list(best.bin_len_dual) == bd_lim == rec["bin_len_dual"]
     rp = min(rec["rows_trials"], key=lambda t: t["ms_primal"])["rows"]
     rd = min(rec["rows_trials"], key=lambda t: t["ms_dual"])["rows"]
     assert list(best.bin_rows_primal) == [rp] * 5 + [1, 1, 1] == rec["bin_rows_primal"]
@@ -56,10 +68,7 @@ def test_autotune_record_and_choice(orc, pd, prec, tmp_path):
     bs = min(rec["shapes"], key=lambda t: t["ms_iter"])
     assert (best.xcd_remap, best.max_grid) == (bs["xcd_remap"], bs["max_grid"])
     assert (rec["xcd_remap"], rec["max_grid"]) == (bs["xcd_remap"], bs["max_grid"])
-    # column slices: each operator's fastest slice trial (ties to the first)
-    sl = rec["slice_trials"]
-    assert best.col_slices == rec["col_slices"] == min(sl, key=lambda t: t["ms_dual"])["col_slices"]
-    assert best.col_slices_t == rec["col_slices_t"] == min(sl, key=lambda t: t["ms_primal"])["col_slices"]
+
     for t in rec["shapes"]:
         assert t["ms_iter"] == pytest.approx(t["ms_primal"] + t["ms_dual"] + t["ms_check"] / 64, rel=1e-6)
     # every other option is the base's
