@@ -266,7 +266,7 @@ def bench_batched(args, emit=True):
     sb.close()
     del sb
     solo = []
-    for i, lp in enumerate(lps):
+    for i, lp in enumerate(lps if not getattr(args, "no_solo", False) else []):
         s = pd.Solver(lp, **kw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -277,7 +277,7 @@ def bench_batched(args, emit=True):
             print(f"[bench] one by one: {i + 1}/{B} solved, {sum(x[0] for x in solo):.1f}s so far", file=sys.stderr,
                   flush=True)
     ts = sum(x[0] for x in solo)
-    same = all(rb[i]["iters"] == solo[i][1]["iters"] for i in range(B))
+    same = all(rb[i]["iters"] == solo[i][1]["iters"] for i in range(len(solo))) if solo else None
     gaps = [abs(r["kkt"]["pobj"] - lp.f_star) / (1 + abs(lp.f_star)) for r, lp in zip(rb, lps)]
     buckets = {}
     for (dt, r, m, z) in solo:
@@ -298,8 +298,9 @@ def bench_batched(args, emit=True):
                       or "default"},
            "batched": {"seconds": tb, "lps_per_s": B / tb, "setup": setup,
                        "status": {k: sum(1 for r in rb if r["status_name"] == k) for k in set(r["status_name"] for r in rb)}},
-           "one_by_one": {"seconds": ts, "lps_per_s": B / ts, "buckets": buckets},
-           "speedup": ts / tb, "iterations_identical": same, "max_rel_obj_gap_vs_planted": max(gaps)}
+           "one_by_one": {"seconds": ts, "lps_per_s": B / ts, "buckets": buckets} if solo else None,
+           "speedup": ts / tb if solo else None, "iterations_identical": same,
+           "max_rel_obj_gap_vs_planted": max(gaps)}
     if emit:
         print(json.dumps(out), flush=True)
     return out
@@ -493,6 +494,8 @@ def main():
                          "c3: batched vs one-by-one; c4: unrolled adjoint")
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--m-max", type=int, default=50000)
+    ap.add_argument("--no-solo", action="store_true",
+                    help="--workload c3: the batched solve only (no one-by-one leg; for kernel traces)")
     ap.add_argument("--resident-bytes", type=int, default=192_000_000,
                     help="batched solve: admission budget of running instances' sweep bytes (0: all at once)")
     ap.add_argument("--calib-copy", action="store_true",
