@@ -213,3 +213,145 @@ def test_c4_backward_f32_vs_oracle(orc, pd, c4_f32, inst):
           flush=True)
     for k, e in errs.items():
         assert e <= 5e-2, (k, e)
+
+
+@pytest.fixture(scope="module")
+def c4_live(pd):
+    """The C4 handle in FP64 kept open: solved to 1e-4, K = 500 recorded steps
+    from the solutions, the gradient of sum_i c_i'x_K,i, and the forward map
+    of the same handle for finite differences (set_data keeps the matrix, the
+    Ruiz factors and the step parameters)."""
+    K, C = 500, 50
+    lps = [lpgen.config4_instance(i) for i in range(4)]
+    s = pd.Solver(lps, precision="f64", eps=1e-4, max_iters=200000, unroll_capacity=K, unroll_checkpoint=C)
+    s.solve()
+    starts = [s.solution(inst=i) for i in range(4)]
+    for i, (x, y) in enumerate(starts):
+        s.set_state(x, y, inst=i)
+    s.iterate(K, record=True)
+    g = s.backward(np.concatenate([lp.c for lp in lps]), np.zeros(sum(lp.m for lp in lps)))
+    c4 = dict(K=K, lps=lps, starts=starts, g=g)
+
+    def losses(data):
+        """Each instance's own loss c_i'x_K,i after K steps from its start with
+        the data (c, q, l, u) given per instance."""
+        s.set_data(c=np.concatenate([d["c"] for d in data]), rhs=np.concatenate([d["q"] for d in data]),
+                   l=np.concatenate([d["l"] for d in data]), u=np.concatenate([d["u"] for d in data]))
+        for i, (x, y) in enumerate(starts):
+            s.set_state(x, y, inst=i)
+        s.iterate(K)
+        return np.array([lp.c @ s.solution(inst=i, which=pd.SOL_CURRENT)[0] for i, lp in enumerate(lps)])
+
+    c4["losses"] = losses
+    yield c4
+    s.close()
+
+
+def _c4_data(lps):
+    return [dict(c=lp.c.copy(), q=lp.rhs.copy(), l=lp.l.copy(), u=lp.u.copy()) for lp in lps]
+
+
+def test_c4_backward_f64_vs_gpu_fd(pd, c4_live):
+    """FP64 at the C4 shape (4 SCED/10 LPs in one handle, K = 500 steps,
+    checkpoint every 50): the adjoint against central differences of the
+    same handle's forward map, per LP, along 32 random directions of
+    (c, q, l, u) and on 32 single coordinates (8 each of c, q and the finite
+    l and u: the 4 largest gradient entries and 4 random ones), the latter
+    with both one-sided differences.  Each
+    evaluation perturbs all four LPs at once, each along its own direction,
+    and reads each LP's own loss: the LPs share no data."""
+    c4 = c4_live
+    lps, losses = c4["lps"], c4["losses"]
+    g = [_split(c4, i) for i in range(4)]
+    rng = np.random.default_rng(7)
+    fams = ("c", "q", "l", "u")
+    fin = [dict(c=np.ones(lp.n, bool), q=np.ones(lp.m, bool), l=np.isfinite(lp.l), u=np.isfinite(lp.u))
+           for lp in lps]
+    # directions: h relative to the data's norm, small enough to cross no clip
+    # decision at the degenerate warm start (as for the oracle's map)
+    h = 1e-10
+    dir_err = [[] for _ in lps]
+    for _ in range(32):
+        vs = []
+        for i, lp in enumerate(lps):
+            base = _c4_data([lp])[0]
+            v = {}
+            for k in fams:
+                a = np.where(fin[i][k], base[k], 0.0)
+                d = rng.standard_normal(a.shape[0]) * fin[i][k]
+                v[k] = d * (np.linalg.norm(a) / max(np.linalg.norm(d), 1e-300))
+            vs.append(v)
+        plus, minus = _c4_data(lps), _c4_data(lps)
+        for i in range(4):
+            for k in fams:
+                plus[i][k] = plus[i][k] + h * vs[i][k]
+                minus[i][k] = minus[i][k] - h * vs[i][k]
+        fd = (losses(plus) - losses(minus)) / (2 * h)
+        for i in range(4):
+            an = sum(g[i][k] @ vs[i][k] for k in fams)
+            scale = sum(np.linalg.norm(g[i][k]) * np.linalg.norm(vs[i][k]) for k in fams)
+            dir_err[i].append(abs(fd[i] - an) / scale)
+    # coordinates: one-sided steps of 1e-7 of the entry's size, at least
+    # 1e-4 (the losses are ~7e7, so one ulp of a loss is ~1.5e-8 and a
+    # difference quotient carries an error of a few ulp / step; that bound,
+    # 8 ulp(L) / step, is added to the tolerances).  Where the two one-sided
+    # slopes agree the map is differentiable there and the central
+    # difference must equal the gradient entry; where they differ the
+    # coordinate sits on or near a kink (a clip decision tied at the
+    # degenerate warm start: a variable at its bound with zero reduced
+    # cost), and the adjoint's entry, the slope of the side its recorded
+    # masks took, must lie between the two one-sided slopes of a 100x
+    # shorter step.
+    coords = []
+    for i, lp in enumerate(lps):
+        cl = []
+        for k in fams:
+            idx = np.flatnonzero(fin[i][k])
+            top = idx[np.argsort(-np.abs(g[i][k][idx]))[:4]]
+            rest = rng.choice(np.setdiff1d(idx, top), 4, replace=False)
+            cl += [(k, int(j)) for j in np.concatenate([top, rest])]
+        coords.append(cl)
+    L0 = losses(_c4_data(lps))
+
+    def one_sided(t, shrink):
+        plus, minus = _c4_data(lps), _c4_data(lps)
+        dl = np.empty(4)
+        for i in range(4):
+            k, j = coords[i][t]
+            dl[i] = max(1e-7 * abs(plus[i][k][j]), 1e-4) / shrink
+            plus[i][k][j] += dl[i]
+            minus[i][k][j] -= dl[i]
+        Lp, Lm = losses(plus), losses(minus)
+        return (L0 - Lm) / dl, (Lp - L0) / dl, 8 * np.spacing(np.abs(L0)) / dl
+
+    co_err = [[] for _ in lps]
+    kinks = [0] * 4
+    for t in range(32):
+        left, right, noise = one_sided(t, 1.0)
+        scale = [max(abs(g[i][coords[i][t][0]][coords[i][t][1]]), abs(right[i]), abs(left[i]), 1e-12)
+                 for i in range(4)]
+        kinked = [abs(right[i] - left[i]) > 1e-4 * scale[i] + 2 * noise[i] for i in range(4)]
+        if any(kinked):
+            # a kink within the step: the one-sided slopes of a 100x shorter
+            # step, closer to the limits at the point itself
+            left2, right2, noise2 = one_sided(t, 100.0)
+        for i in range(4):
+            k, j = coords[i][t]
+            gj = g[i][k][j]
+            if not kinked[i]:
+                co_err[i].append(max(abs(0.5 * (right[i] + left[i]) - gj) - noise[i], 0.0) / scale[i])
+            else:
+                kinks[i] += 1
+                lo, hi = min(left2[i], right2[i]), max(left2[i], right2[i])
+                co_err[i].append(max(lo - noise2[i] - gj, gj - hi - noise2[i], 0.0) / scale[i])
+            if co_err[i][-1] > 1e-4:
+                print(f"[c4-fd] LP {i} {k}[{j}] g {gj:.9g} left {left[i]:.9g} right {right[i]:.9g}"
+                      + (f" (1/100 step: {left2[i]:.9g} {right2[i]:.9g})" if kinked[i] else ""), flush=True)
+    for i in range(4):
+        de, ce = np.array(dir_err[i]), np.array(co_err[i])
+        print(f"[c4-fd] LP {i} (loss {L0[i]:.6g}): 32 directions |fd - <g,v>| / sum |g_k||v_k| median {np.median(de):.2e} max "
+              f"{de.max():.2e}; 32 coordinates ({kinks[i]} on kinks) relative error median {np.median(ce):.2e} "
+              f"max {ce.max():.2e}", flush=True)
+    for i in range(4):
+        assert max(dir_err[i]) <= 1e-5, (i, dir_err[i])
+        assert max(co_err[i]) <= 2e-4, (i, co_err[i], coords[i])
