@@ -189,6 +189,7 @@ def oracle_leg(lp, points=None, small=False, budget_s=15.0, ttt_c1=True):
     ttt = {"C0": _oracle_time_to_tol(lpgen.config0(0))}
     if ttt_c1 and not small:
         ttt["C1"] = _oracle_time_to_tol(lp)
+        ttt["C4[0]"] = _oracle_time_to_tol(lpgen.config4_instance(0))
     cpu["time_to_1e-4"] = ttt
     return cpu, oracle_checks(lp, points or {})
 
@@ -471,6 +472,29 @@ def bench_c2(args, emit=True, shard_leg=True):
     return out, lp, point
 
 
+def measured_copy_gbs(nbytes, reps=20):
+    """Device-to-device copy bandwidth (bytes read + written per second, in
+    GB/s), timed with HIP events on the current stream: two buffer pairs of
+    `nbytes` each, copied alternately, as the iteration alternates its two
+    sweeps (so the copies, like the sweeps, find in the Infinity Cache only
+    what the other left).  The measured ceiling the sweeps are compared with."""
+    import torch
+
+    bufs = [(torch.empty(nbytes, dtype=torch.uint8, device="cuda"),
+             torch.empty(nbytes, dtype=torch.uint8, device="cuda")) for _ in range(2)]
+    for k in range(4):
+        bufs[k & 1][1].copy_(bufs[k & 1][0])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(2 * reps):
+        bufs[k & 1][1].copy_(bufs[k & 1][0])
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / (2 * reps)
+    del bufs
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def _calib_copy():
     """Three plain 256 MiB device copies: the reference kernel against which
     the FETCH_SIZE / WRITE_SIZE counters are scaled under rocprofv3 --pmc."""
@@ -572,8 +596,11 @@ def main():
     pg, dg = pb / (kt["ms_primal"] * 1e-3) / 1e9, db / (kt["ms_dual"] * 1e-3) / 1e9
     dom = "dual" if kt["ms_dual"] >= kt["ms_primal"] else "primal"
     ach = dg if dom == "dual" else pg
+    # copies that read and write as many bytes as the two sweeps move, in turn
+    copy_gbs = measured_copy_gbs(int((db + pb) // 4))
     print(f"[bench] kernels (ms): {json.dumps({k: round(v, 4) for k, v in kt.items() if k != 'reps'})} "
-          f"primal {pg:.0f} GB/s dual {dg:.0f} GB/s", file=sys.stderr, flush=True)
+          f"primal {pg:.0f} GB/s dual {dg:.0f} GB/s; device copy of the same size {copy_gbs:.0f} GB/s",
+          file=sys.stderr, flush=True)
 
     ttt = None
     points = {}  # returned points, checked by the oracle leg
@@ -593,6 +620,20 @@ def main():
         ttt["rel_kkt_fp64_recheck"] = s.kkt(x, y)["rel_kkt"]
         print(f"[bench] time to 1e-4: {tsec:.2f}s {rt['status_name']} iters={rt['iters']} "
               f"restarts={rt['restarts']}", file=sys.stderr, flush=True)
+
+    # the other configurations' time to 1e-4 from a cold start on one LP each
+    # (setup excluded), next to the oracle's in cpu_baseline.time_to_1e-4: C0
+    # in FP64 (its configuration), one C4 LP (SCED/10) in FP32
+    small_ttt = {}
+    if not args.no_ttt:
+        for name, slp, prec in (("C0", lpgen.config0(0), "f64"), ("C4[0]", lpgen.config4_instance(0), "f32")):
+            so = pd.Solver(slp, precision=prec, eps=1e-4, max_iters=400_000)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ro = so.solve()[0]
+            small_ttt[name] = {"seconds": time.perf_counter() - t0, "status": ro["status_name"],
+                               "iters": ro["iters"], "precision": prec, "rel_kkt_gpu": ro["kkt"]["rel_kkt"]}
+            so.close()
 
     # adaptive step size (Algorithm 5): its sweeps' device time and the time
     # to the same tolerance from the same cold start
@@ -740,11 +781,14 @@ def main():
         "roofline": {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": ach / PEAK_HBM_GBS, "traffic": measured_traffic(f"k_{dom}"), "kernel": f"k_{dom}",
                      "algorithmic_bytes": db if dom == "dual" else pb,
-                     "ms_per_launch": kt["ms_dual" if dom == "dual" else "ms_primal"]},
+                     "ms_per_launch": kt["ms_dual" if dom == "dual" else "ms_primal"],
+                     # against device copies that move the two sweeps' bytes in turn
+                     "measured_copy_gbs": copy_gbs, "frac_of_measured_copy": ach / copy_gbs},
         "kernels_ms": {k: v for k, v in kt.items() if k != "reps"},
         "kernel_src_sha": kernel_src_hash(),
         "sweep_gbs": {"primal": pg, "dual": dg},
         "time_to_tol": ttt,
+        "time_to_tol_small": small_ttt,
         "adaptive_step": adaptive,
         "fishnet": fish,
         "fp64_reference": ref64,
