@@ -102,6 +102,30 @@ def test_c2_tenth_scale(orc, pd):
     assert gap <= 1e-5
 
 
+def test_c2_tenth_sliced_steps_f64(orc, pd):
+    """C2 at 1/10 scale (100k x 200k, Zipf(1.5) rows) with the dual sweep in 4
+    column slices and the primal sweep in 2: FP64 fixed steps against the
+    oracle, element by element, after 1 step (1e-12) and 50 (1e-9)."""
+    lp = lpgen.config2(2, m=100_000, n=200_000)
+    o = orc.Oracle(lp)
+    rho, kap = o.ruiz(10)
+    lay = dict(col_slices=4, col_slices_t=2)
+    s = pd.Solver(lp, precision="f64", step_size=1.0, primal_weight=1.0, **lay)
+    eta, omega = 0.9 / s.info()["knorm"], 1.3
+    s.close()
+    s = pd.Solver(lp, precision="f64", step_size=eta, primal_weight=omega, **lay)
+    x0 = np.clip(np.zeros(lp.n), lp.l / kap, lp.u / kap)
+    done = 0
+    for k, tol in ((1, 1e-12), (49, 1e-9)):
+        s.iterate(k)
+        done += k
+        xs, ys = o.steps(x0, np.zeros(lp.m), eta / omega, eta * omega, done, ruiz_iters=10)
+        x, y = s.solution(which=pd.SOL_CURRENT)
+        xo, yo = np.clip(kap * xs, lp.l, lp.u), rho * ys
+        np.testing.assert_allclose(x, xo, rtol=tol, atol=tol * (1 + np.abs(xo).max()))
+        np.testing.assert_allclose(y, yo, rtol=tol, atol=tol * (1 + np.abs(yo).max()))
+
+
 def test_c2_full_solve_1e4_oracle_kkt(orc, pd):
     """C2 at its configured size (m = 1M rows, n = 2M, Zipf(1.5) row lengths,
     ~54M nonzeros), FP32 with its tuned layout: a cold-start solve to the

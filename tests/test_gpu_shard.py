@@ -27,8 +27,10 @@ def base():
     return lpgen.config2(9, m=16000, n=32000, kmax=3000)
 
 
+# lay: whole rows, or both sweeps in column slices (rows of >= 16 S entries)
+@pytest.mark.parametrize("lay", [{}, dict(col_slices=4, col_slices_t=2)], ids=["whole", "sliced"])
 @pytest.mark.parametrize("kind,p", [("rows", 0), ("rows", 7), ("cols", 0), ("cols", 5)])
-def test_shard_fixed_steps_f64(orc, pd, base, kind, p):
+def test_shard_fixed_steps_f64(orc, pd, base, kind, p, lay):
     P = 8
     if kind == "rows":
         lp = lpgen.row_block(base, p * base.m // P, (p + 1) * base.m // P)
@@ -39,7 +41,7 @@ def test_shard_fixed_steps_f64(orc, pd, base, kind, p):
     rho, kap = o.ruiz(10)
     s = pd.Solver(lp, precision="f64", ruiz_iters=10, step_size=1.0, primal_weight=1.0)
     eta, omega = 0.9 / s.info()["knorm"], 1.7
-    s = pd.Solver(lp, precision="f64", ruiz_iters=10, step_size=eta, primal_weight=omega)
+    s = pd.Solver(lp, precision="f64", ruiz_iters=10, step_size=eta, primal_weight=omega, **lay)
     x0s = np.clip(np.zeros(lp.n), lp.l / kap, lp.u / kap)
     y0s = np.zeros(lp.m)
     done = 0
