@@ -321,7 +321,11 @@ def bench_adjoint(args):
     t = time.perf_counter()
     lps = [lpgen.config4_instance(i) for i in range(B)]
     print(f"[bench] generated {B} SCED/10 LPs in {time.perf_counter() - t:.1f}s", file=sys.stderr, flush=True)
-    s = pd.Solver(lps, precision="f32", eps=1e-4, max_iters=200000, unroll_capacity=K, unroll_checkpoint=C)
+    from paper_2508_16806_amd import tuner
+
+    # the layout tuned on this batch (tuner --workload sced_tenth64)
+    tune = tuner.load(os.path.join(ROOT, "paper_2508_16806_amd", "tuning", "sced_tenth64_f32.json"))
+    s = pd.Solver(lps, precision="f32", eps=1e-4, max_iters=200000, unroll_capacity=K, unroll_checkpoint=C, **tune)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rs = s.solve()
@@ -352,7 +356,7 @@ def bench_adjoint(args):
            "steps": K, "warmup": 0, "ms_per_step": tf * 1e3 / K, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"{B} SCED-shaped LPs at 1/10 of C1 (n={lps[0].n}, m={lps[0].m}), "
-                                  f"K={K} unrolled steps, checkpoint every {C}", "nnz_total": nnz},
+                                  f"K={K} unrolled steps, checkpoint every {C}", "nnz_total": nnz, "bins": tune},
            "solve_seconds": tsolve, "solve_iters_max": max(r["iters"] for r in rs),
            "forward_seconds": tf, "backward_seconds": tbw, "backward_over_forward": tbw / tf,
            "envelope_rel_diff_dobj_dc_vs_xstar": env}

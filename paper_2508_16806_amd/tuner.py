@@ -68,7 +68,8 @@ def load(path: str) -> dict:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="sced", choices=["sced", "sced_small", "zipf", "zipf_small", "planted16"])
+    ap.add_argument("--workload", default="sced",
+                    choices=["sced", "sced_small", "sced_tenth64", "zipf", "zipf_small", "planted16"])
     ap.add_argument("--precision", default="f32")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--out", required=True)
@@ -80,7 +81,9 @@ def main():
 
     # planted16: the first 16 planted LPs of the batched workload (m ~ U{1000..50000}, n = 2.5m,
     # density U(0.1%, 1%)), tuned as one batch
+    # sced_tenth64: the differentiation workload's batch of 64 SCED-shaped LPs at 1/10 size
     lp = {"sced": lambda: lpgen.config1(), "sced_small": lambda: lpgen.sced(500, 200, 24, 125, seed=1),
+          "sced_tenth64": lambda: [lpgen.config4_instance(i) for i in range(64)],
           "zipf": lambda: lpgen.config2(), "zipf_small": lambda: lpgen.config2(m=100000, n=200000),
           "planted16": lambda: [lpgen.config3_instance(i) for i in range(16)]}[args.workload]()
     res = autotune(lp, precision=args.precision, reps=args.reps)
