@@ -438,6 +438,24 @@ def bench_c2(args, emit=True, shard_leg=True):
               flush=True)
         s.close()
         del s
+        # adaptive steps (Algorithm 5), the same cold start: the attempts'
+        # dual sweep takes the tuned column slices too
+        s = pd.Solver(lp, precision="f32", eps=1e-4, max_iters=2_000_000, time_limit=120.0, adaptive_step=1, **tune)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ra = s.solve()[0]
+        tsa = time.perf_counter() - t0
+        ka = s.time_kernels(reps=5)
+        ttt["adaptive_step"] = {"seconds": tsa, "status": ra["status_name"], "iters": ra["iters"],
+                                "accepted": ra["accepted"], "restarts": ra["restarts"],
+                                "rel_kkt_gpu": ra["kkt"]["rel_kkt"],
+                                "rel_obj_gap_vs_planted": abs(ra["kkt"]["pobj"] - lp.f_star) / (1 + abs(lp.f_star)),
+                                "ms_primal_ad": ka["ms_primal_ad"], "ms_dual_ad": ka["ms_dual_ad"],
+                                "ms_step_ad": ka["ms_step_ad"]}
+        print(f"[bench] C2 adaptive steps: time to 1e-4: {tsa:.2f}s {ra['status_name']} attempts={ra['iters']}",
+              file=sys.stderr, flush=True)
+        s.close()
+        del s
     shard = None
     if shard_leg:
         # one GPU's share of an 8-way partition, every block

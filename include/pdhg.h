@@ -186,15 +186,17 @@ typedef struct {
      * an n/S-entry slice of xbar that stays in one XCD's L2.  Such rows keep
      * their entries grouped by slice, are binned by their per-slice length,
      * and every product over them sums in that order.  Applies to pdhg_solve
-     * with fixed steps and to pdhg_iterate without recording; the adaptive
-     * step, the recorded steps of the adjoint and fishnet sweep whole rows. */
+     * (the adaptive step's dual sweep included) and to pdhg_iterate without
+     * recording; the recorded steps of the adjoint, the check and fishnet
+     * sweep whole rows. */
     int32_t col_slices;
     /* The same for the primal sweep (the product K~^T y): rows of K~^T
      * (columns of the LP) with at least 16 S entries are swept in S passes
      * over the row ranges [s m/S, (s+1) m/S) of K~ of their instance, so each
      * pass gathers from an m/S-entry slice of y; 0 or 1: none (default).
      * The entries of every column are in row order, so slicing changes no
-     * entry order, only where the FP64 sums are split. */
+     * entry order, only where the FP64 sums are split.  Fixed steps only:
+     * the adaptive step's primal sweep takes whole rows. */
     int32_t col_slices_t;
 } pdhg_opts;
 

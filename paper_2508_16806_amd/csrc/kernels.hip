@@ -283,8 +283,11 @@ __global__ __launch_bounds__(WG) void k_primal_ad(Dev d)
     });
 }
 
-template <typename T, int RM>
-__global__ __launch_bounds__(WG) void k_dual_ad(Dev d)
+// SL: the column-slice role of the launch, as for k_dual (the partial passes
+// write the sliced rows' FP64 partials of K~ x'; the last pass completes
+// them and does everything else, the per-block sums included).
+template <typename T, int RM, int SL>
+__global__ __launch_bounds__(WG) void k_dual_ad(Dev d, int pass)
 {
     __shared__ double red[8];
     __shared__ double lds[8];
@@ -295,6 +298,7 @@ __global__ __launch_bounds__(WG) void k_dual_ad(Dev d)
     for_each_item_split(cnt, d.remap, d.act_split, 0, [&](int it) {
         const int lb = full ? it : d.actK[it];
         const Seg s = block_seg(op, lb);
+        if (SL == 1 && !s.sliced) return;
         const InstState *st = d.st + s.inst;
         const int par = uniform_i(st->par);
         const double eta = uniform_d(st->eta_try), esum = uniform_d(st->eta_sum);
@@ -311,10 +315,16 @@ __global__ __launch_bounds__(WG) void k_dual_ad(Dev d)
         double *__restrict__ kxn = par ? d.kx0 : d.kx1;
         const bool ineq = s.ineq != 0;
         const int bi = lb - s.blk0;
+        if constexpr (SL == 1) {
+            dispatch_lanes<RM>(s.lanes_log2, [&](auto tag, auto rtag) {
+                slice_partial<decltype(tag)::value, decltype(rtag)::value>(op, s, bi, xc, red, pass);
+            });
+            return;
+        }
         double part[2] = {0.0, 0.0};
         dispatch_lanes<RM>(s.lanes_log2, [&](auto tag, auto rtag) {
             constexpr int L = decltype(tag)::value, R = decltype(rtag)::value;
-            using RS = RowSweep<L, 1, T, T, R>;
+            using RS = RowSweep<L, 1, T, T, R, false, true, SL == 2>;
             const typename RS::Pos ps = RS::locate(s, bi);
             T r_y[R], r_q[R], r_a[R], r_0[R];
             double r_k[R];
@@ -328,13 +338,14 @@ __global__ __launch_bounds__(WG) void k_dual_ad(Dev d)
                 r_k[r] = ldo(kx, ii);
             }
             double acc[R][1];
-            RS::dot(op, ps, xc, nullptr, nullptr, red, acc);
+            RS::dot(op, ps, xc, nullptr, nullptr, red, acc, op.sb, s.sliced ? op.slices : 1, s.sliced ? pass : 0);
             if (ps.leader) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     if (r >= ps.nvalid) break;
                     const uint32_t i = (uint32_t)(ps.row0 + r);
-                    const double a = acc[r][0], kxo = r_k[r];
+                    const double a = (SL == 2 && s.sliced) ? op.part[i] + acc[r][0] : acc[r][0];
+                    const double kxo = r_k[r];
                     const double yo = (double)r_y[r], qi = (double)r_q[r], yav = (double)r_a[r];
                     const double wv = yo + sigma * (qi - (2.0 * a - kxo));
                     const double yv = (ineq && wv < 0.0) ? 0.0 : wv;
@@ -1716,7 +1727,15 @@ template <typename T>
 void launch_dual_ad(const Dev &d, hipStream_t s)
 {
     const unsigned g = sweep_grid(d, d.K.nblk);
-    RM_SWITCH(d.K.rmax, { LAUNCH((k_dual_ad<T, RMV>), g, d); });
+    if (d.K.slices > 1) {
+        const int last = d.K.slices - 1;
+        RM_SWITCH(d.K.rmax, {
+            for (int pass = 0; pass < last; ++pass) LAUNCH((k_dual_ad<T, RMV, 1>), g, d, pass);
+            LAUNCH((k_dual_ad<T, RMV, 2>), g, d, last);
+        });
+        return;
+    }
+    RM_SWITCH(d.K.rmax, { LAUNCH((k_dual_ad<T, RMV, 0>), g, d, 0); });
 }
 
 void launch_step_ad(const Dev &d, hipStream_t s)

@@ -65,6 +65,37 @@ def test_adaptive_f64_trajectory_matches_oracle(orc, pd, name, every, iters, res
         assert np.linalg.norm(a - b) <= 1e-8 * (1.0 + np.linalg.norm(b))
 
 
+@pytest.mark.parametrize("iters", [1, 4, 16])
+def test_adaptive_sliced_dual_sweep_f64_matches_oracle(orc, pd, iters):
+    """The adaptive attempts with the dual sweep in 4 column slices (the
+    product K~x' summed slice by slice): the same decisions, step and iterate
+    as the oracle over short windows, as with whole rows."""
+    lp = _cases()["zipf"]
+    assert (np.diff(lp.rowptr) >= 64).sum() > 100
+    kw = dict(eps=1e-13, max_iters=iters, check_every=1, use_restarts=0, use_pw_update=0)
+    s = pd.Solver(lp, precision="f64", adaptive_step=1, col_slices=4, **kw)
+    r = s.solve()[0]
+    ro = orc.Oracle(lp).solve(orc.SolveOpts(adaptive_step=True, **kw))
+    assert (r["iters"], r["accepted"], r["status"]) == (ro.iters, ro.accepted, ro.status)
+    assert r["eta_next"] == pytest.approx(ro.eta_next, rel=1e-9)
+    x, y = s.solution()
+    for a, b in ((x, ro.x), (y, ro.y)):
+        assert np.linalg.norm(a - b) <= 1e-8 * (1.0 + np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_adaptive_sliced_solve(orc, pd, prec):
+    """A whole adaptive solve with the dual sweep in column slices reaches the
+    tolerance with the oracle's KKT check and the planted objective."""
+    lp = _cases()["zipf"]
+    s = pd.Solver(lp, precision=prec, eps=1e-5, max_iters=200000, adaptive_step=1, col_slices=4)
+    r = s.solve()[0]
+    x, y = s.solution()
+    k = orc.Oracle(lp).kkt(x, y)
+    assert r["status_name"] == "OPTIMAL" and k["rel_kkt"] <= 1.05e-5, (r, k)
+    assert _rel(k["pobj"], lp.f_star) <= 1e-5
+
+
 @pytest.mark.parametrize("name", ["c0", "mixed"])
 @pytest.mark.parametrize("iters", [1, 2, 3, 4])
 def test_adaptive_rejections_match_oracle(orc, pd, name, iters):
