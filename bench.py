@@ -418,7 +418,7 @@ def bench_c2(args, emit=True, shard_leg=True):
           flush=True)
     s.close()
     del s
-    ttt, point = None, None
+    ttt, point, point_ad = None, None, None
     if not args.no_ttt:
         # a cold start on a fresh handle (a later solve of one handle starts
         # from its last primal weight); setup not timed
@@ -445,6 +445,7 @@ def bench_c2(args, emit=True, shard_leg=True):
         t0 = time.perf_counter()
         ra = s.solve()[0]
         tsa = time.perf_counter() - t0
+        point_ad = s.solution()
         ka = s.time_kernels(reps=5)
         ttt["adaptive_step"] = {"seconds": tsa, "status": ra["status_name"], "iters": ra["iters"],
                                 "accepted": ra["accepted"], "restarts": ra["restarts"],
@@ -494,7 +495,7 @@ def bench_c2(args, emit=True, shard_leg=True):
            "time_to_tol": ttt, "shard": shard, "cpu_baseline": None}
     if emit:
         print(json.dumps(out), flush=True)
-    return out, lp, point
+    return out, lp, {"time_to_tol": point, "adaptive_step": point_ad}
 
 
 def measured_copy_gbs(nbytes, reps=20):
@@ -794,9 +795,11 @@ def main():
                 if rec is not None and name in checks:
                     rec["rel_kkt_oracle"] = checks[name]["rel_kkt"]
                     rec["rel_obj_gap_fp64_ref"] = abs(checks[name]["pobj"] - fref) / (1 + abs(fref))
-        if c2_point is not None:
-            c2chk = oracle_checks(c2_lp, {"time_to_tol": c2_point})
+        if c2_point is not None and c2_point["time_to_tol"] is not None:
+            c2chk = oracle_checks(c2_lp, {k: v for k, v in c2_point.items() if v is not None})
             c2["time_to_tol"]["rel_kkt_oracle"] = c2chk["time_to_tol"]["rel_kkt"]
+            if "adaptive_step" in c2chk:
+                c2["time_to_tol"]["adaptive_step"]["rel_kkt_oracle"] = c2chk["adaptive_step"]["rel_kkt"]
 
     out = {
         "metric": METRIC,
