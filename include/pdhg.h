@@ -186,9 +186,9 @@ typedef struct {
      * an n/S-entry slice of xbar that stays in one XCD's L2.  Such rows keep
      * their entries grouped by slice, are binned by their per-slice length,
      * and every product over them sums in that order.  Applies to pdhg_solve
-     * (the adaptive step's dual sweep included) and to pdhg_iterate without
-     * recording; the recorded steps of the adjoint, the check and fishnet
-     * sweep whole rows. */
+     * (the adaptive step's dual sweep and the products K~ x of its checks
+     * included) and to pdhg_iterate without recording; the recorded steps of
+     * the adjoint, pdhg_kkt and fishnet sweep whole rows. */
     int32_t col_slices;
     /* The same for the primal sweep (the product K~^T y): rows of K~^T
      * (columns of the LP) with at least 16 S entries are swept in S passes

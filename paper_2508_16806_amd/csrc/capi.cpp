@@ -425,7 +425,9 @@ static void carve(Carve &cv, const Sizes &sz, int prec, const pdhg_opts &o, Dev 
     d.yam = cv.take<char>(M * es);
     const int S = o.col_slices > 1 ? o.col_slices : 1, St = o.col_slices_t > 1 ? o.col_slices_t : 1;
     b.Ksb = S > 1 ? cv.take<int32_t>((size_t)M * (S - 1)) : nullptr;
-    b.Kpart = S > 1 ? cv.take<double>(M) : nullptr;
+    // the sweeps' partials (M), and the solve-time check's for its two
+    // candidates (2 M, the first M shared: the check runs between chunks)
+    b.Kpart = S > 1 ? cv.take<double>(2 * (size_t)M) : nullptr;
     b.Ktsb = St > 1 ? cv.take<int32_t>((size_t)N * (St - 1)) : nullptr;
     b.Ktpart = St > 1 ? cv.take<double>(N) : nullptr;
     d.actK = cv.take<int32_t>(sz.nblkK + 1);

@@ -534,8 +534,48 @@ __device__ __forceinline__ double proj_lambda(double v, double l, double u)
     return v;
 }
 
-// use_list: walk the active lists (solve); otherwise every block (caller KKT).
+// The solve-time check with K in column slices (K.slices = S > 1): passes
+// 0 .. S-2 of the products K~ x of its NC candidates over the sliced rows of
+// K, into FP64 partials (candidate a at K.part + a M); k_check<..., true>
+// adds the last slice.
 template <typename V, int NC, int RM>
+__global__ __launch_bounds__(WG) void k_check_part(Dev d, const V *__restrict__ xa0, const V *__restrict__ xa1,
+                                                   int pass)
+{
+    __shared__ double red[NC * 4];
+    const OpDev &op = d.K;
+    const int nK = d.act_cnt[0];
+    const bool fullK = nK == op.nblk;
+    for_each_item(nK, d.remap, [&](int it) {
+        const int lb = fullK ? it : d.actK[it];
+        const Seg s = block_seg(op, lb);
+        if (!s.sliced) return;
+        const int bi = lb - s.blk0;
+        dispatch_lanes<RM>(s.lanes_log2, [&](auto tag, auto rtag) {
+            constexpr int L = decltype(tag)::value, R = decltype(rtag)::value;
+            using RS = RowSweep<L, NC, double, V, R, false, true, true>;
+            const typename RS::Pos ps = RS::locate(s, bi);
+            double acc[R][NC];
+            RS::dot(op, ps, xa0, xa1, nullptr, red, acc, op.sb, op.slices, pass);
+            if (ps.leader) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (r >= ps.nvalid) break;
+                    const int64_t i = ps.row0 + r;
+#pragma unroll
+                    for (int a = 0; a < NC; ++a) {
+                        double *pa = op.part + (size_t)a * d.M;
+                        pa[i] = pass > 0 ? pa[i] + acc[r][a] : acc[r][a];
+                    }
+                }
+            }
+        });
+    });
+}
+
+// use_list: walk the active lists (solve); otherwise every block (caller KKT).
+// SLC: K's sliced rows add their last slice to k_check_part's partials.
+template <typename V, int NC, int RM, bool SLC = false>
 __global__ __launch_bounds__(WG) void k_check(Dev d, const V *__restrict__ xa0, const V *__restrict__ xa1,
                                               const V *__restrict__ ya0, const V *__restrict__ ya1,
                                               const V *__restrict__ xs, const V *__restrict__ ys,
@@ -562,7 +602,7 @@ __global__ __launch_bounds__(WG) void k_check(Dev d, const V *__restrict__ xa0, 
             for (int k = 0; k < NC * 4; ++k) sum[k] = 0.0;
             dispatch_lanes<RM>(s.lanes_log2, [&](auto tag, auto rtag) {
                 constexpr int L = decltype(tag)::value, R = decltype(rtag)::value;
-                sweep_rows<L, NC, double, V, R>(op, s, bi, xa0, xa1, nullptr, red, [&](int64_t r, const double *acc) {
+                auto row_terms = [&](int64_t r, const double *acc) {
                     const double qi = d.q64[r], rh = d.rho[r];
 #pragma unroll
                     for (int a = 0; a < NC; ++a) {
@@ -576,7 +616,26 @@ __global__ __launch_bounds__(WG) void k_check(Dev d, const V *__restrict__ xa0, 
                         sum[a * 4 + 2] += qi * ya;
                         sum[a * 4 + 3] += dy * dy;
                     }
-                });
+                };
+                if (SLC && s.sliced) {
+                    using RS = RowSweep<L, NC, double, V, R, false, true, true>;
+                    const typename RS::Pos ps = RS::locate(s, bi);
+                    double acc[R][NC];
+                    RS::dot(op, ps, xa0, xa1, nullptr, red, acc, op.sb, op.slices, op.slices - 1);
+                    if (ps.leader) {
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            if (r >= ps.nvalid) break;
+                            const int64_t i = ps.row0 + r;
+                            double tot[NC];
+#pragma unroll
+                            for (int a = 0; a < NC; ++a) tot[a] = op.part[(size_t)a * d.M + i] + acc[r][a];
+                            row_terms(i, tot);
+                        }
+                    }
+                } else {
+                    sweep_rows<L, NC, double, V, R>(op, s, bi, xa0, xa1, nullptr, red, row_terms);
+                }
             });
             block_sum<NC * 4>(sum, red);
             if (threadIdx.x == 0) {
@@ -1778,6 +1837,25 @@ void launch_check(const Dev &d, int avg, hipStream_t s)
     const T *y = (const T *)d.y, *ya = (const T *)d.yam, *y0 = (const T *)d.y0;
     const int rm = d.K.rmax > d.Kt.rmax ? d.K.rmax : d.Kt.rmax;
     if (avg) LAUNCH(k_avg_point<T>, sweep_grid(d, d.K.nblk + d.Kt.nblk), d);
+    if (d.K.slices > 1) {
+        // K's sliced rows in S passes, as the sweeps take them
+        const unsigned gk = sweep_grid(d, d.K.nblk);
+        RM_SWITCH(rm, {
+            for (int pass = 0; pass + 1 < d.K.slices; ++pass) {
+                if (avg) {
+                    LAUNCH((k_check_part<T, 2, RMV>), gk, d, x, xa, pass);
+                } else {
+                    LAUNCH((k_check_part<T, 1, RMV>), gk, d, x, x, pass);
+                }
+            }
+            if (avg) {
+                LAUNCH((k_check<T, 2, RMV, true>), g, d, x, xa, y, ya, x0, y0, 1);
+            } else {
+                LAUNCH((k_check<T, 1, RMV, true>), g, d, x, x, y, y, x0, y0, 1);
+            }
+        });
+        return;
+    }
     RM_SWITCH(rm, {
         if (avg) {
             LAUNCH((k_check<T, 2, RMV>), g, d, x, xa, y, ya, x0, y0, 1);

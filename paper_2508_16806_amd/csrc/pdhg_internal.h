@@ -66,7 +66,8 @@ struct OpDev {
     int32_t rmax;        // largest rows per lane group in any block (1, 2, 4)
     // column slices (S > 1): for every row, the offsets from its first entry
     // where slices 1 .. S-1 begin (nrows x (S - 1); rows of unsliced segments
-    // hold zeros), and the FP64 partial products of the sliced rows (nrows)
+    // hold zeros), and the FP64 partial products of the sliced rows (nrows;
+    // 2 nrows for K, whose solve-time check keeps one set per candidate)
     int32_t slices;
     const int32_t *sb;
     double *part;
