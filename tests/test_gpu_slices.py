@@ -96,13 +96,16 @@ def test_sliced_solve_f32(orc, pd, name, S, St):
     assert abs(k["pobj"] - lp.f_star) / (1 + abs(lp.f_star)) <= 1e-5
 
 
-def test_sliced_batched_equals_solo(pd):
+@pytest.mark.parametrize("budget", [0, 1])
+def test_sliced_batched_equals_solo(pd, budget):
     """Instances with sliced rows, with none (all rows short) and with fewer
-    columns than slices, in one batch: each one bitwise as alone."""
+    columns than slices, in one batch: each one bitwise as alone, with every
+    instance running at once (budget 0) and one at a time (a 1-byte budget:
+    the sliced passes then walk the blocks of the admitted instance only)."""
     lps = [_zipf(), lpgen.planted(90, 200, 0.03, 5, ge_frac=0.4), lpgen.tiny(4, n=3, m=2),
            lpgen.config2(8, m=2000, n=4000, kmax=1500), _tall()]
     kw = dict(precision="f32", eps=1e-5, col_slices=4, col_slices_t=2, max_iters=200000)
-    b = pd.Solver(lps, batch_resident_bytes=0, **kw)
+    b = pd.Solver(lps, batch_resident_bytes=budget, **kw)
     rb = b.solve()
     for i, lp in enumerate(lps):
         s = pd.Solver(lp, **kw)
