@@ -50,6 +50,16 @@ def _same(a, b):
            (ib["knorm"], ib["omega"], ib["nblk_primal"], ib["nblk_dual"])
 
 
+def test_noalloc_with_column_slices(pd):
+    """Both sweeps (and the check) in column slices: the slice starts and the
+    partial products live in the fixed array too, and the solve matches the
+    allocating set-up bit for bit, adaptive steps included."""
+    lp = lpgen.config2(7, m=3000, n=6000, kmax=2000)
+    for extra in ({}, dict(adaptive_step=1)):
+        kw = dict(precision="f32", eps=1e-5, col_slices=4, col_slices_t=2, max_iters=100000, **extra)
+        _same(_run(pd, lp, False, **kw), _run(pd, lp, True, **kw))
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_noalloc_equals_setup_twice_shrinking(pd, prec):
     big = lpgen.planted(400, 1000, 0.02, 31, ge_frac=0.4)
